@@ -1,0 +1,165 @@
+"""Pins of the oracle's multigrid pieces (paper Sec. 4)."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import multigrid as mg
+from oracle.operator import Operator, operator_from_problem, toeplitz_T
+
+
+def test_prolongation_is_bilinear_stencil():
+    # P = T(1 + cos t) K (Sec. 4.1): column J carries 1/2, 1, 1/2 at fine 2J-1, 2J, 2J+1 (1-based).
+    n = 15
+    P = mg.prolong_1d(n)
+    assert P.shape == (15, 7)
+    for J in range(1, 8):
+        col = np.zeros(n)
+        col[2 * J - 2], col[2 * J - 1], col[2 * J] = 0.5, 1.0, 0.5
+        np.testing.assert_array_equal(P[:, J - 1], col)
+
+
+def test_prolongation_reproduces_linear_functions():
+    # Remark after Lemma (lemapp): the transfer operator is bilinear interpolation.
+    n = 31
+    h = 1.0 / (n + 1)
+    xf = h * np.arange(1, n + 1)
+    xc = 2 * h * np.arange(1, 16)
+    f = lambda x, y: 0.3 + 2 * x - 1.5 * y
+    Yc, Xc = np.meshgrid(xc, xc, indexing="ij")
+    Yf, Xf = np.meshgrid(xf, xf, indexing="ij")
+    fine = mg.prolong(f(Xc, Yc), n, n)
+    # exact wherever the 4 surrounding coarse nodes are interior (the boundary value is 0, not f)
+    np.testing.assert_allclose(fine[1:-1, 1:-1], f(Xf, Yf)[1:-1, 1:-1], atol=1e-13)
+
+
+def test_full_weighting_preserves_constants():
+    n = 15
+    r = mg.restrict(np.ones((n, n)), n, n)
+    np.testing.assert_allclose(r, np.ones((7, 7)), atol=1e-15)
+
+
+def test_laplacian_galerkin_is_rediscretisation_1d():
+    # Textbook fact (g = 2 weights, Sec. 4.3): P^T tridiag(1,-2,1)_n P = tridiag(1,-2,1)_k / 2.
+    n = 31
+    T = toeplitz_T(2.0, n)
+    P = mg.prolong_1d(n)
+    np.testing.assert_allclose(P.T @ T @ P, toeplitz_T(2.0, 15) / 2, atol=1e-14)
+
+
+def _c2_op(n, steps=32):
+    p = workloads.config_c2(n, steps)
+    return operator_from_problem(p, 0.0)
+
+
+@pytest.mark.parametrize("n", [15, 31])
+def test_composed_galerkin_equals_dense_triple_product(n):
+    op = _c2_op(n)
+    dense = mg.galerkin_hierarchy_dense(op)
+    comp = mg.galerkin_hierarchy_composed(op)
+    assert len(dense) == len(comp)
+    for d, c in zip(dense[1:], comp[1:]):
+        Ad, Ac = d.dense(), c.dense()
+        np.testing.assert_allclose(Ac, Ad, rtol=1e-12, atol=1e-12 * np.abs(Ad).max())
+        np.testing.assert_allclose(c.diag(), d.diag(), rtol=1e-12)
+
+
+def test_constant_coefficient_galerkin_is_toeplitz():
+    # With constant coefficients one level of P^T (I kron T) P is again Toeplitz in x with entries
+    # (p * t * p)[2m], p = [1/2, 1, 1/2]  (odd n, coarse points injected: no corner correction).
+    n, g = 31, 1.5
+    T = toeplitz_T(g, n)
+    P = mg.prolong_1d(n)
+    C = P.T @ T @ P
+    t = np.zeros(2 * n + 1)  # t[m + n] = T[i, j] with m = i - j
+    for m in range(-n + 1, n):
+        t[m + n] = T[max(m, 0), max(-m, 0)]
+    ptp = np.convolve(np.convolve([0.5, 1, 0.5], t), [0.5, 1, 0.5])  # centre index n + 2
+    for i in range(15):
+        for j in range(15):
+            m = i - j
+            assert C[i, j] == pytest.approx(ptp[n + 2 + 2 * m], abs=1e-13)
+
+
+def test_two_grid_contracts_and_is_flat_in_n():
+    # Theorem (theorem21bis): for constant equal coefficients (SPD, s/r = O(1)) the TGM with damped
+    # Jacobi and bilinear P contracts with a constant independent of N.
+    rhos = []
+    for n in (15, 31):
+        A = operator_from_problem(workloads.config_c1(n), 0.0).dense()
+        G = mg.tgm_iteration_matrix(A, mg.prolong_2d_dense(n, n), 0.7, 1)
+        rhos.append(np.abs(np.linalg.eigvals(G)).max())
+    assert max(rhos) < 0.6 and abs(rhos[1] - rhos[0]) < 0.05, rhos
+
+
+def test_two_grid_contracts_variable_coefficients():
+    # The variable-coefficient extension at the end of Sec. 4.1: still a contraction.
+    n = 31
+    A = operator_from_problem(workloads.config_c2(n, n + 1), 0.0).dense()
+    for nu in (1, 2):
+        G = mg.tgm_iteration_matrix(A, mg.prolong_2d_dense(n, n), 0.7, nu)
+        assert np.abs(np.linalg.eigvals(G)).max() < 0.9
+
+
+def test_jacobi_damping_within_lemma_bound():
+    # Lemma (lemsmo): 0 < omega < 2 a0 / ||F||_inf, a0 = 1/r - 2(d w1^a + s/r e w1^b).
+    from oracle.weights import wsgd
+
+    p = workloads.config_c1(63)
+    a, b = p.alpha, p.beta
+    r = p.tau / (2 * p.hx ** a)
+    s = p.tau / (2 * p.hy ** b)
+    a0 = 1 / r - 2 * (wsgd(a, 2)[1] + s / r * wsgd(b, 2)[1])
+    Finf = (a - 1) * 2 ** (a + 1) + s / r * (b - 1) * 2 ** (b + 1)
+    assert 0.7 < 2 * a0 / Finf
+
+
+@pytest.mark.parametrize("variant", ["geometric", "galerkin"])
+def test_vcycle_contraction_is_mesh_independent(variant):
+    # Sec. 4.2 / Sec. 5 protocol (tau = h): the V-cycle contraction factor stays bounded away from 1
+    # and its growth with n saturates (power iteration on e <- e - V A e).
+    rates = []
+    for n in (15, 31, 63):
+        op = _c2_op(n, n + 1)
+        lv = mg.geometric_hierarchy(op) if variant == "geometric" else mg.galerkin_hierarchy_composed(op)
+        vc = mg.VCycle(lv)
+        e = np.random.default_rng(n).standard_normal((n, n))
+        for _ in range(12):
+            e_new = e - vc(op.apply(e))
+            rate = np.linalg.norm(e_new) / np.linalg.norm(e)
+            e = e_new / np.linalg.norm(e_new)
+        rates.append(rate)
+    assert max(rates) < 0.75, rates
+    assert rates[2] - rates[1] < rates[1] - rates[0], rates
+
+
+def test_geometric_and_galerkin_iteration_counts_agree():
+    # Sec. 5, Example 1 discussion: the geometric and Galerkin preconditioners need the same number
+    # of GMRES iterations.
+    from oracle.krylov import fgmres
+
+    for n in (31, 63):
+        op = _c2_op(n, n + 1)
+        b = np.random.default_rng(1).standard_normal((n, n))
+        its = [fgmres(op.apply, b, mg.VCycle(lv), rtol=1e-7, restart=20).iters
+               for lv in (mg.geometric_hierarchy(op), mg.galerkin_hierarchy_composed(op))]
+        assert abs(its[0] - its[1]) <= 1, its
+
+
+def test_vcycle_matrix_spectral_radius_small_grid():
+    # the dense error-propagation matrix I - V A: spectral radius equals the power-iteration rate
+    op = _c2_op(15, 16)
+    vc = mg.VCycle(mg.geometric_hierarchy(op))
+    G = mg.vcycle_iteration_matrix(vc)
+    assert np.abs(np.linalg.eigvals(G)).max() < 0.7
+
+
+def test_geometric_hierarchy_shapes_and_injection():
+    op = _c2_op(63)
+    lv = mg.geometric_hierarchy(op)
+    assert [l.n1 for l in lv] == [63, 31, 15, 7]
+    assert lv[1].hx == pytest.approx(2 * op.hx)
+    np.testing.assert_array_equal(lv[1].dp, op.dp[1::2, 1::2])
+    # injected coefficients equal the coefficient function sampled at the coarse points
+    p = workloads.config_c2(31, 32)
+    X, Y = np.meshgrid(np.arange(1, 32) / 32, np.arange(1, 32) / 32)
+    np.testing.assert_allclose(lv[1].dp, p.dp(X, Y, 0.0), rtol=1e-15)
