@@ -1,0 +1,189 @@
+/*
+ * fde.h -- C ABI of libfde, an MI355X (gfx950) solver for the per-time-step linear systems of the
+ * Crank-Nicolson weighted-and-shifted-Grunwald (CN-WSGD) discretisation of the 2-D two-sided
+ * space-fractional diffusion equation, preconditioned by multigrid (Moghaderi, Dehghan, Donatelli,
+ * Mazza, "Spectral analysis and multigrid preconditioners for two-dimensional space-fractional
+ * diffusion equations").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - A "field" is an array of n1*n2 values for the interior grid points, row-major [n2][n1]: row j is
+ *    y_{j+1}, column i is x_{i+1}, x varies fastest.  This is the lexicographic ordering of the vectors
+ *    u, d+-, e+-, v in Sec. 2 of the paper.
+ *  - Every array argument is a DEVICE pointer (HIP device memory of the current device), FP64, owned
+ *    by the caller.  The library never frees or retains caller memory after a call returns.
+ *  - The grid: x_i = a1 + i*hx, hx = (b1-a1)/(n1+1), i = 1..n1 (likewise y); tau is the time step
+ *    (Sec. 2, grid definition).
+ *  - The operator.  With T_g = [w_{i-j+1}] the lower-Hessenberg Toeplitz matrix of the WSGD weights
+ *    (eq. (AN): the paper's A^g is -T_g; weights of eq. (w) from the Grunwald coefficients of eq. (gk)),
+ *        L u = D+ (I kron T_a) u/hx^a + D- (I kron T_a^T) u/hx^a + E+ (T_b kron I) u/hy^b
+ *              + E- (T_b^T kron I) u/hy^b                                  (eq. (AxAy)),
+ *    and each CN step solves (I - tau/2 L^(m)) u^(m) = (I + tau/2 L^(m-1)) u^(m-1) + tau v^(m-1/2)
+ *    (eq. (CNWSGD), matrix form eq. (system)).  The paper's scaled matrix of eq. (M) is this system
+ *    matrix times 1/r, r = tau/(2 hx^a): the same solution and the same relative residuals.
+ *  - Work is ordered on the handle's HIP stream.  Calls that return statistics synchronise that
+ *    stream; all others are asynchronous.  One handle must not be used by two host threads at once.
+ *  - Return value: 0 on success, a negative FDE_E* code on a usage or device error, FDE_ENOCONV (> 0)
+ *    when the iteration limit was reached (outputs then hold the last iterate).  The text of the last
+ *    error of a handle is available from fde_last_error; errors raised before a handle exists are
+ *    available from fde_last_error(NULL).  No C++ exception crosses this interface.
+ */
+#ifndef FDE_H
+#define FDE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ---------------------------------------------------------------------------- */
+#define FDE_OK 0
+#define FDE_EINVAL (-1)      /* invalid argument (range, null pointer, unsupported size)            */
+#define FDE_ENEGCOEF (-2)    /* a diffusion coefficient is negative (Sec. 2 requires d, e >= 0)    */
+#define FDE_ENOMEM (-3)      /* device allocation failed or the request exceeds a memory budget    */
+#define FDE_ENONFINITE (-4)  /* NaN or Inf in an input or in the iterate                           */
+#define FDE_EDEVICE (-5)     /* a HIP runtime error                                                */
+#define FDE_EAGAIN (-6)      /* batch: the request does not fit now; retry after others finish     */
+#define FDE_ENOCONV 1        /* iteration limit reached before the tolerance                       */
+
+/* ---- options ---------------------------------------------------------------------------------- */
+#define FDE_FP64 0             /* every kernel in FP64                                              */
+#define FDE_MIXED_FP32 1       /* multigrid preconditioner in FP32 inside FP64 flexible GMRES        */
+#define FDE_MIXED_BF16GEMM 2   /* as FDE_MIXED_FP32, fine-level Toeplitz products as BF16 MFMA GEMMs */
+
+#define FDE_MG_GEOMETRIC 0     /* rediscretised coarse operators, Sec. 4.2 (the paper's P_MGM)      */
+#define FDE_MG_GALERKIN 1      /* Galerkin coarse operators R A P, Sec. 4 TGM step 3 (tilde P_MGM)   */
+
+typedef struct fde_handle fde_handle;
+
+/* Problem and solver description (Sec. 2 problem statement; Sec. 4.2 and Sec. 5 solver settings). */
+typedef struct fde_problem {
+  double alpha, beta;   /* fractional orders, each in (1,2) (Sec. 2)                               */
+  int32_t n1, n2;       /* interior points in x and y; multigrid needs 2^l - 1 with l >= 3         */
+  double a1, b1, a2, b2;/* domain (a1,b1) x (a2,b2), a < b                                         */
+  double tau;           /* time step, > 0                                                          */
+  int32_t precision;    /* FDE_FP64 | FDE_MIXED_FP32 | FDE_MIXED_BF16GEMM                          */
+  int32_t mg_variant;   /* FDE_MG_GEOMETRIC | FDE_MG_GALERKIN                                      */
+  double omega;         /* Jacobi damping (Lemma lemsmo), 0 < omega <= 1; 0 selects 0.7             */
+  int32_t nu_pre;       /* pre-smoothing steps per level, >= 0 (< 0 selects 1)                      */
+  int32_t nu_post;      /* post-smoothing steps per level, >= 0 (< 0 selects 1)                     */
+  int32_t coarsest_n;   /* coarsen while min(n1,n2) > coarsest_n; 0 selects 7 (the 8x8-cell grid)   */
+  int32_t restart;      /* GMRES restart length, 1..32; 0 selects 20 (Sec. 5)                      */
+  int32_t maxit;        /* total iteration limit per solve; 0 selects 200                           */
+  double rtol;          /* stop when ||b - A x||_2 <= rtol ||b||_2; 0 selects 1e-10                */
+} fde_problem;
+
+/* Per-solve statistics. */
+typedef struct fde_stats {
+  int32_t iters;        /* GMRES iterations (preconditioner applications) in this solve           */
+  int32_t restarts;     /* completed restart cycles beyond the first                               */
+  int32_t converged;    /* 1 if the true relative residual met rtol                                */
+  int32_t reserved;
+  double relres_true;   /* ||b - A x|| / ||b|| computed in FP64 from the returned x               */
+  double relres_est;    /* the Arnoldi (Givens) estimate at exit                                   */
+} fde_stats;
+
+/* Fills *p with the defaults above for the given sizes, orders and time step (unit square). */
+void fde_problem_default(fde_problem* p, double alpha, double beta, int32_t n1, int32_t n2,
+                         double tau);
+
+/* Creates a solver handle.  dp, dm, ep, em: the coefficient fields d+, d-, e+, e- at the time level
+ * of the left-hand side (Sec. 2, D+- and E+- of eq. (AxAy)); they are copied, the caller keeps them.
+ * The same fields are used for the explicit half of the next fde_step until fde_update_coeffs is
+ * called.  Builds the multigrid hierarchy on the device (geometric: coefficients injected at the
+ * coarse points, Sec. 4.2; Galerkin: R A P with R = P^T/4, Sec. 4), the Toeplitz symbols, and the
+ * LU factors of the coarsest level.  stream: a hipStream_t (NULL = the default stream).
+ * Errors: FDE_EINVAL, FDE_ENEGCOEF, FDE_ENONFINITE, FDE_ENOMEM, FDE_EDEVICE; *out is NULL then. */
+int fde_setup(const fde_problem* p, const double* dp, const double* dm, const double* ep,
+              const double* em, void* stream, fde_handle** out);
+
+/* Time-dependent coefficients (Sec. 2: D^(m) at t^(m), D^(m-1) at t^(m-1)).  The current left-hand
+ * side fields become the explicit (right-hand side) fields and the given fields become the new
+ * left-hand side; the hierarchy is rebuilt on the device.  Errors as for fde_setup. */
+int fde_update_coeffs(fde_handle* h, const double* dp, const double* dm, const double* ep,
+                      const double* em);
+
+/* One CN step (eq. (system)): b = (I + tau/2 L^(m-1)) u_prev + tau v_half, then solve
+ * (I - tau/2 L^(m)) u_next = b with GMRES(restart) right-preconditioned by one V-cycle, zero initial
+ * guess (Sec. 5).  v_half: the source at t^(m-1/2), may be NULL (no source).  u_next may not alias
+ * u_prev.  stats may be NULL.  Returns 0, FDE_ENOCONV, or an error. */
+int fde_step(fde_handle* h, const double* u_prev, const double* v_half, double* u_next,
+             fde_stats* stats);
+
+/* As fde_step with a separable source v_half = sum_k phi[k] * S[k], k < nsrc <= 4; phi is a HOST
+ * array of scalars, S a HOST array of device pointers to fields. */
+int fde_step_sources(fde_handle* h, const double* u_prev, int32_t nsrc, const double* phi,
+                     const double* const* S, double* u_next, fde_stats* stats);
+
+/* Solves (I - tau/2 L) x = b for the left-hand side operator (Sec. 2, eq. (system)) with the
+ * configured preconditioned GMRES.  x may not alias b.  stats may be NULL. */
+int fde_solve(fde_handle* h, const double* b, double* x, fde_stats* stats);
+
+/* Releases every device buffer of the handle.  NULL is ignored. */
+void fde_destroy(fde_handle* h);
+
+/* Message of the last error on h (or of the last failed fde_setup / batch call when h is NULL). */
+const char* fde_last_error(const fde_handle* h);
+
+/* ---- inspection and test hooks (the same kernels as the solver) ------------------------------ */
+
+/* Number of multigrid levels (level 0 = the fine grid). */
+int fde_num_levels(const fde_handle* h);
+/* Interior sizes of a level: n1 = (n1_{l-1} - 1)/2 (coarse J <-> fine 2J, Sec. 4.1). */
+int fde_level_size(const fde_handle* h, int level, int32_t* n1, int32_t* n2);
+
+/* y = A_level x with A_level the level-`level` matrix of the preconditioner hierarchy (level 0 =
+ * I - tau/2 L).  prec = FDE_FP64 applies the FP64 kernels, FDE_MIXED_FP32 the FP32 kernels (inputs
+ * rounded to FP32, result widened to FP64), FDE_MIXED_BF16GEMM the BF16-MFMA Toeplitz products
+ * (level 0 only).  For level 0 and prec = FDE_FP64 this is the outer operator of the solver. */
+int fde_apply(fde_handle* h, int level, int prec, const double* x, double* y);
+
+/* One damped-Jacobi step on a level (Lemma lemsmo): x <- x + omega D^-1 (b - A x), D = diag(A).
+ * With zero_guess != 0 the incoming x is ignored and treated as 0. */
+int fde_smooth(fde_handle* h, int level, int prec, const double* b, double* x, int zero_guess);
+
+/* Full-weighting restriction rc = P^T r / 4 from `level` to level+1 (Sec. 4.1, Sec. 4.2). */
+int fde_restrict(fde_handle* h, int level, int prec, const double* r, double* rc);
+
+/* Bilinear prolongation and correction x += P e from level+1 to `level` (Sec. 4.1, Lemma lemapp). */
+int fde_prolong(fde_handle* h, int level, int prec, const double* e, double* x);
+
+/* Exact solve on the coarsest level with the FP64 LU factors. */
+int fde_coarse_solve(fde_handle* h, const double* b, double* x);
+
+/* One V(nu_pre, nu_post) cycle with zero initial guess (Sec. 4 V-cycle, Sec. 4.2 settings) in the
+ * handle's preconditioner precision: x = MG(b). */
+int fde_vcycle(fde_handle* h, const double* b, double* x);
+
+/* The pointwise diagonal of A_level (used by the Jacobi smoother), as FP64. */
+int fde_level_diag(fde_handle* h, int level, double* diag);
+
+/* ---- kernel timing -----------------------------------------------------------------------------
+ * For performance reports: launches of the selected kernel families are bracketed by HIP events on
+ * the handle's stream.  Launches issued for Arnoldi steps that the device skipped (after
+ * convergence) are not counted.  bytes: the algorithmic bytes of the counted launches (every input
+ * and output field once). */
+#define FDE_KFAM_OUTER_Y 0   /* FP64 system operator, column (y) pass                            */
+#define FDE_KFAM_OUTER_X 1   /* FP64 system operator, row (x) pass with epilogue                 */
+#define FDE_KFAM_MG0_Y 2     /* fine-level preconditioner operator, column pass                  */
+#define FDE_KFAM_MG0_X 3     /* fine-level preconditioner operator, row pass (residual / Jacobi) */
+#define FDE_KFAM_MGC_Y 4     /* coarser FFT levels, column pass                                  */
+#define FDE_KFAM_MGC_X 5     /* coarser FFT levels, row pass                                     */
+#define FDE_KFAM_CGS 6       /* Gram-Schmidt passes, norms                                       */
+#define FDE_KFAM_TRANSFER 7  /* pre-smoothing from zero, restriction, prolongation               */
+#define FDE_KFAM_COARSE 8    /* one-workgroup V-cycle of the small levels                        */
+#define FDE_KFAM_UPDATE 9    /* x += Z y                                                         */
+#define FDE_KFAM_COUNT 10
+int fde_profile_enable(fde_handle* h, uint32_t family_mask);
+int fde_profile_read(fde_handle* h, int family, int64_t* launches, double* total_ms, double* bytes);
+int fde_profile_reset(fde_handle* h);
+
+/* Synchronises the handle's stream; returns FDE_EDEVICE if an asynchronous error occurred. */
+int fde_sync(fde_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FDE_H */

@@ -80,6 +80,21 @@ class Operator:
         """(I + tau/2 L) U, the explicit half of the Crank-Nicolson step."""
         return U + 0.5 * self.tau * self.L(U)
 
+    def L_points(self, U: np.ndarray, js, is_) -> np.ndarray:
+        """(L U)[j, i] at the listed points only: row j of U against row i of Tx (and Tx^T),
+        column i of U against row j of Ty (and Ty^T).  O(n) per point, for very large grids."""
+        js, is_ = np.asarray(js), np.asarray(is_)
+        out = np.empty(len(js))
+        for k, (j, i) in enumerate(zip(js, is_)):
+            row, col = U[j, :], U[:, i]
+            out[k] = (self.dp[j, i] * (self.Tx[i, :] @ row) + self.dm[j, i] * (self.Tx[:, i] @ row)
+                      + self.ep[j, i] * (self.Ty[j, :] @ col) + self.em[j, i] * (self.Ty[:, j] @ col))
+        return out
+
+    def apply_points(self, U: np.ndarray, js, is_) -> np.ndarray:
+        """(A U)[j, i] = U[j, i] - tau/2 (L U)[j, i] at the listed points."""
+        return U[np.asarray(js), np.asarray(is_)] - 0.5 * self.tau * self.L_points(U, js, is_)
+
     def diag(self) -> np.ndarray:
         """Pointwise diagonal of A: T_g has w_1 on its diagonal."""
         return 1.0 - 0.5 * self.tau * ((self.dp + self.dm) * self.Tx[0, 0]

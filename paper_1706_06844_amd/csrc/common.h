@@ -1,0 +1,156 @@
+// Internal declarations shared by the libfde sources (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+namespace fde {
+
+// Epilogue of an operator application.  With l = tau/2 * L x (both directions):
+//   APPLY  : out = x - l                         (A x, A = I - tau/2 L)
+//   RESID  : out = b - x + l                     (b - A x)
+//   JACOBI : out = x + dinv * (b - x + l)        (damped Jacobi, dinv = omega / diag(A))
+//   RHS    : out = x + l + tau * sum_k phi_k S_k (explicit CN half step plus source)
+//   LOUT   : out = l
+enum Mode : int { EP_APPLY = 0, EP_RESID = 1, EP_JACOBI = 2, EP_RHS = 3, EP_LOUT = 4 };
+
+constexpr int kMaxSrc = 4;
+struct SrcTerms {
+  int n;
+  double phi[kMaxSrc];
+  const double* S[kMaxSrc];
+};
+
+// Device view of one operator level in precision R.
+template <typename R>
+struct OpView {
+  int n1, n2;
+  int L1, L2;
+  const R* dpm;   // [n2][n1][2] = (d+, d-)
+  const R* epm;   // [n2][n1][2] = (e+, e-)
+  const R* dinv;  // [n2][n1] = omega / diag(A)
+  const R* mu_x;  // [L1][2] symbol of the x products (scale and 1/L folded in)
+  const R* mu_y;  // [L2][2]
+  const R* tw_x;  // FFT twiddles for L1
+  const R* tw_y;  // FFT twiddles for L2
+};
+
+// ---- launchers (toeplitz.hip) ------------------------------------------------------------------
+// y-pass into ay, then x-pass with the epilogue.  x may alias out for EP_JACOBI.
+template <typename R, typename Tin>
+hipError_t launch_operator(const OpView<R>& op, const Tin* x, R* ay, R* out, int mode, const R* b,
+                           const SrcTerms* src, double tau, const int* skip, hipStream_t st);
+
+// The two passes separately: ay = y part; out = epilogue(x part + ay).
+template <typename R, typename Tin>
+hipError_t launch_op_y(const OpView<R>& op, const Tin* x, R* ay, const int* skip, hipStream_t st);
+template <typename R, typename Tin>
+hipError_t launch_op_x(const OpView<R>& op, const Tin* x, const R* ay, R* out, int mode, const R* b,
+                       const SrcTerms* src, double tau, const int* skip, hipStream_t st);
+
+bool fft_length_supported(int L);
+// FFT twiddle table for length L and the plan of the given element size (4 or 8 bytes),
+// interleaved complex, computed in double precision; count = 2 * entries.
+void fft_twiddles(int L, int elem_bytes, double* out, int* count);
+int fft_twiddle_count(int L, int elem_bytes);
+// Symbol of one direction: out[k] = scale * lam[k] / L, lam = DFT of the circulant embedding of
+// T = [w_{i-j+1}] (n x n, L = 2(n+1)).  out: 2L doubles (interleaved complex).
+void toeplitz_symbol(const double* w, int n, int L, double scale, double* out);
+
+// ---- multigrid kernels (mg.hip) ----------------------------------------------------------------
+template <typename R, typename Tin>
+hipError_t launch_presmooth(int N, const Tin* b, const double* bscale, const R* dinv, R* x, R* bcopy,
+                            const int* skip, hipStream_t st);
+template <typename R>
+hipError_t launch_restrict(int n1, int n2, const R* r, R* rc, const int* skip, hipStream_t st);
+template <typename R>
+hipError_t launch_prolong(int n1, int n2, const R* e, R* x, const int* skip, hipStream_t st);
+template <typename Tout, typename Tin>
+hipError_t launch_convert(size_t N, const Tin* in, Tout* out, hipStream_t st);
+template <typename R>
+hipError_t launch_fill(size_t N, R* out, R v, hipStream_t st);
+// Interleave two FP64 fields into (a, b) pairs of type R, scaled by s.
+template <typename R>
+hipError_t launch_interleave(size_t N, const double* a, const double* b, R* out, hipStream_t st);
+// Injection of a pair field to the coarse grid: out[J][I] = in[2J+1][2I+1].
+template <typename R>
+hipError_t launch_inject_pairs(int n1, int n2, const R* in, R* out, hipStream_t st);
+// dinv = omega / (1 - sx (d+ + d-) w1a - sy (e+ + e-) w1b)
+template <typename R>
+hipError_t launch_diag(int N, const R* dpm, const R* epm, double sxw1, double syw1, double omega,
+                       R* dinv, double* diag_out, hipStream_t st);
+// Validation scan: flags[0] |= negative, flags[1] |= non-finite.
+hipError_t launch_scan_fields(size_t N, const double* const* f, int nf, int* flags, hipStream_t st);
+
+// Direct (dense Toeplitz sum) coarse levels, one workgroup runs the whole V-cycle below `lc`.
+constexpr int kMaxCoarseLevels = 4;
+template <typename R>
+struct CoarseView {
+  int nlev;                         // levels handled (the last is solved exactly)
+  int n1[kMaxCoarseLevels], n2[kMaxCoarseLevels];
+  const R* dpm[kMaxCoarseLevels];
+  const R* epm[kMaxCoarseLevels];
+  const R* dinv[kMaxCoarseLevels];
+  const R* swx[kMaxCoarseLevels];   // scaled weights sx * w_k, k = 0..n1
+  const R* swy[kMaxCoarseLevels];
+  const double* inv;                // FP64 inverse of the coarsest matrix (row-major Nc x Nc)
+  int nu_pre, nu_post;
+};
+template <typename R>
+hipError_t launch_coarse_vcycle(const CoarseView<R>& cv, const R* b, R* x, const int* skip,
+                                hipStream_t st);
+template <typename R>
+size_t coarse_lds_bytes(const CoarseView<R>& cv);
+// Direct apply of a coarse level (test hook): out = A x via dense Toeplitz sums.
+template <typename R>
+hipError_t launch_direct_apply(const CoarseView<R>& cv, int level, const R* x, R* out, int mode,
+                               const R* b, hipStream_t st);
+// Assemble the dense coarsest matrix from the coarsest level and invert it in place (FP64).
+template <typename R>
+hipError_t launch_coarse_invert(const CoarseView<R>& cv, double* inv, int* status, hipStream_t st);
+// x = inv * b for the coarsest level (test hook)
+template <typename R>
+hipError_t launch_coarse_solve(int Nc, const double* inv, const R* b, R* x, hipStream_t st);
+
+// ---- Krylov kernels (krylov.hip) ---------------------------------------------------------------
+constexpr int kMaxRestart = 32;
+// Device-resident state of one flexible GMRES solve.  The first block of fields is copied to the
+// host to decide about restarts.
+struct GmresState {
+  int done;       // 1: stop issuing Arnoldi steps in this cycle (converged, cycle full, breakdown)
+  int iters;      // Arnoldi steps so far in this solve
+  int nused;      // Arnoldi steps in the current cycle
+  int conv;       // 1: the FP64 true residual met the tolerance
+  double resnorm; // last true residual norm
+  double est;     // last Givens residual estimate
+  double bnorm;
+  double atol;    // rtol * ||b||
+  // configuration
+  double rtol;
+  int maxit, restart, cgs2, pad_;
+  unsigned int ticket[4];
+  double g[kMaxRestart + 1], cs[kMaxRestart], sn[kMaxRestart];
+  double Rm[kMaxRestart * kMaxRestart];  // column j in Rm[j*kMaxRestart + i], i <= j
+  double h1[kMaxRestart + 1], h2[kMaxRestart + 1];
+  double vscale[kMaxRestart + 1];
+  double y[kMaxRestart];
+};
+
+enum CgsKind : int { CGS_DOTS = 0, CGS_UPDATE_DOTS = 1, CGS_UPDATE_NORM = 2, CGS_INIT = 3, CGS_RESNORM = 4 };
+// One fused pass over the basis V[0..nv) (FP64, stride ldv) and w (= V[nv] unless given).
+hipError_t launch_cgs_pass(int kind, size_t N, int nv, double* V, size_t ldv, double* w,
+                           const double* src, GmresState* st, double* partials, int grid,
+                           hipStream_t s);
+int cgs_grid(size_t N);
+size_t cgs_partials_len(size_t N);
+template <typename Tz>
+hipError_t launch_update_x(size_t N, const Tz* Z, size_t ldz, double* x, int first,
+                           GmresState* st, hipStream_t s);
+
+// ---- small helpers -----------------------------------------------------------------------------
+inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
+inline bool is_pow2m1(int n) { return n >= 1 && ((n + 1) & n) == 0; }
+
+}  // namespace fde

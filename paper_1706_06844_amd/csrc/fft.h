@@ -1,0 +1,252 @@
+// Register-resident Stockham FFT for one power-of-two length L per group of T = L/E threads.
+//
+// Used by the Toeplitz operator kernels: a Toeplitz matrix-vector product is a linear convolution,
+// computed through a circulant embedding of length L = 2(n+1) >= 2n-1 (the O(N log N) product the
+// paper relies on, Sec. 1 and the Toeplitz-like structure of Sec. 2).
+//
+// Data layout between stages: thread t holds element t + T*m in register m (natural order), m < E.
+// A stage of radix R with NS = product of the previous radices performs E/R butterflies per thread;
+// butterfly b = t + T*q reads elements b + r*(L/R) (= registers q + r*(E/R)), multiplies element r by
+// exp(sign 2 pi i r (b mod NS) / (NS R)), does a radix-R DFT, and writes element r of its output to
+// position (b / NS) * NS * R + (b mod NS) + r * NS.  After the last stage (NS * R = L) that position
+// is again t + T*m, so the result stays in registers in natural order; earlier stages exchange data
+// through LDS.  Twiddles come from a per-length table laid out [stage][b mod NS][r-1].
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+namespace fde {
+
+template <int V>
+using ic = std::integral_constant<int, V>;
+
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(ic<B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+// cos and sin of 2 pi k / 16, k = 0..15.
+constexpr double kCos16[16] = {1.0,
+                               0.92387953251128675613,
+                               0.70710678118654752440,
+                               0.38268343236508977173,
+                               0.0,
+                               -0.38268343236508977173,
+                               -0.70710678118654752440,
+                               -0.92387953251128675613,
+                               -1.0,
+                               -0.92387953251128675613,
+                               -0.70710678118654752440,
+                               -0.38268343236508977173,
+                               0.0,
+                               0.38268343236508977173,
+                               0.70710678118654752440,
+                               0.92387953251128675613};
+constexpr double kSin16[16] = {0.0,
+                               0.38268343236508977173,
+                               0.70710678118654752440,
+                               0.92387953251128675613,
+                               1.0,
+                               0.92387953251128675613,
+                               0.70710678118654752440,
+                               0.38268343236508977173,
+                               0.0,
+                               -0.38268343236508977173,
+                               -0.70710678118654752440,
+                               -0.92387953251128675613,
+                               -1.0,
+                               -0.92387953251128675613,
+                               -0.70710678118654752440,
+                               -0.38268343236508977173};
+
+// (re, im) *= exp(SIGN * 2 pi i * K / N) for compile-time K and N (N divides 16).
+template <int K, int N, int SIGN, typename R>
+__device__ __forceinline__ void rot(R& re, R& im) {
+  constexpr int k = ((K % N) + N) % N;
+  constexpr int k16 = k * (16 / N);
+  if constexpr (k16 == 0) {
+  } else if constexpr (k16 == 8) {
+    re = -re;
+    im = -im;
+  } else if constexpr ((k16 == 4 && SIGN > 0) || (k16 == 12 && SIGN < 0)) {  // times +i
+    R t = re;
+    re = -im;
+    im = t;
+  } else if constexpr ((k16 == 4 && SIGN < 0) || (k16 == 12 && SIGN > 0)) {  // times -i
+    R t = re;
+    re = im;
+    im = -t;
+  } else {
+    constexpr R c = (R)kCos16[k16];
+    constexpr R s = (R)(SIGN > 0 ? kSin16[k16] : -kSin16[k16]);
+    R t = re * c - im * s;
+    im = re * s + im * c;
+    re = t;
+  }
+}
+
+// In-place DFT of N points held in registers, natural order in and out, sign SIGN.
+template <int N, int SIGN, typename R>
+__device__ __forceinline__ void dft(R (&re)[N], R (&im)[N]) {
+  if constexpr (N == 1) {
+  } else if constexpr (N == 2) {
+    R ar = re[0], ai = im[0];
+    re[0] = ar + re[1];
+    im[0] = ai + im[1];
+    re[1] = ar - re[1];
+    im[1] = ai - im[1];
+  } else if constexpr (N == 4) {
+    R t0r = re[0] + re[2], t0i = im[0] + im[2];
+    R t1r = re[0] - re[2], t1i = im[0] - im[2];
+    R t2r = re[1] + re[3], t2i = im[1] + im[3];
+    R t3r = re[1] - re[3], t3i = im[1] - im[3];
+    rot<1, 4, SIGN>(t3r, t3i);
+    re[0] = t0r + t2r;
+    im[0] = t0i + t2i;
+    re[2] = t0r - t2r;
+    im[2] = t0i - t2i;
+    re[1] = t1r + t3r;
+    im[1] = t1i + t3i;
+    re[3] = t1r - t3r;
+    im[3] = t1i - t3i;
+  } else {
+    // N = N1 * N2 with N1 = 4: input n = N2*n1 + n2, output k = k1 + N1*k2.
+    constexpr int N1 = 4, N2 = N / 4;
+    R yr[N2][N1], yi[N2][N1];
+    static_for<0, N2>([&](auto n2) {
+      R ar[N1], ai[N1];
+      static_for<0, N1>([&](auto n1) {
+        ar[n1] = re[N2 * n1 + n2];
+        ai[n1] = im[N2 * n1 + n2];
+      });
+      dft<N1, SIGN>(ar, ai);
+      static_for<0, N1>([&](auto k1) {
+        rot<decltype(n2)::value * decltype(k1)::value, N, SIGN>(ar[k1], ai[k1]);
+        yr[n2][k1] = ar[k1];
+        yi[n2][k1] = ai[k1];
+      });
+    });
+    static_for<0, N1>([&](auto k1) {
+      R br[N2], bi[N2];
+      static_for<0, N2>([&](auto n2) {
+        br[n2] = yr[n2][k1];
+        bi[n2] = yi[n2][k1];
+      });
+      dft<N2, SIGN>(br, bi);
+      static_for<0, N2>([&](auto k2) {
+        re[k1 + N1 * k2] = br[k2];
+        im[k1 + N1 * k2] = bi[k2];
+      });
+    });
+  }
+}
+
+// LDS index padding: one spare slot every 16 elements keeps strided stage writes conflict-free.
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int lds_len(int L) { return L + L / 16 + 1; }
+
+// Radix plan: E elements per thread, stages of radix E except a smaller last one.
+__host__ __device__ constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
+
+// EMAX: elements per thread for long transforms (register budget: 16 for FP32, 8 for FP64).
+template <int L, int EMAX = 16>
+struct Plan {
+  static constexpr int E = L >= 64 * EMAX ? EMAX : (L >= 128 ? L / 64 : 2);
+  static constexpr int T = L / E;
+  static constexpr int LOGE = ilog2(E);
+  static constexpr int LOGL = ilog2(L);
+  static constexpr int NSTAGES = (LOGL + LOGE - 1) / LOGE;
+  __host__ __device__ static constexpr int radix(int s) {
+    return (s < NSTAGES - 1 || LOGL % LOGE == 0) ? E : (1 << (LOGL % LOGE));
+  }
+  __host__ __device__ static constexpr int ns(int s) {
+    int v = 1;
+    for (int i = 0; i < s; ++i) v *= radix(i);
+    return v;
+  }
+  // complex twiddle entries of stage s (stage 0 has none)
+  __host__ __device__ static constexpr int tw_count(int s) { return s == 0 ? 0 : ns(s) * (radix(s) - 1); }
+  __host__ __device__ static constexpr int tw_offset(int s) {
+    int o = 0;
+    for (int i = 0; i < s; ++i) o += tw_count(i);
+    return o;
+  }
+  __host__ __device__ static constexpr int tw_total() { return tw_offset(NSTAGES); }
+};
+
+template <typename R>
+struct EmaxFor {
+  static constexpr int value = sizeof(R) == 8 ? 8 : 16;
+};
+template <typename R, int L>
+using PlanFor = Plan<L, EmaxFor<R>::value>;
+// The E elements a thread holds for a length-L transform in precision R.
+template <typename R, int L>
+using Reg = R[PlanFor<R, L>::E];
+
+// One Stockham stage.  `rr`/`ri` hold the thread's E elements (natural positions t + T*m).
+// Every stage but the last has one butterfly per thread (radix E), computed in place; its outputs
+// are exchanged through `lds` (L + pad reals, real parts first, then imaginary parts) and read back
+// at positions t + T*m.  The last stage (possibly of smaller radix, several butterflies per thread)
+// writes each butterfly's outputs over its own inputs, which are exactly positions t + T*m.
+template <int L, int S, int SIGN, typename R, typename P = PlanFor<R, L>>
+__device__ __forceinline__ void fft_stage(Reg<R, L>& rr, Reg<R, L>& ri, R* lds,
+                                          const R* __restrict__ tw, int t) {
+  constexpr int E = P::E, T = P::T;
+  constexpr int RADIX = P::radix(S);
+  constexpr int NS = P::ns(S);
+  constexpr int BPT = E / RADIX;
+  constexpr bool LAST = (S == P::NSTAGES - 1);
+  static_assert(LAST || BPT == 1, "only the last stage may use a smaller radix");
+  static_for<0, BPT>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    const int b = t + T * q;
+    const int j = b & (NS - 1);
+    R vr[RADIX], vi[RADIX];
+    static_for<0, RADIX>([&](auto rc) {
+      vr[rc] = rr[q + rc * BPT];
+      vi[rc] = ri[q + rc * BPT];
+    });
+    if constexpr (NS > 1) {
+      const R* w = tw + 2 * (P::tw_offset(S) + j * (RADIX - 1));
+      static_for<1, RADIX>([&](auto rc) {
+        const R c = w[2 * (rc - 1)];
+        const R s = (SIGN > 0) ? -w[2 * (rc - 1) + 1] : w[2 * (rc - 1) + 1];
+        const R a = vr[rc] * c - vi[rc] * s;
+        vi[rc] = vr[rc] * s + vi[rc] * c;
+        vr[rc] = a;
+      });
+    }
+    dft<RADIX, SIGN>(vr, vi);
+    static_for<0, RADIX>([&](auto rc) {
+      rr[q + rc * BPT] = vr[rc];
+      ri[q + rc * BPT] = vi[rc];
+    });
+  });
+  if constexpr (!LAST) {
+    // output r of this thread's butterfly b = t goes to (b / NS) * NS * RADIX + (b mod NS) + r * NS
+    const int base = (t / NS) * NS * RADIX + (t & (NS - 1));
+    static_for<0, RADIX>([&](auto rc) { lds[lpad(base + rc * NS)] = rr[rc]; });
+    __syncthreads();
+    static_for<0, E>([&](auto m) { rr[m] = lds[lpad(t + T * m)]; });
+    __syncthreads();
+    static_for<0, RADIX>([&](auto rc) { lds[lpad(base + rc * NS)] = ri[rc]; });
+    __syncthreads();
+    static_for<0, E>([&](auto m) { ri[m] = lds[lpad(t + T * m)]; });
+    __syncthreads();
+  }
+}
+
+// Full length-L DFT (SIGN = -1 forward, +1 unnormalised inverse) of the thread group's data.
+// Every thread of the workgroup must call this (it contains barriers) even if its group is idle.
+template <int L, int SIGN, typename R>
+__device__ __forceinline__ void fft(Reg<R, L>& rr, Reg<R, L>& ri, R* lds,
+                                    const R* __restrict__ tw, int t) {
+  static_for<0, PlanFor<R, L>::NSTAGES>([&](auto s) { fft_stage<L, decltype(s)::value, SIGN>(rr, ri, lds, tw, t); });
+}
+
+}  // namespace fde

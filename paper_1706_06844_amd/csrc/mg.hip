@@ -1,0 +1,566 @@
+// Multigrid kernels (paper Sec. 4): damped-Jacobi smoothing, full-weighting restriction, bilinear
+// prolongation, coarse-level construction, and a single-workgroup V-cycle for the small levels.
+//
+// Grid transfer: P = T(p) U with p = (1 + cos t1)(1 + cos t2) (Sec. 4.1, Lemma lemapp): coarse point
+// J (0-based) sits on fine point 2J+1, and P spreads it with weights 1, 1/2, 1/4 (bilinear
+// interpolation).  Restriction is R = P^T / 4, the 9-point full-weighting stencil
+// [1 2 1; 2 4 2; 1 2 1] / 16.  Coarse geometric levels rediscretise the operator with h doubled and
+// the coefficient fields injected at the coarse points (Sec. 4.2).
+#include "common.h"
+
+namespace fde {
+
+constexpr int kBlock = 256;
+
+static inline int grid_for(size_t n, int per_block = kBlock) {
+  size_t g = (n + per_block - 1) / per_block;
+  if (g > 65535 * 16) g = 65535 * 16;
+  return (int)(g == 0 ? 1 : g);
+}
+
+// ---- pre-smoothing from a zero initial guess: x = dinv .* b (one Jacobi step with x0 = 0) ------
+template <typename R, typename Tin>
+__global__ void presmooth_kernel(int N, const Tin* __restrict__ b, const double* __restrict__ bscale,
+                                 const R* __restrict__ dinv, R* __restrict__ x, R* __restrict__ bcopy,
+                                 const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const double s = bscale ? *bscale : 1.0;
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < N; p += gridDim.x * blockDim.x) {
+    const R bv = (R)(s * (double)b[p]);
+    if (bcopy) bcopy[p] = bv;
+    x[p] = dinv[p] * bv;
+  }
+}
+
+template <typename R, typename Tin>
+hipError_t launch_presmooth(int N, const Tin* b, const double* bscale, const R* dinv, R* x, R* bcopy,
+                            const int* skip, hipStream_t st) {
+  hipLaunchKernelGGL((presmooth_kernel<R, Tin>), dim3(grid_for(N)), dim3(kBlock), 0, st, N, b, bscale,
+                     dinv, x, bcopy, skip);
+  return hipGetLastError();
+}
+
+// ---- restriction rc = P^T r / 4 ---------------------------------------------------------------
+template <typename R>
+__global__ void restrict_kernel(int n1, int n2, const R* __restrict__ r, R* __restrict__ rc,
+                                const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int k1 = (n1 - 1) / 2, k2 = (n2 - 1) / 2;
+  const int Kc = k1 * k2;
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < Kc; q += gridDim.x * blockDim.x) {
+    const int J = q / k1, I = q - J * k1;
+    const int fj = 2 * J + 1, fi = 2 * I + 1;
+    const R* r0 = r + (size_t)(fj - 1) * n1 + fi;
+    const R* r1 = r0 + n1;
+    const R* r2 = r1 + n1;
+    const R a0 = r0[-1] + 2 * r0[0] + r0[1];
+    const R a1 = r1[-1] + 2 * r1[0] + r1[1];
+    const R a2 = r2[-1] + 2 * r2[0] + r2[1];
+    rc[q] = (a0 + 2 * a1 + a2) * R(0.0625);
+  }
+}
+
+template <typename R>
+hipError_t launch_restrict(int n1, int n2, const R* r, R* rc, const int* skip, hipStream_t st) {
+  const int Kc = ((n1 - 1) / 2) * ((n2 - 1) / 2);
+  hipLaunchKernelGGL((restrict_kernel<R>), dim3(grid_for(Kc)), dim3(kBlock), 0, st, n1, n2, r, rc, skip);
+  return hipGetLastError();
+}
+
+// ---- prolongation and correction x += P e -----------------------------------------------------
+// Coarse neighbours of fine index f (0-based) on a coarse grid of size k: odd f = 2c+1 -> (c, 1);
+// even f = 2c -> (c-1, 1/2), (c, 1/2), dropping indices outside [0, k).
+__device__ __forceinline__ void coarse_nbrs(int f, int k, int* c, float* w, int* cnt) {
+  if (f & 1) {
+    c[0] = (f - 1) >> 1;
+    w[0] = 1.0f;
+    *cnt = 1;
+  } else {
+    int m = 0;
+    const int h = f >> 1;
+    if (h - 1 >= 0) {
+      c[m] = h - 1;
+      w[m++] = 0.5f;
+    }
+    if (h < k) {
+      c[m] = h;
+      w[m++] = 0.5f;
+    }
+    *cnt = m;
+  }
+}
+
+template <typename R>
+__global__ void prolong_kernel(int n1, int n2, const R* __restrict__ e, R* __restrict__ x,
+                               const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int k1 = (n1 - 1) / 2, k2 = (n2 - 1) / 2;
+  const int N = n1 * n2;
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < N; p += gridDim.x * blockDim.x) {
+    const int j = p / n1, i = p - j * n1;
+    int cy[2], cx[2], ny, nx;
+    float wy[2], wx[2];
+    coarse_nbrs(j, k2, cy, wy, &ny);
+    coarse_nbrs(i, k1, cx, wx, &nx);
+    R v = 0;
+    for (int a = 0; a < ny; ++a) {
+      R s = 0;
+      for (int c = 0; c < nx; ++c) s += (R)wx[c] * e[(size_t)cy[a] * k1 + cx[c]];
+      v += (R)wy[a] * s;
+    }
+    x[p] += v;
+  }
+}
+
+template <typename R>
+hipError_t launch_prolong(int n1, int n2, const R* e, R* x, const int* skip, hipStream_t st) {
+  hipLaunchKernelGGL((prolong_kernel<R>), dim3(grid_for((size_t)n1 * n2)), dim3(kBlock), 0, st, n1, n2,
+                     e, x, skip);
+  return hipGetLastError();
+}
+
+// ---- elementwise helpers ----------------------------------------------------------------------
+template <typename Tout, typename Tin>
+__global__ void convert_kernel(size_t N, const Tin* __restrict__ in, Tout* __restrict__ out) {
+  for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < N; p += (size_t)gridDim.x * blockDim.x)
+    out[p] = (Tout)in[p];
+}
+template <typename Tout, typename Tin>
+hipError_t launch_convert(size_t N, const Tin* in, Tout* out, hipStream_t st) {
+  hipLaunchKernelGGL((convert_kernel<Tout, Tin>), dim3(grid_for(N)), dim3(kBlock), 0, st, N, in, out);
+  return hipGetLastError();
+}
+
+template <typename R>
+__global__ void fill_kernel(size_t N, R* __restrict__ out, R v) {
+  for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < N; p += (size_t)gridDim.x * blockDim.x)
+    out[p] = v;
+}
+template <typename R>
+hipError_t launch_fill(size_t N, R* out, R v, hipStream_t st) {
+  hipLaunchKernelGGL((fill_kernel<R>), dim3(grid_for(N)), dim3(kBlock), 0, st, N, out, v);
+  return hipGetLastError();
+}
+
+template <typename R>
+__global__ void interleave_kernel(size_t N, const double* __restrict__ a, const double* __restrict__ b,
+                                  R* __restrict__ out) {
+  for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < N; p += (size_t)gridDim.x * blockDim.x) {
+    out[2 * p] = (R)a[p];
+    out[2 * p + 1] = (R)b[p];
+  }
+}
+template <typename R>
+hipError_t launch_interleave(size_t N, const double* a, const double* b, R* out, hipStream_t st) {
+  hipLaunchKernelGGL((interleave_kernel<R>), dim3(grid_for(N)), dim3(kBlock), 0, st, N, a, b, out);
+  return hipGetLastError();
+}
+
+template <typename R>
+__global__ void inject_pairs_kernel(int n1, int n2, const R* __restrict__ in, R* __restrict__ out) {
+  const int k1 = (n1 - 1) / 2, k2 = (n2 - 1) / 2;
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < k1 * k2; q += gridDim.x * blockDim.x) {
+    const int J = q / k1, I = q - J * k1;
+    const size_t f = (size_t)(2 * J + 1) * n1 + (2 * I + 1);
+    out[2 * q] = in[2 * f];
+    out[2 * q + 1] = in[2 * f + 1];
+  }
+}
+template <typename R>
+hipError_t launch_inject_pairs(int n1, int n2, const R* in, R* out, hipStream_t st) {
+  const int Kc = ((n1 - 1) / 2) * ((n2 - 1) / 2);
+  hipLaunchKernelGGL((inject_pairs_kernel<R>), dim3(grid_for(Kc)), dim3(kBlock), 0, st, n1, n2, in, out);
+  return hipGetLastError();
+}
+
+// diag(A) = 1 - sx w1^a (d+ + d-) - sy w1^b (e+ + e-): T has w_1 on its diagonal (eq. (AN)).
+template <typename R>
+__global__ void diag_kernel(int N, const R* __restrict__ dpm, const R* __restrict__ epm, double sxw1,
+                            double syw1, double omega, R* __restrict__ dinv, double* __restrict__ dout) {
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < N; p += gridDim.x * blockDim.x) {
+    const double d = 1.0 - sxw1 * ((double)dpm[2 * p] + (double)dpm[2 * p + 1]) -
+                     syw1 * ((double)epm[2 * p] + (double)epm[2 * p + 1]);
+    if (dinv) dinv[p] = (R)(omega / d);
+    if (dout) dout[p] = d;
+  }
+}
+template <typename R>
+hipError_t launch_diag(int N, const R* dpm, const R* epm, double sxw1, double syw1, double omega, R* dinv,
+                       double* diag_out, hipStream_t st) {
+  hipLaunchKernelGGL((diag_kernel<R>), dim3(grid_for(N)), dim3(kBlock), 0, st, N, dpm, epm, sxw1, syw1,
+                     omega, dinv, diag_out);
+  return hipGetLastError();
+}
+
+__global__ void scan_fields_kernel(size_t N, const double* f0, const double* f1, const double* f2,
+                                   const double* f3, int nf, int* flags) {
+  int neg = 0, bad = 0;
+  for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < N; p += (size_t)gridDim.x * blockDim.x) {
+    const double* fs[4] = {f0, f1, f2, f3};
+    for (int k = 0; k < nf; ++k) {
+      const double v = fs[k][p];
+      if (!(v == v) || v == __builtin_inf() || v == -__builtin_inf()) bad = 1;
+      else if (v < 0.0) neg = 1;
+    }
+  }
+  if (neg) atomicOr(&flags[0], 1);
+  if (bad) atomicOr(&flags[1], 1);
+}
+hipError_t launch_scan_fields(size_t N, const double* const* f, int nf, int* flags, hipStream_t st) {
+  const double* g[4] = {nullptr, nullptr, nullptr, nullptr};
+  for (int k = 0; k < nf && k < 4; ++k) g[k] = f[k];
+  hipLaunchKernelGGL(scan_fields_kernel, dim3(grid_for(N)), dim3(kBlock), 0, st, N, g[0], g[1], g[2], g[3],
+                     nf, flags);
+  return hipGetLastError();
+}
+
+// ---- direct (dense Toeplitz sum) operator on small levels -------------------------------------
+// l(j,i) = d+ sum_k swx[i-k+1] X[j][k] + d- sum_k swx[k-i+1] X[j][k]
+//        + e+ sum_k swy[j-k+1] X[k][i] + e- sum_k swy[k-j+1] X[k][i]   (only indices >= 0)
+template <typename R>
+__device__ __forceinline__ R direct_l(int n1, int n2, int j, int i, const R* X, const R* swx,
+                                      const R* swy, const R* __restrict__ dpm,
+                                      const R* __restrict__ epm) {
+  R lx = 0, rx = 0, ly = 0, ry = 0;
+  const R* row = X + j * n1;
+  const int kl = min(i + 1, n1 - 1);
+  for (int k = 0; k <= kl; ++k) lx += swx[i - k + 1] * row[k];
+  for (int k = max(i - 1, 0); k < n1; ++k) rx += swx[k - i + 1] * row[k];
+  const int kt = min(j + 1, n2 - 1);
+  for (int k = 0; k <= kt; ++k) ly += swy[j - k + 1] * X[k * n1 + i];
+  for (int k = max(j - 1, 0); k < n2; ++k) ry += swy[k - j + 1] * X[k * n1 + i];
+  const int p = j * n1 + i;
+  return dpm[2 * p] * lx + dpm[2 * p + 1] * rx + epm[2 * p] * ly + epm[2 * p + 1] * ry;
+}
+
+template <typename R>
+struct CoarseLds {
+  R* B[kMaxCoarseLevels];
+  R* X[kMaxCoarseLevels];
+  R* T;
+  R* swx[kMaxCoarseLevels];
+  R* swy[kMaxCoarseLevels];
+};
+
+template <typename R>
+__host__ __device__ size_t coarse_lds_elems(const CoarseView<R>& cv) {
+  size_t n = 0, mx = 0;
+  for (int l = 0; l < cv.nlev; ++l) {
+    const size_t N = (size_t)cv.n1[l] * cv.n2[l];
+    n += 2 * N + (cv.n1[l] + 1) + (cv.n2[l] + 1);
+    if (N > mx) mx = N;
+  }
+  return n + mx;
+}
+template <typename R>
+size_t coarse_lds_bytes(const CoarseView<R>& cv) {
+  return coarse_lds_elems(cv) * sizeof(R);
+}
+
+template <typename R>
+__device__ CoarseLds<R> coarse_carve(const CoarseView<R>& cv, R* base) {
+  CoarseLds<R> s;
+  R* q = base;
+  size_t mx = 0;
+  for (int l = 0; l < cv.nlev; ++l) {
+    const size_t N = (size_t)cv.n1[l] * cv.n2[l];
+    s.B[l] = q;
+    q += N;
+    s.X[l] = q;
+    q += N;
+    s.swx[l] = q;
+    q += cv.n1[l] + 1;
+    s.swy[l] = q;
+    q += cv.n2[l] + 1;
+    if (N > mx) mx = N;
+  }
+  s.T = q;
+  return s;
+}
+
+// One Jacobi step on level l: X <- X + dinv (B - X + l(X)), through the scratch T.
+template <typename R>
+__device__ void coarse_jacobi(const CoarseView<R>& cv, const CoarseLds<R>& s, int l) {
+  const int n1 = cv.n1[l], n2 = cv.n2[l], N = n1 * n2;
+  for (int p = threadIdx.x; p < N; p += blockDim.x) {
+    const int j = p / n1, i = p - j * n1;
+    const R xv = s.X[l][p];
+    const R lv = direct_l(n1, n2, j, i, s.X[l], s.swx[l], s.swy[l], cv.dpm[l], cv.epm[l]);
+    s.T[p] = xv + cv.dinv[l][p] * (s.B[l][p] - xv + lv);
+  }
+  __syncthreads();
+  for (int p = threadIdx.x; p < N; p += blockDim.x) s.X[l][p] = s.T[p];
+  __syncthreads();
+}
+
+template <typename R>
+__global__ __launch_bounds__(1024) void coarse_vcycle_kernel(CoarseView<R> cv, const R* __restrict__ b_in,
+                                                             R* __restrict__ x_out,
+                                                             const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  extern __shared__ unsigned char smem_raw[];
+  R* base = reinterpret_cast<R*>(smem_raw);
+  const CoarseLds<R> s = coarse_carve(cv, base);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int l = 0; l < cv.nlev; ++l) {
+    for (int k = tid; k <= cv.n1[l]; k += nt) s.swx[l][k] = cv.swx[l][k];
+    for (int k = tid; k <= cv.n2[l]; k += nt) s.swy[l][k] = cv.swy[l][k];
+  }
+  {
+    const int N0 = cv.n1[0] * cv.n2[0];
+    for (int p = tid; p < N0; p += nt) s.B[0][p] = b_in[p];
+  }
+  __syncthreads();
+  const int last = cv.nlev - 1;
+  // descend: pre-smooth, residual, restrict
+  for (int l = 0; l < last; ++l) {
+    const int n1 = cv.n1[l], n2 = cv.n2[l], N = n1 * n2;
+    for (int p = tid; p < N; p += nt) s.X[l][p] = cv.nu_pre > 0 ? cv.dinv[l][p] * s.B[l][p] : R(0);
+    __syncthreads();
+    for (int it = 1; it < cv.nu_pre; ++it) coarse_jacobi(cv, s, l);
+    for (int p = tid; p < N; p += nt) {
+      const int j = p / n1, i = p - j * n1;
+      const R xv = s.X[l][p];
+      s.T[p] = s.B[l][p] - xv + direct_l(n1, n2, j, i, s.X[l], s.swx[l], s.swy[l], cv.dpm[l], cv.epm[l]);
+    }
+    __syncthreads();
+    const int k1 = (n1 - 1) / 2, k2 = (n2 - 1) / 2;
+    for (int q = tid; q < k1 * k2; q += nt) {
+      const int J = q / k1, I = q - J * k1;
+      const R* r0 = s.T + (2 * J) * n1 + 2 * I + 1;
+      const R* r1 = r0 + n1;
+      const R* r2 = r1 + n1;
+      const R a0 = r0[-1] + 2 * r0[0] + r0[1];
+      const R a1 = r1[-1] + 2 * r1[0] + r1[1];
+      const R a2 = r2[-1] + 2 * r2[0] + r2[1];
+      s.B[l + 1][q] = (a0 + 2 * a1 + a2) * R(0.0625);
+    }
+    __syncthreads();
+  }
+  // coarsest: X = inv B (FP64 dense inverse from the LU-based Gauss-Jordan factorisation)
+  {
+    const int Nc = cv.n1[last] * cv.n2[last];
+    for (int p = tid; p < Nc; p += nt) {
+      double acc = 0.0;
+      const double* row = cv.inv + (size_t)p * Nc;
+      for (int q = 0; q < Nc; ++q) acc += row[q] * (double)s.B[last][q];
+      s.X[last][p] = (R)acc;
+    }
+    __syncthreads();
+  }
+  // ascend: prolongate, correct, post-smooth
+  for (int l = last - 1; l >= 0; --l) {
+    const int n1 = cv.n1[l], n2 = cv.n2[l], N = n1 * n2;
+    const int k1 = (n1 - 1) / 2, k2 = (n2 - 1) / 2;
+    const R* E = s.X[l + 1];
+    for (int p = tid; p < N; p += nt) {
+      const int j = p / n1, i = p - j * n1;
+      int cy[2], cx[2], ny, nx;
+      float wy[2], wx[2];
+      coarse_nbrs(j, k2, cy, wy, &ny);
+      coarse_nbrs(i, k1, cx, wx, &nx);
+      R v = 0;
+      for (int a = 0; a < ny; ++a) {
+        R t = 0;
+        for (int c = 0; c < nx; ++c) t += (R)wx[c] * E[cy[a] * k1 + cx[c]];
+        v += (R)wy[a] * t;
+      }
+      s.X[l][p] += v;
+    }
+    __syncthreads();
+    for (int it = 0; it < cv.nu_post; ++it) coarse_jacobi(cv, s, l);
+  }
+  {
+    const int N0 = cv.n1[0] * cv.n2[0];
+    for (int p = tid; p < N0; p += nt) x_out[p] = s.X[0][p];
+  }
+}
+
+template <typename R>
+hipError_t launch_coarse_vcycle(const CoarseView<R>& cv, const R* b, R* x, const int* skip, hipStream_t st) {
+  const size_t bytes = coarse_lds_bytes(cv);
+  hipLaunchKernelGGL((coarse_vcycle_kernel<R>), dim3(1), dim3(1024), bytes, st, cv, b, x, skip);
+  return hipGetLastError();
+}
+
+template <typename R>
+__global__ void direct_apply_kernel(CoarseView<R> cv, int l, const R* __restrict__ x, R* __restrict__ out,
+                                    int mode, const R* __restrict__ b) {
+  extern __shared__ unsigned char smem_raw[];
+  R* X = reinterpret_cast<R*>(smem_raw);
+  const int n1 = cv.n1[l], n2 = cv.n2[l], N = n1 * n2;
+  R* swx = X + N;
+  R* swy = swx + n1 + 1;
+  for (int p = threadIdx.x; p < N; p += blockDim.x) X[p] = x[p];
+  for (int k = threadIdx.x; k <= n1; k += blockDim.x) swx[k] = cv.swx[l][k];
+  for (int k = threadIdx.x; k <= n2; k += blockDim.x) swy[k] = cv.swy[l][k];
+  __syncthreads();
+  for (int p = threadIdx.x; p < N; p += blockDim.x) {
+    const int j = p / n1, i = p - j * n1;
+    const R lv = direct_l(n1, n2, j, i, X, swx, swy, cv.dpm[l], cv.epm[l]);
+    const R xv = X[p];
+    R v;
+    if (mode == EP_APPLY) v = xv - lv;
+    else if (mode == EP_RESID) v = b[p] - xv + lv;
+    else if (mode == EP_JACOBI) v = xv + cv.dinv[l][p] * (b[p] - xv + lv);
+    else v = lv;
+    out[p] = v;
+  }
+}
+template <typename R>
+hipError_t launch_direct_apply(const CoarseView<R>& cv, int level, const R* x, R* out, int mode, const R* b,
+                               hipStream_t st) {
+  const size_t N = (size_t)cv.n1[level] * cv.n2[level];
+  const size_t bytes = (N + cv.n1[level] + cv.n2[level] + 2) * sizeof(R);
+  hipLaunchKernelGGL((direct_apply_kernel<R>), dim3(1), dim3(1024), bytes, st, cv, level, x, out, mode, b);
+  return hipGetLastError();
+}
+
+// ---- coarsest matrix: assembly and in-place Gauss-Jordan inversion with partial pivoting --------
+constexpr int kMaxCoarseN = 128;  // unknowns on the coarsest grid
+
+template <typename R>
+__global__ __launch_bounds__(1024) void coarse_invert_kernel(CoarseView<R> cv, double* __restrict__ inv,
+                                                             int* __restrict__ status) {
+  extern __shared__ unsigned char smem_raw[];
+  const int l = cv.nlev - 1;
+  const int n1 = cv.n1[l], n2 = cv.n2[l], n = n1 * n2;
+  double* A = reinterpret_cast<double*>(smem_raw);
+  __shared__ int perm[kMaxCoarseN];
+  __shared__ double fcol[kMaxCoarseN];
+  __shared__ int piv_row;
+  __shared__ int singular;
+  const R* dpm = cv.dpm[l];
+  const R* epm = cv.epm[l];
+  const R* swx = cv.swx[l];
+  const R* swy = cv.swy[l];
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int p = e / n, q = e - p * n;
+    const int j = p / n1, i = p - j * n1, jq = q / n1, iq = q - jq * n1;
+    double a = (p == q) ? 1.0 : 0.0;
+    if (j == jq) {
+      if (i - iq + 1 >= 0) a -= (double)dpm[2 * p] * (double)swx[i - iq + 1];
+      if (iq - i + 1 >= 0) a -= (double)dpm[2 * p + 1] * (double)swx[iq - i + 1];
+    }
+    if (i == iq) {
+      if (j - jq + 1 >= 0) a -= (double)epm[2 * p] * (double)swy[j - jq + 1];
+      if (jq - j + 1 >= 0) a -= (double)epm[2 * p + 1] * (double)swy[jq - j + 1];
+    }
+    A[e] = a;
+  }
+  if (threadIdx.x == 0) singular = 0;
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (threadIdx.x == 0) {
+      int pr = k;
+      double best = fabs(A[k * n + k]);
+      for (int i = k + 1; i < n; ++i) {
+        const double v = fabs(A[i * n + k]);
+        if (v > best) {
+          best = v;
+          pr = i;
+        }
+      }
+      if (best == 0.0) singular = 1;
+      piv_row = pr;
+      perm[k] = pr;
+    }
+    __syncthreads();
+    if (singular) break;
+    const int pr = piv_row;
+    if (pr != k)
+      for (int c = threadIdx.x; c < n; c += blockDim.x) {
+        const double t = A[k * n + c];
+        A[k * n + c] = A[pr * n + c];
+        A[pr * n + c] = t;
+      }
+    __syncthreads();
+    const double pv = A[k * n + k];
+    __syncthreads();
+    for (int c = threadIdx.x; c < n; c += blockDim.x) A[k * n + c] = (c == k ? 1.0 : A[k * n + c]) / pv;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) fcol[i] = A[i * n + k];
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+      const int i = e / n, c = e - i * n;
+      if (i == k) continue;
+      // the pivot column of row i becomes -f / pv, the corresponding entry of the inverse
+      A[e] = (c == k ? 0.0 : A[e]) - fcol[i] * A[k * n + c];
+    }
+    __syncthreads();
+  }
+  if (!singular) {
+    for (int k = n - 1; k >= 0; --k) {
+      const int pr = perm[k];
+      if (pr != k)
+        for (int r = threadIdx.x; r < n; r += blockDim.x) {
+          const double t = A[r * n + k];
+          A[r * n + k] = A[r * n + pr];
+          A[r * n + pr] = t;
+        }
+      __syncthreads();
+    }
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) inv[e] = A[e];
+  }
+  if (threadIdx.x == 0) *status = singular;
+}
+
+template <typename R>
+hipError_t launch_coarse_invert(const CoarseView<R>& cv, double* inv, int* status, hipStream_t st) {
+  const int l = cv.nlev - 1;
+  const int n = cv.n1[l] * cv.n2[l];
+  if (n > kMaxCoarseN) return hipErrorInvalidValue;
+  const size_t bytes = (size_t)n * n * sizeof(double);
+  if (bytes > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&coarse_invert_kernel<R>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((coarse_invert_kernel<R>), dim3(1), dim3(1024), bytes, st, cv, inv, status);
+  return hipGetLastError();
+}
+
+template <typename R>
+__global__ void coarse_solve_kernel(int Nc, const double* __restrict__ inv, const R* __restrict__ b,
+                                    R* __restrict__ x) {
+  for (int p = threadIdx.x; p < Nc; p += blockDim.x) {
+    double acc = 0.0;
+    for (int q = 0; q < Nc; ++q) acc += inv[(size_t)p * Nc + q] * (double)b[q];
+    x[p] = (R)acc;
+  }
+}
+template <typename R>
+hipError_t launch_coarse_solve(int Nc, const double* inv, const R* b, R* x, hipStream_t st) {
+  hipLaunchKernelGGL((coarse_solve_kernel<R>), dim3(1), dim3(256), 0, st, Nc, inv, b, x);
+  return hipGetLastError();
+}
+
+// ---- explicit instantiations ------------------------------------------------------------------
+#define FDE_INST_R(R)                                                                                   \
+  template hipError_t launch_restrict<R>(int, int, const R*, R*, const int*, hipStream_t);             \
+  template hipError_t launch_prolong<R>(int, int, const R*, R*, const int*, hipStream_t);              \
+  template hipError_t launch_fill<R>(size_t, R*, R, hipStream_t);                                      \
+  template hipError_t launch_interleave<R>(size_t, const double*, const double*, R*, hipStream_t);     \
+  template hipError_t launch_inject_pairs<R>(int, int, const R*, R*, hipStream_t);                     \
+  template hipError_t launch_diag<R>(int, const R*, const R*, double, double, double, R*, double*,      \
+                                     hipStream_t);                                                      \
+  template hipError_t launch_coarse_vcycle<R>(const CoarseView<R>&, const R*, R*, const int*,           \
+                                              hipStream_t);                                             \
+  template size_t coarse_lds_bytes<R>(const CoarseView<R>&);                                            \
+  template hipError_t launch_direct_apply<R>(const CoarseView<R>&, int, const R*, R*, int, const R*,    \
+                                             hipStream_t);                                              \
+  template hipError_t launch_coarse_invert<R>(const CoarseView<R>&, double*, int*, hipStream_t);        \
+  template hipError_t launch_coarse_solve<R>(int, const double*, const R*, R*, hipStream_t);
+FDE_INST_R(double)
+FDE_INST_R(float)
+template hipError_t launch_presmooth<double, double>(int, const double*, const double*, const double*,
+                                                     double*, double*, const int*, hipStream_t);
+template hipError_t launch_presmooth<float, double>(int, const double*, const double*, const float*, float*,
+                                                    float*, const int*, hipStream_t);
+template hipError_t launch_presmooth<float, float>(int, const float*, const double*, const float*, float*,
+                                                   float*, const int*, hipStream_t);
+template hipError_t launch_convert<float, double>(size_t, const double*, float*, hipStream_t);
+template hipError_t launch_convert<double, float>(size_t, const float*, double*, hipStream_t);
+template hipError_t launch_convert<double, double>(size_t, const double*, double*, hipStream_t);
+template hipError_t launch_convert<float, float>(size_t, const float*, float*, hipStream_t);
+
+}  // namespace fde

@@ -1,0 +1,1050 @@
+// Host orchestration of the solver: problem validation, the multigrid hierarchy, the V-cycle,
+// flexible GMRES and the Crank-Nicolson step, behind the C ABI declared in include/fde.h.
+//
+// Paper references: eq. (gk) and eq. (w) for the weights; eq. (AN), (AxAy), (system) for the
+// operator; Sec. 4 (TGM, V-cycle paragraph), Sec. 4.2 (geometric coarse levels, V(1,1) with damped
+// Jacobi, coarsest 8x8-cell grid) and Sec. 4.3 / Sec. 5 (GMRES with one multigrid cycle as the
+// preconditioner, restart 20, zero initial guess) for the solver.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/fde.h"
+#include "common.h"
+
+using namespace fde;
+
+namespace {
+
+thread_local std::string g_global_error;
+
+struct DevAlloc {
+  std::vector<void*> ptrs;
+  size_t bytes = 0;
+  ~DevAlloc() { reset(); }
+  void reset() {
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+    bytes = 0;
+  }
+  template <typename T>
+  T* get(size_t n) {
+    if (n == 0) n = 1;
+    void* p = nullptr;
+    if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) return nullptr;
+    ptrs.push_back(p);
+    bytes += n * sizeof(T);
+    return static_cast<T*>(p);
+  }
+};
+
+struct FdeError {
+  int code;
+  std::string msg;
+};
+
+#define HIPCHECK(expr)                                                                    \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      throw FdeError{FDE_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)};     \
+  } while (0)
+
+// Grunwald coefficients and WSGD weights (eq. (gk), eq. (w)), k = 0..K.
+std::vector<double> wsgd_weights(double g, int K) {
+  std::vector<double> gk(K + 1), w(K + 1);
+  gk[0] = 1.0;
+  for (int k = 1; k <= K; ++k) gk[k] = gk[k - 1] * (-(g - k + 1.0) / k);
+  w[0] = 0.5 * g * gk[0];
+  for (int k = 1; k <= K; ++k) w[k] = 0.5 * g * gk[k] + 0.5 * (2.0 - g) * gk[k - 1];
+  return w;
+}
+
+constexpr int kDirectMaxN = 31;  // levels with max(n1, n2) <= this run in the one-workgroup kernel
+
+template <typename R>
+struct Level {
+  int n1 = 0, n2 = 0, L1 = 0, L2 = 0;
+  double sx = 0, sy = 0;
+  R* dpm = nullptr;
+  R* epm = nullptr;
+  R* dinv = nullptr;
+  R* lam_x = nullptr;
+  R* lam_y = nullptr;
+  const R* tw_x = nullptr;
+  const R* tw_y = nullptr;
+  R* swx = nullptr;
+  R* swy = nullptr;
+  R* b = nullptr;
+  R* x = nullptr;
+  R* r = nullptr;
+  R* ay = nullptr;
+  OpView<R> view() const {
+    OpView<R> v;
+    v.n1 = n1;
+    v.n2 = n2;
+    v.L1 = L1;
+    v.L2 = L2;
+    v.dpm = dpm;
+    v.epm = epm;
+    v.dinv = dinv;
+    v.mu_x = lam_x;
+    v.mu_y = lam_y;
+    v.tw_x = tw_x;
+    v.tw_y = tw_y;
+    return v;
+  }
+  size_t N() const { return (size_t)n1 * n2; }
+};
+
+template <typename R>
+struct Hierarchy {
+  std::vector<Level<R>> lv;
+  int lc = 0;  // first level handled by the one-workgroup coarse kernel
+  CoarseView<R> cv{};
+  double* inv = nullptr;
+  int Nc = 0;
+  std::vector<std::pair<int, R*>> tw;  // twiddle tables by length
+};
+
+// Outer FP64 operator (the system matrix of eq. (system) at one time level).
+struct Outer {
+  double* dpm = nullptr;
+  double* epm = nullptr;
+  double* lam_x = nullptr;
+  double* lam_y = nullptr;
+  OpView<double> view(const double* twx, const double* twy, int n1, int n2, int L1, int L2) const {
+    OpView<double> v;
+    v.n1 = n1;
+    v.n2 = n2;
+    v.L1 = L1;
+    v.L2 = L2;
+    v.dpm = dpm;
+    v.epm = epm;
+    v.dinv = nullptr;
+    v.mu_x = lam_x;
+    v.mu_y = lam_y;
+    v.tw_x = twx;
+    v.tw_y = twy;
+    return v;
+  }
+};
+
+// Kernel-family timing (HIP events around launches) for performance reports.
+struct ProfEntry {
+  int fam;
+  hipEvent_t a, b;
+  double bytes;
+  int cycle, j;
+};
+struct Prof {
+  unsigned mask = 0;
+  std::vector<hipEvent_t> freelist;
+  std::vector<ProfEntry> pending;
+  std::vector<int> cycle_nused;
+  int cur_cycle = -1, cur_j = -1;
+  int64_t launches[FDE_KFAM_COUNT] = {};
+  double ms[FDE_KFAM_COUNT] = {};
+  double bytes[FDE_KFAM_COUNT] = {};
+  ~Prof() {
+    for (auto& e : pending) {
+      (void)hipEventDestroy(e.a);
+      (void)hipEventDestroy(e.b);
+    }
+    for (auto ev : freelist) (void)hipEventDestroy(ev);
+  }
+};
+
+}  // namespace
+
+struct fde_handle {
+  fde_problem p{};
+  hipStream_t stream = nullptr;
+  int n1 = 0, n2 = 0, L1 = 0, L2 = 0;
+  size_t N = 0;
+  double hx = 0, hy = 0, sx = 0, sy = 0;
+  std::vector<double> wa, wb;  // WSGD weights for alpha and beta, k = 0..n
+  DevAlloc mem;
+  DevAlloc hier_mem;  // rebuilt on coefficient updates
+  // outer FP64 operators: cur = left-hand side level t^(m), prev = explicit level t^(m-1)
+  Outer cur, prev;
+  bool prev_aliases_cur = true;
+  double* tw64_x = nullptr;
+  double* tw64_y = nullptr;
+  double* ay64 = nullptr;
+  double* rhs = nullptr;  // CN right-hand side
+  // preconditioner hierarchy in FP64 or FP32
+  std::unique_ptr<Hierarchy<double>> h64;
+  std::unique_ptr<Hierarchy<float>> h32;
+  // Krylov storage
+  double* V = nullptr;    // (restart + 1) x N
+  void* Z = nullptr;      // restart x N, FP64 or FP32
+  GmresState* st = nullptr;
+  GmresState* st_host = nullptr;  // pinned mirror
+  double* partials = nullptr;
+  int* flags = nullptr;
+  double* scratch64 = nullptr;  // 2N FP64 for test hooks
+  int cgs_grid = 1;
+  int expected_iters = 0;
+  Prof prof;
+  std::string err;
+  bool fp32() const { return p.precision != FDE_FP64; }
+};
+
+namespace {
+
+int set_err(fde_handle* h, int code, const std::string& msg) {
+  if (h) h->err = msg;
+  g_global_error = msg;
+  return code;
+}
+
+hipEvent_t prof_event(fde_handle* h) {
+  if (!h->prof.freelist.empty()) {
+    hipEvent_t e = h->prof.freelist.back();
+    h->prof.freelist.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HIPCHECK(hipEventCreate(&e));
+  return e;
+}
+
+// Runs `launch`; when family `fam` is being profiled, brackets it with events.
+template <typename F>
+void timed(fde_handle* h, int fam, double bytes, F&& launch) {
+  if (!(h->prof.mask & (1u << fam))) {
+    HIPCHECK(launch());
+    return;
+  }
+  hipEvent_t a = prof_event(h), b = prof_event(h);
+  HIPCHECK(hipEventRecord(a, h->stream));
+  HIPCHECK(launch());
+  HIPCHECK(hipEventRecord(b, h->stream));
+  h->prof.pending.push_back({fam, a, b, bytes, h->prof.cur_cycle, h->prof.cur_j});
+}
+
+// Accumulates finished entries (the stream must be idle).  Launches issued for Arnoldi steps that
+// were skipped on the device (after convergence) are dropped.
+void prof_harvest(fde_handle* h) {
+  Prof& P = h->prof;
+  for (auto& e : P.pending) {
+    const bool skipped = e.j >= 0 && e.cycle >= 0 && e.cycle < (int)P.cycle_nused.size() &&
+                         e.j >= P.cycle_nused[e.cycle];
+    if (!skipped) {
+      float ms = 0.f;
+      HIPCHECK(hipEventElapsedTime(&ms, e.a, e.b));
+      P.launches[e.fam] += 1;
+      P.ms[e.fam] += ms;
+      P.bytes[e.fam] += e.bytes;
+    }
+    P.freelist.push_back(e.a);
+    P.freelist.push_back(e.b);
+  }
+  P.pending.clear();
+  P.cycle_nused.clear();
+  P.cur_cycle = -1;
+  P.cur_j = -1;
+}
+
+// Algorithmic bytes of the operator passes (each input and output field once).
+template <typename R, typename Tin>
+double ybytes(size_t N) {
+  return (double)N * (sizeof(Tin) + 3 * sizeof(R));
+}
+template <typename R, typename Tin>
+double xbytes(size_t N, int mode, int nsrc) {
+  double w = sizeof(Tin) + 3.0 * sizeof(R) + sizeof(R);  // x, (d+,d-), ay, out
+  if (mode == EP_RESID) w += sizeof(R);
+  if (mode == EP_JACOBI) w += 2.0 * sizeof(R);
+  if (mode == EP_RHS) w += 8.0 * nsrc;
+  return (double)N * w;
+}
+
+template <typename R, typename Tin>
+void op_apply(fde_handle* h, bool outer, const OpView<R>& op, const Tin* x, R* ay, R* out, int mode, const R* b,
+              const SrcTerms* src, double tau, const int* skip) {
+  const size_t N = (size_t)op.n1 * op.n2;
+  const bool fine = outer || (op.n1 == h->n1 && op.n2 == h->n2);
+  const int fy = outer ? FDE_KFAM_OUTER_Y : (fine ? FDE_KFAM_MG0_Y : FDE_KFAM_MGC_Y);
+  const int fx = outer ? FDE_KFAM_OUTER_X : (fine ? FDE_KFAM_MG0_X : FDE_KFAM_MGC_X);
+  timed(h, fy, ybytes<R, Tin>(N), [&] { return launch_op_y<R, Tin>(op, x, ay, skip, h->stream); });
+  timed(h, fx, xbytes<R, Tin>(N, mode, src ? src->n : 0),
+        [&] { return launch_op_x<R, Tin>(op, x, ay, out, mode, b, src, tau, skip, h->stream); });
+}
+
+int validate(const fde_problem* p, std::string* why) {
+  auto bad = [&](const std::string& s) {
+    *why = s;
+    return FDE_EINVAL;
+  };
+  if (!p) return bad("problem is NULL");
+  if (!(p->alpha > 1.0 && p->alpha < 2.0) || !(p->beta > 1.0 && p->beta < 2.0))
+    return bad("alpha and beta must lie in (1,2)");
+  if (!is_pow2m1(p->n1) || !is_pow2m1(p->n2) || p->n1 < 7 || p->n2 < 7)
+    return bad("n1 and n2 must be 2^l - 1 with l >= 3");
+  if (p->n1 > 2047 || p->n2 > 2047) return bad("n1 and n2 are limited to 2047 (FFT length 4096)");
+  if (!(p->b1 > p->a1) || !(p->b2 > p->a2)) return bad("domain needs a < b");
+  if (!(p->tau > 0.0) || !std::isfinite(p->tau)) return bad("tau must be positive and finite");
+  if (p->precision < FDE_FP64 || p->precision > FDE_MIXED_BF16GEMM) return bad("unknown precision");
+  if (p->mg_variant != FDE_MG_GEOMETRIC && p->mg_variant != FDE_MG_GALERKIN) return bad("unknown mg_variant");
+  if (p->mg_variant == FDE_MG_GALERKIN) return bad("the Galerkin variant is not available in this build");
+  if (p->precision == FDE_MIXED_BF16GEMM) return bad("the BF16 GEMM path is not available in this build");
+  if (!(p->omega > 0.0 && p->omega <= 1.0)) return bad("omega must lie in (0,1]");
+  if (p->nu_pre < 0 || p->nu_pre > 8 || p->nu_post < 0 || p->nu_post > 8) return bad("nu_pre/nu_post in 0..8");
+  if (p->coarsest_n < 3) return bad("coarsest_n must be >= 3");
+  if (p->restart < 1 || p->restart > kMaxRestart) return bad("restart must lie in 1..32");
+  if (p->maxit < 1) return bad("maxit must be >= 1");
+  if (!(p->rtol >= 0.0)) return bad("rtol must be >= 0");
+  // coarsest grid size of the hierarchy
+  int a = p->n1, b = p->n2;
+  while (std::min(a, b) > p->coarsest_n) {
+    a = (a - 1) / 2;
+    b = (b - 1) / 2;
+  }
+  if (a * b > 128 || std::max(a, b) > kDirectMaxN)
+    return bad("the coarsest grid would exceed 128 unknowns or 31 points per side (n1, n2 too different)");
+  return FDE_OK;
+}
+
+void fill_defaults(fde_problem* q) {
+  if (q->omega == 0.0) q->omega = 0.7;
+  if (q->nu_pre < 0) q->nu_pre = 1;
+  if (q->nu_post < 0) q->nu_post = 1;
+  if (q->coarsest_n == 0) q->coarsest_n = 7;
+  if (q->restart == 0) q->restart = 20;
+  if (q->maxit == 0) q->maxit = 200;
+  if (q->rtol == 0.0) q->rtol = 1e-10;
+}
+
+template <typename R>
+R* upload(DevAlloc& m, const std::vector<double>& v, hipStream_t st) {
+  R* d = m.get<R>(v.size());
+  if (!d) throw FdeError{FDE_ENOMEM, "device allocation failed"};
+  std::vector<R> t(v.begin(), v.end());
+  HIPCHECK(hipMemcpyAsync(d, t.data(), t.size() * sizeof(R), hipMemcpyHostToDevice, st));
+  HIPCHECK(hipStreamSynchronize(st));  // t goes out of scope
+  return d;
+}
+
+template <typename T>
+T* dalloc(DevAlloc& m, size_t n) {
+  T* p = m.get<T>(n);
+  if (!p) throw FdeError{FDE_ENOMEM, "device allocation failed (" + std::to_string(n * sizeof(T)) + " bytes)"};
+  return p;
+}
+
+template <typename R>
+const R* twiddles(Hierarchy<R>& H, DevAlloc& m, int L, hipStream_t st) {
+  for (auto& e : H.tw)
+    if (e.first == L) return e.second;
+  const int cnt = fft_twiddle_count(L, sizeof(R));
+  std::vector<double> t(cnt > 0 ? cnt : 2);
+  int c = 0;
+  fft_twiddles(L, sizeof(R), t.data(), &c);
+  R* d = upload<R>(m, t, st);
+  H.tw.push_back({L, d});
+  return d;
+}
+
+std::vector<double> symbol_host(const std::vector<double>& w, int n, int L, double scale) {
+  std::vector<double> out(2 * (size_t)L);
+  toeplitz_symbol(w.data(), n, L, scale, out.data());
+  return out;
+}
+
+// Build the preconditioner hierarchy in precision R from the outer FP64 fields `cur`.
+template <typename R>
+std::unique_ptr<Hierarchy<R>> build_hierarchy(fde_handle* h) {
+  auto H = std::make_unique<Hierarchy<R>>();
+  DevAlloc& m = h->hier_mem;
+  hipStream_t st = h->stream;
+  const fde_problem& p = h->p;
+  int n1 = h->n1, n2 = h->n2, l = 0;
+  while (true) {
+    Level<R> L;
+    L.n1 = n1;
+    L.n2 = n2;
+    L.L1 = 2 * (n1 + 1);
+    L.L2 = 2 * (n2 + 1);
+    const double hx = h->hx * (double)(1 << l), hy = h->hy * (double)(1 << l);
+    L.sx = p.tau / (2.0 * std::pow(hx, p.alpha));
+    L.sy = p.tau / (2.0 * std::pow(hy, p.beta));
+    const size_t N = L.N();
+    if (l == 0) {
+      if (std::is_same<R, double>::value) {
+        L.dpm = reinterpret_cast<R*>(h->cur.dpm);
+        L.epm = reinterpret_cast<R*>(h->cur.epm);
+      } else {
+        L.dpm = dalloc<R>(m, 2 * N);
+        L.epm = dalloc<R>(m, 2 * N);
+        HIPCHECK((launch_convert<R, double>(2 * N, h->cur.dpm, L.dpm, st)));
+        HIPCHECK((launch_convert<R, double>(2 * N, h->cur.epm, L.epm, st)));
+      }
+    } else {
+      const Level<R>& F = H->lv.back();
+      L.dpm = dalloc<R>(m, 2 * N);
+      L.epm = dalloc<R>(m, 2 * N);
+      HIPCHECK(launch_inject_pairs<R>(F.n1, F.n2, F.dpm, L.dpm, st));
+      HIPCHECK(launch_inject_pairs<R>(F.n1, F.n2, F.epm, L.epm, st));
+    }
+    L.dinv = dalloc<R>(m, N);
+    HIPCHECK(launch_diag<R>((int)N, L.dpm, L.epm, L.sx * h->wa[1], L.sy * h->wb[1], p.omega, L.dinv, nullptr, st));
+    const bool direct = std::max(n1, n2) <= kDirectMaxN;
+    if (direct) {
+      std::vector<double> sx(n1 + 1), sy(n2 + 1);
+      for (int k = 0; k <= n1; ++k) sx[k] = L.sx * h->wa[k];
+      for (int k = 0; k <= n2; ++k) sy[k] = L.sy * h->wb[k];
+      L.swx = upload<R>(m, sx, st);
+      L.swy = upload<R>(m, sy, st);
+    } else {
+      L.lam_x = upload<R>(m, symbol_host(h->wa, n1, L.L1, L.sx), st);
+      L.lam_y = upload<R>(m, symbol_host(h->wb, n2, L.L2, L.sy), st);
+      L.tw_x = twiddles<R>(*H, m, L.L1, st);
+      L.tw_y = twiddles<R>(*H, m, L.L2, st);
+      L.ay = dalloc<R>(m, N);
+      L.r = dalloc<R>(m, N);
+    }
+    L.b = dalloc<R>(m, N);
+    L.x = dalloc<R>(m, N);
+    H->lv.push_back(L);
+    if (std::min(n1, n2) <= p.coarsest_n) break;
+    n1 = (n1 - 1) / 2;
+    n2 = (n2 - 1) / 2;
+    ++l;
+  }
+  const int nlev = (int)H->lv.size();
+  H->lc = nlev - 1;
+  while (H->lc > 0 && std::max(H->lv[H->lc - 1].n1, H->lv[H->lc - 1].n2) <= kDirectMaxN) --H->lc;
+  if (nlev - H->lc > kMaxCoarseLevels) throw FdeError{FDE_EINVAL, "too many direct coarse levels"};
+  CoarseView<R>& cv = H->cv;
+  cv.nlev = nlev - H->lc;
+  for (int k = 0; k < cv.nlev; ++k) {
+    const Level<R>& L = H->lv[H->lc + k];
+    cv.n1[k] = L.n1;
+    cv.n2[k] = L.n2;
+    cv.dpm[k] = L.dpm;
+    cv.epm[k] = L.epm;
+    cv.dinv[k] = L.dinv;
+    cv.swx[k] = L.swx;
+    cv.swy[k] = L.swy;
+  }
+  cv.nu_pre = p.nu_pre;
+  cv.nu_post = p.nu_post;
+  const Level<R>& C = H->lv.back();
+  H->Nc = C.n1 * C.n2;
+  H->inv = dalloc<double>(m, (size_t)H->Nc * H->Nc);
+  HIPCHECK(launch_coarse_invert<R>(cv, H->inv, h->flags + 2, st));
+  cv.inv = H->inv;
+  int status = 0;
+  HIPCHECK(hipMemcpyAsync(&status, h->flags + 2, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  if (status) throw FdeError{FDE_EINVAL, "the coarsest-level matrix is singular"};
+  return H;
+}
+
+void check_fields(fde_handle* h, const double* dp, const double* dm, const double* ep, const double* em) {
+  if (!dp || !dm || !ep || !em) throw FdeError{FDE_EINVAL, "coefficient pointer is NULL"};
+  const double* f[4] = {dp, dm, ep, em};
+  HIPCHECK(hipMemsetAsync(h->flags, 0, 2 * sizeof(int), h->stream));
+  HIPCHECK(launch_scan_fields(h->N, f, 4, h->flags, h->stream));
+  int fl[2] = {0, 0};
+  HIPCHECK(hipMemcpyAsync(fl, h->flags, sizeof(fl), hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(hipStreamSynchronize(h->stream));
+  if (fl[1]) throw FdeError{FDE_ENONFINITE, "a coefficient field contains NaN or Inf"};
+  if (fl[0]) throw FdeError{FDE_ENEGCOEF, "a coefficient field has a negative value"};
+}
+
+void load_outer(fde_handle* h, Outer& o, const double* dp, const double* dm, const double* ep, const double* em) {
+  HIPCHECK(launch_interleave<double>(h->N, dp, dm, o.dpm, h->stream));
+  HIPCHECK(launch_interleave<double>(h->N, ep, em, o.epm, h->stream));
+}
+
+void build_preconditioner(fde_handle* h) {
+  HIPCHECK(hipStreamSynchronize(h->stream));
+  h->h64.reset();
+  h->h32.reset();
+  h->hier_mem.reset();
+  if (h->fp32()) h->h32 = build_hierarchy<float>(h);
+  else h->h64 = build_hierarchy<double>(h);
+}
+
+// ---- V-cycle ------------------------------------------------------------------------------------
+template <typename R>
+void vcycle_from(fde_handle* h, Hierarchy<R>& H, int l, R* x, const int* skip) {
+  hipStream_t st = h->stream;
+  if (l >= H.lc) {
+    timed(h, FDE_KFAM_COARSE, 2.0 * H.lv[l].N() * sizeof(R),
+          [&] { return launch_coarse_vcycle<R>(H.cv, H.lv[l].b, x, skip, st); });
+    return;
+  }
+  Level<R>& L = H.lv[l];
+  const OpView<R> op = L.view();
+  const size_t N = L.N(), Nc = H.lv[l + 1].N();
+  if (l > 0) {
+    if (h->p.nu_pre > 0)
+      timed(h, FDE_KFAM_TRANSFER, 3.0 * N * sizeof(R),
+            [&] { return launch_presmooth<R, R>((int)N, L.b, nullptr, L.dinv, x, nullptr, skip, st); });
+    else HIPCHECK(launch_fill<R>(N, x, R(0), st));
+  }
+  for (int it = 1; it < h->p.nu_pre; ++it) op_apply<R, R>(h, false, op, x, L.ay, x, EP_JACOBI, L.b, nullptr, 0.0, skip);
+  op_apply<R, R>(h, false, op, x, L.ay, L.r, EP_RESID, L.b, nullptr, 0.0, skip);
+  timed(h, FDE_KFAM_TRANSFER, (double)(N + Nc) * sizeof(R),
+        [&] { return launch_restrict<R>(L.n1, L.n2, L.r, H.lv[l + 1].b, skip, st); });
+  vcycle_from<R>(h, H, l + 1, H.lv[l + 1].x, skip);
+  timed(h, FDE_KFAM_TRANSFER, (double)(2 * N + Nc) * sizeof(R),
+        [&] { return launch_prolong<R>(L.n1, L.n2, H.lv[l + 1].x, x, skip, st); });
+  for (int it = 0; it < h->p.nu_post; ++it) op_apply<R, R>(h, false, op, x, L.ay, x, EP_JACOBI, L.b, nullptr, 0.0, skip);
+}
+
+// z = MG(s * v): v is FP64 (a basis column), s a device scalar (or NULL = 1).
+template <typename R>
+void vcycle_top(fde_handle* h, Hierarchy<R>& H, const double* v, const double* s, R* z, const int* skip) {
+  Level<R>& L0 = H.lv[0];
+  const int N = (int)L0.N();
+  const double pb = (double)N * (sizeof(double) + 3 * sizeof(R));
+  if (H.lc == 0) {
+    timed(h, FDE_KFAM_TRANSFER, pb, [&] { return launch_presmooth<R, double>(N, v, s, L0.dinv, L0.x, L0.b, skip, h->stream); });
+    timed(h, FDE_KFAM_COARSE, 2.0 * N * sizeof(R), [&] { return launch_coarse_vcycle<R>(H.cv, L0.b, z, skip, h->stream); });
+    return;
+  }
+  timed(h, FDE_KFAM_TRANSFER, pb, [&] { return launch_presmooth<R, double>(N, v, s, L0.dinv, z, L0.b, skip, h->stream); });
+  if (h->p.nu_pre == 0) HIPCHECK(launch_fill<R>(L0.N(), z, R(0), h->stream));
+  vcycle_from<R>(h, H, 0, z, skip);
+}
+
+// ---- flexible GMRES ----------------------------------------------------------------------------
+void read_state(fde_handle* h) {
+  HIPCHECK(hipMemcpyAsync(h->st_host, h->st, offsetof(GmresState, rtol), hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(hipStreamSynchronize(h->stream));
+}
+
+template <typename R>
+void arnoldi_step(fde_handle* h, Hierarchy<R>& H, int j) {
+  const size_t N = h->N;
+  const int* skip = &h->st->done;
+  R* Z = static_cast<R*>(h->Z);
+  double* vj = h->V + (size_t)j * N;
+  double* w = h->V + (size_t)(j + 1) * N;
+  vcycle_top<R>(h, H, vj, &h->st->vscale[j], Z + (size_t)j * N, skip);
+  const OpView<double> op = h->cur.view(h->tw64_x, h->tw64_y, h->n1, h->n2, h->L1, h->L2);
+  op_apply<double, R>(h, true, op, Z + (size_t)j * N, h->ay64, w, EP_APPLY, nullptr, nullptr, 0.0, skip);
+  const double vb = (double)(j + 2) * N * sizeof(double);
+  timed(h, FDE_KFAM_CGS, vb, [&] {
+    return launch_cgs_pass(CGS_DOTS, N, j + 1, h->V, N, w, nullptr, h->st, h->partials, h->cgs_grid, h->stream);
+  });
+  timed(h, FDE_KFAM_CGS, vb + N * sizeof(double), [&] {
+    return launch_cgs_pass(CGS_UPDATE_DOTS, N, j + 1, h->V, N, w, nullptr, h->st, h->partials, h->cgs_grid, h->stream);
+  });
+  timed(h, FDE_KFAM_CGS, vb + N * sizeof(double), [&] {
+    return launch_cgs_pass(CGS_UPDATE_NORM, N, j + 1, h->V, N, w, nullptr, h->st, h->partials, h->cgs_grid, h->stream);
+  });
+}
+
+template <typename R>
+int fgmres(fde_handle* h, Hierarchy<R>& H, const double* b, double* x, fde_stats* stats) {
+  const size_t N = h->N;
+  const int restart = h->p.restart;
+  timed(h, FDE_KFAM_CGS, 2.0 * N * sizeof(double), [&] {
+    return launch_cgs_pass(CGS_INIT, N, 0, h->V, N, h->V, b, h->st, h->partials, h->cgs_grid, h->stream);
+  });
+  const OpView<double> op = h->cur.view(h->tw64_x, h->tw64_y, h->n1, h->n2, h->L1, h->L2);
+  int cycles = 0;
+  // Arnoldi steps are issued without waiting; the host reads the device state only once the
+  // previous solve's iteration count is reached (kernels after convergence return immediately).
+  const int hint = h->expected_iters > 0 ? h->expected_iters : 1;
+  int total_issued = 0;
+  while (true) {
+    int j = 0;
+    h->prof.cur_cycle = cycles;
+    for (; j < restart; ++j) {
+      h->prof.cur_j = j;
+      arnoldi_step<R>(h, H, j);
+      ++total_issued;
+      if (total_issued >= hint - 1 || j + 1 == restart) {
+        read_state(h);
+        if (h->st_host->done) break;
+      }
+    }
+    h->prof.cycle_nused.push_back(h->st_host->nused);
+    h->prof.cur_j = -1;
+    const int nu = h->st_host->nused;
+    timed(h, FDE_KFAM_UPDATE, (double)N * (nu * sizeof(R) + (cycles == 0 ? 1 : 2) * sizeof(double)), [&] {
+      return launch_update_x<R>(N, static_cast<const R*>(h->Z), N, x, cycles == 0 ? 1 : 0, h->st, h->stream);
+    });
+    op_apply<double, double>(h, true, op, x, h->ay64, h->V, EP_RESID, b, nullptr, 0.0, nullptr);
+    timed(h, FDE_KFAM_CGS, (double)N * sizeof(double), [&] {
+      return launch_cgs_pass(CGS_RESNORM, N, 0, h->V, N, h->V, nullptr, h->st, h->partials, h->cgs_grid, h->stream);
+    });
+    read_state(h);
+    ++cycles;
+    if (h->st_host->conv || h->st_host->iters >= h->p.maxit) break;
+    if (!std::isfinite(h->st_host->resnorm)) break;
+  }
+  const GmresState& s = *h->st_host;
+  h->expected_iters = s.iters;
+  if (h->prof.mask) prof_harvest(h);
+  if (stats) {
+    stats->iters = s.iters;
+    stats->restarts = cycles - 1;
+    stats->converged = s.conv;
+    stats->relres_true = s.bnorm > 0 ? s.resnorm / s.bnorm : 0.0;
+    stats->relres_est = s.bnorm > 0 ? s.est / s.bnorm : 0.0;
+  }
+  if (!std::isfinite(s.resnorm)) return set_err(h, FDE_ENONFINITE, "the iterate became non-finite");
+  if (!s.conv) return set_err(h, FDE_ENOCONV, "iteration limit reached before the tolerance");
+  return FDE_OK;
+}
+
+int solve_impl(fde_handle* h, const double* b, double* x, fde_stats* stats) {
+  if (h->fp32()) return fgmres<float>(h, *h->h32, b, x, stats);
+  return fgmres<double>(h, *h->h64, b, x, stats);
+}
+
+template <typename F>
+int guarded(fde_handle* h, F&& f) {
+  try {
+    return f();
+  } catch (const FdeError& e) {
+    return set_err(h, e.code, e.msg);
+  } catch (const std::bad_alloc&) {
+    return set_err(h, FDE_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return set_err(h, FDE_EDEVICE, "unexpected exception");
+  }
+}
+
+}  // namespace
+
+// ================================ C ABI =========================================================
+extern "C" {
+
+void fde_problem_default(fde_problem* p, double alpha, double beta, int32_t n1, int32_t n2, double tau) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->alpha = alpha;
+  p->beta = beta;
+  p->n1 = n1;
+  p->n2 = n2;
+  p->a1 = 0.0;
+  p->b1 = 1.0;
+  p->a2 = 0.0;
+  p->b2 = 1.0;
+  p->tau = tau;
+  p->precision = FDE_FP64;
+  p->mg_variant = FDE_MG_GEOMETRIC;
+  p->omega = 0.7;
+  p->nu_pre = 1;
+  p->nu_post = 1;
+  p->coarsest_n = 7;
+  p->restart = 20;
+  p->maxit = 200;
+  p->rtol = 1e-10;
+}
+
+const char* fde_last_error(const fde_handle* h) { return h ? h->err.c_str() : g_global_error.c_str(); }
+
+int fde_setup(const fde_problem* pin, const double* dp, const double* dm, const double* ep, const double* em,
+              void* stream, fde_handle** out) {
+  if (!out) return set_err(nullptr, FDE_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!pin) return set_err(nullptr, FDE_EINVAL, "problem is NULL");
+  fde_problem p = *pin;
+  fill_defaults(&p);
+  std::string why;
+  if (validate(&p, &why) != FDE_OK) return set_err(nullptr, FDE_EINVAL, why);
+  if (!dp || !dm || !ep || !em) return set_err(nullptr, FDE_EINVAL, "coefficient pointer is NULL");
+  std::unique_ptr<fde_handle> h(new fde_handle());
+  int rc = guarded(h.get(), [&]() -> int {
+    h->p = p;
+    h->stream = static_cast<hipStream_t>(stream);
+    h->n1 = p.n1;
+    h->n2 = p.n2;
+    h->L1 = 2 * (p.n1 + 1);
+    h->L2 = 2 * (p.n2 + 1);
+    h->N = (size_t)p.n1 * p.n2;
+    h->hx = (p.b1 - p.a1) / (p.n1 + 1);
+    h->hy = (p.b2 - p.a2) / (p.n2 + 1);
+    h->sx = p.tau / (2.0 * std::pow(h->hx, p.alpha));
+    h->sy = p.tau / (2.0 * std::pow(h->hy, p.beta));
+    h->wa = wsgd_weights(p.alpha, p.n1 + 1);
+    h->wb = wsgd_weights(p.beta, p.n2 + 1);
+    DevAlloc& m = h->mem;
+    h->flags = dalloc<int>(m, 4);
+    check_fields(h.get(), dp, dm, ep, em);
+    const size_t N = h->N;
+    h->cur.dpm = dalloc<double>(m, 2 * N);
+    h->cur.epm = dalloc<double>(m, 2 * N);
+    load_outer(h.get(), h->cur, dp, dm, ep, em);
+    h->cur.lam_x = upload<double>(m, symbol_host(h->wa, p.n1, h->L1, h->sx), h->stream);
+    h->cur.lam_y = upload<double>(m, symbol_host(h->wb, p.n2, h->L2, h->sy), h->stream);
+    h->prev = h->cur;
+    h->prev_aliases_cur = true;
+    {
+      std::vector<double> t(fft_twiddle_count(h->L1, 8) + 2);
+      fft_twiddles(h->L1, 8, t.data(), nullptr);
+      h->tw64_x = upload<double>(m, t, h->stream);
+      std::vector<double> u(fft_twiddle_count(h->L2, 8) + 2);
+      fft_twiddles(h->L2, 8, u.data(), nullptr);
+      h->tw64_y = upload<double>(m, u, h->stream);
+    }
+    h->ay64 = dalloc<double>(m, N);
+    h->rhs = dalloc<double>(m, N);
+    h->scratch64 = dalloc<double>(m, 2 * N);
+    h->V = dalloc<double>(m, (size_t)(p.restart + 1) * N);
+    if (h->fp32()) h->Z = dalloc<float>(m, (size_t)p.restart * N);
+    else h->Z = dalloc<double>(m, (size_t)p.restart * N);
+    h->st = dalloc<GmresState>(m, 1);
+    h->cgs_grid = cgs_grid(N);
+    h->partials = dalloc<double>(m, cgs_partials_len(N));
+    HIPCHECK(hipHostMalloc((void**)&h->st_host, sizeof(GmresState), hipHostMallocDefault));
+    GmresState init{};
+    init.rtol = p.rtol;
+    init.maxit = p.maxit;
+    init.restart = p.restart;
+    init.cgs2 = 1;
+    HIPCHECK(hipMemcpyAsync(h->st, &init, sizeof(init), hipMemcpyHostToDevice, h->stream));
+    build_preconditioner(h.get());
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    return FDE_OK;
+  });
+  if (rc != FDE_OK) {
+    g_global_error = h->err;
+    if (h->st_host) (void)hipHostFree(h->st_host);
+    return rc;
+  }
+  *out = h.release();
+  return FDE_OK;
+}
+
+void fde_destroy(fde_handle* h) {
+  if (!h) return;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  else (void)hipDeviceSynchronize();
+  if (h->st_host) (void)hipHostFree(h->st_host);
+  delete h;
+}
+
+int fde_update_coeffs(fde_handle* h, const double* dp, const double* dm, const double* ep, const double* em) {
+  if (!h) return set_err(nullptr, FDE_EINVAL, "handle is NULL");
+  return guarded(h, [&]() -> int {
+    check_fields(h, dp, dm, ep, em);
+    if (h->prev_aliases_cur) {
+      h->prev.dpm = dalloc<double>(h->mem, 2 * h->N);
+      h->prev.epm = dalloc<double>(h->mem, 2 * h->N);
+      h->prev_aliases_cur = false;
+    }
+    std::swap(h->prev.dpm, h->cur.dpm);
+    std::swap(h->prev.epm, h->cur.epm);
+    load_outer(h, h->cur, dp, dm, ep, em);
+    build_preconditioner(h);
+    return FDE_OK;
+  });
+}
+
+int fde_solve(fde_handle* h, const double* b, double* x, fde_stats* stats) {
+  if (!h) return set_err(nullptr, FDE_EINVAL, "handle is NULL");
+  if (!b || !x) return set_err(h, FDE_EINVAL, "b or x is NULL");
+  if (b == x) return set_err(h, FDE_EINVAL, "x may not alias b");
+  return guarded(h, [&]() -> int { return solve_impl(h, b, x, stats); });
+}
+
+int fde_step_sources(fde_handle* h, const double* u_prev, int32_t nsrc, const double* phi, const double* const* S,
+                     double* u_next, fde_stats* stats) {
+  if (!h) return set_err(nullptr, FDE_EINVAL, "handle is NULL");
+  if (!u_prev || !u_next) return set_err(h, FDE_EINVAL, "u_prev or u_next is NULL");
+  if (u_prev == u_next) return set_err(h, FDE_EINVAL, "u_next may not alias u_prev");
+  if (nsrc < 0 || nsrc > kMaxSrc || (nsrc > 0 && (!phi || !S))) return set_err(h, FDE_EINVAL, "bad source list");
+  return guarded(h, [&]() -> int {
+    SrcTerms src{};
+    src.n = nsrc;
+    for (int k = 0; k < nsrc; ++k) {
+      if (!S[k]) throw FdeError{FDE_EINVAL, "source field is NULL"};
+      src.phi[k] = phi[k];
+      src.S[k] = S[k];
+    }
+    const OpView<double> op = h->prev.view(h->tw64_x, h->tw64_y, h->n1, h->n2, h->L1, h->L2);
+    op_apply<double, double>(h, true, op, u_prev, h->ay64, h->rhs, EP_RHS, nullptr, &src, h->p.tau, nullptr);
+    return solve_impl(h, h->rhs, u_next, stats);
+  });
+}
+
+int fde_step(fde_handle* h, const double* u_prev, const double* v_half, double* u_next, fde_stats* stats) {
+  const double one = 1.0;
+  const double* S[1] = {v_half};
+  return fde_step_sources(h, u_prev, v_half ? 1 : 0, &one, S, u_next, stats);
+}
+
+int fde_profile_enable(fde_handle* h, uint32_t mask) {
+  if (!h) return set_err(nullptr, FDE_EINVAL, "handle is NULL");
+  return guarded(h, [&]() -> int {
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    prof_harvest(h);
+    h->prof.mask = mask & ((1u << FDE_KFAM_COUNT) - 1);
+    return FDE_OK;
+  });
+}
+
+int fde_profile_read(fde_handle* h, int family, int64_t* launches, double* total_ms, double* bytes) {
+  if (!h) return set_err(nullptr, FDE_EINVAL, "handle is NULL");
+  if (family < 0 || family >= FDE_KFAM_COUNT) return set_err(h, FDE_EINVAL, "unknown kernel family");
+  return guarded(h, [&]() -> int {
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    prof_harvest(h);
+    if (launches) *launches = h->prof.launches[family];
+    if (total_ms) *total_ms = h->prof.ms[family];
+    if (bytes) *bytes = h->prof.bytes[family];
+    return FDE_OK;
+  });
+}
+
+int fde_profile_reset(fde_handle* h) {
+  if (!h) return set_err(nullptr, FDE_EINVAL, "handle is NULL");
+  return guarded(h, [&]() -> int {
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    prof_harvest(h);
+    for (int k = 0; k < FDE_KFAM_COUNT; ++k) {
+      h->prof.launches[k] = 0;
+      h->prof.ms[k] = 0.0;
+      h->prof.bytes[k] = 0.0;
+    }
+    return FDE_OK;
+  });
+}
+
+int fde_sync(fde_handle* h) {
+  if (!h) return set_err(nullptr, FDE_EINVAL, "handle is NULL");
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return set_err(h, FDE_EDEVICE, hipGetErrorString(e));
+  return FDE_OK;
+}
+
+int fde_num_levels(const fde_handle* h) {
+  if (!h) return FDE_EINVAL;
+  return h->h32 ? (int)h->h32->lv.size() : (int)h->h64->lv.size();
+}
+
+int fde_level_size(const fde_handle* h, int level, int32_t* n1, int32_t* n2) {
+  if (!h || level < 0 || level >= fde_num_levels(h)) return FDE_EINVAL;
+  int a = h->h32 ? h->h32->lv[level].n1 : h->h64->lv[level].n1;
+  int b = h->h32 ? h->h32->lv[level].n2 : h->h64->lv[level].n2;
+  if (n1) *n1 = a;
+  if (n2) *n2 = b;
+  return FDE_OK;
+}
+
+}  // extern "C"
+
+// ---- test hooks ---------------------------------------------------------------------------------
+namespace {
+
+template <typename R>
+struct HookIO {
+  // FP64 caller arrays <-> precision-R scratch
+  static R* in(fde_handle* h, const double* x, size_t n, int slot) {
+    if (std::is_same<R, double>::value) return const_cast<R*>(reinterpret_cast<const R*>(x));
+    R* s = reinterpret_cast<R*>(h->scratch64) + (size_t)slot * n;
+    HIPCHECK((launch_convert<R, double>(n, x, s, h->stream)));
+    return s;
+  }
+};
+
+template <typename R>
+Hierarchy<R>& hier(fde_handle* h);
+template <>
+Hierarchy<double>& hier<double>(fde_handle* h) {
+  if (!h->h64) throw FdeError{FDE_EINVAL, "precision does not match the handle's preconditioner"};
+  return *h->h64;
+}
+template <>
+Hierarchy<float>& hier<float>(fde_handle* h) {
+  if (!h->h32) throw FdeError{FDE_EINVAL, "precision does not match the handle's preconditioner"};
+  return *h->h32;
+}
+
+// copy a level-sized result of type R into the caller's FP64 array
+template <typename R>
+void out64(fde_handle* h, const R* src, double* dst, size_t n) {
+  if (std::is_same<R, double>::value) {
+    if ((const void*)src != (const void*)dst)
+      HIPCHECK(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  } else {
+    HIPCHECK((launch_convert<double, R>(n, src, dst, h->stream)));
+  }
+}
+
+template <typename R>
+int apply_hook(fde_handle* h, int level, const double* x, double* y, int mode, const double* b) {
+  Hierarchy<R>& H = hier<R>(h);
+  if (level < 0 || level >= (int)H.lv.size()) throw FdeError{FDE_EINVAL, "level out of range"};
+  Level<R>& L = H.lv[level];
+  const size_t n = L.N();
+  R* xi = HookIO<R>::in(h, x, n, 0);
+  const R* bi = b ? HookIO<R>::in(h, b, n, 1) : nullptr;
+  R* res = std::is_same<R, double>::value ? reinterpret_cast<R*>(y) : L.x;
+  if (level >= H.lc) {
+    const int k = level - H.lc;
+    HIPCHECK(launch_direct_apply<R>(H.cv, k, xi, res, mode, bi, h->stream));
+  } else {
+    if (mode == EP_JACOBI && (const void*)res != (const void*)xi) {
+      // Jacobi is applied in place on x
+      HIPCHECK(hipMemcpyAsync(res, xi, n * sizeof(R), hipMemcpyDeviceToDevice, h->stream));
+      xi = res;
+    }
+    HIPCHECK((launch_operator<R, R>(L.view(), xi, L.ay, res, mode, bi, nullptr, 0.0, nullptr, h->stream)));
+  }
+  out64<R>(h, res, y, n);
+  HIPCHECK(hipStreamSynchronize(h->stream));
+  return FDE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fde_apply(fde_handle* h, int level, int prec, const double* x, double* y) {
+  if (!h) return set_err(nullptr, FDE_EINVAL, "handle is NULL");
+  if (!x || !y || x == y) return set_err(h, FDE_EINVAL, "bad x/y");
+  return guarded(h, [&]() -> int {
+    if (level == 0 && prec == FDE_FP64) {
+      const OpView<double> op = h->cur.view(h->tw64_x, h->tw64_y, h->n1, h->n2, h->L1, h->L2);
+      HIPCHECK((launch_operator<double, double>(op, x, h->ay64, y, EP_APPLY, nullptr, nullptr, 0.0, nullptr,
+                                                h->stream)));
+      HIPCHECK(hipStreamSynchronize(h->stream));
+      return FDE_OK;
+    }
+    if (prec == FDE_FP64) return apply_hook<double>(h, level, x, y, EP_APPLY, nullptr);
+    if (prec == FDE_MIXED_FP32) return apply_hook<float>(h, level, x, y, EP_APPLY, nullptr);
+    throw FdeError{FDE_EINVAL, "unsupported precision for fde_apply"};
+  });
+}
+
+int fde_smooth(fde_handle* h, int level, int prec, const double* b, double* x, int zero_guess) {
+  if (!h) return set_err(nullptr, FDE_EINVAL, "handle is NULL");
+  if (!b || !x) return set_err(h, FDE_EINVAL, "bad b/x");
+  return guarded(h, [&]() -> int {
+    if (zero_guess) {
+      int32_t n1, n2;
+      if (fde_level_size(h, level, &n1, &n2)) throw FdeError{FDE_EINVAL, "level out of range"};
+      HIPCHECK(hipMemsetAsync(x, 0, sizeof(double) * (size_t)n1 * n2, h->stream));
+    }
+    // x <- x + omega D^-1 (b - A x); the hook computes it out of place through scratch
+    double* tmp = h->scratch64 + h->N;
+    int rc;
+    if (prec == FDE_FP64) rc = apply_hook<double>(h, level, x, tmp, EP_JACOBI, b);
+    else if (prec == FDE_MIXED_FP32) rc = apply_hook<float>(h, level, x, tmp, EP_JACOBI, b);
+    else throw FdeError{FDE_EINVAL, "unsupported precision"};
+    int32_t n1, n2;
+    fde_level_size(h, level, &n1, &n2);
+    HIPCHECK(hipMemcpyAsync(x, tmp, sizeof(double) * (size_t)n1 * n2, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    return rc;
+  });
+}
+
+int fde_level_diag(fde_handle* h, int level, double* diag) {
+  if (!h || !diag) return set_err(h, FDE_EINVAL, "bad arguments");
+  return guarded(h, [&]() -> int {
+    if (h->h64) {
+      auto& L = h->h64->lv.at(level);
+      HIPCHECK(launch_diag<double>((int)L.N(), L.dpm, L.epm, L.sx * h->wa[1], L.sy * h->wb[1], h->p.omega, nullptr,
+                                   diag, h->stream));
+    } else {
+      auto& L = h->h32->lv.at(level);
+      HIPCHECK(launch_diag<float>((int)L.N(), L.dpm, L.epm, L.sx * h->wa[1], L.sy * h->wb[1], h->p.omega, nullptr,
+                                  diag, h->stream));
+    }
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    return FDE_OK;
+  });
+}
+
+}  // extern "C"
+
+namespace {
+template <typename R>
+int transfer_hook(fde_handle* h, int level, const double* in, double* out, bool restrict_) {
+  Hierarchy<R>& H = hier<R>(h);
+  if (level < 0 || level + 1 >= (int)H.lv.size()) throw FdeError{FDE_EINVAL, "level out of range"};
+  Level<R>& F = H.lv[level];
+  Level<R>& C = H.lv[level + 1];
+  if (restrict_) {
+    R* ri = HookIO<R>::in(h, in, F.N(), 0);
+    HIPCHECK(launch_restrict<R>(F.n1, F.n2, ri, C.b, nullptr, h->stream));
+    out64<R>(h, C.b, out, C.N());
+  } else {
+    R* ei = HookIO<R>::in(h, in, C.N(), 0);
+    if (std::is_same<R, double>::value) {
+      HIPCHECK(launch_prolong<R>(F.n1, F.n2, ei, reinterpret_cast<R*>(out), nullptr, h->stream));
+    } else {
+      HIPCHECK((launch_convert<R, double>(F.N(), out, F.x, h->stream)));
+      HIPCHECK(launch_prolong<R>(F.n1, F.n2, ei, F.x, nullptr, h->stream));
+      out64<R>(h, F.x, out, F.N());
+    }
+  }
+  HIPCHECK(hipStreamSynchronize(h->stream));
+  return FDE_OK;
+}
+
+template <typename R>
+int vcycle_hook(fde_handle* h, const double* b, double* x) {
+  Hierarchy<R>& H = hier<R>(h);
+  R* z = std::is_same<R, double>::value ? reinterpret_cast<R*>(x) : H.lv[0].x;
+  if (!std::is_same<R, double>::value && H.lc == 0) z = reinterpret_cast<R*>(h->scratch64);
+  vcycle_top<R>(h, H, b, nullptr, z, nullptr);
+  out64<R>(h, z, x, h->N);
+  HIPCHECK(hipStreamSynchronize(h->stream));
+  return FDE_OK;
+}
+
+template <typename R>
+int coarse_hook(fde_handle* h, const double* b, double* x) {
+  Hierarchy<R>& H = hier<R>(h);
+  R* bi = HookIO<R>::in(h, b, H.Nc, 0);
+  R* xo = reinterpret_cast<R*>(h->scratch64 + h->N);
+  HIPCHECK(launch_coarse_solve<R>(H.Nc, H.inv, bi, xo, h->stream));
+  out64<R>(h, xo, x, H.Nc);
+  HIPCHECK(hipStreamSynchronize(h->stream));
+  return FDE_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int fde_restrict(fde_handle* h, int level, int prec, const double* r, double* rc) {
+  if (!h) return set_err(nullptr, FDE_EINVAL, "handle is NULL");
+  if (!r || !rc) return set_err(h, FDE_EINVAL, "bad arguments");
+  return guarded(h, [&]() -> int {
+    if (prec == FDE_FP64) return transfer_hook<double>(h, level, r, rc, true);
+    if (prec == FDE_MIXED_FP32) return transfer_hook<float>(h, level, r, rc, true);
+    throw FdeError{FDE_EINVAL, "unsupported precision"};
+  });
+}
+
+int fde_prolong(fde_handle* h, int level, int prec, const double* e, double* x) {
+  if (!h) return set_err(nullptr, FDE_EINVAL, "handle is NULL");
+  if (!e || !x) return set_err(h, FDE_EINVAL, "bad arguments");
+  return guarded(h, [&]() -> int {
+    if (prec == FDE_FP64) return transfer_hook<double>(h, level, e, x, false);
+    if (prec == FDE_MIXED_FP32) return transfer_hook<float>(h, level, e, x, false);
+    throw FdeError{FDE_EINVAL, "unsupported precision"};
+  });
+}
+
+int fde_coarse_solve(fde_handle* h, const double* b, double* x) {
+  if (!h) return set_err(nullptr, FDE_EINVAL, "handle is NULL");
+  if (!b || !x) return set_err(h, FDE_EINVAL, "bad arguments");
+  return guarded(h, [&]() -> int { return h->fp32() ? coarse_hook<float>(h, b, x) : coarse_hook<double>(h, b, x); });
+}
+
+int fde_vcycle(fde_handle* h, const double* b, double* x) {
+  if (!h) return set_err(nullptr, FDE_EINVAL, "handle is NULL");
+  if (!b || !x || b == x) return set_err(h, FDE_EINVAL, "bad arguments");
+  return guarded(h, [&]() -> int { return h->fp32() ? vcycle_hook<float>(h, b, x) : vcycle_hook<double>(h, b, x); });
+}
+
+}  // extern "C"

@@ -1,0 +1,90 @@
+"""CPU checks of the C ABI: the library loads, exports every function of include/fde.h, its struct
+layout matches the Python binding, and argument validation fails cleanly before any device work."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1706_06844_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fde.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fde_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return L.load()
+
+
+def test_every_declared_function_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    # and every exported binding signature refers to a declared function
+    assert set(n for n in L.SIGNATURES if hasattr(lib, n)) >= set(names)
+
+
+def test_struct_layout_matches_c(tmp_path):
+    exe = tmp_path / "abi_layout"
+    src = os.path.join(ROOT, "tests", "abi_layout.c")
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), src, "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    c = dict(line.rsplit(" ", 1) for line in out if line.strip())
+    assert int(c["fde_problem"]) == ctypes.sizeof(L.fde_problem)
+    assert int(c["fde_stats"]) == ctypes.sizeof(L.fde_stats)
+    for key, val in c.items():
+        if "." in key:
+            struct, field = key.split(".")
+            cls = getattr(L, struct)
+            assert getattr(cls, field).offset == int(val), key
+
+
+def test_problem_default(lib):
+    p = L.fde_problem()
+    lib.fde_problem_default(ctypes.byref(p), 1.5, 1.6, 63, 31, 0.01)
+    assert (p.alpha, p.beta, p.n1, p.n2, p.tau) == (1.5, 1.6, 63, 31, 0.01)
+    assert (p.a1, p.b1, p.a2, p.b2) == (0.0, 1.0, 0.0, 1.0)
+    assert p.omega == 0.7 and p.nu_pre == 1 and p.nu_post == 1 and p.coarsest_n == 7
+    assert p.restart == 20 and p.maxit == 200 and p.rtol == 1e-10
+
+
+@pytest.mark.parametrize("field,value,needle", [
+    ("alpha", 2.0, "alpha"), ("alpha", 1.0, "alpha"), ("beta", 0.5, "alpha and beta"),
+    ("n1", 10, "2^l - 1"), ("n2", 3, "2^l - 1"), ("n1", 4095, "2047"),
+    ("tau", 0.0, "tau"), ("tau", -1.0, "tau"), ("restart", 40, "restart"),
+    ("omega", 1.5, "omega"), ("b1", -1.0, "a < b"), ("precision", 7, "precision"),
+])
+def test_setup_rejects_invalid_problems(lib, field, value, needle):
+    p = L.fde_problem()
+    lib.fde_problem_default(ctypes.byref(p), 1.5, 1.5, 63, 63, 0.01)
+    setattr(p, field, value)
+    out = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x1000)
+    rc = lib.fde_setup(ctypes.byref(p), fake, fake, fake, fake, None, ctypes.byref(out))
+    assert rc == L.FDE_EINVAL and out.value is None
+    assert needle in lib.fde_last_error(None).decode()
+
+
+def test_setup_rejects_null_arguments(lib):
+    p = L.fde_problem()
+    lib.fde_problem_default(ctypes.byref(p), 1.5, 1.5, 63, 63, 0.01)
+    out = ctypes.c_void_p()
+    assert lib.fde_setup(ctypes.byref(p), None, None, None, None, None, ctypes.byref(out)) == L.FDE_EINVAL
+    assert lib.fde_setup(None, None, None, None, None, None, ctypes.byref(out)) == L.FDE_EINVAL
+    assert lib.fde_setup(ctypes.byref(p), None, None, None, None, None, None) == L.FDE_EINVAL
+
+
+def test_null_handle_calls_fail_cleanly(lib):
+    assert lib.fde_solve(None, None, None, None) == L.FDE_EINVAL
+    assert lib.fde_step(None, None, None, None, None) == L.FDE_EINVAL
+    assert lib.fde_num_levels(None) == L.FDE_EINVAL
+    lib.fde_destroy(None)

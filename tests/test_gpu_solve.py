@@ -1,0 +1,154 @@
+"""Solver-level parity: one linear solve and whole CN runs against the FP64 oracle.
+
+Tolerance: relative 2-norm <= 1e-9 against the oracle, with GMRES tolerance 1e-10 (the oracle
+solves exactly by dense LU on small grids, or with its own FGMRES at 1e-13 on larger ones).
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle.cn import DirectSolver, IterativeSolver, cn_run
+from oracle.operator import operator_from_problem
+from paper_1706_06844_amd import fde
+
+from .gpu_util import dev, host, make_handle, note, rel
+
+pytestmark = pytest.mark.gpu
+
+PRECS = [fde.FDE_FP64, fde.FDE_MIXED_FP32]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("n", [7, 15, 31, 63])
+def test_single_solve_matches_dense_lu(n, prec):
+    note(f"solve n={n} prec={prec}")
+    p = workloads.config_c2(n, 32)
+    h = make_handle(p, precision=prec)
+    op = operator_from_problem(p, 0.0)
+    B = np.random.default_rng(n).standard_normal((n, n))
+    x = dev(np.zeros_like(B))
+    st = fde.fde_solve(h, dev(B), x)
+    ref = np.linalg.solve(op.dense(), B.ravel()).reshape(B.shape)
+    assert st["converged"] and st["relres_true"] <= 1e-10
+    assert rel(host(x), ref) <= 1e-9
+
+
+def _run_gpu(p, prec, steps=None, **kw):
+    h = make_handle(p, precision=prec, **kw)
+    phis, fields = workloads.source_terms(p)
+    S = [dev(f) for f in fields]
+    u = dev(workloads.sample_u0(p))
+    un = dev(np.zeros((p.n2, p.n1)))
+    iters = []
+    for m in range(1, (steps or p.M) + 1):
+        t_half = (m - 0.5) * p.tau
+        st = fde.fde_step_sources(h, u, [f(t_half) for f in phis], S, un)
+        assert st["converged"], (m, st)
+        iters.append(st["iters"])
+        u, un = un, u
+    return host(u), iters
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_c1_full_run_matches_oracle(prec):
+    note(f"C1 full run prec={prec}")
+    p = workloads.config_c1(63)
+    u, iters = _run_gpu(p, prec)
+    ref = cn_run(p, solver=DirectSolver()).u
+    assert rel(u, ref) <= 1e-9
+    X, Y = workloads.grid(p)
+    err = np.abs(u - p.u_exact(X, Y, p.T)).max()
+    assert err == pytest.approx(np.abs(ref - p.u_exact(X, Y, p.T)).max(), rel=1e-6)
+    assert max(iters) <= 20
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_c2_steps_match_oracle(prec):
+    note(f"C2 two steps prec={prec}")
+    p = workloads.config_c2(511, 32)
+    u, iters = _run_gpu(p, prec, steps=2)
+    # the oracle reaches its rounding floor (~2e-13) at 511^2, so it solves to 1e-12
+    ref = cn_run(p, steps=2, solver=IterativeSolver(rtol=1e-12)).u
+    assert rel(u, ref) <= 1e-9, rel(u, ref)
+
+
+def test_c3_step_residual_sampled_by_oracle():
+    # at full size the oracle checks the residual of the returned step at sampled points
+    note("C3 2047 one step")
+    p = workloads.config_c3(2047, 16)
+    # the anisotropic instance needs several hundred iterations with the paper's V-cycle
+    h = make_handle(p, precision=fde.FDE_MIXED_FP32, maxit=4000)
+    phis, fields = workloads.source_terms(p)
+    u0 = workloads.sample_u0(p)
+    un = dev(np.zeros((p.n2, p.n1)))
+    st = fde.fde_step_sources(h, dev(u0), [f(0.5 * p.tau) for f in phis], [dev(f) for f in fields], un)
+    assert st["converged"] and st["relres_true"] <= 1e-10
+    op = operator_from_problem(p, 0.0)
+    rng = np.random.default_rng(1)
+    js, is_ = rng.integers(0, 2047, 40), rng.integers(0, 2047, 40)
+    x = host(un)
+    b_pts = (op.rhs(u0)[js, is_] if False else
+             u0[js, is_] + 0.5 * p.tau * op.L_points(u0, js, is_)
+             + p.tau * workloads.sample_source(p, 0.5 * p.tau)[js, is_])
+    r_pts = b_pts - op.apply_points(x, js, is_)
+    # the true relative residual is <= 1e-10 in 2-norm; sampled entries are far below ||b||
+    bnorm_rms = np.sqrt(np.mean(b_pts ** 2))
+    assert np.max(np.abs(r_pts)) <= 1e-7 * bnorm_rms
+
+
+def test_fp64_and_mixed_agree_at_2047():
+    note("C3 2047 fp64 vs mixed")
+    p = workloads.config_c3(2047, 16)
+    phis, fields = workloads.source_terms(p)
+    u0 = dev(workloads.sample_u0(p))
+    S = [dev(f) for f in fields]
+    out = []
+    for prec in PRECS:
+        h = make_handle(p, precision=prec, maxit=4000)
+        un = dev(np.zeros((p.n2, p.n1)))
+        st = fde.fde_step_sources(h, u0, [f(0.5 * p.tau) for f in phis], S, un)
+        assert st["converged"]
+        out.append(host(un))
+        h.close()
+    assert rel(out[1], out[0]) <= 1e-9
+
+
+def test_error_codes():
+    p = workloads.config_c2(31, 32)
+    fields = [dev(f) for f in workloads.sample(p, 0.0)]
+    from .gpu_util import problem_struct
+    bad = fields[0].clone()
+    bad[3, 4] = -1.0
+    with pytest.raises(fde.FdeError) as e:
+        fde.fde_setup(problem_struct(p), bad, *fields[1:])
+    assert e.value.code == fde.FDE_ENEGCOEF
+    bad[3, 4] = float("nan")
+    with pytest.raises(fde.FdeError) as e:
+        fde.fde_setup(problem_struct(p), bad, *fields[1:])
+    assert e.value.code == fde.FDE_ENONFINITE
+    h = fde.fde_setup(problem_struct(p, maxit=1), *fields)
+    b = dev(np.random.default_rng(0).standard_normal((31, 31)))
+    x = dev(np.zeros((31, 31)))
+    st = fde.fde_solve(h, b, x)
+    assert st["rc"] == fde.FDE_ENOCONV and not st["converged"] and st["iters"] == 1
+
+
+def test_zero_rhs_gives_zero():
+    p = workloads.config_c2(31, 32)
+    h = make_handle(p)
+    x = dev(np.ones((31, 31)))
+    st = fde.fde_solve(h, dev(np.zeros((31, 31))), x)
+    assert st["converged"] and st["iters"] == 0
+    assert np.all(host(x) == 0.0)
+
+
+def test_solve_is_deterministic():
+    p = workloads.config_c2(255, 32)
+    h = make_handle(p, precision=fde.FDE_MIXED_FP32)
+    b = dev(np.random.default_rng(4).standard_normal((255, 255)))
+    xs = []
+    for _ in range(2):
+        x = dev(np.zeros((255, 255)))
+        fde.fde_solve(h, b, x)
+        xs.append(host(x))
+    assert np.array_equal(xs[0], xs[1])
