@@ -79,13 +79,18 @@ def run_precision(prec, p, dev_fields, S, phis, u0, steps, warmup, maxit, profil
     run(warmup, "warmup")
     prof = fde.fde_profile_read(h)
     fam = profile_family
-    if fam is None:
-        cand = {k: v for k, v in prof.items() if v["launches"] > 0}
+    cand = {k: v for k, v in prof.items() if v["launches"] > 0}
+    if fam is None and cand:
         fam = max(cand, key=lambda k: cand[k]["ms"])
     fde.fde_profile_reset(h)
-    fde.fde_profile_enable(h, 1 << fde.L.KFAM.index(fam))
+    # without warmup there is nothing to choose from: time every family in the timed run
+    fde.fde_profile_enable(h, 1 << fde.L.KFAM.index(fam) if fam else (1 << len(fde.L.KFAM)) - 1)
     elapsed, lat, its, u_final = run(steps, "timed")
-    live = fde.fde_profile_read(h)[fam]
+    timed = fde.fde_profile_read(h)
+    if fam is None:
+        prof = timed
+        fam = max(timed, key=lambda k: timed[k]["ms"])
+    live = timed[fam]
     out = {"elapsed": elapsed, "lat": lat, "iters": its, "u": u_final.clone(), "family": fam,
            "live": live, "warm_profile": prof}
     h.close()

@@ -80,7 +80,7 @@ typedef struct fde_stats {
   int32_t iters;        /* GMRES iterations (preconditioner applications) in this solve           */
   int32_t restarts;     /* completed restart cycles beyond the first                               */
   int32_t converged;    /* 1 if the true relative residual met rtol                                */
-  int32_t reserved;
+  int32_t reorth_steps;  /* Arnoldi steps that needed a second Gram-Schmidt pass                   */
   double relres_true;   /* ||b - A x|| / ||b|| computed in FP64 from the returned x               */
   double relres_est;    /* the Arnoldi (Givens) estimate at exit                                   */
 } fde_stats;

@@ -48,12 +48,12 @@ class fde_problem(ctypes.Structure):
 class fde_stats(ctypes.Structure):
     _fields_ = [
         ("iters", ctypes.c_int32), ("restarts", ctypes.c_int32),
-        ("converged", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("converged", ctypes.c_int32), ("reorth_steps", ctypes.c_int32),
         ("relres_true", ctypes.c_double), ("relres_est", ctypes.c_double),
     ]
 
     def as_dict(self):
-        return {"iters": self.iters, "restarts": self.restarts, "converged": bool(self.converged),
+        return {"iters": self.iters, "restarts": self.restarts, "converged": bool(self.converged), "reorth_steps": self.reorth_steps,
                 "relres_true": self.relres_true, "relres_est": self.relres_est}
 
 

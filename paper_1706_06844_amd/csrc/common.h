@@ -35,6 +35,9 @@ struct OpView {
   const R* mu_y;  // [L2][2]
   const R* tw_x;  // FFT twiddles for L1
   const R* tw_y;  // FFT twiddles for L2
+  const R* swx;   // direct levels: sx * w_k, k = 0..n1
+  const R* swy;   // direct levels: sy * w_k, k = 0..n2
+  int direct;     // 1: apply with the direct dense-Toeplitz kernel instead of the FFT passes
 };
 
 // ---- launchers (toeplitz.hip) ------------------------------------------------------------------
@@ -50,6 +53,13 @@ template <typename R, typename Tin>
 hipError_t launch_op_x(const OpView<R>& op, const Tin* x, const R* ay, R* out, int mode, const R* b,
                        const SrcTerms* src, double tau, const int* skip, hipStream_t st);
 
+// Direct dense-Toeplitz operator for small levels (n1 <= 512): one launch for both directions and
+// the epilogue; swx/swy are sx*w_k, sy*w_k for k = 0..n.
+template <typename R, typename Tin>
+hipError_t launch_direct_op(int n1, int n2, const Tin* x, const R* dpm, const R* epm, const R* swx, const R* swy,
+                            R* out, int mode, const R* b, const R* dinv, const SrcTerms* src, double tau,
+                            const int* skip, hipStream_t st);
+
 bool fft_length_supported(int L);
 // FFT twiddle table for length L and the plan of the given element size (4 or 8 bytes),
 // interleaved complex, computed in double precision; count = 2 * entries.
@@ -64,7 +74,8 @@ template <typename R, typename Tin>
 hipError_t launch_presmooth(int N, const Tin* b, const double* bscale, const R* dinv, R* x, R* bcopy,
                             const int* skip, hipStream_t st);
 template <typename R>
-hipError_t launch_restrict(int n1, int n2, const R* r, R* rc, const int* skip, hipStream_t st);
+hipError_t launch_restrict(int n1, int n2, const R* r, R* rc, const R* dinv_c, R* xc, const int* skip,
+                           hipStream_t st);
 template <typename R>
 hipError_t launch_prolong(int n1, int n2, const R* e, R* x, const int* skip, hipStream_t st);
 template <typename Tout, typename Tin>
@@ -123,14 +134,17 @@ struct GmresState {
   int iters;      // Arnoldi steps so far in this solve
   int nused;      // Arnoldi steps in the current cycle
   int conv;       // 1: the FP64 true residual met the tolerance
+  int nreorth;    // Arnoldi steps in this solve that took a second Gram-Schmidt pass
+  unsigned reorth_mask;  // bit j: step j of the current cycle took the second pass
   double resnorm; // last true residual norm
   double est;     // last Givens residual estimate
   double bnorm;
   double atol;    // rtol * ||b||
   // configuration
   double rtol;
-  int maxit, restart, cgs2, pad_;
-  unsigned int ticket[4];
+  int maxit, restart;
+  int orth;       // Gram-Schmidt policy: 0 one pass, 1 always two passes, 2 second pass when needed
+  int reorth;     // 1: the current Arnoldi step takes the second pass
   double g[kMaxRestart + 1], cs[kMaxRestart], sn[kMaxRestart];
   double Rm[kMaxRestart * kMaxRestart];  // column j in Rm[j*kMaxRestart + i], i <= j
   double h1[kMaxRestart + 1], h2[kMaxRestart + 1];
@@ -138,13 +152,19 @@ struct GmresState {
   double y[kMaxRestart];
 };
 
+// Passes of one Arnoldi step: DOTS (h1 = V^T w and ||w||^2, decides the second pass), UPDATE_DOTS
+// (second pass only: w -= V h1, h2 = V^T w), UPDATE_NORM (w -= V h, h = h2 or h1, then ||w|| and the
+// Givens update); INIT (w = src, ||src||) and RESNORM (||w||) start a solve and a cycle.
 enum CgsKind : int { CGS_DOTS = 0, CGS_UPDATE_DOTS = 1, CGS_UPDATE_NORM = 2, CGS_INIT = 3, CGS_RESNORM = 4 };
-// One fused pass over the basis V[0..nv) (FP64, stride ldv) and w (= V[nv] unless given).
+// One fused pass over the basis V[0..nv) (FP64, column stride ldv: even, columns 16-byte aligned)
+// and w (16-byte aligned, readable up to N rounded up to even).
 hipError_t launch_cgs_pass(int kind, size_t N, int nv, double* V, size_t ldv, double* w,
                            const double* src, GmresState* st, double* partials, int grid,
                            hipStream_t s);
 int cgs_grid(size_t N);
 size_t cgs_partials_len(size_t N);
+// Column stride of the Krylov basis for N unknowns (multiple of 64 doubles).
+size_t basis_ld(size_t N);
 template <typename Tz>
 hipError_t launch_update_x(size_t N, const Tz* Z, size_t ldz, double* x, int first,
                            GmresState* st, hipStream_t s);

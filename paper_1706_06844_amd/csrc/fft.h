@@ -10,7 +10,9 @@
 // exp(sign 2 pi i r (b mod NS) / (NS R)), does a radix-R DFT, and writes element r of its output to
 // position (b / NS) * NS * R + (b mod NS) + r * NS.  After the last stage (NS * R = L) that position
 // is again t + T*m, so the result stays in registers in natural order; earlier stages exchange data
-// through LDS.  Twiddles come from a per-length table laid out [stage][b mod NS][r-1].
+// through LDS.  Twiddles: a thread needs w^r, r = 1..R-1, with w = exp(sign 2 pi i (b mod NS)/(NS R));
+// it loads the single base value w of each stage (compact table [stage][b mod NS]) once per kernel
+// and forms the powers with a product tree of depth <= 4.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -148,6 +150,13 @@ __device__ __forceinline__ void dft(R (&re)[N], R (&im)[N]) {
 // LDS index padding: one spare slot every 16 elements keeps strided stage writes conflict-free.
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
 __host__ __device__ constexpr int lds_len(int L) { return L + L / 16 + 1; }
+// Exchange of a stage: real and imaginary parts together (one barrier pair per stage) or one after
+// the other through a single buffer (half the LDS, two barrier pairs).
+#ifndef FDE_EXCH_SPLIT
+#define FDE_EXCH_SPLIT 0
+#endif
+// LDS reals one transform's exchange needs.
+__host__ __device__ constexpr int lds_exchange(int L) { return FDE_EXCH_SPLIT ? lds_len(L) : 2 * lds_len(L); }
 
 // Radix plan: E elements per thread, stages of radix E except a smaller last one.
 __host__ __device__ constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
@@ -155,7 +164,7 @@ __host__ __device__ constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v
 // EMAX: elements per thread for long transforms (register budget: 16 for FP32, 8 for FP64).
 template <int L, int EMAX = 16>
 struct Plan {
-  static constexpr int E = L >= 64 * EMAX ? EMAX : (L >= 128 ? L / 64 : 2);
+  static constexpr int E = L >= 2 * EMAX ? EMAX : L / 2;
   static constexpr int T = L / E;
   static constexpr int LOGE = ilog2(E);
   static constexpr int LOGL = ilog2(L);
@@ -168,8 +177,8 @@ struct Plan {
     for (int i = 0; i < s; ++i) v *= radix(i);
     return v;
   }
-  // complex twiddle entries of stage s (stage 0 has none)
-  __host__ __device__ static constexpr int tw_count(int s) { return s == 0 ? 0 : ns(s) * (radix(s) - 1); }
+  // complex base-twiddle entries of stage s (stage 0 has none)
+  __host__ __device__ static constexpr int tw_count(int s) { return s == 0 ? 0 : ns(s); }
   __host__ __device__ static constexpr int tw_offset(int s) {
     int o = 0;
     for (int i = 0; i < s; ++i) o += tw_count(i);
@@ -178,24 +187,36 @@ struct Plan {
   __host__ __device__ static constexpr int tw_total() { return tw_offset(NSTAGES); }
 };
 
-template <typename R>
-struct EmaxFor {
-  static constexpr int value = sizeof(R) == 8 ? 8 : 16;
-};
+#ifndef FDE_EMAX_F32
+#define FDE_EMAX_F32 16
+#endif
+#ifndef FDE_EMAX_F64
+#define FDE_EMAX_F64 8
+#endif
+#ifndef FDE_EMAX_F32_SHORT
+#define FDE_EMAX_F32_SHORT 8
+#endif
+#ifndef FDE_SHORT_L
+#define FDE_SHORT_L 2048
+#endif
+// Elements per thread for a length-L transform with elements of `bytes` bytes.  Measured on gfx950:
+// FP32 transforms of length 4096 run fastest with 16 elements (three radix-16 stages), shorter ones
+// with 8 (more threads per transform, more waves resident); FP64 with 8.
+__host__ __device__ constexpr int emax_for(int bytes, int L) {
+  return bytes == 8 ? FDE_EMAX_F64 : (L <= FDE_SHORT_L ? FDE_EMAX_F32_SHORT : FDE_EMAX_F32);
+}
 template <typename R, int L>
-using PlanFor = Plan<L, EmaxFor<R>::value>;
+using PlanFor = Plan<L, emax_for(sizeof(R), L)>;
 // The E elements a thread holds for a length-L transform in precision R.
 template <typename R, int L>
 using Reg = R[PlanFor<R, L>::E];
 
 // One Stockham stage.  `rr`/`ri` hold the thread's E elements (natural positions t + T*m).
 // Every stage but the last has one butterfly per thread (radix E), computed in place; its outputs
-// are exchanged through `lds` (L + pad reals, real parts first, then imaginary parts) and read back
-// at positions t + T*m.  The last stage (possibly of smaller radix, several butterflies per thread)
+// are exchanged through `lds` (lds_exchange(L) reals) and read back at positions t + T*m.  The last stage (possibly of smaller radix, several butterflies per thread)
 // writes each butterfly's outputs over its own inputs, which are exactly positions t + T*m.
 template <int L, int S, int SIGN, typename R, typename P = PlanFor<R, L>>
-__device__ __forceinline__ void fft_stage(Reg<R, L>& rr, Reg<R, L>& ri, R* lds,
-                                          const R* __restrict__ tw, int t) {
+__device__ __forceinline__ void fft_stage(Reg<R, L>& rr, Reg<R, L>& ri, R* lds, const R* bw, int t) {
   constexpr int E = P::E, T = P::T;
   constexpr int RADIX = P::radix(S);
   constexpr int NS = P::ns(S);
@@ -204,18 +225,25 @@ __device__ __forceinline__ void fft_stage(Reg<R, L>& rr, Reg<R, L>& ri, R* lds,
   static_assert(LAST || BPT == 1, "only the last stage may use a smaller radix");
   static_for<0, BPT>([&](auto qc) {
     constexpr int q = decltype(qc)::value;
-    const int b = t + T * q;
-    const int j = b & (NS - 1);
     R vr[RADIX], vi[RADIX];
     static_for<0, RADIX>([&](auto rc) {
       vr[rc] = rr[q + rc * BPT];
       vi[rc] = ri[q + rc * BPT];
     });
     if constexpr (NS > 1) {
-      const R* w = tw + 2 * (P::tw_offset(S) + j * (RADIX - 1));
+      // base twiddle of butterfly q (preloaded), powers by a product tree
+      R pr_[RADIX], pi_[RADIX];
+      pr_[1] = bw[2 * q];
+      pi_[1] = (SIGN > 0) ? -bw[2 * q + 1] : bw[2 * q + 1];
+      static_for<2, RADIX>([&](auto rc) {
+        constexpr int r = decltype(rc)::value;
+        constexpr int a = (r & (r - 1)) == 0 ? r / 2 : (1 << (31 - __builtin_clz(r)));
+        constexpr int c = r - a;
+        pr_[r] = pr_[a] * pr_[c] - pi_[a] * pi_[c];
+        pi_[r] = pr_[a] * pi_[c] + pi_[a] * pr_[c];
+      });
       static_for<1, RADIX>([&](auto rc) {
-        const R c = w[2 * (rc - 1)];
-        const R s = (SIGN > 0) ? -w[2 * (rc - 1) + 1] : w[2 * (rc - 1) + 1];
+        const R c = pr_[rc], s = pi_[rc];
         const R a = vr[rc] * c - vi[rc] * s;
         vi[rc] = vr[rc] * s + vi[rc] * c;
         vr[rc] = a;
@@ -228,25 +256,69 @@ __device__ __forceinline__ void fft_stage(Reg<R, L>& rr, Reg<R, L>& ri, R* lds,
     });
   });
   if constexpr (!LAST) {
-    // output r of this thread's butterfly b = t goes to (b / NS) * NS * RADIX + (b mod NS) + r * NS
+    // output r of this thread's butterfly b = t goes to (b / NS) * NS * RADIX + (b mod NS) + r * NS;
+    // real parts in lds[0 .. lds_len), imaginary parts in lds[lds_len .. 2 lds_len)
     const int base = (t / NS) * NS * RADIX + (t & (NS - 1));
-    static_for<0, RADIX>([&](auto rc) { lds[lpad(base + rc * NS)] = rr[rc]; });
-    __syncthreads();
-    static_for<0, E>([&](auto m) { rr[m] = lds[lpad(t + T * m)]; });
-    __syncthreads();
-    static_for<0, RADIX>([&](auto rc) { lds[lpad(base + rc * NS)] = ri[rc]; });
-    __syncthreads();
-    static_for<0, E>([&](auto m) { ri[m] = lds[lpad(t + T * m)]; });
-    __syncthreads();
+    if constexpr (FDE_EXCH_SPLIT) {
+      static_for<0, RADIX>([&](auto rc) { lds[lpad(base + rc * NS)] = rr[rc]; });
+      __syncthreads();
+      static_for<0, E>([&](auto m) { rr[m] = lds[lpad(t + T * m)]; });
+      __syncthreads();
+      static_for<0, RADIX>([&](auto rc) { lds[lpad(base + rc * NS)] = ri[rc]; });
+      __syncthreads();
+      static_for<0, E>([&](auto m) { ri[m] = lds[lpad(t + T * m)]; });
+      __syncthreads();
+    } else {
+      R* lre = lds;
+      R* lim = lds + lds_len(L);
+      static_for<0, RADIX>([&](auto rc) {
+        lre[lpad(base + rc * NS)] = rr[rc];
+        lim[lpad(base + rc * NS)] = ri[rc];
+      });
+      __syncthreads();
+      static_for<0, E>([&](auto m) {
+        rr[m] = lre[lpad(t + T * m)];
+        ri[m] = lim[lpad(t + T * m)];
+      });
+      __syncthreads();
+    }
   }
 }
+
+// Base twiddles of every stage for this thread: bw[s][2q], bw[s][2q+1] = exp(-2 pi i j/(NS R)),
+// j = (t + T q) mod NS, loaded once per kernel from the compact table.
+template <typename R, int L>
+struct Twiddles {
+  using P = PlanFor<R, L>;
+  static constexpr int NST = P::NSTAGES > 1 ? P::NSTAGES : 2;
+  static constexpr int BPTMAX = P::E / P::radix(P::NSTAGES - 1);
+  R w[NST][2 * BPTMAX];
+  __device__ __forceinline__ void load(const R* __restrict__ tab, int t) {
+    static_for<1, P::NSTAGES>([&](auto sc) {
+      constexpr int S = decltype(sc)::value;
+      constexpr int NS = P::ns(S);
+      constexpr int BPT = P::E / P::radix(S);
+      static_for<0, BPT>([&](auto qc) {
+        const int j = (t + P::T * decltype(qc)::value) & (NS - 1);
+        w[S][2 * qc] = tab[2 * (P::tw_offset(S) + j)];
+        w[S][2 * qc + 1] = tab[2 * (P::tw_offset(S) + j) + 1];
+      });
+    });
+  }
+};
 
 // Full length-L DFT (SIGN = -1 forward, +1 unnormalised inverse) of the thread group's data.
 // Every thread of the workgroup must call this (it contains barriers) even if its group is idle.
 template <int L, int SIGN, typename R>
-__device__ __forceinline__ void fft(Reg<R, L>& rr, Reg<R, L>& ri, R* lds,
-                                    const R* __restrict__ tw, int t) {
-  static_for<0, PlanFor<R, L>::NSTAGES>([&](auto s) { fft_stage<L, decltype(s)::value, SIGN>(rr, ri, lds, tw, t); });
+__device__ __forceinline__ void fft(Reg<R, L>& rr, Reg<R, L>& ri, R* lds, const Twiddles<R, L>& tw, int t_in) {
+  // An opaque copy of the thread index: without it the compiler computes the LDS addresses of all
+  // transforms of a kernel once and keeps them live throughout, which exhausts the registers.
+  int t = t_in;
+  __asm__ volatile("" : "+v"(t));
+  static_for<0, PlanFor<R, L>::NSTAGES>([&](auto s) {
+    constexpr int S = decltype(s)::value;
+    fft_stage<L, S, SIGN>(rr, ri, lds, tw.w[S < Twiddles<R, L>::NST ? S : 0], t);
+  });
 }
 
 }  // namespace fde

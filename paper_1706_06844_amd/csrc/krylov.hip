@@ -5,43 +5,43 @@
 // The basis V is stored unnormalised: column k holds a multiple of v_k and vscale[k] turns it into
 // v_k.  This saves the separate normalisation pass; every consumer applies the scale.
 //
+// Orthogonalisation is classical Gram-Schmidt with a second pass only when the first one cancelled
+// more than half of the squared norm (the criterion of Daniel, Gragg, Kaufman and Stewart, 1976):
+// usually two passes over the basis per step instead of three.
+//
 // Reductions: every thread accumulates a fixed strided subset, a fixed tree combines the block's
-// values, each block writes its partials, and the last block to finish (ticket counter) combines
-// the partials in block order.  The result does not depend on scheduling, so runs are bitwise
+// values, each block writes its partials, and a one-workgroup kernel combines the partials in block
+// order.  The result does not depend on scheduling, so runs are bitwise
 // reproducible for a given launch shape.
 #include "common.h"
 
 namespace fde {
 
 constexpr int kCgsBlock = 256;
+constexpr int kCgsWaves = kCgsBlock / 64;
 constexpr int kCgsMaxGrid = 512;
 
 int cgs_grid(size_t N) {
-  size_t g = (N + (size_t)kCgsBlock * 8 - 1) / ((size_t)kCgsBlock * 8);
+  const size_t pairs = (N + 1) / 2;
+  size_t g = (pairs + (size_t)kCgsBlock * 4 - 1) / ((size_t)kCgsBlock * 4);
   if (g < 1) g = 1;
   if (g > kCgsMaxGrid) g = kCgsMaxGrid;
   return (int)g;
 }
-size_t cgs_partials_len(size_t) { return (size_t)(kMaxRestart + 1) * kCgsMaxGrid; }
+size_t cgs_partials_len(size_t) { return (size_t)(kMaxRestart + 2) * kCgsMaxGrid; }
+size_t basis_ld(size_t N) { return (N + 63) / 64 * 64; }
 
-// Sum of v over the block in a fixed order; the result is valid in thread 0.
-__device__ __forceinline__ double block_sum(double v, double* red) {
+// Sum over the wavefront in a fixed order; the result is valid in lane 0.
+__device__ __forceinline__ double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) red[wid] = v;
-  __syncthreads();
-  double s = 0.0;
-  if (threadIdx.x == 0)
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
-  return s;
+  return v;
 }
 
 // Givens update after column j of the Hessenberg matrix is known (single thread).
 __device__ void givens_step(GmresState* st, int j, double nrm) {
   constexpr int K = kMaxRestart;
   double col[kMaxRestart + 1];
-  for (int i = 0; i <= j; ++i) col[i] = st->h1[i] + (st->cgs2 ? st->h2[i] : 0.0);
+  for (int i = 0; i <= j; ++i) col[i] = st->h1[i] + (st->reorth ? st->h2[i] : 0.0);
   col[j + 1] = nrm;
   for (int i = 0; i < j; ++i) {
     const double c = st->cs[i], s = st->sn[i];
@@ -65,140 +65,197 @@ __device__ void givens_step(GmresState* st, int j, double nrm) {
   st->est = est;
   st->iters += 1;
   st->nused = j + 1;
+  st->nreorth += st->reorth;
+  if (st->reorth) st->reorth_mask |= 1u << j;
   st->vscale[j + 1] = nrm > 0.0 ? 1.0 / nrm : 0.0;
   // breakdown: the new direction vanished relative to the column (the Krylov space is invariant)
   const bool breakdown = !(nrm > 1e-14 * r);
   if (est <= st->atol || st->iters >= st->maxit || breakdown || j + 1 >= st->restart) st->done = 1;
 }
 
+// One pass over the basis.  Each thread handles pairs of consecutive entries (16-byte loads); the
+// basis columns and w are padded to an even length, so the second entry of the last pair is
+// readable and is masked to zero.
 template <int MAXV>
-__global__ __launch_bounds__(kCgsBlock) void cgs_kernel(int kind, size_t N, int nv, const double* __restrict__ V,
+__global__ __launch_bounds__(kCgsBlock) void cgs_kernel(int kind, int N, int nv, const double* __restrict__ V,
                                                         size_t ldv, double* __restrict__ w,
                                                         const double* __restrict__ src, GmresState* st,
                                                         double* __restrict__ partials) {
-  if ((kind == CGS_DOTS || kind == CGS_UPDATE_DOTS || kind == CGS_UPDATE_NORM) && st->done) return;
+  if (kind == CGS_DOTS || kind == CGS_UPDATE_DOTS || kind == CGS_UPDATE_NORM) {
+    if (st->done) return;
+    if (kind == CGS_UPDATE_DOTS && !st->reorth) return;
+  }
   __shared__ double hc[MAXV];
-  __shared__ double red[16];
-  __shared__ int is_last;
+  __shared__ double red[kCgsWaves][MAXV + 1];
   // coefficients of the unnormalised columns for the update passes
   if (threadIdx.x < MAXV) {
     double c = 0.0;
     if ((int)threadIdx.x < nv) {
       if (kind == CGS_UPDATE_DOTS) c = st->h1[threadIdx.x] * st->vscale[threadIdx.x];
-      if (kind == CGS_UPDATE_NORM) c = (st->cgs2 ? st->h2[threadIdx.x] : st->h1[threadIdx.x]) * st->vscale[threadIdx.x];
+      if (kind == CGS_UPDATE_NORM) c = (st->reorth ? st->h2[threadIdx.x] : st->h1[threadIdx.x]) * st->vscale[threadIdx.x];
     }
     hc[threadIdx.x] = c;
   }
   __syncthreads();
   const bool dots = (kind == CGS_DOTS || kind == CGS_UPDATE_DOTS);
   const bool upd = (kind == CGS_UPDATE_DOTS || kind == CGS_UPDATE_NORM);
+  const bool norm = (kind != CGS_UPDATE_DOTS);
   double acc[MAXV];
 #pragma unroll
   for (int k = 0; k < MAXV; ++k) acc[k] = 0.0;
   double nacc = 0.0;
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += stride) {
+  const int P = (N + 1) >> 1;
+  const int stride = gridDim.x * kCgsBlock;
+  for (int i = blockIdx.x * kCgsBlock + threadIdx.x; i < P; i += stride) {
+    const int p = 2 * i;
+    const bool two = p + 1 < N;
     if (kind == CGS_INIT) {
-      const double b = src[p];
-      w[p] = b;
-      nacc += b * b;
+      const double b0 = src[p];
+      const double b1 = two ? src[p + 1] : 0.0;
+      w[p] = b0;
+      if (two) w[p + 1] = b1;
+      nacc += b0 * b0 + b1 * b1;
       continue;
     }
+    double2 wv = *reinterpret_cast<const double2*>(w + p);
+    if (!two) wv.y = 0.0;
     if (kind == CGS_RESNORM) {
-      const double r = w[p];
-      nacc += r * r;
+      nacc += wv.x * wv.x + wv.y * wv.y;
       continue;
     }
-    double wv = w[p];
-    double vk[MAXV];
+    double2 vk[MAXV];
 #pragma unroll
-    for (int k = 0; k < MAXV; ++k) vk[k] = (k < nv) ? V[(size_t)k * ldv + p] : 0.0;
+    for (int k = 0; k < MAXV; ++k) {
+      vk[k] = (k < nv) ? *reinterpret_cast<const double2*>(V + (size_t)k * ldv + p) : make_double2(0.0, 0.0);
+      if (!two) vk[k].y = 0.0;
+    }
     if (upd) {
 #pragma unroll
       for (int k = 0; k < MAXV; ++k)
-        if (k < nv) wv -= hc[k] * vk[k];
-      w[p] = wv;
+        if (k < nv) {
+          wv.x -= hc[k] * vk[k].x;
+          wv.y -= hc[k] * vk[k].y;
+        }
+      if (two) *reinterpret_cast<double2*>(w + p) = wv;
+      else w[p] = wv.x;
     }
     if (dots) {
 #pragma unroll
       for (int k = 0; k < MAXV; ++k)
-        if (k < nv) acc[k] += vk[k] * wv;
-    } else {
-      nacc += wv * wv;
+        if (k < nv) acc[k] += vk[k].x * wv.x + vk[k].y * wv.y;
     }
+    if (norm) nacc += wv.x * wv.x + wv.y * wv.y;
   }
-  // block reductions -> partials[k * gridDim.x + blockIdx.x]
-  const int G = gridDim.x;
+  // rows of this pass: the nv dot products (DOTS, UPDATE_DOTS), then the squared norm (DOTS,
+  // UPDATE_NORM, INIT, RESNORM)
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nd = dots ? nv : 0;
+  const int nres = nd + (norm ? 1 : 0);
   if (dots) {
-    for (int k = 0; k < nv; ++k) {
-      const double s = block_sum(acc[k], red);
-      if (threadIdx.x == 0) partials[(size_t)k * G + blockIdx.x] = s;
-    }
-  } else {
-    const double s = block_sum(nacc, red);
-    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+#pragma unroll
+    for (int k = 0; k < MAXV; ++k)
+      if (k < nv) {
+        const double s = wave_sum(acc[k]);
+        if (lane == 0) red[wid][k] = s;
+      }
   }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned int t = atomicAdd(&st->ticket[0], 1u);
-    is_last = (t == (unsigned int)G - 1);
+  if (norm) {
+    const double s = wave_sum(nacc);
+    if (lane == 0) red[wid][nd] = s;
   }
   __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  const volatile double* vp = partials;
-  const int nres = dots ? nv : 1;
-  for (int k = 0; k < nres; ++k) {
+  if ((int)threadIdx.x < nres) {
+    double s = 0.0;
+    for (int q = 0; q < kCgsWaves; ++q) s += red[q][threadIdx.x];
+    partials[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+// Combines the G per-block partials of a pass in block order (one workgroup) and updates the
+// solver state.  A separate launch instead of a last-block ticket: one counter hit by every block
+// of a wide grid serialises at the memory side.
+__global__ __launch_bounds__(kCgsBlock) void cgs_finalize_kernel(int kind, int nv, int G,
+                                                                 const double* __restrict__ partials,
+                                                                 GmresState* st) {
+  if (kind == CGS_DOTS || kind == CGS_UPDATE_DOTS || kind == CGS_UPDATE_NORM) {
+    if (st->done) return;
+    if (kind == CGS_UPDATE_DOTS && !st->reorth) return;
+  }
+  __shared__ double fin[kMaxRestart + 2];
+  const bool dots = (kind == CGS_DOTS || kind == CGS_UPDATE_DOTS);
+  const bool norm = (kind != CGS_UPDATE_DOTS);
+  const int nres = (dots ? nv : 0) + (norm ? 1 : 0);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int r = wid; r < nres; r += kCgsWaves) {
     double v = 0.0;
-    for (int b = threadIdx.x; b < G; b += blockDim.x) v += vp[(size_t)k * G + b];
-    const double s = block_sum(v, red);
-    if (threadIdx.x == 0) {
-      if (kind == CGS_DOTS) st->h1[k] = s * st->vscale[k];
-      else if (kind == CGS_UPDATE_DOTS) st->h2[k] = s * st->vscale[k];
-      else red[15] = s;
-    }
+    for (int b = lane; b < G; b += 64) v += partials[(size_t)r * G + b];
+    v = wave_sum(v);
+    if (lane == 0) fin[r] = v;
   }
-  if (threadIdx.x == 0) {
-    st->ticket[0] = 0;
-    if (kind == CGS_UPDATE_NORM) {
-      givens_step(st, nv - 1, sqrt(red[15]));
-    } else if (kind == CGS_INIT) {
-      const double bn = sqrt(red[15]);
-      st->bnorm = bn;
-      st->atol = st->rtol * bn;
-      st->resnorm = bn;
-      st->est = bn;
-      st->g[0] = bn;
-      st->vscale[0] = bn > 0.0 ? 1.0 / bn : 0.0;
-      st->iters = 0;
-      st->nused = 0;
-      st->conv = (bn == 0.0);
-      st->done = (bn == 0.0);
-    } else if (kind == CGS_RESNORM) {
-      const double rn = sqrt(red[15]);
-      st->resnorm = rn;
-      st->conv = (rn <= st->atol);
-      st->g[0] = rn;
-      st->vscale[0] = rn > 0.0 ? 1.0 / rn : 0.0;
-      st->nused = 0;
-      st->done = (st->conv || st->iters >= st->maxit) ? 1 : 0;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  if (kind == CGS_DOTS) {
+    double hh = 0.0;
+    for (int k = 0; k < nv; ++k) {
+      const double h = fin[k] * st->vscale[k];
+      st->h1[k] = h;
+      hh += h * h;
     }
+    // After one projection ||w - V h||^2 = ||w||^2 - ||h||^2 (orthonormal V).  A second pass is
+    // needed when the projection removed more than half of ||w||^2 (norm ratio below 1/sqrt 2).
+    const double ww = fin[nv];
+    st->reorth = st->orth == 1 ? 1 : st->orth == 0 ? 0 : (hh > 0.5 * ww ? 1 : 0);
+  } else if (kind == CGS_UPDATE_DOTS) {
+    for (int k = 0; k < nv; ++k) st->h2[k] = fin[k] * st->vscale[k];
+  } else if (kind == CGS_UPDATE_NORM) {
+    givens_step(st, nv - 1, sqrt(fin[0]));
+  } else if (kind == CGS_INIT) {
+    const double bn = sqrt(fin[0]);
+    st->bnorm = bn;
+    st->atol = st->rtol * bn;
+    st->resnorm = bn;
+    st->est = bn;
+    st->g[0] = bn;
+    st->vscale[0] = bn > 0.0 ? 1.0 / bn : 0.0;
+    st->iters = 0;
+    st->nreorth = 0;
+    st->reorth_mask = 0;
+    st->nused = 0;
+    st->conv = (bn == 0.0);
+    st->done = (bn == 0.0);
+  } else if (kind == CGS_RESNORM) {
+    const double rn = sqrt(fin[0]);
+    st->resnorm = rn;
+    st->conv = (rn <= st->atol);
+    st->g[0] = rn;
+    st->vscale[0] = rn > 0.0 ? 1.0 / rn : 0.0;
+    st->nused = 0;
+    st->reorth_mask = 0;
+    st->done = (st->conv || st->iters >= st->maxit) ? 1 : 0;
   }
 }
 
 hipError_t launch_cgs_pass(int kind, size_t N, int nv, double* V, size_t ldv, double* w, const double* src,
                            GmresState* st, double* partials, int grid, hipStream_t s) {
-  if (nv > kMaxRestart + 1) return hipErrorInvalidValue;
+  if (nv > kMaxRestart + 1 || N > (size_t)0x7ffffffe || grid < 1 || grid > kCgsMaxGrid) return hipErrorInvalidValue;
+  if (ldv % 2 || (reinterpret_cast<uintptr_t>(V) | reinterpret_cast<uintptr_t>(w)) % 16) return hipErrorInvalidValue;
+  if (kind == CGS_INIT && !src) return hipErrorInvalidValue;
+  const int n = (int)N;
+  // Wide passes (many columns) stream best with one workgroup per CU; narrow ones with two.
+  if (nv > 8 && grid > kCgsMaxGrid / 2) grid = kCgsMaxGrid / 2;
 #define L_(M)                                                                                            \
-  hipLaunchKernelGGL((cgs_kernel<M>), dim3(grid), dim3(kCgsBlock), 0, s, kind, N, nv, V, ldv, w, src, st, \
+  hipLaunchKernelGGL((cgs_kernel<M>), dim3(grid), dim3(kCgsBlock), 0, s, kind, n, nv, V, ldv, w, src, st, \
                      partials)
   if (nv <= 4) L_(4);
   else if (nv <= 8) L_(8);
+  else if (nv <= 12) L_(12);
   else if (nv <= 16) L_(16);
   else if (nv <= 24) L_(24);
   else L_(kMaxRestart + 1);
 #undef L_
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(cgs_finalize_kernel, dim3(1), dim3(kCgsBlock), 0, s, kind, nv, grid, partials, st);
   return hipGetLastError();
 }
 

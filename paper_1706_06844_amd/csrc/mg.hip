@@ -41,9 +41,11 @@ hipError_t launch_presmooth(int N, const Tin* b, const double* bscale, const R* 
 }
 
 // ---- restriction rc = P^T r / 4 ---------------------------------------------------------------
+// With xc given, also the coarse level's first Jacobi sweep from zero: xc = dinv_c .* rc (the same
+// product the pre-smoothing kernel forms, fused to save a launch).
 template <typename R>
 __global__ void restrict_kernel(int n1, int n2, const R* __restrict__ r, R* __restrict__ rc,
-                                const int* __restrict__ skip) {
+                                const R* __restrict__ dinv_c, R* __restrict__ xc, const int* __restrict__ skip) {
   if (skip && *skip) return;
   const int k1 = (n1 - 1) / 2, k2 = (n2 - 1) / 2;
   const int Kc = k1 * k2;
@@ -56,14 +58,19 @@ __global__ void restrict_kernel(int n1, int n2, const R* __restrict__ r, R* __re
     const R a0 = r0[-1] + 2 * r0[0] + r0[1];
     const R a1 = r1[-1] + 2 * r1[0] + r1[1];
     const R a2 = r2[-1] + 2 * r2[0] + r2[1];
-    rc[q] = (a0 + 2 * a1 + a2) * R(0.0625);
+    const R v = (a0 + 2 * a1 + a2) * R(0.0625);
+    rc[q] = v;
+    if (xc) xc[q] = dinv_c[q] * v;
   }
 }
 
 template <typename R>
-hipError_t launch_restrict(int n1, int n2, const R* r, R* rc, const int* skip, hipStream_t st) {
+hipError_t launch_restrict(int n1, int n2, const R* r, R* rc, const R* dinv_c, R* xc, const int* skip,
+                           hipStream_t st) {
+  if (xc && !dinv_c) return hipErrorInvalidValue;
   const int Kc = ((n1 - 1) / 2) * ((n2 - 1) / 2);
-  hipLaunchKernelGGL((restrict_kernel<R>), dim3(grid_for(Kc)), dim3(kBlock), 0, st, n1, n2, r, rc, skip);
+  hipLaunchKernelGGL((restrict_kernel<R>), dim3(grid_for(Kc)), dim3(kBlock), 0, st, n1, n2, r, rc, dinv_c, xc,
+                     skip);
   return hipGetLastError();
 }
 
@@ -240,21 +247,31 @@ struct CoarseLds {
   R* T;
   R* swx[kMaxCoarseLevels];
   R* swy[kMaxCoarseLevels];
+  R* dpm[kMaxCoarseLevels];
+  R* epm[kMaxCoarseLevels];
+  R* dinv[kMaxCoarseLevels];
+  double* inv;
 };
 
+// LDS of the one-workgroup V-cycle: per level b, x, the weights and the coefficient fields
+// (d+-, e+- pairs and omega/diag), one scratch field, and the FP64 coarsest inverse.
 template <typename R>
 __host__ __device__ size_t coarse_lds_elems(const CoarseView<R>& cv) {
   size_t n = 0, mx = 0;
   for (int l = 0; l < cv.nlev; ++l) {
     const size_t N = (size_t)cv.n1[l] * cv.n2[l];
-    n += 2 * N + (cv.n1[l] + 1) + (cv.n2[l] + 1);
+    n += 2 * N + (cv.n1[l] + 1) + (cv.n2[l] + 1) + 5 * N;
     if (N > mx) mx = N;
   }
-  return n + mx;
+  n += mx;
+  n += (sizeof(double) / sizeof(R)) + 1;  // alignment slack for the FP64 inverse
+  return n;
 }
 template <typename R>
 size_t coarse_lds_bytes(const CoarseView<R>& cv) {
-  return coarse_lds_elems(cv) * sizeof(R);
+  const int l = cv.nlev - 1;
+  const size_t Nc = (size_t)cv.n1[l] * cv.n2[l];
+  return coarse_lds_elems(cv) * sizeof(R) + Nc * Nc * sizeof(double);
 }
 
 template <typename R>
@@ -272,9 +289,19 @@ __device__ CoarseLds<R> coarse_carve(const CoarseView<R>& cv, R* base) {
     q += cv.n1[l] + 1;
     s.swy[l] = q;
     q += cv.n2[l] + 1;
+    s.dpm[l] = q;
+    q += 2 * N;
+    s.epm[l] = q;
+    q += 2 * N;
+    s.dinv[l] = q;
+    q += N;
     if (N > mx) mx = N;
   }
   s.T = q;
+  q += mx;
+  uintptr_t a = reinterpret_cast<uintptr_t>(q);
+  a = (a + sizeof(double) - 1) & ~(uintptr_t)(sizeof(double) - 1);
+  s.inv = reinterpret_cast<double*>(a);
   return s;
 }
 
@@ -285,8 +312,8 @@ __device__ void coarse_jacobi(const CoarseView<R>& cv, const CoarseLds<R>& s, in
   for (int p = threadIdx.x; p < N; p += blockDim.x) {
     const int j = p / n1, i = p - j * n1;
     const R xv = s.X[l][p];
-    const R lv = direct_l(n1, n2, j, i, s.X[l], s.swx[l], s.swy[l], cv.dpm[l], cv.epm[l]);
-    s.T[p] = xv + cv.dinv[l][p] * (s.B[l][p] - xv + lv);
+    const R lv = direct_l(n1, n2, j, i, s.X[l], s.swx[l], s.swy[l], s.dpm[l], s.epm[l]);
+    s.T[p] = xv + s.dinv[l][p] * (s.B[l][p] - xv + lv);
   }
   __syncthreads();
   for (int p = threadIdx.x; p < N; p += blockDim.x) s.X[l][p] = s.T[p];
@@ -302,9 +329,20 @@ __global__ __launch_bounds__(1024) void coarse_vcycle_kernel(CoarseView<R> cv, c
   R* base = reinterpret_cast<R*>(smem_raw);
   const CoarseLds<R> s = coarse_carve(cv, base);
   const int tid = threadIdx.x, nt = blockDim.x;
+  // everything the cycle reads is copied into LDS once, with independent loads
   for (int l = 0; l < cv.nlev; ++l) {
+    const int N = cv.n1[l] * cv.n2[l];
     for (int k = tid; k <= cv.n1[l]; k += nt) s.swx[l][k] = cv.swx[l][k];
     for (int k = tid; k <= cv.n2[l]; k += nt) s.swy[l][k] = cv.swy[l][k];
+    for (int k = tid; k < 2 * N; k += nt) {
+      s.dpm[l][k] = cv.dpm[l][k];
+      s.epm[l][k] = cv.epm[l][k];
+    }
+    for (int k = tid; k < N; k += nt) s.dinv[l][k] = cv.dinv[l][k];
+  }
+  {
+    const int Nc = cv.n1[cv.nlev - 1] * cv.n2[cv.nlev - 1];
+    for (int k = tid; k < Nc * Nc; k += nt) s.inv[k] = cv.inv[k];
   }
   {
     const int N0 = cv.n1[0] * cv.n2[0];
@@ -315,13 +353,13 @@ __global__ __launch_bounds__(1024) void coarse_vcycle_kernel(CoarseView<R> cv, c
   // descend: pre-smooth, residual, restrict
   for (int l = 0; l < last; ++l) {
     const int n1 = cv.n1[l], n2 = cv.n2[l], N = n1 * n2;
-    for (int p = tid; p < N; p += nt) s.X[l][p] = cv.nu_pre > 0 ? cv.dinv[l][p] * s.B[l][p] : R(0);
+    for (int p = tid; p < N; p += nt) s.X[l][p] = cv.nu_pre > 0 ? s.dinv[l][p] * s.B[l][p] : R(0);
     __syncthreads();
     for (int it = 1; it < cv.nu_pre; ++it) coarse_jacobi(cv, s, l);
     for (int p = tid; p < N; p += nt) {
       const int j = p / n1, i = p - j * n1;
       const R xv = s.X[l][p];
-      s.T[p] = s.B[l][p] - xv + direct_l(n1, n2, j, i, s.X[l], s.swx[l], s.swy[l], cv.dpm[l], cv.epm[l]);
+      s.T[p] = s.B[l][p] - xv + direct_l(n1, n2, j, i, s.X[l], s.swx[l], s.swy[l], s.dpm[l], s.epm[l]);
     }
     __syncthreads();
     const int k1 = (n1 - 1) / 2, k2 = (n2 - 1) / 2;
@@ -342,7 +380,7 @@ __global__ __launch_bounds__(1024) void coarse_vcycle_kernel(CoarseView<R> cv, c
     const int Nc = cv.n1[last] * cv.n2[last];
     for (int p = tid; p < Nc; p += nt) {
       double acc = 0.0;
-      const double* row = cv.inv + (size_t)p * Nc;
+      const double* row = s.inv + (size_t)p * Nc;
       for (int q = 0; q < Nc; ++q) acc += row[q] * (double)s.B[last][q];
       s.X[last][p] = (R)acc;
     }
@@ -379,6 +417,12 @@ __global__ __launch_bounds__(1024) void coarse_vcycle_kernel(CoarseView<R> cv, c
 template <typename R>
 hipError_t launch_coarse_vcycle(const CoarseView<R>& cv, const R* b, R* x, const int* skip, hipStream_t st) {
   const size_t bytes = coarse_lds_bytes(cv);
+  if (bytes > 160 * 1024 || !cv.inv) return hipErrorInvalidValue;
+  if (bytes > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&coarse_vcycle_kernel<R>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL((coarse_vcycle_kernel<R>), dim3(1), dim3(1024), bytes, st, cv, b, x, skip);
   return hipGetLastError();
 }
@@ -536,7 +580,7 @@ hipError_t launch_coarse_solve(int Nc, const double* inv, const R* b, R* x, hipS
 
 // ---- explicit instantiations ------------------------------------------------------------------
 #define FDE_INST_R(R)                                                                                   \
-  template hipError_t launch_restrict<R>(int, int, const R*, R*, const int*, hipStream_t);             \
+  template hipError_t launch_restrict<R>(int, int, const R*, R*, const R*, R*, const int*, hipStream_t); \
   template hipError_t launch_prolong<R>(int, int, const R*, R*, const int*, hipStream_t);              \
   template hipError_t launch_fill<R>(size_t, R*, R, hipStream_t);                                      \
   template hipError_t launch_interleave<R>(size_t, const double*, const double*, R*, hipStream_t);     \

@@ -64,7 +64,8 @@ std::vector<double> wsgd_weights(double g, int K) {
   return w;
 }
 
-constexpr int kDirectMaxN = 31;  // levels with max(n1, n2) <= this run in the one-workgroup kernel
+constexpr int kDirectMaxN = 31;    // levels with max(n1, n2) <= this run in the one-workgroup kernel
+constexpr int kDirectOpMax = 255;  // levels with max(n1, n2) <= this use the direct operator kernel
 
 template <typename R>
 struct Level {
@@ -82,9 +83,11 @@ struct Level {
   R* b = nullptr;
   R* x = nullptr;
   R* r = nullptr;
+  R* x2 = nullptr;  // second iterate buffer of direct levels
   R* ay = nullptr;
+  bool direct = false;
   OpView<R> view() const {
-    OpView<R> v;
+    OpView<R> v{};
     v.n1 = n1;
     v.n2 = n2;
     v.L1 = L1;
@@ -96,6 +99,9 @@ struct Level {
     v.mu_y = lam_y;
     v.tw_x = tw_x;
     v.tw_y = tw_y;
+    v.swx = swx;
+    v.swy = swy;
+    v.direct = direct ? 1 : 0;
     return v;
   }
   size_t N() const { return (size_t)n1 * n2; }
@@ -117,8 +123,10 @@ struct Outer {
   double* epm = nullptr;
   double* lam_x = nullptr;
   double* lam_y = nullptr;
+  double* swx = nullptr;
+  double* swy = nullptr;
   OpView<double> view(const double* twx, const double* twy, int n1, int n2, int L1, int L2) const {
-    OpView<double> v;
+    OpView<double> v{};
     v.n1 = n1;
     v.n2 = n2;
     v.L1 = L1;
@@ -130,6 +138,9 @@ struct Outer {
     v.mu_y = lam_y;
     v.tw_x = twx;
     v.tw_y = twy;
+    v.swx = swx;
+    v.swy = swy;
+    v.direct = std::max(n1, n2) <= kDirectOpMax ? 1 : 0;
     return v;
   }
 };
@@ -140,12 +151,14 @@ struct ProfEntry {
   hipEvent_t a, b;
   double bytes;
   int cycle, j;
+  bool second_pass;  // the conditional second Gram-Schmidt pass of step j
 };
 struct Prof {
   unsigned mask = 0;
   std::vector<hipEvent_t> freelist;
   std::vector<ProfEntry> pending;
   std::vector<int> cycle_nused;
+  std::vector<unsigned> cycle_reorth;
   int cur_cycle = -1, cur_j = -1;
   int64_t launches[FDE_KFAM_COUNT] = {};
   double ms[FDE_KFAM_COUNT] = {};
@@ -181,13 +194,14 @@ struct fde_handle {
   std::unique_ptr<Hierarchy<double>> h64;
   std::unique_ptr<Hierarchy<float>> h32;
   // Krylov storage
-  double* V = nullptr;    // (restart + 1) x N
+  double* V = nullptr;    // restart + 1 columns of N, column stride ldv
+  size_t ldv = 0;
   void* Z = nullptr;      // restart x N, FP64 or FP32
   GmresState* st = nullptr;
   GmresState* st_host = nullptr;  // pinned mirror
   double* partials = nullptr;
   int* flags = nullptr;
-  double* scratch64 = nullptr;  // 2N FP64 for test hooks
+  double* scratch64 = nullptr;  // 4N FP64 for test hooks
   int cgs_grid = 1;
   int expected_iters = 0;
   Prof prof;
@@ -214,7 +228,8 @@ hipEvent_t prof_event(fde_handle* h) {
   return e;
 }
 
-// Runs `launch`; when family `fam` is being profiled, brackets it with events.
+// Runs `launch`; when family `fam` is being profiled, brackets it with events.  Negative `bytes`
+// mark the conditional second Gram-Schmidt pass (dropped from the totals when it did not run).
 template <typename F>
 void timed(fde_handle* h, int fam, double bytes, F&& launch) {
   if (!(h->prof.mask & (1u << fam))) {
@@ -225,7 +240,7 @@ void timed(fde_handle* h, int fam, double bytes, F&& launch) {
   HIPCHECK(hipEventRecord(a, h->stream));
   HIPCHECK(launch());
   HIPCHECK(hipEventRecord(b, h->stream));
-  h->prof.pending.push_back({fam, a, b, bytes, h->prof.cur_cycle, h->prof.cur_j});
+  h->prof.pending.push_back({fam, a, b, std::fabs(bytes), h->prof.cur_cycle, h->prof.cur_j, bytes < 0});
 }
 
 // Accumulates finished entries (the stream must be idle).  Launches issued for Arnoldi steps that
@@ -233,8 +248,9 @@ void timed(fde_handle* h, int fam, double bytes, F&& launch) {
 void prof_harvest(fde_handle* h) {
   Prof& P = h->prof;
   for (auto& e : P.pending) {
-    const bool skipped = e.j >= 0 && e.cycle >= 0 && e.cycle < (int)P.cycle_nused.size() &&
-                         e.j >= P.cycle_nused[e.cycle];
+    const bool known = e.j >= 0 && e.cycle >= 0 && e.cycle < (int)P.cycle_nused.size();
+    bool skipped = known && e.j >= P.cycle_nused[e.cycle];
+    if (known && e.second_pass && !((P.cycle_reorth[e.cycle] >> e.j) & 1u)) skipped = true;
     if (!skipped) {
       float ms = 0.f;
       HIPCHECK(hipEventElapsedTime(&ms, e.a, e.b));
@@ -247,6 +263,7 @@ void prof_harvest(fde_handle* h) {
   }
   P.pending.clear();
   P.cycle_nused.clear();
+  P.cycle_reorth.clear();
   P.cur_cycle = -1;
   P.cur_j = -1;
 }
@@ -272,6 +289,15 @@ void op_apply(fde_handle* h, bool outer, const OpView<R>& op, const Tin* x, R* a
   const bool fine = outer || (op.n1 == h->n1 && op.n2 == h->n2);
   const int fy = outer ? FDE_KFAM_OUTER_Y : (fine ? FDE_KFAM_MG0_Y : FDE_KFAM_MGC_Y);
   const int fx = outer ? FDE_KFAM_OUTER_X : (fine ? FDE_KFAM_MG0_X : FDE_KFAM_MGC_X);
+  if (op.direct) {
+    // x, four coefficient fields, output, plus the mode's extra fields
+    const double by = xbytes<R, Tin>(N, mode, src ? src->n : 0) + (double)N * sizeof(R);
+    timed(h, fx, by, [&] {
+      return launch_direct_op<R, Tin>(op.n1, op.n2, x, op.dpm, op.epm, op.swx, op.swy, out, mode, b, op.dinv, src, tau,
+                                      skip, h->stream);
+    });
+    return;
+  }
   timed(h, fy, ybytes<R, Tin>(N), [&] { return launch_op_y<R, Tin>(op, x, ay, skip, h->stream); });
   timed(h, fx, xbytes<R, Tin>(N, mode, src ? src->n : 0),
         [&] { return launch_op_x<R, Tin>(op, x, ay, out, mode, b, src, tau, skip, h->stream); });
@@ -394,8 +420,8 @@ std::unique_ptr<Hierarchy<R>> build_hierarchy(fde_handle* h) {
     }
     L.dinv = dalloc<R>(m, N);
     HIPCHECK(launch_diag<R>((int)N, L.dpm, L.epm, L.sx * h->wa[1], L.sy * h->wb[1], p.omega, L.dinv, nullptr, st));
-    const bool direct = std::max(n1, n2) <= kDirectMaxN;
-    if (direct) {
+    L.direct = std::max(n1, n2) <= kDirectOpMax;
+    if (L.direct) {
       std::vector<double> sx(n1 + 1), sy(n2 + 1);
       for (int k = 0; k <= n1; ++k) sx[k] = L.sx * h->wa[k];
       for (int k = 0; k <= n2; ++k) sy[k] = L.sy * h->wb[k];
@@ -407,8 +433,9 @@ std::unique_ptr<Hierarchy<R>> build_hierarchy(fde_handle* h) {
       L.tw_x = twiddles<R>(*H, m, L.L1, st);
       L.tw_y = twiddles<R>(*H, m, L.L2, st);
       L.ay = dalloc<R>(m, N);
-      L.r = dalloc<R>(m, N);
     }
+    if (std::max(n1, n2) > kDirectMaxN) L.r = dalloc<R>(m, N);
+    if (L.direct && std::max(n1, n2) > kDirectMaxN) L.x2 = dalloc<R>(m, N);
     L.b = dalloc<R>(m, N);
     L.x = dalloc<R>(m, N);
     H->lv.push_back(L);
@@ -474,31 +501,51 @@ void build_preconditioner(fde_handle* h) {
 }
 
 // ---- V-cycle ------------------------------------------------------------------------------------
+// Returns the buffer that holds the level's result: x itself, or on direct levels possibly the
+// level's second iterate buffer (the direct kernel cannot update x in place, so successive sweeps
+// alternate between the two buffers instead of copying back).
 template <typename R>
-void vcycle_from(fde_handle* h, Hierarchy<R>& H, int l, R* x, const int* skip) {
+R* vcycle_from(fde_handle* h, Hierarchy<R>& H, int l, R* x, const int* skip, bool x_ready) {
   hipStream_t st = h->stream;
   if (l >= H.lc) {
     timed(h, FDE_KFAM_COARSE, 2.0 * H.lv[l].N() * sizeof(R),
           [&] { return launch_coarse_vcycle<R>(H.cv, H.lv[l].b, x, skip, st); });
-    return;
+    return x;
   }
   Level<R>& L = H.lv[l];
   const OpView<R> op = L.view();
   const size_t N = L.N(), Nc = H.lv[l + 1].N();
-  if (l > 0) {
+  if (l > 0 && !x_ready) {
     if (h->p.nu_pre > 0)
       timed(h, FDE_KFAM_TRANSFER, 3.0 * N * sizeof(R),
             [&] { return launch_presmooth<R, R>((int)N, L.b, nullptr, L.dinv, x, nullptr, skip, st); });
     else HIPCHECK(launch_fill<R>(N, x, R(0), st));
   }
-  for (int it = 1; it < h->p.nu_pre; ++it) op_apply<R, R>(h, false, op, x, L.ay, x, EP_JACOBI, L.b, nullptr, 0.0, skip);
-  op_apply<R, R>(h, false, op, x, L.ay, L.r, EP_RESID, L.b, nullptr, 0.0, skip);
-  timed(h, FDE_KFAM_TRANSFER, (double)(N + Nc) * sizeof(R),
-        [&] { return launch_restrict<R>(L.n1, L.n2, L.r, H.lv[l + 1].b, skip, st); });
-  vcycle_from<R>(h, H, l + 1, H.lv[l + 1].x, skip);
+  // One damped-Jacobi sweep on the current iterate.  The FFT row pass reads only its own rows and
+  // updates in place; the direct kernel reads whole columns and writes the other buffer.
+  R* cur = x;
+  auto jacobi_sweep = [&]() {
+    if (L.direct) {
+      R* nxt = (cur == x) ? L.x2 : x;
+      op_apply<R, R>(h, false, op, cur, L.ay, nxt, EP_JACOBI, L.b, nullptr, 0.0, skip);
+      cur = nxt;
+    } else {
+      op_apply<R, R>(h, false, op, cur, L.ay, cur, EP_JACOBI, L.b, nullptr, 0.0, skip);
+    }
+  };
+  for (int it = 1; it < h->p.nu_pre; ++it) jacobi_sweep();
+  op_apply<R, R>(h, false, op, cur, L.ay, L.r, EP_RESID, L.b, nullptr, 0.0, skip);
+  // the restriction also takes the coarse level's first sweep when that level smooths
+  Level<R>& C = H.lv[l + 1];
+  const bool fuse = (l + 1 < H.lc) && h->p.nu_pre > 0;
+  timed(h, FDE_KFAM_TRANSFER, (double)(N + (fuse ? 3 : 1) * Nc) * sizeof(R), [&] {
+    return launch_restrict<R>(L.n1, L.n2, L.r, C.b, fuse ? C.dinv : nullptr, fuse ? C.x : nullptr, skip, st);
+  });
+  const R* ec = vcycle_from<R>(h, H, l + 1, C.x, skip, fuse);
   timed(h, FDE_KFAM_TRANSFER, (double)(2 * N + Nc) * sizeof(R),
-        [&] { return launch_prolong<R>(L.n1, L.n2, H.lv[l + 1].x, x, skip, st); });
-  for (int it = 0; it < h->p.nu_post; ++it) op_apply<R, R>(h, false, op, x, L.ay, x, EP_JACOBI, L.b, nullptr, 0.0, skip);
+        [&] { return launch_prolong<R>(L.n1, L.n2, ec, cur, skip, st); });
+  for (int it = 0; it < h->p.nu_post; ++it) jacobi_sweep();
+  return cur;
 }
 
 // z = MG(s * v): v is FP64 (a basis column), s a device scalar (or NULL = 1).
@@ -514,7 +561,8 @@ void vcycle_top(fde_handle* h, Hierarchy<R>& H, const double* v, const double* s
   }
   timed(h, FDE_KFAM_TRANSFER, pb, [&] { return launch_presmooth<R, double>(N, v, s, L0.dinv, z, L0.b, skip, h->stream); });
   if (h->p.nu_pre == 0) HIPCHECK(launch_fill<R>(L0.N(), z, R(0), h->stream));
-  vcycle_from<R>(h, H, 0, z, skip);
+  R* res = vcycle_from<R>(h, H, 0, z, skip, false);
+  if (res != z) HIPCHECK(hipMemcpyAsync(z, res, L0.N() * sizeof(R), hipMemcpyDeviceToDevice, h->stream));
 }
 
 // ---- flexible GMRES ----------------------------------------------------------------------------
@@ -528,20 +576,23 @@ void arnoldi_step(fde_handle* h, Hierarchy<R>& H, int j) {
   const size_t N = h->N;
   const int* skip = &h->st->done;
   R* Z = static_cast<R*>(h->Z);
-  double* vj = h->V + (size_t)j * N;
-  double* w = h->V + (size_t)(j + 1) * N;
+  const size_t ldv = h->ldv;
+  double* vj = h->V + (size_t)j * ldv;
+  double* w = h->V + (size_t)(j + 1) * ldv;
   vcycle_top<R>(h, H, vj, &h->st->vscale[j], Z + (size_t)j * N, skip);
   const OpView<double> op = h->cur.view(h->tw64_x, h->tw64_y, h->n1, h->n2, h->L1, h->L2);
   op_apply<double, R>(h, true, op, Z + (size_t)j * N, h->ay64, w, EP_APPLY, nullptr, nullptr, 0.0, skip);
+  // bytes of a pass: j + 1 basis columns and w read, w written by the update passes (a skipped
+  // second pass is counted as a launch of zero bytes)
   const double vb = (double)(j + 2) * N * sizeof(double);
   timed(h, FDE_KFAM_CGS, vb, [&] {
-    return launch_cgs_pass(CGS_DOTS, N, j + 1, h->V, N, w, nullptr, h->st, h->partials, h->cgs_grid, h->stream);
+    return launch_cgs_pass(CGS_DOTS, N, j + 1, h->V, ldv, w, nullptr, h->st, h->partials, h->cgs_grid, h->stream);
+  });
+  timed(h, FDE_KFAM_CGS, -(vb + N * sizeof(double)), [&] {
+    return launch_cgs_pass(CGS_UPDATE_DOTS, N, j + 1, h->V, ldv, w, nullptr, h->st, h->partials, h->cgs_grid, h->stream);
   });
   timed(h, FDE_KFAM_CGS, vb + N * sizeof(double), [&] {
-    return launch_cgs_pass(CGS_UPDATE_DOTS, N, j + 1, h->V, N, w, nullptr, h->st, h->partials, h->cgs_grid, h->stream);
-  });
-  timed(h, FDE_KFAM_CGS, vb + N * sizeof(double), [&] {
-    return launch_cgs_pass(CGS_UPDATE_NORM, N, j + 1, h->V, N, w, nullptr, h->st, h->partials, h->cgs_grid, h->stream);
+    return launch_cgs_pass(CGS_UPDATE_NORM, N, j + 1, h->V, ldv, w, nullptr, h->st, h->partials, h->cgs_grid, h->stream);
   });
 }
 
@@ -550,7 +601,7 @@ int fgmres(fde_handle* h, Hierarchy<R>& H, const double* b, double* x, fde_stats
   const size_t N = h->N;
   const int restart = h->p.restart;
   timed(h, FDE_KFAM_CGS, 2.0 * N * sizeof(double), [&] {
-    return launch_cgs_pass(CGS_INIT, N, 0, h->V, N, h->V, b, h->st, h->partials, h->cgs_grid, h->stream);
+    return launch_cgs_pass(CGS_INIT, N, 0, h->V, h->ldv, h->V, b, h->st, h->partials, h->cgs_grid, h->stream);
   });
   const OpView<double> op = h->cur.view(h->tw64_x, h->tw64_y, h->n1, h->n2, h->L1, h->L2);
   int cycles = 0;
@@ -571,6 +622,7 @@ int fgmres(fde_handle* h, Hierarchy<R>& H, const double* b, double* x, fde_stats
       }
     }
     h->prof.cycle_nused.push_back(h->st_host->nused);
+    h->prof.cycle_reorth.push_back(h->st_host->reorth_mask);
     h->prof.cur_j = -1;
     const int nu = h->st_host->nused;
     timed(h, FDE_KFAM_UPDATE, (double)N * (nu * sizeof(R) + (cycles == 0 ? 1 : 2) * sizeof(double)), [&] {
@@ -578,7 +630,7 @@ int fgmres(fde_handle* h, Hierarchy<R>& H, const double* b, double* x, fde_stats
     });
     op_apply<double, double>(h, true, op, x, h->ay64, h->V, EP_RESID, b, nullptr, 0.0, nullptr);
     timed(h, FDE_KFAM_CGS, (double)N * sizeof(double), [&] {
-      return launch_cgs_pass(CGS_RESNORM, N, 0, h->V, N, h->V, nullptr, h->st, h->partials, h->cgs_grid, h->stream);
+      return launch_cgs_pass(CGS_RESNORM, N, 0, h->V, h->ldv, h->V, nullptr, h->st, h->partials, h->cgs_grid, h->stream);
     });
     read_state(h);
     ++cycles;
@@ -592,6 +644,7 @@ int fgmres(fde_handle* h, Hierarchy<R>& H, const double* b, double* x, fde_stats
     stats->iters = s.iters;
     stats->restarts = cycles - 1;
     stats->converged = s.conv;
+    stats->reorth_steps = s.nreorth;
     stats->relres_true = s.bnorm > 0 ? s.resnorm / s.bnorm : 0.0;
     stats->relres_est = s.bnorm > 0 ? s.est / s.bnorm : 0.0;
   }
@@ -682,6 +735,13 @@ int fde_setup(const fde_problem* pin, const double* dp, const double* dm, const 
     load_outer(h.get(), h->cur, dp, dm, ep, em);
     h->cur.lam_x = upload<double>(m, symbol_host(h->wa, p.n1, h->L1, h->sx), h->stream);
     h->cur.lam_y = upload<double>(m, symbol_host(h->wb, p.n2, h->L2, h->sy), h->stream);
+    {
+      std::vector<double> sx(p.n1 + 1), sy(p.n2 + 1);
+      for (int k = 0; k <= p.n1; ++k) sx[k] = h->sx * h->wa[k];
+      for (int k = 0; k <= p.n2; ++k) sy[k] = h->sy * h->wb[k];
+      h->cur.swx = upload<double>(m, sx, h->stream);
+      h->cur.swy = upload<double>(m, sy, h->stream);
+    }
     h->prev = h->cur;
     h->prev_aliases_cur = true;
     {
@@ -694,8 +754,9 @@ int fde_setup(const fde_problem* pin, const double* dp, const double* dm, const 
     }
     h->ay64 = dalloc<double>(m, N);
     h->rhs = dalloc<double>(m, N);
-    h->scratch64 = dalloc<double>(m, 2 * N);
-    h->V = dalloc<double>(m, (size_t)(p.restart + 1) * N);
+    h->scratch64 = dalloc<double>(m, 4 * N);
+    h->ldv = basis_ld(N);
+    h->V = dalloc<double>(m, (size_t)(p.restart + 1) * h->ldv);
     if (h->fp32()) h->Z = dalloc<float>(m, (size_t)p.restart * N);
     else h->Z = dalloc<double>(m, (size_t)p.restart * N);
     h->st = dalloc<GmresState>(m, 1);
@@ -706,7 +767,7 @@ int fde_setup(const fde_problem* pin, const double* dp, const double* dm, const 
     init.rtol = p.rtol;
     init.maxit = p.maxit;
     init.restart = p.restart;
-    init.cgs2 = 1;
+    init.orth = 2;
     HIPCHECK(hipMemcpyAsync(h->st, &init, sizeof(init), hipMemcpyHostToDevice, h->stream));
     build_preconditioner(h.get());
     HIPCHECK(hipStreamSynchronize(h->stream));
@@ -895,7 +956,15 @@ int apply_hook(fde_handle* h, int level, const double* x, double* y, int mode, c
       HIPCHECK(hipMemcpyAsync(res, xi, n * sizeof(R), hipMemcpyDeviceToDevice, h->stream));
       xi = res;
     }
-    HIPCHECK((launch_operator<R, R>(L.view(), xi, L.ay, res, mode, bi, nullptr, 0.0, nullptr, h->stream)));
+    if (L.direct) {
+      // the direct kernel reads whole columns of x, so it never writes x in place
+      R* tmp = reinterpret_cast<R*>(h->scratch64) + 2 * n;
+      HIPCHECK((launch_direct_op<R, R>(L.n1, L.n2, xi, L.dpm, L.epm, L.swx, L.swy, tmp, mode, bi, L.dinv, nullptr, 0.0,
+                                       nullptr, h->stream)));
+      HIPCHECK(hipMemcpyAsync(res, tmp, n * sizeof(R), hipMemcpyDeviceToDevice, h->stream));
+    } else {
+      HIPCHECK((launch_operator<R, R>(L.view(), xi, L.ay, res, mode, bi, nullptr, 0.0, nullptr, h->stream)));
+    }
   }
   out64<R>(h, res, y, n);
   HIPCHECK(hipStreamSynchronize(h->stream));
@@ -912,8 +981,7 @@ int fde_apply(fde_handle* h, int level, int prec, const double* x, double* y) {
   return guarded(h, [&]() -> int {
     if (level == 0 && prec == FDE_FP64) {
       const OpView<double> op = h->cur.view(h->tw64_x, h->tw64_y, h->n1, h->n2, h->L1, h->L2);
-      HIPCHECK((launch_operator<double, double>(op, x, h->ay64, y, EP_APPLY, nullptr, nullptr, 0.0, nullptr,
-                                                h->stream)));
+      op_apply<double, double>(h, true, op, x, h->ay64, y, EP_APPLY, nullptr, nullptr, 0.0, nullptr);
       HIPCHECK(hipStreamSynchronize(h->stream));
       return FDE_OK;
     }
@@ -974,7 +1042,7 @@ int transfer_hook(fde_handle* h, int level, const double* in, double* out, bool 
   Level<R>& C = H.lv[level + 1];
   if (restrict_) {
     R* ri = HookIO<R>::in(h, in, F.N(), 0);
-    HIPCHECK(launch_restrict<R>(F.n1, F.n2, ri, C.b, nullptr, h->stream));
+    HIPCHECK(launch_restrict<R>(F.n1, F.n2, ri, C.b, nullptr, nullptr, nullptr, h->stream));
     out64<R>(h, C.b, out, C.N());
   } else {
     R* ei = HookIO<R>::in(h, in, C.N(), 0);

@@ -23,108 +23,185 @@
 #include "common.h"
 #include "fft.h"
 
+// Minimum waves per SIMD the operator kernels are compiled for (register budget 256 at 2).
+#ifndef FDE_XW
+#define FDE_XW 2
+#endif
+#ifndef FDE_YW
+#define FDE_YW 2
+#endif
+
 namespace fde {
 
-// (zr, zi) <- lam .* Z  and  (pr, pi) <- conj(lam) .* Z, lam the scaled symbol.
+// The forward spectrum Z is stashed in LDS (zs: real parts then imaginary parts, natural order) so
+// that only one spectrum is live in registers at a time:
+//   pass 1: (zr, zi) <- lam .* Z, inverse -> (T a, T b)
+//   pass 2: (zr, zi) <- conj(lam) .* Z, inverse -> (T^T a, T^T b)
+// Between the passes the partial results of pass 1 take Z's place in LDS.
 template <int L, typename R>
-__device__ __forceinline__ void symbol_multiply(Reg<R, L>& zr, Reg<R, L>& zi, Reg<R, L>& pr,
-                                                Reg<R, L>& pi,
-                                                const R* __restrict__ lam, int t) {
+__device__ __forceinline__ void stash(const Reg<R, L>& zr, const Reg<R, L>& zi, R* zs, int t) {
+  constexpr int E = PlanFor<R, L>::E, T = PlanFor<R, L>::T;
+  static_for<0, E>([&](auto m) {
+    zs[t + T * m] = zr[m];
+    zs[L + t + T * m] = zi[m];
+  });
+}
+
+template <int L, int CONJ, typename R>
+__device__ __forceinline__ void symbol_times(Reg<R, L>& zr, Reg<R, L>& zi, const R* zs, const R* __restrict__ lam,
+                                             int t) {
   constexpr int E = PlanFor<R, L>::E, T = PlanFor<R, L>::T;
   static_for<0, E>([&](auto m) {
     const int k = t + T * m;
-    const R lr = lam[2 * k], li = lam[2 * k + 1];
-    const R a = zr[m], b = zi[m];
+    const R lr = lam[2 * k], li = CONJ ? -lam[2 * k + 1] : lam[2 * k + 1];
+    const R a = zs[k], b = zs[L + k];
     zr[m] = lr * a - li * b;
     zi[m] = lr * b + li * a;
-    pr[m] = lr * a + li * b;
-    pi[m] = lr * b - li * a;
   });
 }
 
-template <typename R, typename Tin>
-__device__ __forceinline__ void epilogue_point(size_t p, R lx, const Tin* x, const R* __restrict__ ay,
-                                               const R* __restrict__ b, const R* __restrict__ dinv,
-                                               int mode, const SrcTerms& src, double tau, R* out) {
-  R l = lx;
-  if (ay) l += ay[p];
-  R v;
-  if (mode == EP_LOUT) {
-    v = l;
-  } else {
-    const R xv = (R)x[p];
-    if (mode == EP_APPLY) {
-      v = xv - l;
-    } else if (mode == EP_RESID) {
-      v = b[p] - xv + l;
-    } else if (mode == EP_JACOBI) {
-      v = xv + dinv[p] * (b[p] - xv + l);
-    } else {  // EP_RHS
-      double s = 0.0;
-      for (int k = 0; k < src.n; ++k) s += src.phi[k] * src.S[k][p];
-      v = xv + l + (R)(tau * s);
-    }
-  }
-  out[p] = v;
+// A pointer that is the same for the whole wavefront, kept in scalar registers: loads then use a
+// scalar base plus a 32-bit per-lane offset instead of one 64-bit address per element.
+template <typename T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+  const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return reinterpret_cast<T*>(((unsigned long long)hi << 32) | lo);
 }
 
-template <typename R, typename Tin, int L>
-__global__ __launch_bounds__((PlanFor<R, L>::T), 2) void toep_x_kernel(
+// Runs f(m) for m = 0..E-1 in groups of G, with scheduling barriers between groups so that the
+// compiler does not hoist every group's global loads at once (which would exhaust registers).
+template <int E, int G0, class F>
+__device__ __forceinline__ void chunked_for(F&& f) {
+  constexpr int G = G0 < E ? G0 : E;
+  static_for<0, E / G>([&](auto gc) {
+    __builtin_amdgcn_sched_barrier(0);
+    static_for<0, G>([&](auto mc) { f(ic<decltype(gc)::value * G + decltype(mc)::value>{}); });
+  });
+  __builtin_amdgcn_sched_barrier(0);
+}
+#ifndef FDE_EPI_GROUP
+#define FDE_EPI_GROUP 16
+#endif
+constexpr int kEpiGroup = FDE_EPI_GROUP;
+
+// Epilogue at one point, MODE fixed at compile time.  l = x part + y part of tau/2 L x.
+template <int MODE, typename R, typename Tin>
+__device__ __forceinline__ R epilogue_value(R l, Tin xv, R bv, R dv, double srcv, double tau) {
+  if constexpr (MODE == EP_LOUT) return l;
+  else if constexpr (MODE == EP_APPLY) return (R)xv - l;
+  else if constexpr (MODE == EP_RESID) return bv - (R)xv + l;
+  else if constexpr (MODE == EP_JACOBI) return (R)xv + dv * (bv - (R)xv + l);
+  else return (R)xv + l + (R)(tau * srcv);  // EP_RHS
+}
+
+// Row pairs (transforms) per workgroup of the row pass: short transforms share a wavefront.
+template <typename R, int L>
+struct XCfg {
+  static constexpr int S = PlanFor<R, L>::T >= 64 ? 1 : 64 / PlanFor<R, L>::T;
+  static constexpr int THREADS = PlanFor<R, L>::T * S;
+};
+
+template <typename R, typename Tin, int L, int MODE>
+__global__ __launch_bounds__((XCfg<R, L>::THREADS), FDE_XW) void toep_x_kernel(
     int n1, int n2, const Tin* x, const R* __restrict__ dpm, const R* __restrict__ mu,
-    const R* __restrict__ tw, const R* __restrict__ ay, const R* __restrict__ b,
-    const R* __restrict__ dinv, int mode, SrcTerms src, double tau, R* out,
-    const int* __restrict__ skip) {
+    const R* __restrict__ twtab, const R* __restrict__ ay, const R* __restrict__ b,
+    const R* __restrict__ dinv, SrcTerms src, double tau, R* out, const int* __restrict__ skip) {
   if (skip && *skip) return;
   using P = PlanFor<R, L>;
-  constexpr int E = P::E, T = P::T;
-  __shared__ R lds[lds_len(L)];
-  const int t = threadIdx.x;
-  const int rowA = 2 * blockIdx.x;
-  const int rowB = rowA + 1;
-  const bool hasB = rowB < n2;
-  const Tin* xa = x + (size_t)rowA * n1;
-  const Tin* xb = x + (size_t)rowB * n1;
-  R zr[E], zi[E], pr[E], pi[E];
+  constexpr int E = P::E, T = P::T, S = XCfg<R, L>::S;
+  constexpr int SLOT = lds_exchange(L) + 2 * L;
+  __shared__ R lds_all[S * SLOT];
+  const int slot = threadIdx.x / T;
+  const int t = threadIdx.x - slot * T;
+  R* lds = lds_all + slot * SLOT;
+  R* zs = lds + lds_exchange(L);
+  Twiddles<R, L> tw;
+  tw.load(twtab, t);
+  const int rowA = 2 * (blockIdx.x * S + slot);
+  const bool hasA = rowA < n2;
+  const bool hasB = rowA + 1 < n2;
+  // per-row base pointers (uniform when a workgroup holds one row pair); in-row offsets are 32-bit
+  const size_t oA = (size_t)rowA * n1, oB = oA + n1;
+  auto U = [&](auto* ptr) { return S == 1 ? uniform_ptr(ptr) : ptr; };
+  const Tin* xa = U(x + oA);
+  const Tin* xb = U(x + oB);
+  const R* dA = U(dpm + 2 * oA);
+  const R* dB = U(dpm + 2 * oB);
+  R zr[E], zi[E];
   static_for<0, E>([&](auto m) {
     const int i = t + T * m;
-    zr[m] = i < n1 ? (R)xa[i] : R(0);
+    zr[m] = (hasA && i < n1) ? (R)xa[i] : R(0);
     zi[m] = (hasB && i < n1) ? (R)xb[i] : R(0);
   });
   fft<L, -1>(zr, zi, lds, tw, t);
-  symbol_multiply<L>(zr, zi, pr, pi, mu, t);
-  fft<L, +1>(zr, zi, lds, tw, t);  // real part: T xa, imaginary part: T xb
-  static_for<0, E>([&](auto m) {
+  stash<L>(zr, zi, zs, t);
+  symbol_times<L, 0>(zr, zi, zs, mu, t);  // each thread reads back only what it wrote
+  fft<L, +1>(zr, zi, lds, tw, t);         // real part: T xa, imaginary part: T xb
+  R pr[E], pi[E];
+  symbol_times<L, 1>(pr, pi, zs, mu, t);
+  chunked_for<E, kEpiGroup>([&](auto m) {
     const int i = t + T * m;
-    const size_t pa = (size_t)rowA * n1 + i, pb = (size_t)rowB * n1 + i;
-    zr[m] = i < n1 ? dpm[2 * pa] * zr[m] : R(0);
-    zi[m] = (hasB && i < n1) ? dpm[2 * pb] * zi[m] : R(0);
+    zs[i] = (hasA && i < n1) ? dA[2 * i] * zr[m] : R(0);
+    zs[L + i] = (hasB && i < n1) ? dB[2 * i] * zi[m] : R(0);
   });
   fft<L, +1>(pr, pi, lds, tw, t);  // real part: T^T xa, imaginary part: T^T xb
-  static_for<0, E>([&](auto m) {
+  const R* ayA = ay ? U(ay + oA) : nullptr;
+  const R* ayB = ay ? U(ay + oB) : nullptr;
+  const R* bA = b ? U(b + oA) : nullptr;
+  const R* bB = b ? U(b + oB) : nullptr;
+  const R* diA = dinv ? U(dinv + oA) : nullptr;
+  const R* diB = dinv ? U(dinv + oB) : nullptr;
+  R* outA = U(out + oA);
+  R* outB = U(out + oB);
+  auto finish = [&](const Tin* xr, const R* d, const R* ayr, const R* br, const R* dir, R* outr, size_t o,
+                    R lpart, R rpart, int i) {
+    R l = lpart + d[2 * i + 1] * rpart;
+    if (ayr) l += ayr[i];
+    R bv = R(0), dv = R(0);
+    double sv = 0.0;
+    Tin xv = Tin(0);
+    if constexpr (MODE != EP_LOUT) xv = xr[i];
+    if constexpr (MODE == EP_RESID || MODE == EP_JACOBI) bv = br[i];
+    if constexpr (MODE == EP_JACOBI) dv = dir[i];
+    if constexpr (MODE == EP_RHS) {
+      for (int k = 0; k < src.n; ++k) sv += src.phi[k] * src.S[k][o + i];
+    }
+    outr[i] = epilogue_value<MODE, R, Tin>(l, xv, bv, dv, sv, tau);
+  };
+  chunked_for<E, kEpiGroup>([&](auto m) {
     const int i = t + T * m;
-    if (i < n1) {
-      const size_t pa = (size_t)rowA * n1 + i;
-      epilogue_point<R, Tin>(pa, zr[m] + dpm[2 * pa + 1] * pr[m], x, ay, b, dinv, mode, src, tau, out);
-      if (hasB) {
-        const size_t pb = (size_t)rowB * n1 + i;
-        epilogue_point<R, Tin>(pb, zi[m] + dpm[2 * pb + 1] * pi[m], x, ay, b, dinv, mode, src, tau, out);
-      }
+    if (hasA && i < n1) {
+      finish(xa, dA, ayA, bA, diA, outA, oA, zs[i], pr[m], i);
+      if (hasB) finish(xb, dB, ayB, bB, diB, outB, oB, zs[L + i], pi[m], i);
     }
   });
 }
 
-// Slots (transforms) per workgroup of the column pass.
+#ifndef FDE_Y_THREADS
+#define FDE_Y_THREADS 512
+#endif
+#ifndef FDE_Y_COLS_PER_SLOT_L
+#define FDE_Y_COLS_PER_SLOT_L 1024
+#endif
+// Slots (transforms, two columns each) per workgroup of the column pass: adjacent columns make the
+// row reads of a workgroup contiguous, but too many slots leave CUs idle on the shorter levels.
+// Measured on gfx950: L/1024 slots (at least a full wavefront, at most 512 threads) is best for
+// L = 1024..4096.
 template <typename R, int L>
 struct YCfg {
-  static constexpr int S0 = sizeof(R) == 8 ? 2 : 4;
-  static constexpr int S = PlanFor<R, L>::T * S0 <= 512 ? S0 : (PlanFor<R, L>::T >= 512 ? 1 : 512 / PlanFor<R, L>::T);
+  static constexpr int T_ = PlanFor<R, L>::T;
+  static constexpr int SW = L / FDE_Y_COLS_PER_SLOT_L > 1 ? L / FDE_Y_COLS_PER_SLOT_L : 1;
+  static constexpr int S0 = SW > 64 / T_ ? SW : 64 / T_;
+  static constexpr int S = T_ * S0 <= FDE_Y_THREADS ? S0 : (T_ >= FDE_Y_THREADS ? 1 : FDE_Y_THREADS / T_);
   static constexpr int THREADS = PlanFor<R, L>::T * S;
 };
 
 template <typename R, typename Tin, int L>
-__global__ __launch_bounds__((YCfg<R, L>::THREADS), 2) void toep_y_kernel(
+__global__ __launch_bounds__((YCfg<R, L>::THREADS), FDE_YW) void toep_y_kernel(
     int n1, int n2, const Tin* __restrict__ x, const R* __restrict__ epm, const R* __restrict__ mu,
-    const R* __restrict__ tw, R* __restrict__ ay, int nstrips, const int* __restrict__ skip) {
+    const R* __restrict__ twtab, R* __restrict__ ay, int nstrips, const int* __restrict__ skip) {
   if (skip && *skip) return;
   using P = PlanFor<R, L>;
   constexpr int E = P::E, T = P::T, S = YCfg<R, L>::S;
@@ -133,35 +210,43 @@ __global__ __launch_bounds__((YCfg<R, L>::THREADS), 2) void toep_y_kernel(
   const int per = gridDim.x / 8;
   const int strip = (blockIdx.x % 8) * per + blockIdx.x / 8;
   if (strip >= nstrips) return;
-  __shared__ R lds_all[S * lds_len(L)];
+  constexpr int SLOT = lds_exchange(L) + 2 * L;
+  __shared__ R lds_all[S * SLOT];
   const int slot = threadIdx.x % S;
   const int t = threadIdx.x / S;
-  R* lds = lds_all + slot * lds_len(L);
+  R* lds = lds_all + slot * SLOT;
+  R* zs = lds + lds_exchange(L);
+  Twiddles<R, L> tw;
+  tw.load(twtab, t);
   const int c0 = strip * 2 * S + 2 * slot;
   const bool v0 = c0 < n1, v1 = c0 + 1 < n1;
-  R zr[E], zi[E], pr[E], pi[E];
+  R zr[E], zi[E];
+  // element offsets fit in 32 bits (n1 * n2 < 2^23); the base pointers are kernel arguments
   static_for<0, E>([&](auto m) {
     const int row = t + T * m;
-    const size_t p = (size_t)row * n1 + c0;
+    const unsigned p = (unsigned)row * (unsigned)n1 + (unsigned)c0;
     zr[m] = (row < n2 && v0) ? (R)x[p] : R(0);
     zi[m] = (row < n2 && v1) ? (R)x[p + 1] : R(0);
   });
   fft<L, -1>(zr, zi, lds, tw, t);
-  symbol_multiply<L>(zr, zi, pr, pi, mu, t);
+  stash<L>(zr, zi, zs, t);
+  symbol_times<L, 0>(zr, zi, zs, mu, t);
   fft<L, +1>(zr, zi, lds, tw, t);  // T a + i T b along the columns
-  static_for<0, E>([&](auto m) {
+  R pr[E], pi[E];
+  symbol_times<L, 1>(pr, pi, zs, mu, t);
+  chunked_for<E, kEpiGroup>([&](auto m) {
     const int row = t + T * m;
-    const size_t p = (size_t)row * n1 + c0;
-    zr[m] = (row < n2 && v0) ? epm[2 * p] * zr[m] : R(0);
-    zi[m] = (row < n2 && v1) ? epm[2 * p + 2] * zi[m] : R(0);
+    const unsigned p = (unsigned)row * (unsigned)n1 + (unsigned)c0;
+    zs[row] = (row < n2 && v0) ? epm[2 * p] * zr[m] : R(0);
+    zs[L + row] = (row < n2 && v1) ? epm[2 * p + 2] * zi[m] : R(0);
   });
   fft<L, +1>(pr, pi, lds, tw, t);  // T^T a + i T^T b
-  static_for<0, E>([&](auto m) {
+  chunked_for<E, kEpiGroup>([&](auto m) {
     const int row = t + T * m;
     if (row < n2) {
-      const size_t p = (size_t)row * n1 + c0;
-      if (v0) ay[p] = zr[m] + epm[2 * p + 1] * pr[m];
-      if (v1) ay[p + 1] = zi[m] + epm[2 * p + 3] * pi[m];
+      const unsigned p = (unsigned)row * (unsigned)n1 + (unsigned)c0;
+      if (v0) ay[p] = zs[row] + epm[2 * p + 1] * pr[m];
+      if (v1) ay[p + 1] = zs[L + row] + epm[2 * p + 3] * pi[m];
     }
   });
 }
@@ -176,18 +261,47 @@ static hipError_t launch_y(const OpView<R>& op, const Tin* x, R* ay, const int* 
   return hipGetLastError();
 }
 
+template <typename R, typename Tin, int L, int MODE>
+static hipError_t launch_x_mode(const OpView<R>& op, const Tin* x, const R* ay, R* out, const R* b,
+                                const SrcTerms& src, double tau, const int* skip, hipStream_t st) {
+  const int grid = ceil_div(op.n2, 2 * XCfg<R, L>::S);
+  hipLaunchKernelGGL((toep_x_kernel<R, Tin, L, MODE>), dim3(grid), dim3((XCfg<R, L>::THREADS)), 0, st, op.n1,
+                     op.n2, x, op.dpm, op.mu_x, op.tw_x, ay, b, op.dinv, src, tau, out, skip);
+  return hipGetLastError();
+}
+
+// The (precision, input, epilogue) combinations the solver uses.
+template <typename R, typename Tin>
+struct ModeSet {
+  static constexpr bool ok(int m) {
+    if (sizeof(R) == 8 && sizeof(Tin) == 8) return true;
+    if (sizeof(R) == 8) return m == EP_APPLY;
+    return m == EP_APPLY || m == EP_RESID || m == EP_JACOBI;
+  }
+};
+
 template <typename R, typename Tin, int L>
 static hipError_t launch_x(const OpView<R>& op, const Tin* x, const R* ay, R* out, int mode,
                            const R* b, const SrcTerms& src, double tau, const int* skip,
                            hipStream_t st) {
-  const int grid = ceil_div(op.n2, 2);
-  hipLaunchKernelGGL((toep_x_kernel<R, Tin, L>), dim3(grid), dim3((PlanFor<R, L>::T)), 0, st, op.n1, op.n2, x,
-                     op.dpm, op.mu_x, op.tw_x, ay, b, op.dinv, mode, src, tau, out, skip);
-  return hipGetLastError();
+  switch (mode) {
+#define M_(MM)                                                                                   \
+  case MM:                                                                                       \
+    if constexpr (ModeSet<R, Tin>::ok(MM))                                                       \
+      return launch_x_mode<R, Tin, L, MM>(op, x, ay, out, b, src, tau, skip, st);                \
+    else                                                                                         \
+      return hipErrorInvalidValue;
+    M_(EP_APPLY) M_(EP_RESID) M_(EP_JACOBI) M_(EP_RHS) M_(EP_LOUT)
+#undef M_
+    default:
+      return hipErrorInvalidValue;
+  }
 }
 
+#ifndef FDE_L_CASES
 #define FDE_L_CASES(MACRO) \
   MACRO(16) MACRO(32) MACRO(64) MACRO(128) MACRO(256) MACRO(512) MACRO(1024) MACRO(2048) MACRO(4096)
+#endif
 
 bool fft_length_supported(int L) {
   switch (L) {
@@ -202,6 +316,7 @@ bool fft_length_supported(int L) {
 
 template <typename R, typename Tin>
 hipError_t launch_op_y(const OpView<R>& op, const Tin* x, R* ay, const int* skip, hipStream_t st) {
+  if (!x || !ay || !op.epm || !op.mu_y || !op.tw_y || op.L2 != 2 * (op.n2 + 1)) return hipErrorInvalidValue;
   switch (op.L2) {
 #define C_(LL) \
   case LL:     \
@@ -216,6 +331,9 @@ hipError_t launch_op_y(const OpView<R>& op, const Tin* x, R* ay, const int* skip
 template <typename R, typename Tin>
 hipError_t launch_op_x(const OpView<R>& op, const Tin* x, const R* ay, R* out, int mode, const R* b,
                        const SrcTerms* src, double tau, const int* skip, hipStream_t st) {
+  if (!x || !out || !op.dpm || !op.mu_x || !op.tw_x || op.L1 != 2 * (op.n1 + 1)) return hipErrorInvalidValue;
+  if ((mode == EP_RESID || mode == EP_JACOBI) && !b) return hipErrorInvalidValue;
+  if (mode == EP_JACOBI && !op.dinv) return hipErrorInvalidValue;
   SrcTerms s{};
   if (src) s = *src;
   switch (op.L1) {
@@ -255,6 +373,114 @@ template hipError_t launch_operator<float, float>(const OpView<float>&, const fl
                                                   int, const float*, const SrcTerms*, double,
                                                   const int*, hipStream_t);
 
+// ---- direct operator for small levels ------------------------------------------------------------
+// One workgroup per output row j, one thread per column i (n1 <= blockDim):
+//   row part:    sum_k swx[i-k+1] x[j][k] (left) and sum_k swx[k-i+1] x[j][k] (right), x[j][:] in LDS;
+//   column part: sum_k swy[j-k+1] x[k][i] and sum_k swy[k-j+1] x[k][i], rows k read coalesced (the
+//                whole field is cache resident at these sizes).
+// The weight tables are stored zero-extended (w[m] for m >= 0, 0 for m < 0) so every term is
+// branch-free.  swx, swy: sx*w_k and sy*w_k, k = 0..n.
+template <typename R, typename Tin, int MODE>
+__global__ __launch_bounds__(512) void direct_op_kernel(int n1, int n2, const Tin* __restrict__ x,
+                                                        const R* __restrict__ dpm, const R* __restrict__ epm,
+                                                        const R* __restrict__ swx, const R* __restrict__ swy,
+                                                        const R* __restrict__ b, const R* __restrict__ dinv,
+                                                        SrcTerms src, double tau, R* __restrict__ out,
+                                                        const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  extern __shared__ unsigned char smem_raw[];
+  R* xr = reinterpret_cast<R*>(smem_raw);  // n1
+  R* wx = xr + n1;                          // 2 n1 + 2: wx[n1 + m] = swx[m] (m >= 0), 0 below
+  R* wy = wx + 2 * n1 + 2;                  // 2 n2 + 2
+  const int j = blockIdx.x;
+  const int i = threadIdx.x;
+  const Tin* xrow = x + (size_t)j * n1;
+  for (int k = threadIdx.x; k < n1; k += blockDim.x) xr[k] = (R)xrow[k];
+  for (int m = threadIdx.x; m < 2 * n1 + 2; m += blockDim.x) wx[m] = m >= n1 && m - n1 <= n1 ? swx[m - n1] : R(0);
+  for (int m = threadIdx.x; m < 2 * n2 + 2; m += blockDim.x) wy[m] = m >= n2 && m - n2 <= n2 ? swy[m - n2] : R(0);
+  __syncthreads();
+  if (i >= n1) return;
+  R lx = 0, rx = 0, ly = 0, ry = 0;
+  const R* wl = wx + n1 + i + 1;  // wl[-k] = swx[i-k+1]
+  const R* wr = wx + n1 - i + 1;  // wr[k]  = swx[k-i+1]
+#pragma unroll 4
+  for (int k = 0; k < n1; ++k) {
+    const R v = xr[k];
+    lx += wl[-k] * v;
+    rx += wr[k] * v;
+  }
+  const R* vl = wy + n2 + j + 1;
+  const R* vr = wy + n2 - j + 1;
+  const Tin* xc = x + i;
+  // column values are independent loads: fetch 16 at a time so their latencies overlap
+  constexpr int CH = 16;
+  int k0 = 0;
+  for (; k0 + CH <= n2; k0 += CH) {
+    R v[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) v[c] = (R)xc[(size_t)(k0 + c) * n1];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      ly += vl[-(k0 + c)] * v[c];
+      ry += vr[k0 + c] * v[c];
+    }
+  }
+  for (int k = k0; k < n2; ++k) {
+    const R v = (R)xc[(size_t)k * n1];
+    ly += vl[-k] * v;
+    ry += vr[k] * v;
+  }
+  const size_t p = (size_t)j * n1 + i;
+  const R l = dpm[2 * p] * lx + dpm[2 * p + 1] * rx + epm[2 * p] * ly + epm[2 * p + 1] * ry;
+  R bv = R(0), dv = R(0);
+  double sv = 0.0;
+  if constexpr (MODE == EP_RESID || MODE == EP_JACOBI) bv = b[p];
+  if constexpr (MODE == EP_JACOBI) dv = dinv[p];
+  if constexpr (MODE == EP_RHS) {
+    for (int k = 0; k < src.n; ++k) sv += src.phi[k] * src.S[k][p];
+  }
+  out[p] = epilogue_value<MODE, R, Tin>(l, xr[i], bv, dv, sv, tau);
+}
+
+template <typename R, typename Tin>
+hipError_t launch_direct_op(int n1, int n2, const Tin* x, const R* dpm, const R* epm, const R* swx, const R* swy,
+                            R* out, int mode, const R* b, const R* dinv, const SrcTerms* src, double tau,
+                            const int* skip, hipStream_t st) {
+  if (n1 > 512 || n1 < 1 || n2 < 1 || !x || !dpm || !epm || !swx || !swy || !out) return hipErrorInvalidValue;
+  if ((mode == EP_RESID || mode == EP_JACOBI) && !b) return hipErrorInvalidValue;
+  if (mode == EP_JACOBI && !dinv) return hipErrorInvalidValue;
+  SrcTerms s{};
+  if (src) s = *src;
+  const int threads = ((n1 + 63) / 64) * 64;
+  const size_t bytes = (size_t)(n1 + 2 * n1 + 2 + 2 * n2 + 2) * sizeof(R);
+  switch (mode) {
+#define M_(MM)                                                                                                  \
+  case MM:                                                                                                      \
+    if constexpr (ModeSet<R, Tin>::ok(MM)) {                                                                    \
+      hipLaunchKernelGGL((direct_op_kernel<R, Tin, MM>), dim3(n2), dim3(threads), bytes, st, n1, n2, x, dpm, epm, \
+                         swx, swy, b, dinv, s, tau, out, skip);                                                 \
+      return hipGetLastError();                                                                                 \
+    } else {                                                                                                    \
+      return hipErrorInvalidValue;                                                                              \
+    }
+    M_(EP_APPLY) M_(EP_RESID) M_(EP_JACOBI) M_(EP_RHS) M_(EP_LOUT)
+#undef M_
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+template hipError_t launch_direct_op<double, double>(int, int, const double*, const double*, const double*,
+                                                     const double*, const double*, double*, int, const double*,
+                                                     const double*, const SrcTerms*, double, const int*,
+                                                     hipStream_t);
+template hipError_t launch_direct_op<double, float>(int, int, const float*, const double*, const double*,
+                                                    const double*, const double*, double*, int, const double*,
+                                                    const double*, const SrcTerms*, double, const int*,
+                                                    hipStream_t);
+template hipError_t launch_direct_op<float, float>(int, int, const float*, const float*, const float*,
+                                                   const float*, const float*, float*, int, const float*,
+                                                   const float*, const SrcTerms*, double, const int*, hipStream_t);
+
 // ---- host side: twiddle tables and symbols ---------------------------------------------------
 struct RtPlan {
   int E, T, nst;
@@ -262,7 +488,7 @@ struct RtPlan {
 };
 static RtPlan rt_plan(int L, int emax) {
   RtPlan p{};
-  p.E = L >= 64 * emax ? emax : (L >= 128 ? L / 64 : 2);
+  p.E = L >= 2 * emax ? emax : L / 2;
   p.T = L / p.E;
   int logL = 0, logE = 0;
   while ((1 << logL) < L) ++logL;
@@ -278,9 +504,9 @@ static RtPlan rt_plan(int L, int emax) {
 }
 
 int fft_twiddle_count(int L, int elem_bytes) {
-  RtPlan p = rt_plan(L, elem_bytes == 8 ? 8 : 16);
+  RtPlan p = rt_plan(L, emax_for(elem_bytes, L));
   int c = 0;
-  for (int s = 1; s < p.nst; ++s) c += p.ns[s] * (p.radix[s] - 1);
+  for (int s = 1; s < p.nst; ++s) c += p.ns[s];
   return 2 * c;
 }
 
@@ -292,15 +518,14 @@ static void unit_root(long long k, long long M, double* re, double* im) {
 }
 
 void fft_twiddles(int L, int elem_bytes, double* out, int* count) {
-  RtPlan p = rt_plan(L, elem_bytes == 8 ? 8 : 16);
+  RtPlan p = rt_plan(L, emax_for(elem_bytes, L));
   int o = 0;
   for (int s = 1; s < p.nst; ++s) {
     const int R = p.radix[s], NS = p.ns[s];
-    for (int j = 0; j < NS; ++j)
-      for (int r = 1; r < R; ++r) {
-        unit_root((long long)r * j, (long long)NS * R, &out[o], &out[o + 1]);
-        o += 2;
-      }
+    for (int j = 0; j < NS; ++j) {
+      unit_root((long long)j, (long long)NS * R, &out[o], &out[o + 1]);
+      o += 2;
+    }
   }
   if (count) *count = o;
 }
