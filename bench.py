@@ -29,6 +29,29 @@ if ROOT not in sys.path:
 METRIC = "MG-GMRES CN time-steps/s at 2047² + p50/p99 latency, mixed vs FP64 plain"
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs of this workload
+# (scaled by a copy of known size), keyed by kernel family, with the hash of the source file the
+# kernels were built from: the figure is reported only while that source is unchanged.
+PMC_TRAFFIC = {
+    "cgs": {"bytes_per_launch": 396.98e6, "source": "paper_1706_06844_amd/csrc/krylov.hip",
+            "sha256": "30ed1c7dd8db1a5f9ae70a84a55906ba20b0655fef489e8df2eb1f4f302baef9", "summary": "profiles/cgs_pass_c3_2047_mixed.md"},
+}
+
+
+def measured_traffic(family):
+    import hashlib
+
+    e = PMC_TRAFFIC.get(family)
+    if not e:
+        return None
+    try:
+        with open(os.path.join(ROOT, e["source"]), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != e["sha256"]:
+                return None
+    except OSError:
+        return None
+    return e["bytes_per_launch"]
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -38,8 +61,11 @@ def parse():
     ap.add_argument("--n", type=int, default=2047)
     ap.add_argument("--maxit", type=int, default=4000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-iters", type=int, default=3)
+    ap.add_argument("--cpu-sample-iters", type=int, default=24)
     ap.add_argument("--only", choices=["mixed", "fp64"], default=None)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy a 2047^2 FP64 field (33.5 MB) three times with torch, so that a "
+                         "counter run sees a kernel of known traffic")
     return ap.parse_args()
 
 
@@ -59,7 +85,7 @@ def run_precision(prec, p, dev_fields, S, phis, u0, steps, warmup, maxit, profil
 
     def run(k, tag):
         u.copy_(u0)
-        lat, its = [], []
+        lat, its, reo = [], [], []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         a, b = u, un
@@ -68,11 +94,12 @@ def run_precision(prec, p, dev_fields, S, phis, u0, steps, warmup, maxit, profil
             st = fde.fde_step_sources(h, a, [f((m - 0.5) * p.tau) for f in phis], S, b)
             lat.append(time.perf_counter() - ts)
             its.append(st["iters"])
+            reo.append(st["reorth_steps"])
             if not st["converged"]:
                 raise RuntimeError(f"{tag}: step {m} did not converge: {st}")
             a, b = b, a
         torch.cuda.synchronize()
-        return time.perf_counter() - t0, lat, its, a
+        return time.perf_counter() - t0, lat, its, reo, a
 
     # warmup, with every kernel family timed to find the dominant one
     fde.fde_profile_enable(h)
@@ -85,14 +112,14 @@ def run_precision(prec, p, dev_fields, S, phis, u0, steps, warmup, maxit, profil
     fde.fde_profile_reset(h)
     # without warmup there is nothing to choose from: time every family in the timed run
     fde.fde_profile_enable(h, 1 << fde.L.KFAM.index(fam) if fam else (1 << len(fde.L.KFAM)) - 1)
-    elapsed, lat, its, u_final = run(steps, "timed")
+    elapsed, lat, its, reo, u_final = run(steps, "timed")
     timed = fde.fde_profile_read(h)
     if fam is None:
         prof = timed
         fam = max(timed, key=lambda k: timed[k]["ms"])
     live = timed[fam]
     out = {"elapsed": elapsed, "lat": lat, "iters": its, "u": u_final.clone(), "family": fam,
-           "live": live, "warm_profile": prof}
+           "live": live, "warm_profile": prof, "reorth": reo}
     h.close()
     return out
 
@@ -161,6 +188,12 @@ def main():
     phis, fields = workloads.source_terms(p)
     S = [d(f) for f in fields]
     u0 = d(workloads.sample_u0(p))
+    if args.copy_calibration:
+        dst = torch.empty_like(u0)
+        for _ in range(3):
+            dst.copy_(u0)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 copies of {u0.numel() * 8} bytes")
     res = {}
     order = [("mixed", fde.FDE_MIXED_FP32), ("fp64", fde.FDE_FP64)]
     for name, prec in order:
@@ -199,9 +232,10 @@ def main():
         "p50_ms": float(np.percentile(lat_ms, 50)),
         "p99_ms": float(np.percentile(lat_ms, 99)),
         "iters_per_step": float(np.mean(m["iters"])),
+        "reorth_fraction": float(np.sum(m["reorth"]) / max(np.sum(m["iters"]), 1)),
         "roofline": {"bound": "hbm", "kernel_family": m["family"], "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "bytes_per_launch": bytes_per_launch,
+                     "traffic": measured_traffic(m["family"]), "bytes_per_launch": bytes_per_launch,
                      "us_per_launch": 1e3 * ms_per_launch, "launches": live["launches"]},
     }
     if "fp64" in res and main_name == "mixed":
