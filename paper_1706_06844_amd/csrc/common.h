@@ -119,11 +119,50 @@ template <typename R>
 hipError_t launch_direct_apply(const CoarseView<R>& cv, int level, const R* x, R* out, int mode,
                                const R* b, hipStream_t st);
 // Assemble the dense coarsest matrix from the coarsest level and invert it in place (FP64).
+// With `dense` given (row-major FP64, the coarsest level's matrix), that matrix is inverted instead.
 template <typename R>
-hipError_t launch_coarse_invert(const CoarseView<R>& cv, double* inv, int* status, hipStream_t st);
+hipError_t launch_coarse_invert(const CoarseView<R>& cv, const double* dense, double* inv, int* status,
+                                hipStream_t st);
 // x = inv * b for the coarsest level (test hook)
 template <typename R>
-hipError_t launch_coarse_solve(int Nc, const double* inv, const R* b, R* x, hipStream_t st);
+hipError_t launch_coarse_solve(int Nc, const double* inv, const R* b, R* x, const int* skip, hipStream_t st);
+
+// ---- Galerkin coarse operators (galerkin.hip) ----------------------------------------------------
+// Level l of the Galerkin hierarchy in factored form: coarse grid nlx x nly, fine grid n0x x n0y,
+// H = 2^logH.  cx0/cx1: [nly][n0x] pairs (c+_D, c-_D) for D = 0, 1; ey0/ey1: [n0y][nlx] pairs.
+// V: [nly][n0x] pairs and W: [n0y][nlx] pairs of transform results (scratch shared by the levels).
+template <typename R>
+struct GalView {
+  int n0x, n0y, nlx, nly, logH;
+  int L0x, L0y;
+  const R* cx0;
+  const R* cx1;
+  const R* ey0;
+  const R* ey1;
+  const R* mu_x;  // fine-grid symbols and twiddles in precision R
+  const R* mu_y;
+  const R* tw_x;
+  const R* tw_y;
+  const R* dinv;
+  R* V;
+  R* W;
+  double m0x, m1x, m0y, m1y;  // mass (P^T P) stencils per direction
+  double scale;               // 4^-l
+};
+// out = A_l x (EP_APPLY), b - A_l x (EP_RESID) or x + dinv (b - A_l x) (EP_JACOBI, out != x).
+template <typename R>
+hipError_t launch_gal_apply(const GalView<R>& g, const R* x, R* out, int mode, const R* b, const int* skip,
+                            hipStream_t st);
+// cx0/cx1/ey0/ey1 from the fine FP64 coefficient pairs (the pointers in g are written).
+template <typename R>
+hipError_t launch_gal_setup(GalView<R>& g, const double* dpm, const double* epm, hipStream_t st);
+// Diagonal: dinv = omega / diag and/or dout = diag; qx, qy: [2][2H-1] factor-times-hat tables.
+template <typename R>
+hipError_t launch_gal_diag(const GalView<R>& g, const double* qx, const double* qy, double omega, R* dinv,
+                           double* dout, hipStream_t st);
+// Dense FP64 matrix of the level (row-major, (nlx*nly)^2); Qx: [2][nlx][n0x], Qy: [2][nly][n0y].
+template <typename R>
+hipError_t launch_gal_dense(const GalView<R>& g, const double* Qx, const double* Qy, double* A, hipStream_t st);
 
 // ---- Krylov kernels (krylov.hip) ---------------------------------------------------------------
 constexpr int kMaxRestart = 32;

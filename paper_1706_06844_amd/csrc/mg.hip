@@ -464,8 +464,8 @@ hipError_t launch_direct_apply(const CoarseView<R>& cv, int level, const R* x, R
 constexpr int kMaxCoarseN = 128;  // unknowns on the coarsest grid
 
 template <typename R>
-__global__ __launch_bounds__(1024) void coarse_invert_kernel(CoarseView<R> cv, double* __restrict__ inv,
-                                                             int* __restrict__ status) {
+__global__ __launch_bounds__(1024) void coarse_invert_kernel(CoarseView<R> cv, const double* __restrict__ dense,
+                                                             double* __restrict__ inv, int* __restrict__ status) {
   extern __shared__ unsigned char smem_raw[];
   const int l = cv.nlev - 1;
   const int n1 = cv.n1[l], n2 = cv.n2[l], n = n1 * n2;
@@ -479,6 +479,10 @@ __global__ __launch_bounds__(1024) void coarse_invert_kernel(CoarseView<R> cv, d
   const R* swx = cv.swx[l];
   const R* swy = cv.swy[l];
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    if (dense) {
+      A[e] = dense[e];
+      continue;
+    }
     const int p = e / n, q = e - p * n;
     const int j = p / n1, i = p - j * n1, jq = q / n1, iq = q - jq * n1;
     double a = (p == q) ? 1.0 : 0.0;
@@ -549,7 +553,8 @@ __global__ __launch_bounds__(1024) void coarse_invert_kernel(CoarseView<R> cv, d
 }
 
 template <typename R>
-hipError_t launch_coarse_invert(const CoarseView<R>& cv, double* inv, int* status, hipStream_t st) {
+hipError_t launch_coarse_invert(const CoarseView<R>& cv, const double* dense, double* inv, int* status,
+                                hipStream_t st) {
   const int l = cv.nlev - 1;
   const int n = cv.n1[l] * cv.n2[l];
   if (n > kMaxCoarseN) return hipErrorInvalidValue;
@@ -559,13 +564,14 @@ hipError_t launch_coarse_invert(const CoarseView<R>& cv, double* inv, int* statu
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((coarse_invert_kernel<R>), dim3(1), dim3(1024), bytes, st, cv, inv, status);
+  hipLaunchKernelGGL((coarse_invert_kernel<R>), dim3(1), dim3(1024), bytes, st, cv, dense, inv, status);
   return hipGetLastError();
 }
 
 template <typename R>
 __global__ void coarse_solve_kernel(int Nc, const double* __restrict__ inv, const R* __restrict__ b,
-                                    R* __restrict__ x) {
+                                    R* __restrict__ x, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   for (int p = threadIdx.x; p < Nc; p += blockDim.x) {
     double acc = 0.0;
     for (int q = 0; q < Nc; ++q) acc += inv[(size_t)p * Nc + q] * (double)b[q];
@@ -573,8 +579,8 @@ __global__ void coarse_solve_kernel(int Nc, const double* __restrict__ inv, cons
   }
 }
 template <typename R>
-hipError_t launch_coarse_solve(int Nc, const double* inv, const R* b, R* x, hipStream_t st) {
-  hipLaunchKernelGGL((coarse_solve_kernel<R>), dim3(1), dim3(256), 0, st, Nc, inv, b, x);
+hipError_t launch_coarse_solve(int Nc, const double* inv, const R* b, R* x, const int* skip, hipStream_t st) {
+  hipLaunchKernelGGL((coarse_solve_kernel<R>), dim3(1), dim3(256), 0, st, Nc, inv, b, x, skip);
   return hipGetLastError();
 }
 
@@ -592,8 +598,8 @@ hipError_t launch_coarse_solve(int Nc, const double* inv, const R* b, R* x, hipS
   template size_t coarse_lds_bytes<R>(const CoarseView<R>&);                                            \
   template hipError_t launch_direct_apply<R>(const CoarseView<R>&, int, const R*, R*, int, const R*,    \
                                              hipStream_t);                                              \
-  template hipError_t launch_coarse_invert<R>(const CoarseView<R>&, double*, int*, hipStream_t);        \
-  template hipError_t launch_coarse_solve<R>(int, const double*, const R*, R*, hipStream_t);
+  template hipError_t launch_coarse_invert<R>(const CoarseView<R>&, const double*, double*, int*, hipStream_t); \
+  template hipError_t launch_coarse_solve<R>(int, const double*, const R*, R*, const int*, hipStream_t);
 FDE_INST_R(double)
 FDE_INST_R(float)
 template hipError_t launch_presmooth<double, double>(int, const double*, const double*, const double*,

@@ -83,9 +83,14 @@ struct Level {
   R* b = nullptr;
   R* x = nullptr;
   R* r = nullptr;
-  R* x2 = nullptr;  // second iterate buffer of direct levels
+  R* x2 = nullptr;  // second iterate buffer of levels that cannot smooth in place
   R* ay = nullptr;
   bool direct = false;
+  bool gal = false;          // Galerkin level (factored form)
+  GalView<R> gv{};
+  double* qx = nullptr;      // factor-times-hat tables of the Galerkin diagonal
+  double* qy = nullptr;
+  bool in_place() const { return !direct && !gal; }
   OpView<R> view() const {
     OpView<R> v{};
     v.n1 = n1;
@@ -110,7 +115,10 @@ struct Level {
 template <typename R>
 struct Hierarchy {
   std::vector<Level<R>> lv;
-  int lc = 0;  // first level handled by the one-workgroup coarse kernel
+  int lc = 0;  // first level handled by the one-workgroup coarse kernel (Galerkin: the coarsest)
+  bool galerkin = false;
+  R* galV = nullptr;  // transform scratch of the Galerkin levels
+  R* galW = nullptr;
   CoarseView<R> cv{};
   double* inv = nullptr;
   int Nc = 0;
@@ -318,7 +326,6 @@ int validate(const fde_problem* p, std::string* why) {
   if (!(p->tau > 0.0) || !std::isfinite(p->tau)) return bad("tau must be positive and finite");
   if (p->precision < FDE_FP64 || p->precision > FDE_MIXED_BF16GEMM) return bad("unknown precision");
   if (p->mg_variant != FDE_MG_GEOMETRIC && p->mg_variant != FDE_MG_GALERKIN) return bad("unknown mg_variant");
-  if (p->mg_variant == FDE_MG_GALERKIN) return bad("the Galerkin variant is not available in this build");
   if (p->precision == FDE_MIXED_BF16GEMM) return bad("the BF16 GEMM path is not available in this build");
   if (!(p->omega > 0.0 && p->omega <= 1.0)) return bad("omega must lie in (0,1]");
   if (p->nu_pre < 0 || p->nu_pre > 8 || p->nu_post < 0 || p->nu_post > 8) return bad("nu_pre/nu_post in 0..8");
@@ -383,6 +390,92 @@ std::vector<double> symbol_host(const std::vector<double>& w, int n, int L, doub
   return out;
 }
 
+// Composite hat of half-width H at offset d (the 1-D factor of P_1 ... P_l, bilinear).
+double hat_w(int d, int H) {
+  const int a = d < 0 ? -d : d;
+  return a < H ? 1.0 - (double)a / H : 0.0;
+}
+
+// Entry k of the fine Toeplitz factor s*T: T[i][i'] = s w_{i-i'+1} with k = i - i' (zero below -1).
+double toep_entry(const std::vector<double>& w, double s, long k) {
+  const long m = k + 1;
+  return (m >= 0 && m < (long)w.size()) ? s * w[(size_t)m] : 0.0;
+}
+
+// Factor times hat over the hat's own support: q[d + H - 1] = (sT hat)(d), q[K + d + H - 1] =
+// (sT^T hat)(d), |d| < H, K = 2H - 1.
+std::vector<double> gal_q(const std::vector<double>& w, double s, int H) {
+  const int K = 2 * H - 1;
+  std::vector<double> q(2 * (size_t)K, 0.0);
+  for (int d = -H + 1; d < H; ++d)
+    for (int e = -H + 1; e < H; ++e) {
+      q[d + H - 1] += toep_entry(w, s, d - e) * hat_w(e, H);
+      q[K + d + H - 1] += toep_entry(w, s, e - d) * hat_w(e, H);
+    }
+  return q;
+}
+
+// Factor times each coarse hat over the whole fine line: Q[k][I][i], k = 0 (T), 1 (T^T).
+std::vector<double> gal_Q(const std::vector<double>& w, double s, int H, int nl, int n0) {
+  std::vector<double> Q(2 * (size_t)nl * n0, 0.0);
+  for (int I = 0; I < nl; ++I) {
+    const int c = H * (I + 1) - 1;
+    for (int i = 0; i < n0; ++i) {
+      double a = 0.0, b = 0.0;
+      for (int e = -H + 1; e < H; ++e) {
+        const double hw = hat_w(e, H);
+        a += toep_entry(w, s, (long)i - (c + e)) * hw;
+        b += toep_entry(w, s, (long)(c + e) - i) * hw;
+      }
+      Q[(size_t)I * n0 + i] = a;
+      Q[((size_t)nl + I) * n0 + i] = b;
+    }
+  }
+  return Q;
+}
+
+// Galerkin level l >= 1 over the fine level F0 (which supplies symbols and twiddles).
+template <typename R>
+void build_gal_level(fde_handle* h, Hierarchy<R>& H, Level<R>& L, int l) {
+  DevAlloc& m = h->hier_mem;
+  hipStream_t st = h->stream;
+  const Level<R>& F0 = H.lv[0];
+  const int Hw = 1 << l;
+  GalView<R>& g = L.gv;
+  g.n0x = h->n1;
+  g.n0y = h->n2;
+  g.nlx = L.n1;
+  g.nly = L.n2;
+  g.logH = l;
+  g.L0x = F0.L1;
+  g.L0y = F0.L2;
+  g.mu_x = F0.lam_x;
+  g.mu_y = F0.lam_y;
+  g.tw_x = F0.tw_x;
+  g.tw_y = F0.tw_y;
+  g.cx0 = dalloc<R>(m, 2 * (size_t)g.nly * g.n0x);
+  g.cx1 = dalloc<R>(m, 2 * (size_t)g.nly * g.n0x);
+  g.ey0 = dalloc<R>(m, 2 * (size_t)g.n0y * g.nlx);
+  g.ey1 = dalloc<R>(m, 2 * (size_t)g.n0y * g.nlx);
+  if (!H.galV) {  // level 1 is the largest
+    H.galV = dalloc<R>(m, 2 * (size_t)g.nly * g.n0x);
+    H.galW = dalloc<R>(m, 2 * (size_t)g.n0y * g.nlx);
+  }
+  g.V = H.galV;
+  g.W = H.galW;
+  g.m0x = g.m0y = 1.0 + (double)(Hw - 1) * (2 * Hw - 1) / (3.0 * Hw);
+  g.m1x = g.m1y = ((double)Hw * Hw - 1.0) / (6.0 * Hw);
+  g.scale = std::ldexp(1.0, -2 * l);
+  HIPCHECK(launch_gal_setup<R>(g, h->cur.dpm, h->cur.epm, st));
+  L.qx = upload<double>(m, gal_q(h->wa, F0.sx, Hw), st);
+  L.qy = upload<double>(m, gal_q(h->wb, F0.sy, Hw), st);
+  L.dinv = dalloc<R>(m, L.N());
+  HIPCHECK(launch_gal_diag<R>(g, L.qx, L.qy, h->p.omega, L.dinv, nullptr, st));
+  g.dinv = L.dinv;
+  L.gal = true;
+  L.direct = false;
+}
+
 // Build the preconditioner hierarchy in precision R from the outer FP64 fields `cur`.
 template <typename R>
 std::unique_ptr<Hierarchy<R>> build_hierarchy(fde_handle* h) {
@@ -390,6 +483,8 @@ std::unique_ptr<Hierarchy<R>> build_hierarchy(fde_handle* h) {
   DevAlloc& m = h->hier_mem;
   hipStream_t st = h->stream;
   const fde_problem& p = h->p;
+  const bool galerkin = p.mg_variant == FDE_MG_GALERKIN && std::min(h->n1, h->n2) > p.coarsest_n;
+  H->galerkin = galerkin;
   int n1 = h->n1, n2 = h->n2, l = 0;
   while (true) {
     Level<R> L;
@@ -401,41 +496,49 @@ std::unique_ptr<Hierarchy<R>> build_hierarchy(fde_handle* h) {
     L.sx = p.tau / (2.0 * std::pow(hx, p.alpha));
     L.sy = p.tau / (2.0 * std::pow(hy, p.beta));
     const size_t N = L.N();
-    if (l == 0) {
-      if (std::is_same<R, double>::value) {
-        L.dpm = reinterpret_cast<R*>(h->cur.dpm);
-        L.epm = reinterpret_cast<R*>(h->cur.epm);
+    if (galerkin && l > 0) {
+      build_gal_level<R>(h, *H, L, l);
+    } else {
+      if (l == 0) {
+        if (std::is_same<R, double>::value) {
+          L.dpm = reinterpret_cast<R*>(h->cur.dpm);
+          L.epm = reinterpret_cast<R*>(h->cur.epm);
+        } else {
+          L.dpm = dalloc<R>(m, 2 * N);
+          L.epm = dalloc<R>(m, 2 * N);
+          HIPCHECK((launch_convert<R, double>(2 * N, h->cur.dpm, L.dpm, st)));
+          HIPCHECK((launch_convert<R, double>(2 * N, h->cur.epm, L.epm, st)));
+        }
       } else {
+        const Level<R>& F = H->lv.back();
         L.dpm = dalloc<R>(m, 2 * N);
         L.epm = dalloc<R>(m, 2 * N);
-        HIPCHECK((launch_convert<R, double>(2 * N, h->cur.dpm, L.dpm, st)));
-        HIPCHECK((launch_convert<R, double>(2 * N, h->cur.epm, L.epm, st)));
+        HIPCHECK(launch_inject_pairs<R>(F.n1, F.n2, F.dpm, L.dpm, st));
+        HIPCHECK(launch_inject_pairs<R>(F.n1, F.n2, F.epm, L.epm, st));
       }
-    } else {
-      const Level<R>& F = H->lv.back();
-      L.dpm = dalloc<R>(m, 2 * N);
-      L.epm = dalloc<R>(m, 2 * N);
-      HIPCHECK(launch_inject_pairs<R>(F.n1, F.n2, F.dpm, L.dpm, st));
-      HIPCHECK(launch_inject_pairs<R>(F.n1, F.n2, F.epm, L.epm, st));
+      L.dinv = dalloc<R>(m, N);
+      HIPCHECK(launch_diag<R>((int)N, L.dpm, L.epm, L.sx * h->wa[1], L.sy * h->wb[1], p.omega, L.dinv, nullptr, st));
+      L.direct = std::max(n1, n2) <= kDirectOpMax;
+      if (L.direct) {
+        std::vector<double> sx(n1 + 1), sy(n2 + 1);
+        for (int k = 0; k <= n1; ++k) sx[k] = L.sx * h->wa[k];
+        for (int k = 0; k <= n2; ++k) sy[k] = L.sy * h->wb[k];
+        L.swx = upload<R>(m, sx, st);
+        L.swy = upload<R>(m, sy, st);
+      }
+      // FFT levels need symbols and twiddles; so does the fine level of a Galerkin hierarchy, whose
+      // transforms every coarse level reuses
+      if (!L.direct || (galerkin && l == 0)) {
+        L.lam_x = upload<R>(m, symbol_host(h->wa, n1, L.L1, L.sx), st);
+        L.lam_y = upload<R>(m, symbol_host(h->wb, n2, L.L2, L.sy), st);
+        L.tw_x = twiddles<R>(*H, m, L.L1, st);
+        L.tw_y = twiddles<R>(*H, m, L.L2, st);
+      }
+      if (!L.direct) L.ay = dalloc<R>(m, N);
     }
-    L.dinv = dalloc<R>(m, N);
-    HIPCHECK(launch_diag<R>((int)N, L.dpm, L.epm, L.sx * h->wa[1], L.sy * h->wb[1], p.omega, L.dinv, nullptr, st));
-    L.direct = std::max(n1, n2) <= kDirectOpMax;
-    if (L.direct) {
-      std::vector<double> sx(n1 + 1), sy(n2 + 1);
-      for (int k = 0; k <= n1; ++k) sx[k] = L.sx * h->wa[k];
-      for (int k = 0; k <= n2; ++k) sy[k] = L.sy * h->wb[k];
-      L.swx = upload<R>(m, sx, st);
-      L.swy = upload<R>(m, sy, st);
-    } else {
-      L.lam_x = upload<R>(m, symbol_host(h->wa, n1, L.L1, L.sx), st);
-      L.lam_y = upload<R>(m, symbol_host(h->wb, n2, L.L2, L.sy), st);
-      L.tw_x = twiddles<R>(*H, m, L.L1, st);
-      L.tw_y = twiddles<R>(*H, m, L.L2, st);
-      L.ay = dalloc<R>(m, N);
-    }
-    if (std::max(n1, n2) > kDirectMaxN) L.r = dalloc<R>(m, N);
-    if (L.direct && std::max(n1, n2) > kDirectMaxN) L.x2 = dalloc<R>(m, N);
+    const bool coarse_one_wg = !galerkin && std::max(n1, n2) <= kDirectMaxN;
+    if (!coarse_one_wg) L.r = dalloc<R>(m, N);
+    if (!L.in_place() && !coarse_one_wg) L.x2 = dalloc<R>(m, N);
     L.b = dalloc<R>(m, N);
     L.x = dalloc<R>(m, N);
     H->lv.push_back(L);
@@ -445,27 +548,45 @@ std::unique_ptr<Hierarchy<R>> build_hierarchy(fde_handle* h) {
     ++l;
   }
   const int nlev = (int)H->lv.size();
-  H->lc = nlev - 1;
-  while (H->lc > 0 && std::max(H->lv[H->lc - 1].n1, H->lv[H->lc - 1].n2) <= kDirectMaxN) --H->lc;
-  if (nlev - H->lc > kMaxCoarseLevels) throw FdeError{FDE_EINVAL, "too many direct coarse levels"};
   CoarseView<R>& cv = H->cv;
-  cv.nlev = nlev - H->lc;
-  for (int k = 0; k < cv.nlev; ++k) {
-    const Level<R>& L = H->lv[H->lc + k];
-    cv.n1[k] = L.n1;
-    cv.n2[k] = L.n2;
-    cv.dpm[k] = L.dpm;
-    cv.epm[k] = L.epm;
-    cv.dinv[k] = L.dinv;
-    cv.swx[k] = L.swx;
-    cv.swy[k] = L.swy;
-  }
-  cv.nu_pre = p.nu_pre;
-  cv.nu_post = p.nu_post;
   const Level<R>& C = H->lv.back();
   H->Nc = C.n1 * C.n2;
   H->inv = dalloc<double>(m, (size_t)H->Nc * H->Nc);
-  HIPCHECK(launch_coarse_invert<R>(cv, H->inv, h->flags + 2, st));
+  if (galerkin) {
+    // the coarsest level is solved with the inverse of its dense Galerkin matrix
+    H->lc = nlev - 1;
+    cv.nlev = 1;
+    cv.n1[0] = C.n1;
+    cv.n2[0] = C.n2;
+    const int Hw = 1 << (nlev - 1);
+    std::vector<double> Qx = gal_Q(h->wa, H->lv[0].sx, Hw, C.n1, h->n1);
+    std::vector<double> Qy = gal_Q(h->wb, H->lv[0].sy, Hw, C.n2, h->n2);
+    DevAlloc tmp;
+    double* dQx = upload<double>(tmp, Qx, st);
+    double* dQy = upload<double>(tmp, Qy, st);
+    double* A = dalloc<double>(tmp, (size_t)H->Nc * H->Nc);
+    HIPCHECK(launch_gal_dense<R>(C.gv, dQx, dQy, A, st));
+    HIPCHECK(launch_coarse_invert<R>(cv, A, H->inv, h->flags + 2, st));
+    HIPCHECK(hipStreamSynchronize(st));  // tmp is freed on return
+  } else {
+    H->lc = nlev - 1;
+    while (H->lc > 0 && std::max(H->lv[H->lc - 1].n1, H->lv[H->lc - 1].n2) <= kDirectMaxN) --H->lc;
+    if (nlev - H->lc > kMaxCoarseLevels) throw FdeError{FDE_EINVAL, "too many direct coarse levels"};
+    cv.nlev = nlev - H->lc;
+    for (int k = 0; k < cv.nlev; ++k) {
+      const Level<R>& L = H->lv[H->lc + k];
+      cv.n1[k] = L.n1;
+      cv.n2[k] = L.n2;
+      cv.dpm[k] = L.dpm;
+      cv.epm[k] = L.epm;
+      cv.dinv[k] = L.dinv;
+      cv.swx[k] = L.swx;
+      cv.swy[k] = L.swy;
+    }
+    cv.nu_pre = p.nu_pre;
+    cv.nu_post = p.nu_post;
+    HIPCHECK(launch_coarse_invert<R>(cv, nullptr, H->inv, h->flags + 2, st));
+  }
   cv.inv = H->inv;
   int status = 0;
   HIPCHECK(hipMemcpyAsync(&status, h->flags + 2, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -501,6 +622,20 @@ void build_preconditioner(fde_handle* h) {
 }
 
 // ---- V-cycle ------------------------------------------------------------------------------------
+// out = A_l x, b_l - A_l x or the Jacobi update of x (mode), for any kind of level.
+template <typename R>
+void level_apply(fde_handle* h, Level<R>& L, const R* x, R* out, int mode, const int* skip) {
+  if (L.gal) {
+    const GalView<R>& g = L.gv;
+    const double nf = (double)g.nly * g.n0x + (double)g.n0y * g.nlx;  // fine-by-coarse points
+    const double by = (6.0 * nf + 4.0 * L.N()) * 2.0 * sizeof(R);
+    timed(h, FDE_KFAM_MGC_X, by,
+          [&] { return launch_gal_apply<R>(g, x, out, mode, L.b, skip, h->stream); });
+    return;
+  }
+  op_apply<R, R>(h, false, L.view(), x, L.ay, out, mode, L.b, nullptr, 0.0, skip);
+}
+
 // Returns the buffer that holds the level's result: x itself, or on direct levels possibly the
 // level's second iterate buffer (the direct kernel cannot update x in place, so successive sweeps
 // alternate between the two buffers instead of copying back).
@@ -508,12 +643,15 @@ template <typename R>
 R* vcycle_from(fde_handle* h, Hierarchy<R>& H, int l, R* x, const int* skip, bool x_ready) {
   hipStream_t st = h->stream;
   if (l >= H.lc) {
-    timed(h, FDE_KFAM_COARSE, 2.0 * H.lv[l].N() * sizeof(R),
-          [&] { return launch_coarse_vcycle<R>(H.cv, H.lv[l].b, x, skip, st); });
+    if (H.galerkin)
+      timed(h, FDE_KFAM_COARSE, 2.0 * H.lv[l].N() * sizeof(R) + (double)H.Nc * H.Nc * sizeof(double),
+            [&] { return launch_coarse_solve<R>(H.Nc, H.inv, H.lv[l].b, x, skip, st); });
+    else
+      timed(h, FDE_KFAM_COARSE, 2.0 * H.lv[l].N() * sizeof(R),
+            [&] { return launch_coarse_vcycle<R>(H.cv, H.lv[l].b, x, skip, st); });
     return x;
   }
   Level<R>& L = H.lv[l];
-  const OpView<R> op = L.view();
   const size_t N = L.N(), Nc = H.lv[l + 1].N();
   if (l > 0 && !x_ready) {
     if (h->p.nu_pre > 0)
@@ -522,19 +660,20 @@ R* vcycle_from(fde_handle* h, Hierarchy<R>& H, int l, R* x, const int* skip, boo
     else HIPCHECK(launch_fill<R>(N, x, R(0), st));
   }
   // One damped-Jacobi sweep on the current iterate.  The FFT row pass reads only its own rows and
-  // updates in place; the direct kernel reads whole columns and writes the other buffer.
+  // updates in place; the direct and Galerkin kernels read neighbouring rows and columns, so they
+  // write the other buffer.
   R* cur = x;
   auto jacobi_sweep = [&]() {
-    if (L.direct) {
-      R* nxt = (cur == x) ? L.x2 : x;
-      op_apply<R, R>(h, false, op, cur, L.ay, nxt, EP_JACOBI, L.b, nullptr, 0.0, skip);
-      cur = nxt;
+    if (L.in_place()) {
+      level_apply<R>(h, L, cur, cur, EP_JACOBI, skip);
     } else {
-      op_apply<R, R>(h, false, op, cur, L.ay, cur, EP_JACOBI, L.b, nullptr, 0.0, skip);
+      R* nxt = (cur == x) ? L.x2 : x;
+      level_apply<R>(h, L, cur, nxt, EP_JACOBI, skip);
+      cur = nxt;
     }
   };
   for (int it = 1; it < h->p.nu_pre; ++it) jacobi_sweep();
-  op_apply<R, R>(h, false, op, cur, L.ay, L.r, EP_RESID, L.b, nullptr, 0.0, skip);
+  level_apply<R>(h, L, cur, L.r, EP_RESID, skip);
   // the restriction also takes the coarse level's first sweep when that level smooths
   Level<R>& C = H.lv[l + 1];
   const bool fuse = (l + 1 < H.lc) && h->p.nu_pre > 0;
@@ -947,7 +1086,12 @@ int apply_hook(fde_handle* h, int level, const double* x, double* y, int mode, c
   R* xi = HookIO<R>::in(h, x, n, 0);
   const R* bi = b ? HookIO<R>::in(h, b, n, 1) : nullptr;
   R* res = std::is_same<R, double>::value ? reinterpret_cast<R*>(y) : L.x;
-  if (level >= H.lc) {
+  if (L.gal) {
+    // the Galerkin kernels read neighbouring rows and columns of x: out of place
+    R* tmp = reinterpret_cast<R*>(h->scratch64) + 2 * n;
+    HIPCHECK(launch_gal_apply<R>(L.gv, xi, tmp, mode, bi, nullptr, h->stream));
+    HIPCHECK(hipMemcpyAsync(res, tmp, n * sizeof(R), hipMemcpyDeviceToDevice, h->stream));
+  } else if (level >= H.lc) {
     const int k = level - H.lc;
     HIPCHECK(launch_direct_apply<R>(H.cv, k, xi, res, mode, bi, h->stream));
   } else {
@@ -1019,12 +1163,16 @@ int fde_level_diag(fde_handle* h, int level, double* diag) {
   return guarded(h, [&]() -> int {
     if (h->h64) {
       auto& L = h->h64->lv.at(level);
-      HIPCHECK(launch_diag<double>((int)L.N(), L.dpm, L.epm, L.sx * h->wa[1], L.sy * h->wb[1], h->p.omega, nullptr,
-                                   diag, h->stream));
+      if (L.gal) HIPCHECK(launch_gal_diag<double>(L.gv, L.qx, L.qy, h->p.omega, nullptr, diag, h->stream));
+      else
+        HIPCHECK(launch_diag<double>((int)L.N(), L.dpm, L.epm, L.sx * h->wa[1], L.sy * h->wb[1], h->p.omega,
+                                     nullptr, diag, h->stream));
     } else {
       auto& L = h->h32->lv.at(level);
-      HIPCHECK(launch_diag<float>((int)L.N(), L.dpm, L.epm, L.sx * h->wa[1], L.sy * h->wb[1], h->p.omega, nullptr,
-                                  diag, h->stream));
+      if (L.gal) HIPCHECK(launch_gal_diag<float>(L.gv, L.qx, L.qy, h->p.omega, nullptr, diag, h->stream));
+      else
+        HIPCHECK(launch_diag<float>((int)L.N(), L.dpm, L.epm, L.sx * h->wa[1], L.sy * h->wb[1], h->p.omega,
+                                    nullptr, diag, h->stream));
     }
     HIPCHECK(hipStreamSynchronize(h->stream));
     return FDE_OK;
@@ -1074,7 +1222,7 @@ int coarse_hook(fde_handle* h, const double* b, double* x) {
   Hierarchy<R>& H = hier<R>(h);
   R* bi = HookIO<R>::in(h, b, H.Nc, 0);
   R* xo = reinterpret_cast<R*>(h->scratch64 + h->N);
-  HIPCHECK(launch_coarse_solve<R>(H.Nc, H.inv, bi, xo, h->stream));
+  HIPCHECK(launch_coarse_solve<R>(H.Nc, H.inv, bi, xo, nullptr, h->stream));
   out64<R>(h, xo, x, H.Nc);
   HIPCHECK(hipStreamSynchronize(h->stream));
   return FDE_OK;

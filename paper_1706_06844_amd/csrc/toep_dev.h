@@ -1,0 +1,106 @@
+// Device helpers shared by the Toeplitz operator kernels (toeplitz.hip) and the Galerkin
+// coarse-operator kernels (galerkin.hip): symbol products, uniform pointers, launch shapes.
+#pragma once
+#include "common.h"
+#include "fft.h"
+
+// Minimum waves per SIMD the operator kernels are compiled for (register budget 256 at 2).
+#ifndef FDE_XW
+#define FDE_XW 2
+#endif
+#ifndef FDE_YW
+#define FDE_YW 2
+#endif
+
+// Transform lengths the launchers instantiate.
+#ifndef FDE_L_CASES
+#define FDE_L_CASES(MACRO) \
+  MACRO(16) MACRO(32) MACRO(64) MACRO(128) MACRO(256) MACRO(512) MACRO(1024) MACRO(2048) MACRO(4096)
+#endif
+
+namespace fde {
+
+// Only one spectrum is live in registers at a time; the second product waits in LDS:
+//   pass 1: (zr, zi) <- lam .* Z, inverse -> (T a, T b)
+//   pass 2: (pr, pi) <- conj(lam) .* Z, inverse -> (T^T a, T^T b)
+// Both symbol products from one read of the symbol: Z = (zr, zi) becomes lam * Z in registers and
+// conj(lam) * Z goes to zs (real parts zs[0, L), imaginary parts zs[L, 2L)), each thread at its own
+// positions t + T*m, so no barrier is needed before it reads them back.  Between the two inverse
+// transforms the partial results of the first take the second product's place in zs.
+template <int L, typename R>
+__device__ __forceinline__ void symbol_both(Reg<R, L>& zr, Reg<R, L>& zi, R* zs, const R* __restrict__ lam,
+                                            int t) {
+  constexpr int E = PlanFor<R, L>::E, T = PlanFor<R, L>::T;
+  static_for<0, E>([&](auto m) {
+    const int k = t + T * m;
+    const R lr = lam[2 * k], li = lam[2 * k + 1];
+    const R a = zr[m], b = zi[m];
+    zr[m] = lr * a - li * b;
+    zi[m] = lr * b + li * a;
+    zs[k] = lr * a + li * b;
+    zs[L + k] = lr * b - li * a;
+  });
+}
+
+template <int L, typename R>
+__device__ __forceinline__ void unstash(Reg<R, L>& pr, Reg<R, L>& pi, const R* zs, int t) {
+  constexpr int E = PlanFor<R, L>::E, T = PlanFor<R, L>::T;
+  static_for<0, E>([&](auto m) {
+    pr[m] = zs[t + T * m];
+    pi[m] = zs[L + t + T * m];
+  });
+}
+
+// A pointer that is the same for the whole wavefront, kept in scalar registers: loads then use a
+// scalar base plus a 32-bit per-lane offset instead of one 64-bit address per element.
+template <typename T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+  const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return reinterpret_cast<T*>(((unsigned long long)hi << 32) | lo);
+}
+
+// Runs f(m) for m = 0..E-1 in groups of G, with scheduling barriers between groups so that the
+// compiler does not hoist every group's global loads at once (which would exhaust registers).
+template <int E, int G0, class F>
+__device__ __forceinline__ void chunked_for(F&& f) {
+  constexpr int G = G0 < E ? G0 : E;
+  static_for<0, E / G>([&](auto gc) {
+    __builtin_amdgcn_sched_barrier(0);
+    static_for<0, G>([&](auto mc) { f(ic<decltype(gc)::value * G + decltype(mc)::value>{}); });
+  });
+  __builtin_amdgcn_sched_barrier(0);
+}
+#ifndef FDE_EPI_GROUP
+#define FDE_EPI_GROUP 16
+#endif
+constexpr int kEpiGroup = FDE_EPI_GROUP;
+
+// Row pairs (transforms) per workgroup of the row pass: short transforms share a wavefront.
+template <typename R, int L>
+struct XCfg {
+  static constexpr int S = PlanFor<R, L>::T >= 64 ? 1 : 64 / PlanFor<R, L>::T;
+  static constexpr int THREADS = PlanFor<R, L>::T * S;
+};
+
+#ifndef FDE_Y_THREADS
+#define FDE_Y_THREADS 512
+#endif
+#ifndef FDE_Y_COLS_PER_SLOT_L
+#define FDE_Y_COLS_PER_SLOT_L 1024
+#endif
+// Slots (transforms, two columns each) per workgroup of the column pass: adjacent columns make the
+// row reads of a workgroup contiguous, but too many slots leave CUs idle on the shorter levels.
+// Measured on gfx950: L/1024 slots (at least a full wavefront, at most 512 threads) is best for
+// L = 1024..4096.
+template <typename R, int L>
+struct YCfg {
+  static constexpr int T_ = PlanFor<R, L>::T;
+  static constexpr int SW = L / FDE_Y_COLS_PER_SLOT_L > 1 ? L / FDE_Y_COLS_PER_SLOT_L : 1;
+  static constexpr int S0 = SW > 64 / T_ ? SW : 64 / T_;
+  static constexpr int S = T_ * S0 <= FDE_Y_THREADS ? S0 : (T_ >= FDE_Y_THREADS ? 1 : FDE_Y_THREADS / T_);
+  static constexpr int THREADS = PlanFor<R, L>::T * S;
+};
+
+}  // namespace fde

@@ -22,69 +22,9 @@
 
 #include "common.h"
 #include "fft.h"
-
-// Minimum waves per SIMD the operator kernels are compiled for (register budget 256 at 2).
-#ifndef FDE_XW
-#define FDE_XW 2
-#endif
-#ifndef FDE_YW
-#define FDE_YW 2
-#endif
+#include "toep_dev.h"
 
 namespace fde {
-
-// The forward spectrum Z is stashed in LDS (zs: real parts then imaginary parts, natural order) so
-// that only one spectrum is live in registers at a time:
-//   pass 1: (zr, zi) <- lam .* Z, inverse -> (T a, T b)
-//   pass 2: (zr, zi) <- conj(lam) .* Z, inverse -> (T^T a, T^T b)
-// Between the passes the partial results of pass 1 take Z's place in LDS.
-template <int L, typename R>
-__device__ __forceinline__ void stash(const Reg<R, L>& zr, const Reg<R, L>& zi, R* zs, int t) {
-  constexpr int E = PlanFor<R, L>::E, T = PlanFor<R, L>::T;
-  static_for<0, E>([&](auto m) {
-    zs[t + T * m] = zr[m];
-    zs[L + t + T * m] = zi[m];
-  });
-}
-
-template <int L, int CONJ, typename R>
-__device__ __forceinline__ void symbol_times(Reg<R, L>& zr, Reg<R, L>& zi, const R* zs, const R* __restrict__ lam,
-                                             int t) {
-  constexpr int E = PlanFor<R, L>::E, T = PlanFor<R, L>::T;
-  static_for<0, E>([&](auto m) {
-    const int k = t + T * m;
-    const R lr = lam[2 * k], li = CONJ ? -lam[2 * k + 1] : lam[2 * k + 1];
-    const R a = zs[k], b = zs[L + k];
-    zr[m] = lr * a - li * b;
-    zi[m] = lr * b + li * a;
-  });
-}
-
-// A pointer that is the same for the whole wavefront, kept in scalar registers: loads then use a
-// scalar base plus a 32-bit per-lane offset instead of one 64-bit address per element.
-template <typename T>
-__device__ __forceinline__ T* uniform_ptr(T* p) {
-  const unsigned long long v = reinterpret_cast<unsigned long long>(p);
-  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
-  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
-  return reinterpret_cast<T*>(((unsigned long long)hi << 32) | lo);
-}
-
-// Runs f(m) for m = 0..E-1 in groups of G, with scheduling barriers between groups so that the
-// compiler does not hoist every group's global loads at once (which would exhaust registers).
-template <int E, int G0, class F>
-__device__ __forceinline__ void chunked_for(F&& f) {
-  constexpr int G = G0 < E ? G0 : E;
-  static_for<0, E / G>([&](auto gc) {
-    __builtin_amdgcn_sched_barrier(0);
-    static_for<0, G>([&](auto mc) { f(ic<decltype(gc)::value * G + decltype(mc)::value>{}); });
-  });
-  __builtin_amdgcn_sched_barrier(0);
-}
-#ifndef FDE_EPI_GROUP
-#define FDE_EPI_GROUP 16
-#endif
-constexpr int kEpiGroup = FDE_EPI_GROUP;
 
 // Epilogue at one point, MODE fixed at compile time.  l = x part + y part of tau/2 L x.
 template <int MODE, typename R, typename Tin>
@@ -95,13 +35,6 @@ __device__ __forceinline__ R epilogue_value(R l, Tin xv, R bv, R dv, double srcv
   else if constexpr (MODE == EP_JACOBI) return (R)xv + dv * (bv - (R)xv + l);
   else return (R)xv + l + (R)(tau * srcv);  // EP_RHS
 }
-
-// Row pairs (transforms) per workgroup of the row pass: short transforms share a wavefront.
-template <typename R, int L>
-struct XCfg {
-  static constexpr int S = PlanFor<R, L>::T >= 64 ? 1 : 64 / PlanFor<R, L>::T;
-  static constexpr int THREADS = PlanFor<R, L>::T * S;
-};
 
 template <typename R, typename Tin, int L, int MODE>
 __global__ __launch_bounds__((XCfg<R, L>::THREADS), FDE_XW) void toep_x_kernel(
@@ -136,11 +69,10 @@ __global__ __launch_bounds__((XCfg<R, L>::THREADS), FDE_XW) void toep_x_kernel(
     zi[m] = (hasB && i < n1) ? (R)xb[i] : R(0);
   });
   fft<L, -1>(zr, zi, lds, tw, t);
-  stash<L>(zr, zi, zs, t);
-  symbol_times<L, 0>(zr, zi, zs, mu, t);  // each thread reads back only what it wrote
-  fft<L, +1>(zr, zi, lds, tw, t);         // real part: T xa, imaginary part: T xb
+  symbol_both<L>(zr, zi, zs, mu, t);
+  fft<L, +1>(zr, zi, lds, tw, t);  // real part: T xa, imaginary part: T xb
   R pr[E], pi[E];
-  symbol_times<L, 1>(pr, pi, zs, mu, t);
+  unstash<L>(pr, pi, zs, t);
   chunked_for<E, kEpiGroup>([&](auto m) {
     const int i = t + T * m;
     zs[i] = (hasA && i < n1) ? dA[2 * i] * zr[m] : R(0);
@@ -179,25 +111,6 @@ __global__ __launch_bounds__((XCfg<R, L>::THREADS), FDE_XW) void toep_x_kernel(
   });
 }
 
-#ifndef FDE_Y_THREADS
-#define FDE_Y_THREADS 512
-#endif
-#ifndef FDE_Y_COLS_PER_SLOT_L
-#define FDE_Y_COLS_PER_SLOT_L 1024
-#endif
-// Slots (transforms, two columns each) per workgroup of the column pass: adjacent columns make the
-// row reads of a workgroup contiguous, but too many slots leave CUs idle on the shorter levels.
-// Measured on gfx950: L/1024 slots (at least a full wavefront, at most 512 threads) is best for
-// L = 1024..4096.
-template <typename R, int L>
-struct YCfg {
-  static constexpr int T_ = PlanFor<R, L>::T;
-  static constexpr int SW = L / FDE_Y_COLS_PER_SLOT_L > 1 ? L / FDE_Y_COLS_PER_SLOT_L : 1;
-  static constexpr int S0 = SW > 64 / T_ ? SW : 64 / T_;
-  static constexpr int S = T_ * S0 <= FDE_Y_THREADS ? S0 : (T_ >= FDE_Y_THREADS ? 1 : FDE_Y_THREADS / T_);
-  static constexpr int THREADS = PlanFor<R, L>::T * S;
-};
-
 template <typename R, typename Tin, int L>
 __global__ __launch_bounds__((YCfg<R, L>::THREADS), FDE_YW) void toep_y_kernel(
     int n1, int n2, const Tin* __restrict__ x, const R* __restrict__ epm, const R* __restrict__ mu,
@@ -229,11 +142,10 @@ __global__ __launch_bounds__((YCfg<R, L>::THREADS), FDE_YW) void toep_y_kernel(
     zi[m] = (row < n2 && v1) ? (R)x[p + 1] : R(0);
   });
   fft<L, -1>(zr, zi, lds, tw, t);
-  stash<L>(zr, zi, zs, t);
-  symbol_times<L, 0>(zr, zi, zs, mu, t);
+  symbol_both<L>(zr, zi, zs, mu, t);
   fft<L, +1>(zr, zi, lds, tw, t);  // T a + i T b along the columns
   R pr[E], pi[E];
-  symbol_times<L, 1>(pr, pi, zs, mu, t);
+  unstash<L>(pr, pi, zs, t);
   chunked_for<E, kEpiGroup>([&](auto m) {
     const int row = t + T * m;
     const unsigned p = (unsigned)row * (unsigned)n1 + (unsigned)c0;
@@ -298,10 +210,6 @@ static hipError_t launch_x(const OpView<R>& op, const Tin* x, const R* ay, R* ou
   }
 }
 
-#ifndef FDE_L_CASES
-#define FDE_L_CASES(MACRO) \
-  MACRO(16) MACRO(32) MACRO(64) MACRO(128) MACRO(256) MACRO(512) MACRO(1024) MACRO(2048) MACRO(4096)
-#endif
 
 bool fft_length_supported(int L) {
   switch (L) {
