@@ -62,7 +62,9 @@ def parse():
     ap.add_argument("--maxit", type=int, default=4000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=24)
-    ap.add_argument("--only", choices=["mixed", "fp64"], default=None)
+    ap.add_argument("--only", choices=["mixed", "fp64", "bf16"], default=None)
+    ap.add_argument("--bf16", action="store_true",
+                    help="also time the V-cycle with BF16 MFMA operator passes on its large levels")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy a 2047^2 FP64 field (33.5 MB) three times with torch, so that a "
                          "counter run sees a kernel of known traffic")
@@ -195,16 +197,18 @@ def main():
         torch.cuda.synchronize()
         log(f"copy calibration: 3 copies of {u0.numel() * 8} bytes")
     res = {}
-    order = [("mixed", fde.FDE_MIXED_FP32), ("fp64", fde.FDE_FP64)]
+    order = [("mixed", fde.FDE_MIXED_FP32), ("fp64", fde.FDE_FP64), ("bf16", fde.FDE_MIXED_BF16GEMM)]
     for name, prec in order:
         if args.only and args.only != name:
+            continue
+        if name == "bf16" and not (args.bf16 or args.only == "bf16"):
             continue
         log(f"{name}: {args.warmup} warmup + {args.steps} timed CN steps at {args.n}^2")
         res[name] = run_precision(prec, p, dev_fields, S, phis, u0, args.steps, args.warmup, args.maxit)
         r = res[name]
         log(f"{name}: {args.steps / r['elapsed']:.3f} steps/s, mean iters {np.mean(r['iters']):.1f}, "
             f"dominant {r['family']}")
-    main_name = "mixed" if "mixed" in res else "fp64"
+    main_name = "mixed" if "mixed" in res else ("fp64" if "fp64" in res else "bf16")
     m = res[main_name]
     lat_ms = np.array(m["lat"]) * 1e3
     live = m["live"]
@@ -222,12 +226,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64+f32" if main_name == "mixed" else "f64",
+        "dtype": {"mixed": "f64+f32", "fp64": "f64", "bf16": "f64+f32+bf16"}[main_name],
         "data": "synthetic",
         "config": {"workload": f"C3 anisotropic instance {args.n}x{args.n}, alpha=1.2, beta=1.9, "
                                "C2 variable coefficients, tau=1/16, manufactured + N(0,1) source "
                                "(seed 3)",
-                   "precision": "FP32 V-cycle in FP64 flexible GMRES" if main_name == "mixed" else "FP64",
+                   "precision": {"mixed": "FP32 V-cycle in FP64 flexible GMRES", "fp64": "FP64",
+                                 "bf16": "V-cycle with BF16 MFMA operator passes (FP32 accumulation) in FP64 "
+                                         "flexible GMRES"}[main_name],
                    "gmres": "GMRES(20), rtol 1e-10, x0 = 0", "multigrid": "geometric V(1,1), damped Jacobi 0.7"},
         "p50_ms": float(np.percentile(lat_ms, 50)),
         "p99_ms": float(np.percentile(lat_ms, 99)),
@@ -248,6 +254,14 @@ def main():
         du = (m["u"] - f["u"]).double()
         out["err_mixed_vs_fp64"] = float(torch.linalg.norm(du) / torch.linalg.norm(f["u"]))
         out["mixed_speedup_vs_fp64"] = out["value"] / out["fp64_value"]
+    if "bf16" in res and main_name != "bf16":
+        g = res["bf16"]
+        ref = res["fp64"]["u"] if "fp64" in res else m["u"]
+        out["bf16_value"] = args.steps / g["elapsed"]
+        out["bf16_ms_per_step"] = 1e3 * g["elapsed"] / args.steps
+        out["bf16_iters_per_step"] = float(np.mean(g["iters"]))
+        out["err_bf16_vs_fp64"] = float(torch.linalg.norm((g["u"] - ref).double()) / torch.linalg.norm(ref))
+        out["bf16_warm_profile_ms"] = {k: round(v["ms"], 3) for k, v in g["warm_profile"].items()}
     out["warm_profile_ms"] = {k: round(v["ms"], 3) for k, v in m["warm_profile"].items()}
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on a bounded sample")

@@ -164,6 +164,23 @@ hipError_t launch_gal_diag(const GalView<R>& g, const double* qx, const double* 
 template <typename R>
 hipError_t launch_gal_dense(const GalView<R>& g, const double* Qx, const double* Qy, double* A, hipStream_t st);
 
+// ---- BF16 MFMA operator passes (mfma.hip) ----------------------------------------------------------
+// Precomputed Toeplitz B fragments of one level: tx1/tx2 for the x factors (length n1, scale sx),
+// ty1/ty2 for the y factors; each mfma_table_entries(n) * 64 * 8 BF16 values.
+struct MfmaView {
+  int n1, n2;
+  const uint16_t* tx1;
+  const uint16_t* tx2;
+  const uint16_t* ty1;
+  const uint16_t* ty2;
+};
+int mfma_table_entries(int n);
+int mfma_table_omin(int n);
+void mfma_tables(const double* w, int n, double s, uint16_t* t1, uint16_t* t2);
+// ay = y part (BF16 products, FP32 accumulation), then out = epilogue(x part + ay); out != x.
+hipError_t launch_mfma_op(const MfmaView& v, const float* dpm, const float* epm, const float* x, float* ay,
+                          float* out, int mode, const float* b, const float* dinv, const int* skip, hipStream_t st);
+
 // ---- Krylov kernels (krylov.hip) ---------------------------------------------------------------
 constexpr int kMaxRestart = 32;
 // Device-resident state of one flexible GMRES solve.  The first block of fields is copied to the

@@ -87,10 +87,12 @@ struct Level {
   R* ay = nullptr;
   bool direct = false;
   bool gal = false;          // Galerkin level (factored form)
+  bool mfma = false;         // operator passes as BF16 MFMA products
+  MfmaView mv{};
   GalView<R> gv{};
   double* qx = nullptr;      // factor-times-hat tables of the Galerkin diagonal
   double* qy = nullptr;
-  bool in_place() const { return !direct && !gal; }
+  bool in_place() const { return !direct && !gal && !mfma; }
   OpView<R> view() const {
     OpView<R> v{};
     v.n1 = n1;
@@ -326,7 +328,6 @@ int validate(const fde_problem* p, std::string* why) {
   if (!(p->tau > 0.0) || !std::isfinite(p->tau)) return bad("tau must be positive and finite");
   if (p->precision < FDE_FP64 || p->precision > FDE_MIXED_BF16GEMM) return bad("unknown precision");
   if (p->mg_variant != FDE_MG_GEOMETRIC && p->mg_variant != FDE_MG_GALERKIN) return bad("unknown mg_variant");
-  if (p->precision == FDE_MIXED_BF16GEMM) return bad("the BF16 GEMM path is not available in this build");
   if (!(p->omega > 0.0 && p->omega <= 1.0)) return bad("omega must lie in (0,1]");
   if (p->nu_pre < 0 || p->nu_pre > 8 || p->nu_post < 0 || p->nu_post > 8) return bad("nu_pre/nu_post in 0..8");
   if (p->coarsest_n < 3) return bad("coarsest_n must be >= 3");
@@ -361,6 +362,15 @@ R* upload(DevAlloc& m, const std::vector<double>& v, hipStream_t st) {
   std::vector<R> t(v.begin(), v.end());
   HIPCHECK(hipMemcpyAsync(d, t.data(), t.size() * sizeof(R), hipMemcpyHostToDevice, st));
   HIPCHECK(hipStreamSynchronize(st));  // t goes out of scope
+  return d;
+}
+
+template <typename T>
+T* upload_raw(DevAlloc& m, const std::vector<T>& v, hipStream_t st) {
+  T* d = m.get<T>(v.size());
+  if (!d) throw FdeError{FDE_ENOMEM, "device allocation failed"};
+  HIPCHECK(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  HIPCHECK(hipStreamSynchronize(st));
   return d;
 }
 
@@ -535,6 +545,19 @@ std::unique_ptr<Hierarchy<R>> build_hierarchy(fde_handle* h) {
         L.tw_y = twiddles<R>(*H, m, L.L2, st);
       }
       if (!L.direct) L.ay = dalloc<R>(m, N);
+      if (std::is_same<R, float>::value && p.precision == FDE_MIXED_BF16GEMM && !L.direct) {
+        L.mfma = true;
+        L.mv.n1 = n1;
+        L.mv.n2 = n2;
+        const int ex = mfma_table_entries(n1), ey = mfma_table_entries(n2);
+        std::vector<uint16_t> t1((size_t)ex * 512), t2((size_t)ex * 512), u1((size_t)ey * 512), u2((size_t)ey * 512);
+        mfma_tables(h->wa.data(), n1, L.sx, t1.data(), t2.data());
+        mfma_tables(h->wb.data(), n2, L.sy, u1.data(), u2.data());
+        L.mv.tx1 = upload_raw(m, t1, st);
+        L.mv.tx2 = upload_raw(m, t2, st);
+        L.mv.ty1 = upload_raw(m, u1, st);
+        L.mv.ty2 = upload_raw(m, u2, st);
+      }
     }
     const bool coarse_one_wg = !galerkin && std::max(n1, n2) <= kDirectMaxN;
     if (!coarse_one_wg) L.r = dalloc<R>(m, N);
@@ -632,6 +655,17 @@ void level_apply(fde_handle* h, Level<R>& L, const R* x, R* out, int mode, const
     timed(h, FDE_KFAM_MGC_X, by,
           [&] { return launch_gal_apply<R>(g, x, out, mode, L.b, skip, h->stream); });
     return;
+  }
+  if constexpr (std::is_same<R, float>::value) {
+    if (L.mfma) {
+      // n^3 multiply-adds per direction (both factors of one direction together)
+      const double fl = 2.0 * std::pow((double)L.n1, 2) * L.n2 + 2.0 * std::pow((double)L.n2, 2) * L.n1;
+      const bool fine = L.n1 == h->n1 && L.n2 == h->n2;
+      timed(h, fine ? FDE_KFAM_MG0_X : FDE_KFAM_MGC_X, fl, [&] {
+        return launch_mfma_op(L.mv, L.dpm, L.epm, x, L.ay, out, mode, L.b, L.dinv, skip, h->stream);
+      });
+      return;
+    }
   }
   op_apply<R, R>(h, false, L.view(), x, L.ay, out, mode, L.b, nullptr, 0.0, skip);
 }
@@ -1086,10 +1120,14 @@ int apply_hook(fde_handle* h, int level, const double* x, double* y, int mode, c
   R* xi = HookIO<R>::in(h, x, n, 0);
   const R* bi = b ? HookIO<R>::in(h, b, n, 1) : nullptr;
   R* res = std::is_same<R, double>::value ? reinterpret_cast<R*>(y) : L.x;
-  if (L.gal) {
-    // the Galerkin kernels read neighbouring rows and columns of x: out of place
+  if (L.gal || L.mfma) {
+    // these kernels read neighbouring rows and columns of x: out of place
     R* tmp = reinterpret_cast<R*>(h->scratch64) + 2 * n;
-    HIPCHECK(launch_gal_apply<R>(L.gv, xi, tmp, mode, bi, nullptr, h->stream));
+    if (L.gal) {
+      HIPCHECK(launch_gal_apply<R>(L.gv, xi, tmp, mode, bi, nullptr, h->stream));
+    } else if constexpr (std::is_same<R, float>::value) {
+      HIPCHECK(launch_mfma_op(L.mv, L.dpm, L.epm, xi, L.ay, tmp, mode, bi, L.dinv, nullptr, h->stream));
+    }
     HIPCHECK(hipMemcpyAsync(res, tmp, n * sizeof(R), hipMemcpyDeviceToDevice, h->stream));
   } else if (level >= H.lc) {
     const int k = level - H.lc;
