@@ -63,6 +63,13 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=24)
     ap.add_argument("--only", choices=["mixed", "fp64", "bf16"], default=None)
+    ap.add_argument("--workload", choices=["c3", "c4", "c5"], default="c3",
+                    help="c3: the single 2047^2 instance (default, the headline line); c4: 64 batched "
+                         "instances; c5: served requests with Poisson arrivals")
+    ap.add_argument("--c5-count", type=int, default=60, help="measured requests (after 10 warm-up)")
+    ap.add_argument("--c5-kmax", type=int, default=10, help="largest grid 2^k - 1 of the served requests")
+    ap.add_argument("--c5-qps", type=str, default="auto",
+                    help="comma-separated arrival rates, or 'auto' for 50%% and 90%% of the saturation rate")
     ap.add_argument("--bf16", action="store_true",
                     help="also time the V-cycle with BF16 MFMA operator passes on its large levels")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -171,6 +178,201 @@ def cpu_baseline(p, iters_per_step, sample_iters):
             "host_cpus": os.cpu_count(), "cpu_model": model}
 
 
+def exp_terms(p):
+    """(coef, rate, fields) with phi_k(t) = coef_k exp(rate_k t) for the workload's source terms."""
+    import math
+
+    import workloads
+
+    phis, fields = workloads.source_terms(p)
+    coef, rate = [], []
+    for f in phis:
+        c0, c1 = float(f(0.0)), float(f(1.0))
+        coef.append(c0)
+        rate.append(math.log(c1 / c0) if c0 != 0.0 else 0.0)
+    return coef, rate, fields
+
+
+def host_request(p):
+    import workloads
+
+    coef, rate, fields = exp_terms(p)
+    return {"p": p, "F": [np.ascontiguousarray(f) for f in workloads.sample(p, 0.0)], "S": fields,
+            "u0": workloads.sample_u0(p), "coef": coef, "rate": rate}
+
+
+def admit(b, hr, precision, rtol, maxit):
+    import torch
+
+    from paper_1706_06844_amd import fde
+
+    p = hr["p"]
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda:0")
+    s = fde.fde_problem_default(p.alpha, p.beta, p.n1, p.n2, p.tau, precision=precision, rtol=rtol, maxit=maxit)
+    s.a1, s.b1, s.a2, s.b2 = p.a1, p.b1, p.a2, p.b2
+    F = [d(f) for f in hr["F"]]
+    return fde.fde_batch_admit(b, s, *F, d(hr["u0"]), p.M, 0.0, hr["coef"], hr["rate"], [d(f) for f in hr["S"]])
+
+
+def run_c4(args):
+    """64 uneven instances (n in {127,255,511}, 8 CN steps, mixed precision, rtol 1e-9) resident
+    together and stepped as one batch, against the same instances run one after another."""
+    import torch
+
+    import workloads
+    from paper_1706_06844_amd import fde
+
+    probs = workloads.config_c4_instances(64, 4, 8)
+    reqs = [host_request(p) for p in probs]
+    unknown_steps = sum(p.n1 * p.n2 * p.M for p in probs)
+    steps = sum(p.M for p in probs)
+    out = {}
+    for prec_name, prec in (("mixed", fde.FDE_MIXED_FP32), ("fp64", fde.FDE_FP64)):
+        # batched: admission (resident setup) outside the timed region
+        b = fde.fde_batch_create(200 << 30)
+        ids = [admit(b, r, prec, 1e-9, 2000) for r in reqs]
+        assert min(ids) >= 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while fde.fde_batch_step(b) > 0:
+            pass
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        finals, iters = {}, 0
+        for rid, p in zip(ids, probs):
+            u = torch.empty((p.n2, p.n1), dtype=torch.float64, device="cuda:0")
+            st, it = fde.fde_batch_poll(b, rid, u)
+            assert st == 1, (rid, st)
+            finals[rid] = u
+            iters += it
+        b.close()
+        # sequential: one resident instance at a time, same steps (setup outside the timed region)
+        ts = 0.0
+        maxdiff = 0.0
+        for rid, (r, p) in zip(ids, zip(reqs, probs)):
+            b1 = fde.fde_batch_create(200 << 30)
+            i1 = admit(b1, r, prec, 1e-9, 2000)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            while fde.fde_batch_step(b1) > 0:
+                pass
+            torch.cuda.synchronize()
+            ts += time.perf_counter() - t1
+            u = torch.empty((p.n2, p.n1), dtype=torch.float64, device="cuda:0")
+            fde.fde_batch_poll(b1, i1, u)
+            maxdiff = max(maxdiff, float((u - finals[rid]).abs().max()))
+            b1.close()
+        out[prec_name] = {"batched_s": tb, "sequential_s": ts, "iters": iters, "max_diff_alone_vs_mix": maxdiff}
+        log(f"c4 {prec_name}: batched {tb:.2f} s, one at a time {ts:.2f} s, {iters} iterations")
+    m = out["mixed"]
+    line = {
+        "metric": "C4 batched CN steps/s (64 uneven instances, mixed precision)",
+        "value": steps / m["batched_s"], "unit": "CN steps/s", "n_gpus": 1, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": "C4: 64 instances (seed 4), n in {127,255,511}, alpha,beta ~ U[1.1,1.9], "
+                               "c(1+ax+by^2) coefficients, tau=1/8, 8 CN steps, rtol 1e-9"},
+        "unknown_updates_per_s": unknown_steps / m["batched_s"],
+        "one_at_a_time_steps_per_s": steps / m["sequential_s"],
+        "batching_speedup": m["sequential_s"] / m["batched_s"],
+        "fp64_value": steps / out["fp64"]["batched_s"],
+        "fp64_one_at_a_time_steps_per_s": steps / out["fp64"]["sequential_s"],
+        "iters_mixed": m["iters"], "iters_fp64": out["fp64"]["iters"],
+        "max_abs_diff_alone_vs_mix": max(m["max_diff_alone_vs_mix"], out["fp64"]["max_diff_alone_vs_mix"]),
+    }
+    print(json.dumps(line), flush=True)
+
+
+def serve(reqs, prec, budget, warm):
+    """Continuous batching: requests join the batch as they arrive and memory allows; returns
+    per-request latencies (arrival -> result copied out) of the measured requests and the span."""
+    import torch
+
+    from paper_1706_06844_amd import fde
+
+    b = fde.fde_batch_create(budget)
+    pending = sorted(range(len(reqs)), key=lambda i: reqs[i]["arrival"])
+    queue, inflight, lat, done_t = [], {}, {}, {}
+    t_start = time.perf_counter()
+    while pending or queue or inflight:
+        now = time.perf_counter() - t_start
+        while pending and reqs[pending[0]]["arrival"] <= now:
+            queue.append(pending.pop(0))
+        while queue:
+            i = queue[0]
+            rid = admit(b, reqs[i]["hr"], prec, 1e-9, 4000)
+            if rid == fde.FDE_EAGAIN:
+                if not inflight:
+                    raise RuntimeError("a request does not fit the budget on its own")
+                break
+            inflight[rid] = i
+            queue.pop(0)
+        if not inflight:
+            if pending:
+                time.sleep(max(0.0, reqs[pending[0]]["arrival"] - (time.perf_counter() - t_start)))
+            continue
+        fde.fde_batch_step(b)
+        for rid, i in list(inflight.items()):
+            p = reqs[i]["hr"]["p"]
+            u = torch.empty((p.n2, p.n1), dtype=torch.float64, device="cuda:0")
+            st, _ = fde.fde_batch_poll(b, rid, u)
+            if st:
+                t = time.perf_counter() - t_start
+                lat[i] = t - reqs[i]["arrival"]
+                done_t[i] = t
+                del inflight[rid]
+    b.close()
+    meas = [i for i in range(len(reqs)) if i >= warm]
+    span = max(done_t[i] for i in meas) - min(reqs[i]["arrival"] for i in meas)
+    return [lat[i] for i in meas], span
+
+
+def run_c5(args):
+    """Served requests (Poisson arrivals, seed 5): n = 2^k - 1 with k uniform in 6..kmax, 8..128
+    steps each, mixed precision and plain FP64; solves/s, CN steps/s, p50/p99 latency."""
+    import workloads
+
+    warm = 10
+    count = warm + args.c5_count
+    ks = tuple(range(6, args.c5_kmax + 1))
+    base = workloads.config_c5_requests(1.0, count=count, seed=5, ks=ks)
+    hrs = [host_request(r.problem) for r in base]
+    gaps = np.diff([0.0] + [r.arrival for r in base])  # arrivals at qps 1; scaled per run
+    budget = 200 << 30
+
+    def reqs_at(qps):
+        t = np.cumsum(gaps) / qps
+        return [{"hr": hrs[i], "arrival": float(t[i])} for i in range(count)]
+
+    from paper_1706_06844_amd import fde
+
+    steps_meas = sum(hrs[i]["p"].M for i in range(warm, count))
+    # saturation: every request present at t = 0
+    lat0, span0 = serve(reqs_at(1e9), fde.FDE_MIXED_FP32, budget, warm)
+    sat = args.c5_count / span0
+    log(f"c5 saturation: {sat:.3f} solves/s")
+    rates = [0.5 * sat, 0.9 * sat] if args.c5_qps == "auto" else [float(q) for q in args.c5_qps.split(",")]
+    runs = []
+    for qps in rates:
+        for name, prec in (("mixed", fde.FDE_MIXED_FP32), ("fp64", fde.FDE_FP64)):
+            lat, span = serve(reqs_at(qps), prec, budget, warm)
+            lat_ms = np.array(lat) * 1e3
+            runs.append({"qps": qps, "precision": name, "solves_per_s": args.c5_count / span,
+                         "cn_steps_per_s": steps_meas / span, "p50_ms": float(np.percentile(lat_ms, 50)),
+                         "p99_ms": float(np.percentile(lat_ms, 99))})
+            log(f"c5 qps {qps:.3f} {name}: {runs[-1]}")
+    hi = [r for r in runs if r["precision"] == "mixed"][-1]
+    line = {
+        "metric": "C5 served solves/s with p50/p99 latency (continuous batching, mixed vs FP64)",
+        "value": hi["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": f"C5: Poisson arrivals (seed 5), {args.c5_count} measured requests after "
+                               f"{warm} warm-up, n = 2^k - 1 with k in 6..{args.c5_kmax}, 8..128 CN "
+                               "steps each (tau = 1/M), rtol 1e-9"},
+        "saturation_solves_per_s": sat, "saturation_cn_steps_per_s": steps_meas / span0, "runs": runs,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -184,6 +386,10 @@ def main():
     from paper_1706_06844_amd import fde
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "c4":
+        return run_c4(args)
+    if args.workload == "c5":
+        return run_c5(args)
     p = workloads.config_c3(args.n, 16)
     d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda:0")
     dev_fields = [d(f) for f in workloads.sample(p, 0.0)]

@@ -183,6 +183,55 @@ int fde_profile_reset(fde_handle* h);
 /* Synchronises the handle's stream; returns FDE_EDEVICE if an asynchronous error occurred. */
 int fde_sync(fde_handle* h);
 
+/* ---- batching and serving ---------------------------------------------------------------------
+ * A batch owns independent CN time-stepping requests (the recursion of eq. (CNWSGD)/(system), each
+ * request with its own sizes, orders, coefficients and source), resident on the device and advanced
+ * together: every request has its own stream, its restart cycles are replayed from a captured HIP
+ * graph, and the host never blocks on one request while others can run.  Requests are admitted
+ * against a device-memory budget (bytes); one that does not fit returns FDE_EAGAIN and can be
+ * retried after others leave.  A request runs exactly the kernels it would run alone, in the same
+ * order, so its result does not depend on the mix.  A batch is used from one host thread.
+ */
+typedef struct fde_batch fde_batch;
+
+/* Device bytes a solver handle for problem *p needs while resident (hierarchy, Krylov storage,
+ * fields); 0 if *p is invalid.  A batch request needs (2 + nsrc) * n1 * n2 * 8 bytes more. */
+size_t fde_footprint(const fde_problem* p);
+
+/* Creates an empty batch with a device-memory budget; `stream` is unused (every request gets a
+ * stream of its own).  FDE_EINVAL if out is NULL. */
+int fde_batch_create(size_t budget_bytes, void* stream, fde_batch** out);
+void fde_batch_destroy(fde_batch* b);
+
+/* Admits a request: problem *p (as for fde_setup), coefficient fields (copied), initial field u0
+ * (device, copied), nsteps CN steps from t0, and a separable source sum_k phi_k(t) S_k with
+ * phi_k(t) = coef[k] * exp(rate[k] * t) evaluated at the half steps (nsrc <= 4; coef, rate host
+ * arrays; S host array of device fields, copied).  Blocks until the request is resident.  Returns
+ * a request id >= 0, FDE_EAGAIN if it does not fit the budget, or an error code. */
+int fde_batch_admit(fde_batch* b, const fde_problem* p, const double* dp, const double* dm,
+                    const double* ep, const double* em, const double* u0, int32_t nsteps,
+                    double t0, int32_t nsrc, const double* coef, const double* rate,
+                    const double* const* S);
+
+/* Makes progress on every active request (starting steps, issuing restart cycles) and returns once
+ * at least one CN step has completed somewhere, or when no request is active.  Returns the number
+ * of requests still stepping (>= 0) or an error.  Requests may be admitted between calls. */
+int fde_batch_step(fde_batch* b);
+
+/* Status of request id: 1 finished, 2 finished but some steps stopped at the iteration limit (their
+ * last iterates were kept), 0 still stepping, < 0 an error (unknown id: FDE_EINVAL; a failed
+ * request returns its error code once and is released).  With u_out (device, n1*n2 FP64) a finished
+ * request's final field is copied out and the request is released.  iters_out (host, may be NULL)
+ * receives the GMRES iterations so far. */
+int fde_batch_poll(fde_batch* b, int id, double* u_out, int64_t* iters_out);
+
+/* Cancels a request (waiting for its in-flight work) and releases its memory. */
+int fde_batch_cancel(fde_batch* b, int id);
+
+/* Number of requests still stepping and the budgeted bytes in use. */
+int fde_batch_info(const fde_batch* b, int32_t* active, size_t* bytes_in_use);
+
+
 #ifdef __cplusplus
 }
 #endif

@@ -214,6 +214,16 @@ struct fde_handle {
   double* scratch64 = nullptr;  // 4N FP64 for test hooks
   int cgs_grid = 1;
   int expected_iters = 0;
+  // asynchronous solves (batch engine): one restart cycle per issue, optionally as a captured graph
+  struct Async {
+    bool active = false;
+    int cycles = 0;
+    bool use_graph = true;
+    double* xsol = nullptr;  // solution of the current solve (fixed address, so graphs can bake it in)
+    hipEvent_t ev = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+  } as;
   Prof prof;
   std::string err;
   bool fp32() const { return p.precision != FDE_FP64; }
@@ -635,8 +645,11 @@ void load_outer(fde_handle* h, Outer& o, const double* dp, const double* dm, con
   HIPCHECK(launch_interleave<double>(h->N, ep, em, o.epm, h->stream));
 }
 
+void drop_graph(fde_handle* h);
+
 void build_preconditioner(fde_handle* h) {
   HIPCHECK(hipStreamSynchronize(h->stream));
+  drop_graph(h);
   h->h64.reset();
   h->h32.reset();
   h->hier_mem.reset();
@@ -832,6 +845,183 @@ int solve_impl(fde_handle* h, const double* b, double* x, fde_stats* stats) {
 }
 
 template <typename F>
+int guarded(fde_handle* h, F&& f);
+
+// ---- asynchronous solves -------------------------------------------------------------------------
+// The solve of h->rhs into h->as.xsol as a sequence of restart cycles, each issued without waiting:
+// restart Arnoldi steps (skipped on the device once the cycle is done), x += Z y, the FP64 true
+// residual and its norm.  The pointers are fixed, so the cycle is captured once as a HIP graph and
+// replayed.  Results equal those of fde_solve: the same kernels run in the same order.
+template <typename R>
+void cycle_body(fde_handle* h, Hierarchy<R>& H) {
+  const size_t N = h->N;
+  for (int j = 0; j < h->p.restart; ++j) arnoldi_step<R>(h, H, j);
+  HIPCHECK(launch_update_x<R>(N, static_cast<const R*>(h->Z), N, h->as.xsol, 0, h->st, h->stream));
+  const OpView<double> op = h->cur.view(h->tw64_x, h->tw64_y, h->n1, h->n2, h->L1, h->L2);
+  op_apply<double, double>(h, true, op, h->as.xsol, h->ay64, h->V, EP_RESID, h->rhs, nullptr, 0.0, nullptr);
+  HIPCHECK(launch_cgs_pass(CGS_RESNORM, N, 0, h->V, h->ldv, h->V, nullptr, h->st, h->partials, h->cgs_grid,
+                           h->stream));
+}
+
+void issue_cycle(fde_handle* h) {
+  auto body = [&] {
+    if (h->fp32()) cycle_body<float>(h, *h->h32);
+    else cycle_body<double>(h, *h->h64);
+  };
+  if (h->as.use_graph && !h->prof.mask) {
+    if (!h->as.gexec) {
+      HIPCHECK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+      try {
+        body();
+      } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(h->stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      HIPCHECK(hipStreamEndCapture(h->stream, &h->as.graph));
+      HIPCHECK(hipGraphInstantiate(&h->as.gexec, h->as.graph, nullptr, nullptr, 0));
+    }
+    HIPCHECK(hipGraphLaunch(h->as.gexec, h->stream));
+  } else {
+    body();
+  }
+  HIPCHECK(hipMemcpyAsync(h->st_host, h->st, offsetof(GmresState, rtol), hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(hipEventRecord(h->as.ev, h->stream));
+}
+
+// Graphs bake in the hierarchy's buffers: drop them when the hierarchy is rebuilt.
+void drop_graph(fde_handle* h) {
+  if (h->as.gexec) (void)hipGraphExecDestroy(h->as.gexec);
+  if (h->as.graph) (void)hipGraphDestroy(h->as.graph);
+  h->as.gexec = nullptr;
+  h->as.graph = nullptr;
+}
+
+}  // namespace
+
+namespace fde {
+
+int async_step_start(fde_handle* h, const double* u_prev, int nsrc, const double* phi, const double* const* S) {
+  if (!h || !u_prev) return set_err(h, FDE_EINVAL, "bad arguments");
+  if (h->as.active) return set_err(h, FDE_EINVAL, "a step is already in flight");
+  if (nsrc < 0 || nsrc > kMaxSrc || (nsrc > 0 && (!phi || !S))) return set_err(h, FDE_EINVAL, "bad source list");
+  return guarded(h, [&]() -> int {
+    SrcTerms src{};
+    src.n = nsrc;
+    for (int k = 0; k < nsrc; ++k) {
+      if (!S[k]) throw FdeError{FDE_EINVAL, "source field is NULL"};
+      src.phi[k] = phi[k];
+      src.S[k] = S[k];
+    }
+    const size_t N = h->N;
+    if (!h->as.xsol) h->as.xsol = dalloc<double>(h->mem, N);
+    if (!h->as.ev) HIPCHECK(hipEventCreateWithFlags(&h->as.ev, hipEventDisableTiming));
+    const OpView<double> op = h->prev.view(h->tw64_x, h->tw64_y, h->n1, h->n2, h->L1, h->L2);
+    op_apply<double, double>(h, true, op, u_prev, h->ay64, h->rhs, EP_RHS, nullptr, &src, h->p.tau, nullptr);
+    HIPCHECK(launch_fill<double>(N, h->as.xsol, 0.0, h->stream));
+    HIPCHECK(launch_cgs_pass(CGS_INIT, N, 0, h->V, h->ldv, h->V, h->rhs, h->st, h->partials, h->cgs_grid,
+                             h->stream));
+    h->as.cycles = 0;
+    h->as.active = true;
+    issue_cycle(h);
+    return FDE_OK;
+  });
+}
+
+int async_poll(fde_handle* h, int* finished, fde_stats* stats) {
+  if (!h || !finished) return set_err(h, FDE_EINVAL, "bad arguments");
+  *finished = 0;
+  if (!h->as.active) return set_err(h, FDE_EINVAL, "no step in flight");
+  const hipError_t q = hipEventQuery(h->as.ev);
+  if (q == hipErrorNotReady) return FDE_OK;
+  if (q != hipSuccess) {
+    h->as.active = false;
+    return set_err(h, FDE_EDEVICE, hipGetErrorString(q));
+  }
+  return guarded(h, [&]() -> int {
+    const GmresState s = *h->st_host;
+    ++h->as.cycles;
+    const bool bad = !std::isfinite(s.resnorm);
+    if (!(s.conv || s.iters >= h->p.maxit || bad)) {
+      issue_cycle(h);
+      return FDE_OK;
+    }
+    h->as.active = false;
+    *finished = 1;
+    if (stats) {
+      stats->iters = s.iters;
+      stats->restarts = h->as.cycles - 1;
+      stats->converged = s.conv;
+      stats->reorth_steps = s.nreorth;
+      stats->relres_true = s.bnorm > 0 ? s.resnorm / s.bnorm : 0.0;
+      stats->relres_est = s.bnorm > 0 ? s.est / s.bnorm : 0.0;
+    }
+    if (bad) return set_err(h, FDE_ENONFINITE, "the iterate became non-finite");
+    if (!s.conv) return set_err(h, FDE_ENOCONV, "iteration limit reached before the tolerance");
+    return FDE_OK;
+  });
+}
+
+const double* async_result(const fde_handle* h) { return h ? h->as.xsol : nullptr; }
+
+// Device bytes of a handle for problem p (defaults filled), following the allocations of fde_setup,
+// the hierarchy build and the asynchronous solve; 0 if p is invalid.
+size_t footprint_bytes(const fde_problem* pin) {
+  if (!pin) return 0;
+  fde_problem p = *pin;
+  fill_defaults(&p);
+  std::string why;
+  if (validate(&p, &why) != FDE_OK) return 0;
+  const bool f32 = p.precision != FDE_FP64;
+  const double R = f32 ? 4.0 : 8.0;
+  const double N = (double)p.n1 * p.n2;
+  const int L1 = 2 * (p.n1 + 1), L2 = 2 * (p.n2 + 1);
+  double b = 0;
+  b += 4 * N * 8;                                   // outer coefficient pairs
+  b += 2.0 * (L1 + L2) * 8 + 4.0 * (L1 + L2) * 8;   // symbols, twiddles
+  b += (1 + 1 + 4 + 1) * N * 8;                     // ay64, rhs, scratch, async solution
+  b += (p.restart + 1.0) * (double)basis_ld((size_t)N) * 8 + p.restart * N * R;
+  b += (double)cgs_partials_len((size_t)N) * 8 + sizeof(GmresState) + 4096;
+  const bool gal = p.mg_variant == FDE_MG_GALERKIN && std::min(p.n1, p.n2) > p.coarsest_n;
+  int a1 = p.n1, a2 = p.n2, l = 0;
+  double galscratch = 0;
+  while (true) {
+    const double Nl = (double)a1 * a2;
+    const bool direct = std::max(a1, a2) <= kDirectOpMax;
+    const bool one_wg = !gal && std::max(a1, a2) <= kDirectMaxN;
+    if (gal && l > 0) {
+      b += 4.0 * a2 * p.n1 * R + 4.0 * p.n2 * a1 * R + 2.0 * Nl * R;  // fields, dinv, qx/qy (small)
+      if (galscratch == 0) galscratch = (2.0 * a2 * p.n1 + 2.0 * p.n2 * a1) * R;
+    } else {
+      if (l > 0 || f32) b += 4 * Nl * R;
+      b += Nl * R;
+      if (!direct || (gal && l == 0)) b += 4.0 * (2 * (a1 + 1) + 2 * (a2 + 1)) * R;
+      if (!direct) b += Nl * R;
+      if (f32 && p.precision == FDE_MIXED_BF16GEMM && !direct)
+        b += 2.0 * 1024 * (mfma_table_entries(a1) + mfma_table_entries(a2));
+    }
+    if (!one_wg) b += 2 * Nl * R;  // r, second iterate
+    b += 2 * Nl * R;               // b, x
+    if (std::min(a1, a2) <= p.coarsest_n) break;
+    a1 = (a1 - 1) / 2;
+    a2 = (a2 - 1) / 2;
+    ++l;
+  }
+  b += galscratch;
+  b += (double)a1 * a2 * a1 * a2 * 8;  // coarsest inverse
+  return (size_t)(b * 1.05) + ((size_t)8 << 20);
+}
+hipStream_t handle_stream(const fde_handle* h) { return h ? h->stream : nullptr; }
+void async_use_graph(fde_handle* h, bool on) {
+  if (h) h->as.use_graph = on;
+}
+
+}  // namespace fde
+
+namespace {
+
+template <typename F>
 int guarded(fde_handle* h, F&& f) {
   try {
     return f();
@@ -959,6 +1149,9 @@ void fde_destroy(fde_handle* h) {
   if (!h) return;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   else (void)hipDeviceSynchronize();
+  if (h->as.gexec) (void)hipGraphExecDestroy(h->as.gexec);
+  if (h->as.graph) (void)hipGraphDestroy(h->as.graph);
+  if (h->as.ev) (void)hipEventDestroy(h->as.ev);
   if (h->st_host) (void)hipHostFree(h->st_host);
   delete h;
 }

@@ -187,3 +187,85 @@ def fde_profile_read(h: Handle) -> Dict[str, Dict]:
         _check(_lib().fde_profile_read(h.ptr, k, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)), h)
         out[name] = {"launches": n.value, "ms": ms.value, "bytes": by.value}
     return out
+
+
+# ---- batching and serving --------------------------------------------------------------------------
+def fde_footprint(problem: fde_problem) -> int:
+    return int(_lib().fde_footprint(ctypes.byref(problem)))
+
+
+class Batch:
+    """Owns an fde_batch; destroyed with fde_batch_destroy."""
+
+    def __init__(self, ptr: int, budget: int):
+        self.ptr = ptr
+        self.budget = budget
+        self._keep = {}
+
+    def close(self):
+        if self.ptr:
+            _lib().fde_batch_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fde_batch_create(budget_bytes: int, stream=None) -> Batch:
+    out = ctypes.c_void_p()
+    rc = _lib().fde_batch_create(ctypes.c_size_t(budget_bytes), _stream_ptr(stream), ctypes.byref(out))
+    _check(rc)
+    return Batch(out.value, budget_bytes)
+
+
+def fde_batch_destroy(b: Batch) -> None:
+    b.close()
+
+
+def fde_batch_admit(b: Batch, problem: fde_problem, dp, dm, ep, em, u0, nsteps: int, t0: float = 0.0,
+                    coef: Sequence[float] = (), rate: Sequence[float] = (),
+                    fields: Sequence[torch.Tensor] = ()) -> int:
+    """Returns the request id (>= 0) or FDE_EAGAIN (the request does not fit the budget now)."""
+    n = len(fields)
+    if len(coef) != n or len(rate) != n:
+        raise ValueError("coef, rate and fields must have the same length")
+    c = (ctypes.c_double * max(n, 1))(*coef)
+    r = (ctypes.c_double * max(n, 1))(*rate)
+    S = (ctypes.c_void_p * max(n, 1))(*[_ptr(f, "source") for f in fields])
+    rc = _lib().fde_batch_admit(b.ptr, ctypes.byref(problem), _ptr(dp, "dp"), _ptr(dm, "dm"), _ptr(ep, "ep"),
+                                _ptr(em, "em"), _ptr(u0, "u0"), int(nsteps), float(t0), n, c, r, S)
+    if rc == FDE_EAGAIN:
+        return rc
+    if rc < 0:
+        raise FdeError(rc, "fde_batch_admit failed")
+    return rc
+
+
+def fde_batch_step(b: Batch) -> int:
+    rc = _lib().fde_batch_step(b.ptr)
+    if rc < 0:
+        raise FdeError(rc, "fde_batch_step failed")
+    return rc
+
+
+def fde_batch_poll(b: Batch, rid: int, u_out=None):
+    """(status, iterations): status 1 finished, 2 finished with steps at the iteration limit,
+    0 still stepping; raises on errors."""
+    it = ctypes.c_int64()
+    rc = _lib().fde_batch_poll(b.ptr, rid, _ptr(u_out, "u_out"), ctypes.byref(it))
+    if rc < 0:
+        raise FdeError(rc, f"request {rid} failed")
+    return rc, it.value
+
+
+def fde_batch_cancel(b: Batch, rid: int) -> None:
+    _check(_lib().fde_batch_cancel(b.ptr, rid))
+
+
+def fde_batch_info(b: Batch):
+    a, by = ctypes.c_int32(), ctypes.c_size_t()
+    _check(_lib().fde_batch_info(b.ptr, ctypes.byref(a), ctypes.byref(by)))
+    return a.value, by.value

@@ -39,3 +39,38 @@ def rel(a, b):
 def note(msg):
     print(msg, flush=True)
     sys.stdout.flush()
+
+
+def exp_source_terms(p):
+    """Source terms of p as (coef, rate, fields) with phi_k(t) = coef_k exp(rate_k t); the problems'
+    time factors are exponentials (or constants), recovered from their values at t = 0 and 1."""
+    import math
+
+    phis, fields = workloads.source_terms(p)
+    coef, rate = [], []
+    for f in phis:
+        c0, c1 = float(f(0.0)), float(f(1.0))
+        coef.append(c0)
+        rate.append(math.log(c1 / c0) if c0 != 0.0 else 0.0)
+    return coef, rate, fields
+
+
+def solo_run(p, steps, precision=fde.FDE_FP64, **kw):
+    """The reference for batched runs: fde_step_sources step by step on one handle."""
+    import math
+
+    h = make_handle(p, precision, **kw)
+    coef, rate, fields = exp_source_terms(p)
+    S = [dev(f) for f in fields]
+    u = dev(workloads.sample_u0(p))
+    un = torch.empty_like(u)
+    iters = 0
+    for m in range(1, steps + 1):
+        t = (m - 0.5) * p.tau
+        phi = [c * math.exp(r * t) for c, r in zip(coef, rate)]
+        st = fde.fde_step_sources(h, u, phi, S, un)
+        iters += st["iters"]
+        u, un = un, u
+    out = host(u)
+    h.close()
+    return out, iters

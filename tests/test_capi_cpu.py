@@ -88,3 +88,30 @@ def test_null_handle_calls_fail_cleanly(lib):
     assert lib.fde_step(None, None, None, None, None) == L.FDE_EINVAL
     assert lib.fde_num_levels(None) == L.FDE_EINVAL
     lib.fde_destroy(None)
+
+
+def test_footprint_and_budget_admission_on_host():
+    import ctypes
+
+    from paper_1706_06844_amd import _lib as L
+    from paper_1706_06844_amd import fde
+
+    lib = L.load()
+    small = fde.fde_problem_default(1.5, 1.5, 127, 127, 0.01)
+    big = fde.fde_problem_default(1.5, 1.5, 2047, 2047, 0.01)
+    fs, fb = fde.fde_footprint(small), fde.fde_footprint(big)
+    assert 0 < fs < fb
+    # FP64 C3: outer fields, 21 basis vectors, 20 FP64 preconditioned vectors, hierarchy
+    assert 1.0e9 < fb < 4.0e9
+    bad = fde.fde_problem_default(2.5, 1.5, 127, 127, 0.01)
+    assert fde.fde_footprint(bad) == 0
+    # a request that does not fit is refused before any device memory is touched
+    out = ctypes.c_void_p()
+    assert lib.fde_batch_create(ctypes.c_size_t(fs // 2), None, ctypes.byref(out)) == 0
+    fake = ctypes.c_void_p(0x1000)
+    rc = lib.fde_batch_admit(out, ctypes.byref(small), fake, fake, fake, fake, fake, 4, 0.0, 0, None, None, None)
+    assert rc == L.FDE_EAGAIN
+    active, used = ctypes.c_int32(), ctypes.c_size_t()
+    assert lib.fde_batch_info(out, ctypes.byref(active), ctypes.byref(used)) == 0
+    assert active.value == 0 and used.value == 0
+    lib.fde_batch_destroy(out)
