@@ -7,10 +7,13 @@
 // preconditioner, restart 20, zero initial guess) for the solver.
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/fde.h"
@@ -410,6 +413,69 @@ std::vector<double> symbol_host(const std::vector<double>& w, int n, int L, doub
   return out;
 }
 
+// ---- autotuner -------------------------------------------------------------------------------
+// The operator of a level can run as the dense-Toeplitz kernel (one launch, O(n) work per point) or
+// as the two FFT passes (O(log n) per point, more launches and transform overhead).  Which is faster
+// depends on the size and the precision, so levels whose larger side lies in (kDirectMaxN,
+// kDirectTuneMax] are timed both ways the first time their shape occurs in the process, and the
+// faster one is kept for every later hierarchy (FDE_AUTOTUNE=0 keeps the static size rule).
+constexpr int kDirectTuneMax = 511;
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, bool> g_tune_direct;
+
+// True if the level has to be timed now; otherwise *direct holds the cached or static choice.
+bool tune_level(int n1, int n2, int bytes, bool* direct) {
+  const int mx = std::max(n1, n2);
+  if (mx <= kDirectMaxN || mx > kDirectTuneMax) return false;
+  const char* e = std::getenv("FDE_AUTOTUNE");
+  if (e && e[0] == '0') return false;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune_direct.find({n1, n2, bytes});
+  if (it == g_tune_direct.end()) return true;
+  *direct = it->second;
+  return false;
+}
+
+template <typename R>
+bool time_direct_vs_fft(fde_handle* h, Level<R>& L) {
+  hipStream_t st = h->stream;
+  const size_t N = L.N();
+  R* x = reinterpret_cast<R*>(h->scratch64);  // the fine-level scratch holds 4 fine FP64 fields
+  R* y = x + N;
+  HIPCHECK(launch_fill<R>(N, x, R(0.5), st));
+  hipEvent_t a, b;
+  HIPCHECK(hipEventCreate(&a));
+  HIPCHECK(hipEventCreate(&b));
+  auto run = [&](bool direct) {
+    L.direct = direct;
+    const OpView<R> v = L.view();
+    if (direct)
+      HIPCHECK((launch_direct_op<R, R>(L.n1, L.n2, x, L.dpm, L.epm, L.swx, L.swy, y, EP_APPLY, nullptr, L.dinv,
+                                       nullptr, 0.0, nullptr, st)));
+    else
+      HIPCHECK((launch_operator<R, R>(v, x, L.ay, y, EP_APPLY, nullptr, nullptr, 0.0, nullptr, st)));
+  };
+  float best[2] = {1e30f, 1e30f};
+  for (int d = 0; d < 2; ++d) {
+    run(d == 1);  // warm-up
+    for (int r = 0; r < 5; ++r) {
+      HIPCHECK(hipEventRecord(a, st));
+      run(d == 1);
+      HIPCHECK(hipEventRecord(b, st));
+      HIPCHECK(hipEventSynchronize(b));
+      float ms = 0.f;
+      HIPCHECK(hipEventElapsedTime(&ms, a, b));
+      best[d] = std::min(best[d], ms);
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  const bool direct = best[1] < best[0];
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_direct[{L.n1, L.n2, (int)sizeof(R)}] = direct;
+  return direct;
+}
+
 // Composite hat of half-width H at offset d (the 1-D factor of P_1 ... P_l, bilinear).
 double hat_w(int d, int H) {
   const int a = d < 0 ? -d : d;
@@ -539,7 +605,8 @@ std::unique_ptr<Hierarchy<R>> build_hierarchy(fde_handle* h) {
       L.dinv = dalloc<R>(m, N);
       HIPCHECK(launch_diag<R>((int)N, L.dpm, L.epm, L.sx * h->wa[1], L.sy * h->wb[1], p.omega, L.dinv, nullptr, st));
       L.direct = std::max(n1, n2) <= kDirectOpMax;
-      if (L.direct) {
+      const bool tune = !galerkin && tune_level(n1, n2, (int)sizeof(R), &L.direct);
+      if (L.direct || tune) {
         std::vector<double> sx(n1 + 1), sy(n2 + 1);
         for (int k = 0; k <= n1; ++k) sx[k] = L.sx * h->wa[k];
         for (int k = 0; k <= n2; ++k) sy[k] = L.sy * h->wb[k];
@@ -548,13 +615,14 @@ std::unique_ptr<Hierarchy<R>> build_hierarchy(fde_handle* h) {
       }
       // FFT levels need symbols and twiddles; so does the fine level of a Galerkin hierarchy, whose
       // transforms every coarse level reuses
-      if (!L.direct || (galerkin && l == 0)) {
+      if (!L.direct || tune || (galerkin && l == 0)) {
         L.lam_x = upload<R>(m, symbol_host(h->wa, n1, L.L1, L.sx), st);
         L.lam_y = upload<R>(m, symbol_host(h->wb, n2, L.L2, L.sy), st);
         L.tw_x = twiddles<R>(*H, m, L.L1, st);
         L.tw_y = twiddles<R>(*H, m, L.L2, st);
       }
-      if (!L.direct) L.ay = dalloc<R>(m, N);
+      if (!L.direct || tune) L.ay = dalloc<R>(m, N);
+      if (tune) L.direct = time_direct_vs_fft<R>(h, L);
       if (std::is_same<R, float>::value && p.precision == FDE_MIXED_BF16GEMM && !L.direct) {
         L.mfma = true;
         L.mv.n1 = n1;
