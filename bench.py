@@ -120,15 +120,22 @@ def run_precision(prec, p, dev_fields, S, phis, u0, steps, warmup, maxit, profil
         fam = max(cand, key=lambda k: cand[k]["ms"])
     fde.fde_profile_reset(h)
     # without warmup there is nothing to choose from: time every family in the timed run
-    fde.fde_profile_enable(h, 1 << fde.L.KFAM.index(fam) if fam else (1 << len(fde.L.KFAM)) - 1)
+    if fam is None:
+        mask = (1 << len(fde.L.KFAM)) - 1
+    else:
+        mask = 1 << fde.L.KFAM.index(fam)
+        if fam == "cgs":  # the passes' partials are combined by a separate one-workgroup kernel
+            mask |= 1 << fde.L.KFAM.index("cgs_finalize")
+    fde.fde_profile_enable(h, mask)
     elapsed, lat, its, reo, u_final = run(steps, "timed")
     timed = fde.fde_profile_read(h)
     if fam is None:
         prof = timed
         fam = max(timed, key=lambda k: timed[k]["ms"])
     live = timed[fam]
+    fin = timed.get("cgs_finalize") if fam == "cgs" else None
     out = {"elapsed": elapsed, "lat": lat, "iters": its, "u": u_final.clone(), "family": fam,
-           "live": live, "warm_profile": prof, "reorth": reo}
+           "live": live, "fin": fin, "warm_profile": prof, "reorth": reo}
     h.close()
     return out
 
@@ -450,6 +457,13 @@ def main():
                      "traffic": measured_traffic(m["family"]), "bytes_per_launch": bytes_per_launch,
                      "us_per_launch": 1e3 * ms_per_launch, "launches": live["launches"]},
     }
+    if m.get("fin") and m["fin"]["launches"]:
+        f = m["fin"]
+        us_fin = 1e3 * f["ms"] / f["launches"]
+        stage_us = 1e3 * ms_per_launch + us_fin
+        out["roofline"]["finalize_us_per_launch"] = us_fin
+        # the whole Gram-Schmidt stage: pass plus the combination of its partials
+        out["roofline"]["stage_achieved_with_finalize"] = bytes_per_launch / (stage_us * 1e-6) / 1e9
     if "fp64" in res and main_name == "mixed":
         f = res["fp64"]
         out["fp64_value"] = args.steps / f["elapsed"]

@@ -171,11 +171,12 @@ int fde_level_diag(fde_handle* h, int level, double* diag);
 #define FDE_KFAM_MG0_X 3     /* fine-level preconditioner operator, row pass (residual / Jacobi) */
 #define FDE_KFAM_MGC_Y 4     /* coarser FFT levels, column pass                                  */
 #define FDE_KFAM_MGC_X 5     /* coarser FFT levels, row pass                                     */
-#define FDE_KFAM_CGS 6       /* Gram-Schmidt passes, norms                                       */
+#define FDE_KFAM_CGS 6       /* Gram-Schmidt passes, norms (the streaming kernels)               */
 #define FDE_KFAM_TRANSFER 7  /* pre-smoothing from zero, restriction, prolongation               */
 #define FDE_KFAM_COARSE 8    /* one-workgroup V-cycle of the small levels                        */
 #define FDE_KFAM_UPDATE 9    /* x += Z y                                                         */
-#define FDE_KFAM_COUNT 10
+#define FDE_KFAM_CGS_FINALIZE 10 /* one-workgroup combination of the Gram-Schmidt partials, Givens  */
+#define FDE_KFAM_COUNT 11
 int fde_profile_enable(fde_handle* h, uint32_t family_mask);
 int fde_profile_read(fde_handle* h, int family, int64_t* launches, double* total_ms, double* bytes);
 int fde_profile_reset(fde_handle* h);

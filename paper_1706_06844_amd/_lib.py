@@ -27,7 +27,8 @@ FDE_MIXED_BF16GEMM = 2
 FDE_MG_GEOMETRIC = 0
 FDE_MG_GALERKIN = 1
 
-KFAM = ["outer_y", "outer_x", "mg0_y", "mg0_x", "mgc_y", "mgc_x", "cgs", "transfer", "coarse", "update"]
+KFAM = ["outer_y", "outer_x", "mg0_y", "mg0_x", "mgc_y", "mgc_x", "cgs", "transfer", "coarse", "update",
+        "cgs_finalize"]
 
 
 class fde_problem(ctypes.Structure):

@@ -214,9 +214,12 @@ struct GmresState {
 enum CgsKind : int { CGS_DOTS = 0, CGS_UPDATE_DOTS = 1, CGS_UPDATE_NORM = 2, CGS_INIT = 3, CGS_RESNORM = 4 };
 // One fused pass over the basis V[0..nv) (FP64, column stride ldv: even, columns 16-byte aligned)
 // and w (16-byte aligned, readable up to N rounded up to even).
+// Streams the pass and writes per-workgroup partials; `cap` bounds the grid (cgs_grid(N)).
 hipError_t launch_cgs_pass(int kind, size_t N, int nv, double* V, size_t ldv, double* w,
-                           const double* src, GmresState* st, double* partials, int grid,
+                           const double* src, GmresState* st, double* partials, int cap,
                            hipStream_t s);
+// Combines the partials of the preceding pass (same kind, nv, cap) and updates the solver state.
+hipError_t launch_cgs_finalize(int kind, int nv, double* partials, GmresState* st, int cap, hipStream_t s);
 int cgs_grid(size_t N);
 size_t cgs_partials_len(size_t N);
 // Column stride of the Krylov basis for N unknowns (multiple of 64 doubles).

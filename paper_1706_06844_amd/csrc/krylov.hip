@@ -20,6 +20,8 @@ namespace fde {
 constexpr int kCgsBlock = 256;
 constexpr int kCgsWaves = kCgsBlock / 64;
 constexpr int kCgsMaxGrid = 512;
+constexpr int kFinBlock = 1024;  // finalize: one workgroup
+constexpr int kFinLds = 6144;    // doubles of partials staged at a time (48 KB; >= one row of kCgsMaxGrid)
 
 int cgs_grid(size_t N) {
   const size_t pairs = (N + 1) / 2;
@@ -174,75 +176,110 @@ __global__ __launch_bounds__(kCgsBlock) void cgs_kernel(int kind, int N, int nv,
 // Combines the G per-block partials of a pass in block order (one workgroup) and updates the
 // solver state.  A separate launch instead of a last-block ticket: one counter hit by every block
 // of a wide grid serialises at the memory side.
-__global__ __launch_bounds__(kCgsBlock) void cgs_finalize_kernel(int kind, int nv, int G,
+__global__ __launch_bounds__(kFinBlock) void cgs_finalize_kernel(int kind, int nv, int G,
                                                                  const double* __restrict__ partials,
-                                                                 GmresState* st) {
-  if (kind == CGS_DOTS || kind == CGS_UPDATE_DOTS || kind == CGS_UPDATE_NORM) {
-    if (st->done) return;
-    if (kind == CGS_UPDATE_DOTS && !st->reorth) return;
-  }
+                                                                 GmresState* gst) {
+  // The state is copied into LDS by the whole workgroup (one round of independent loads), updated
+  // there by one thread, and copied back: the update's many small dependent accesses then stay on
+  // chip instead of paying a device-memory round trip each.
+  constexpr int kWords = sizeof(GmresState) / 4;
+  static_assert(sizeof(GmresState) % 4 == 0, "state is copied as 32-bit words");
+  __shared__ GmresState ls;
   __shared__ double fin[kMaxRestart + 2];
+  __shared__ double pl[kFinLds];
+  {
+    const unsigned* src = reinterpret_cast<const unsigned*>(gst);
+    unsigned* dst = reinterpret_cast<unsigned*>(&ls);
+    for (int k = threadIdx.x; k < kWords; k += blockDim.x) dst[k] = src[k];
+  }
   const bool dots = (kind == CGS_DOTS || kind == CGS_UPDATE_DOTS);
   const bool norm = (kind != CGS_UPDATE_DOTS);
   const int nres = (dots ? nv : 0) + (norm ? 1 : 0);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int r = wid; r < nres; r += kCgsWaves) {
-    double v = 0.0;
-    for (int b = lane; b < G; b += 64) v += partials[(size_t)r * G + b];
-    v = wave_sum(v);
-    if (lane == 0) fin[r] = v;
+  // the partials are fetched in rounds of independent loads (as many rows as fit the LDS buffer,
+  // usually all of them), then summed from LDS in block order
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int rows = kFinLds / G;
+  for (int r0 = 0; r0 < nres; r0 += rows) {
+    const int nr = min(rows, nres - r0);
+    for (int e = threadIdx.x; e < nr * G; e += blockDim.x) pl[e] = partials[(size_t)r0 * G + e];
+    __syncthreads();
+    for (int r = wid; r < nr; r += nw) {
+      double v = 0.0;
+      for (int b = lane; b < G; b += 64) v += pl[r * G + b];
+      v = wave_sum(v);
+      if (lane == 0) fin[r0 + r] = v;
+    }
+    __syncthreads();
+  }
+  if (kind == CGS_DOTS || kind == CGS_UPDATE_DOTS || kind == CGS_UPDATE_NORM) {
+    if (ls.done) return;
+    if (kind == CGS_UPDATE_DOTS && !ls.reorth) return;
+  }
+  GmresState* st = &ls;
+  if (threadIdx.x == 0) {
+    if (kind == CGS_DOTS) {
+      double hh = 0.0;
+      for (int k = 0; k < nv; ++k) {
+        const double h = fin[k] * st->vscale[k];
+        st->h1[k] = h;
+        hh += h * h;
+      }
+      // After one projection ||w - V h||^2 = ||w||^2 - ||h||^2 (orthonormal V).  A second pass is
+      // needed when the projection removed more than half of ||w||^2 (norm ratio below 1/sqrt 2).
+      const double ww = fin[nv];
+      st->reorth = st->orth == 1 ? 1 : st->orth == 0 ? 0 : (hh > 0.5 * ww ? 1 : 0);
+    } else if (kind == CGS_UPDATE_DOTS) {
+      for (int k = 0; k < nv; ++k) st->h2[k] = fin[k] * st->vscale[k];
+    } else if (kind == CGS_UPDATE_NORM) {
+      givens_step(st, nv - 1, sqrt(fin[0]));
+    } else if (kind == CGS_INIT) {
+      const double bn = sqrt(fin[0]);
+      st->bnorm = bn;
+      st->atol = st->rtol * bn;
+      st->resnorm = bn;
+      st->est = bn;
+      st->g[0] = bn;
+      st->vscale[0] = bn > 0.0 ? 1.0 / bn : 0.0;
+      st->iters = 0;
+      st->nreorth = 0;
+      st->reorth_mask = 0;
+      st->nused = 0;
+      st->conv = (bn == 0.0);
+      st->done = (bn == 0.0);
+    } else if (kind == CGS_RESNORM) {
+      const double rn = sqrt(fin[0]);
+      st->resnorm = rn;
+      st->conv = (rn <= st->atol);
+      st->g[0] = rn;
+      st->vscale[0] = rn > 0.0 ? 1.0 / rn : 0.0;
+      st->nused = 0;
+      st->reorth_mask = 0;
+      st->done = (st->conv || st->iters >= st->maxit) ? 1 : 0;
+    }
   }
   __syncthreads();
-  if (threadIdx.x != 0) return;
-  if (kind == CGS_DOTS) {
-    double hh = 0.0;
-    for (int k = 0; k < nv; ++k) {
-      const double h = fin[k] * st->vscale[k];
-      st->h1[k] = h;
-      hh += h * h;
-    }
-    // After one projection ||w - V h||^2 = ||w||^2 - ||h||^2 (orthonormal V).  A second pass is
-    // needed when the projection removed more than half of ||w||^2 (norm ratio below 1/sqrt 2).
-    const double ww = fin[nv];
-    st->reorth = st->orth == 1 ? 1 : st->orth == 0 ? 0 : (hh > 0.5 * ww ? 1 : 0);
-  } else if (kind == CGS_UPDATE_DOTS) {
-    for (int k = 0; k < nv; ++k) st->h2[k] = fin[k] * st->vscale[k];
-  } else if (kind == CGS_UPDATE_NORM) {
-    givens_step(st, nv - 1, sqrt(fin[0]));
-  } else if (kind == CGS_INIT) {
-    const double bn = sqrt(fin[0]);
-    st->bnorm = bn;
-    st->atol = st->rtol * bn;
-    st->resnorm = bn;
-    st->est = bn;
-    st->g[0] = bn;
-    st->vscale[0] = bn > 0.0 ? 1.0 / bn : 0.0;
-    st->iters = 0;
-    st->nreorth = 0;
-    st->reorth_mask = 0;
-    st->nused = 0;
-    st->conv = (bn == 0.0);
-    st->done = (bn == 0.0);
-  } else if (kind == CGS_RESNORM) {
-    const double rn = sqrt(fin[0]);
-    st->resnorm = rn;
-    st->conv = (rn <= st->atol);
-    st->g[0] = rn;
-    st->vscale[0] = rn > 0.0 ? 1.0 / rn : 0.0;
-    st->nused = 0;
-    st->reorth_mask = 0;
-    st->done = (st->conv || st->iters >= st->maxit) ? 1 : 0;
+  {
+    const unsigned* src = reinterpret_cast<const unsigned*>(&ls);
+    unsigned* dst = reinterpret_cast<unsigned*>(gst);
+    for (int k = threadIdx.x; k < kWords; k += blockDim.x) dst[k] = src[k];
   }
 }
 
+// Grid of a pass: wide passes (many columns) stream best with one workgroup per CU, narrow ones with
+// two; `cap` is the size-dependent maximum (cgs_grid).
+int cgs_pass_grid(int nv, int cap) {
+  int g = cap < 1 ? 1 : (cap > kCgsMaxGrid ? kCgsMaxGrid : cap);
+  if (nv > 8 && g > kCgsMaxGrid / 2) g = kCgsMaxGrid / 2;
+  return g;
+}
+
 hipError_t launch_cgs_pass(int kind, size_t N, int nv, double* V, size_t ldv, double* w, const double* src,
-                           GmresState* st, double* partials, int grid, hipStream_t s) {
-  if (nv > kMaxRestart + 1 || N > (size_t)0x7ffffffe || grid < 1 || grid > kCgsMaxGrid) return hipErrorInvalidValue;
+                           GmresState* st, double* partials, int cap, hipStream_t s) {
+  if (nv > kMaxRestart + 1 || N > (size_t)0x7ffffffe || cap < 1) return hipErrorInvalidValue;
   if (ldv % 2 || (reinterpret_cast<uintptr_t>(V) | reinterpret_cast<uintptr_t>(w)) % 16) return hipErrorInvalidValue;
   if (kind == CGS_INIT && !src) return hipErrorInvalidValue;
   const int n = (int)N;
-  // Wide passes (many columns) stream best with one workgroup per CU; narrow ones with two.
-  if (nv > 8 && grid > kCgsMaxGrid / 2) grid = kCgsMaxGrid / 2;
+  const int grid = cgs_pass_grid(nv, cap);
 #define L_(M)                                                                                            \
   hipLaunchKernelGGL((cgs_kernel<M>), dim3(grid), dim3(kCgsBlock), 0, s, kind, n, nv, V, ldv, w, src, st, \
                      partials)
@@ -253,9 +290,13 @@ hipError_t launch_cgs_pass(int kind, size_t N, int nv, double* V, size_t ldv, do
   else if (nv <= 24) L_(24);
   else L_(kMaxRestart + 1);
 #undef L_
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(cgs_finalize_kernel, dim3(1), dim3(kCgsBlock), 0, s, kind, nv, grid, partials, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_cgs_finalize(int kind, int nv, double* partials, GmresState* st, int cap, hipStream_t s) {
+  if (nv > kMaxRestart + 1 || cap < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(cgs_finalize_kernel, dim3(1), dim3(kFinBlock), 0, s, kind, nv, cgs_pass_grid(nv, cap), partials,
+                     st);
   return hipGetLastError();
 }
 

@@ -825,6 +825,16 @@ void read_state(fde_handle* h) {
   HIPCHECK(hipStreamSynchronize(h->stream));
 }
 
+// One Gram-Schmidt pass (timed as the CGS family) and the combination of its partials (timed
+// separately).  Negative `bytes` mark the conditional second pass.
+void cgs(fde_handle* h, int kind, int nv, double* w, const double* src, double bytes) {
+  timed(h, FDE_KFAM_CGS, bytes, [&] {
+    return launch_cgs_pass(kind, h->N, nv, h->V, h->ldv, w, src, h->st, h->partials, h->cgs_grid, h->stream);
+  });
+  timed(h, FDE_KFAM_CGS_FINALIZE, bytes < 0 ? -1e-300 : 0.0,
+        [&] { return launch_cgs_finalize(kind, nv, h->partials, h->st, h->cgs_grid, h->stream); });
+}
+
 template <typename R>
 void arnoldi_step(fde_handle* h, Hierarchy<R>& H, int j) {
   const size_t N = h->N;
@@ -839,24 +849,16 @@ void arnoldi_step(fde_handle* h, Hierarchy<R>& H, int j) {
   // bytes of a pass: j + 1 basis columns and w read, w written by the update passes (a skipped
   // second pass is counted as a launch of zero bytes)
   const double vb = (double)(j + 2) * N * sizeof(double);
-  timed(h, FDE_KFAM_CGS, vb, [&] {
-    return launch_cgs_pass(CGS_DOTS, N, j + 1, h->V, ldv, w, nullptr, h->st, h->partials, h->cgs_grid, h->stream);
-  });
-  timed(h, FDE_KFAM_CGS, -(vb + N * sizeof(double)), [&] {
-    return launch_cgs_pass(CGS_UPDATE_DOTS, N, j + 1, h->V, ldv, w, nullptr, h->st, h->partials, h->cgs_grid, h->stream);
-  });
-  timed(h, FDE_KFAM_CGS, vb + N * sizeof(double), [&] {
-    return launch_cgs_pass(CGS_UPDATE_NORM, N, j + 1, h->V, ldv, w, nullptr, h->st, h->partials, h->cgs_grid, h->stream);
-  });
+  cgs(h, CGS_DOTS, j + 1, w, nullptr, vb);
+  cgs(h, CGS_UPDATE_DOTS, j + 1, w, nullptr, -(vb + N * sizeof(double)));
+  cgs(h, CGS_UPDATE_NORM, j + 1, w, nullptr, vb + N * sizeof(double));
 }
 
 template <typename R>
 int fgmres(fde_handle* h, Hierarchy<R>& H, const double* b, double* x, fde_stats* stats) {
   const size_t N = h->N;
   const int restart = h->p.restart;
-  timed(h, FDE_KFAM_CGS, 2.0 * N * sizeof(double), [&] {
-    return launch_cgs_pass(CGS_INIT, N, 0, h->V, h->ldv, h->V, b, h->st, h->partials, h->cgs_grid, h->stream);
-  });
+  cgs(h, CGS_INIT, 0, h->V, b, 2.0 * N * sizeof(double));
   const OpView<double> op = h->cur.view(h->tw64_x, h->tw64_y, h->n1, h->n2, h->L1, h->L2);
   int cycles = 0;
   // Arnoldi steps are issued without waiting; the host reads the device state only once the
@@ -883,9 +885,7 @@ int fgmres(fde_handle* h, Hierarchy<R>& H, const double* b, double* x, fde_stats
       return launch_update_x<R>(N, static_cast<const R*>(h->Z), N, x, cycles == 0 ? 1 : 0, h->st, h->stream);
     });
     op_apply<double, double>(h, true, op, x, h->ay64, h->V, EP_RESID, b, nullptr, 0.0, nullptr);
-    timed(h, FDE_KFAM_CGS, (double)N * sizeof(double), [&] {
-      return launch_cgs_pass(CGS_RESNORM, N, 0, h->V, h->ldv, h->V, nullptr, h->st, h->partials, h->cgs_grid, h->stream);
-    });
+    cgs(h, CGS_RESNORM, 0, h->V, nullptr, (double)N * sizeof(double));
     read_state(h);
     ++cycles;
     if (h->st_host->conv || h->st_host->iters >= h->p.maxit) break;
@@ -927,8 +927,7 @@ void cycle_body(fde_handle* h, Hierarchy<R>& H) {
   HIPCHECK(launch_update_x<R>(N, static_cast<const R*>(h->Z), N, h->as.xsol, 0, h->st, h->stream));
   const OpView<double> op = h->cur.view(h->tw64_x, h->tw64_y, h->n1, h->n2, h->L1, h->L2);
   op_apply<double, double>(h, true, op, h->as.xsol, h->ay64, h->V, EP_RESID, h->rhs, nullptr, 0.0, nullptr);
-  HIPCHECK(launch_cgs_pass(CGS_RESNORM, N, 0, h->V, h->ldv, h->V, nullptr, h->st, h->partials, h->cgs_grid,
-                           h->stream));
+  cgs(h, CGS_RESNORM, 0, h->V, nullptr, (double)N * sizeof(double));
 }
 
 void issue_cycle(fde_handle* h) {
@@ -988,8 +987,7 @@ int async_step_start(fde_handle* h, const double* u_prev, int nsrc, const double
     const OpView<double> op = h->prev.view(h->tw64_x, h->tw64_y, h->n1, h->n2, h->L1, h->L2);
     op_apply<double, double>(h, true, op, u_prev, h->ay64, h->rhs, EP_RHS, nullptr, &src, h->p.tau, nullptr);
     HIPCHECK(launch_fill<double>(N, h->as.xsol, 0.0, h->stream));
-    HIPCHECK(launch_cgs_pass(CGS_INIT, N, 0, h->V, h->ldv, h->V, h->rhs, h->st, h->partials, h->cgs_grid,
-                             h->stream));
+    cgs(h, CGS_INIT, 0, h->V, h->rhs, 2.0 * N * sizeof(double));
     h->as.cycles = 0;
     h->as.active = true;
     issue_cycle(h);
