@@ -67,7 +67,8 @@ std::vector<double> wsgd_weights(double g, int K) {
   return w;
 }
 
-constexpr int kDirectMaxN = 31;    // levels with max(n1, n2) <= this run in the one-workgroup kernel
+constexpr int kDirectMaxN = 31;    // the coarsest level may have up to this many points per side
+constexpr int kOneWgMaxN = 15;     // levels with max(n1, n2) <= this run in the one-workgroup kernel
 constexpr int kDirectOpMax = 255;  // levels with max(n1, n2) <= this use the direct operator kernel
 
 template <typename R>
@@ -416,7 +417,7 @@ std::vector<double> symbol_host(const std::vector<double>& w, int n, int L, doub
 // ---- autotuner -------------------------------------------------------------------------------
 // The operator of a level can run as the dense-Toeplitz kernel (one launch, O(n) work per point) or
 // as the two FFT passes (O(log n) per point, more launches and transform overhead).  Which is faster
-// depends on the size and the precision, so levels whose larger side lies in (kDirectMaxN,
+// depends on the size and the precision, so levels whose larger side lies in (kOneWgMaxN,
 // kDirectTuneMax] are timed both ways the first time their shape occurs in the process, and the
 // faster one is kept for every later hierarchy (FDE_AUTOTUNE=0 keeps the static size rule).
 constexpr int kDirectTuneMax = 511;
@@ -426,7 +427,7 @@ std::map<std::tuple<int, int, int>, bool> g_tune_direct;
 // True if the level has to be timed now; otherwise *direct holds the cached or static choice.
 bool tune_level(int n1, int n2, int bytes, bool* direct) {
   const int mx = std::max(n1, n2);
-  if (mx <= kDirectMaxN || mx > kDirectTuneMax) return false;
+  if (mx <= kOneWgMaxN || mx > kDirectTuneMax) return false;
   const char* e = std::getenv("FDE_AUTOTUNE");
   if (e && e[0] == '0') return false;
   std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -637,7 +638,7 @@ std::unique_ptr<Hierarchy<R>> build_hierarchy(fde_handle* h) {
         L.mv.ty2 = upload_raw(m, u2, st);
       }
     }
-    const bool coarse_one_wg = !galerkin && std::max(n1, n2) <= kDirectMaxN;
+    const bool coarse_one_wg = !galerkin && std::max(n1, n2) <= kOneWgMaxN;
     if (!coarse_one_wg) L.r = dalloc<R>(m, N);
     if (!L.in_place() && !coarse_one_wg) L.x2 = dalloc<R>(m, N);
     L.b = dalloc<R>(m, N);
@@ -671,7 +672,7 @@ std::unique_ptr<Hierarchy<R>> build_hierarchy(fde_handle* h) {
     HIPCHECK(hipStreamSynchronize(st));  // tmp is freed on return
   } else {
     H->lc = nlev - 1;
-    while (H->lc > 0 && std::max(H->lv[H->lc - 1].n1, H->lv[H->lc - 1].n2) <= kDirectMaxN) --H->lc;
+    while (H->lc > 0 && std::max(H->lv[H->lc - 1].n1, H->lv[H->lc - 1].n2) <= kOneWgMaxN) --H->lc;
     if (nlev - H->lc > kMaxCoarseLevels) throw FdeError{FDE_EINVAL, "too many direct coarse levels"};
     cv.nlev = nlev - H->lc;
     for (int k = 0; k < cv.nlev; ++k) {
@@ -1055,7 +1056,7 @@ size_t footprint_bytes(const fde_problem* pin) {
   while (true) {
     const double Nl = (double)a1 * a2;
     const bool direct = std::max(a1, a2) <= kDirectOpMax;
-    const bool one_wg = !gal && std::max(a1, a2) <= kDirectMaxN;
+    const bool one_wg = !gal && std::max(a1, a2) <= kOneWgMaxN;
     if (gal && l > 0) {
       b += 4.0 * a2 * p.n1 * R + 4.0 * p.n2 * a1 * R + 2.0 * Nl * R;  // fields, dinv, qx/qy (small)
       if (galscratch == 0) galscratch = (2.0 * a2 * p.n1 + 2.0 * p.n2 * a1) * R;
