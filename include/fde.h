@@ -51,7 +51,9 @@ extern "C" {
 /* ---- options ---------------------------------------------------------------------------------- */
 #define FDE_FP64 0             /* every kernel in FP64                                              */
 #define FDE_MIXED_FP32 1       /* multigrid preconditioner in FP32 inside FP64 flexible GMRES        */
-#define FDE_MIXED_BF16GEMM 2   /* as FDE_MIXED_FP32, fine-level Toeplitz products as BF16 MFMA GEMMs */
+#define FDE_MIXED_BF16GEMM 2   /* as FDE_MIXED_FP32; the rediscretised levels too large for the dense
+                                  kernel (n > 255) apply their Toeplitz factors as BF16 MFMA products
+                                  with FP32 accumulation instead of FP32 FFTs                        */
 
 #define FDE_MG_GEOMETRIC 0     /* rediscretised coarse operators, Sec. 4.2 (the paper's P_MGM)      */
 #define FDE_MG_GALERKIN 1      /* Galerkin coarse operators R A P, Sec. 4 TGM step 3 (tilde P_MGM)   */
@@ -94,7 +96,7 @@ void fde_problem_default(fde_problem* p, double alpha, double beta, int32_t n1, 
  * The same fields are used for the explicit half of the next fde_step until fde_update_coeffs is
  * called.  Builds the multigrid hierarchy on the device (geometric: coefficients injected at the
  * coarse points, Sec. 4.2; Galerkin: R A P with R = P^T/4, Sec. 4), the Toeplitz symbols, and the
- * LU factors of the coarsest level.  stream: a hipStream_t (NULL = the default stream).
+ * FP64 inverse of the coarsest-level matrix (Gauss-Jordan with partial pivoting).  stream: a hipStream_t (NULL = the default stream).
  * Errors: FDE_EINVAL, FDE_ENEGCOEF, FDE_ENONFINITE, FDE_ENOMEM, FDE_EDEVICE; *out is NULL then. */
 int fde_setup(const fde_problem* p, const double* dp, const double* dm, const double* ep,
               const double* em, void* stream, fde_handle** out);
@@ -135,9 +137,10 @@ int fde_num_levels(const fde_handle* h);
 int fde_level_size(const fde_handle* h, int level, int32_t* n1, int32_t* n2);
 
 /* y = A_level x with A_level the level-`level` matrix of the preconditioner hierarchy (level 0 =
- * I - tau/2 L).  prec = FDE_FP64 applies the FP64 kernels, FDE_MIXED_FP32 the FP32 kernels (inputs
- * rounded to FP32, result widened to FP64), FDE_MIXED_BF16GEMM the BF16-MFMA Toeplitz products
- * (level 0 only).  For level 0 and prec = FDE_FP64 this is the outer operator of the solver. */
+ * I - tau/2 L).  prec names the hierarchy: FDE_FP64 (FP64 handles) or FDE_MIXED_FP32 (the FP32
+ * hierarchy of FDE_MIXED_FP32 and FDE_MIXED_BF16GEMM handles; inputs rounded to FP32, result widened
+ * to FP64; BF16 levels use their MFMA products).  For level 0 and prec = FDE_FP64 this is the outer
+ * FP64 operator of the solver, available on every handle. */
 int fde_apply(fde_handle* h, int level, int prec, const double* x, double* y);
 
 /* One damped-Jacobi step on a level (Lemma lemsmo): x <- x + omega D^-1 (b - A x), D = diag(A).
@@ -150,7 +153,7 @@ int fde_restrict(fde_handle* h, int level, int prec, const double* r, double* rc
 /* Bilinear prolongation and correction x += P e from level+1 to `level` (Sec. 4.1, Lemma lemapp). */
 int fde_prolong(fde_handle* h, int level, int prec, const double* e, double* x);
 
-/* Exact solve on the coarsest level with the FP64 LU factors. */
+/* Exact solve on the coarsest level with the FP64 inverse of its matrix. */
 int fde_coarse_solve(fde_handle* h, const double* b, double* x);
 
 /* One V(nu_pre, nu_post) cycle with zero initial guess (Sec. 4 V-cycle, Sec. 4.2 settings) in the
@@ -167,10 +170,10 @@ int fde_level_diag(fde_handle* h, int level, double* diag);
  * and output field once). */
 #define FDE_KFAM_OUTER_Y 0   /* FP64 system operator, column (y) pass                            */
 #define FDE_KFAM_OUTER_X 1   /* FP64 system operator, row (x) pass with epilogue                 */
-#define FDE_KFAM_MG0_Y 2     /* fine-level preconditioner operator, column pass                  */
-#define FDE_KFAM_MG0_X 3     /* fine-level preconditioner operator, row pass (residual / Jacobi) */
-#define FDE_KFAM_MGC_Y 4     /* coarser FFT levels, column pass                                  */
-#define FDE_KFAM_MGC_X 5     /* coarser FFT levels, row pass                                     */
+#define FDE_KFAM_MG0_Y 2     /* fine-level preconditioner operator, FFT column pass               */
+#define FDE_KFAM_MG0_X 3     /* fine level: FFT row pass (residual / Jacobi), dense or MFMA passes */
+#define FDE_KFAM_MGC_Y 4     /* coarser levels, FFT column pass                                  */
+#define FDE_KFAM_MGC_X 5     /* coarser levels: FFT row pass, dense, Galerkin or MFMA kernels    */
 #define FDE_KFAM_CGS 6       /* Gram-Schmidt passes, norms (the streaming kernels)               */
 #define FDE_KFAM_TRANSFER 7  /* pre-smoothing from zero, restriction, prolongation               */
 #define FDE_KFAM_COARSE 8    /* one-workgroup V-cycle of the small levels                        */

@@ -375,7 +375,7 @@ __global__ __launch_bounds__(1024) void coarse_vcycle_kernel(CoarseView<R> cv, c
     }
     __syncthreads();
   }
-  // coarsest: X = inv B (FP64 dense inverse from the LU-based Gauss-Jordan factorisation)
+  // coarsest: X = inv B (FP64 inverse from Gauss-Jordan elimination with partial pivoting)
   {
     const int Nc = cv.n1[last] * cv.n2[last];
     for (int p = tid; p < Nc; p += nt) {
