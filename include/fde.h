@@ -57,6 +57,9 @@ extern "C" {
 
 #define FDE_MG_GEOMETRIC 0     /* rediscretised coarse operators, Sec. 4.2 (the paper's P_MGM)      */
 #define FDE_MG_GALERKIN 1      /* Galerkin coarse operators R A P, Sec. 4 TGM step 3 (tilde P_MGM)   */
+#define FDE_MG_BAND 2          /* the band preconditioner P_2 of Sec. 4.3: the same system with the
+                                  Laplacian (order 2) in place of both fractional factors, applied
+                                  as one Galerkin V-cycle; the outer operator stays fractional      */
 
 typedef struct fde_handle fde_handle;
 
@@ -67,7 +70,7 @@ typedef struct fde_problem {
   double a1, b1, a2, b2;/* domain (a1,b1) x (a2,b2), a < b                                         */
   double tau;           /* time step, > 0                                                          */
   int32_t precision;    /* FDE_FP64 | FDE_MIXED_FP32 | FDE_MIXED_BF16GEMM                          */
-  int32_t mg_variant;   /* FDE_MG_GEOMETRIC | FDE_MG_GALERKIN                                      */
+  int32_t mg_variant;   /* FDE_MG_GEOMETRIC | FDE_MG_GALERKIN | FDE_MG_BAND                        */
   double omega;         /* Jacobi damping (Lemma lemsmo), 0 < omega <= 1; 0 selects 0.7             */
   int32_t nu_pre;       /* pre-smoothing steps per level, >= 0 (< 0 selects 1)                      */
   int32_t nu_post;      /* post-smoothing steps per level, >= 0 (< 0 selects 1)                     */
@@ -122,6 +125,14 @@ int fde_step_sources(fde_handle* h, const double* u_prev, int32_t nsrc, const do
 /* Solves (I - tau/2 L) x = b for the left-hand side operator (Sec. 2, eq. (system)) with the
  * configured preconditioned GMRES.  x may not alias b.  stats may be NULL. */
 int fde_solve(fde_handle* h, const double* b, double* x, fde_stats* stats);
+
+/* Multigrid as a stand-alone solver (the V-cycle iteration of Sec. 4 without a Krylov method):
+ * x_{k+1} = x_k + MG(b - A x_k) from x_0 = 0, one V(nu_pre, nu_post) cycle in the handle's
+ * preconditioner precision per iteration and the FP64 true residual after each, until
+ * ||b - A x||_2 <= rtol ||b||_2 or max_cycles (>= 1) cycles.  stats->iters = cycles.  The error
+ * contracts by the spectral radius of the V-cycle iteration matrix per cycle.  x may not alias b.
+ * Returns 0, FDE_ENOCONV (x = last iterate) or an error. */
+int fde_solve_mg(fde_handle* h, const double* b, double* x, int32_t max_cycles, fde_stats* stats);
 
 /* Releases every device buffer of the handle.  NULL is ignored. */
 void fde_destroy(fde_handle* h);

@@ -243,3 +243,24 @@ def vcycle_iteration_matrix(vc: VCycle) -> np.ndarray:
         e[c] = 1.0
         V[:, c] = vc(e.reshape(L0.n2, L0.n1)).ravel()
     return np.eye(N) - V @ A
+
+
+# ----------------------------------------------------------------------------------------------
+# Multigrid as a stand-alone solver (the V-cycle iteration of Sec. 4 without a Krylov method)
+# ----------------------------------------------------------------------------------------------
+def mg_solve(apply_A, b: np.ndarray, vc: VCycle, rtol: float, max_cycles: int):
+    """x_{k+1} = x_k + V(b - A x_k) from x_0 = 0 until ||b - A x||_2 <= rtol ||b||_2.
+
+    Returns (x, cycles, residual norms [||r_0||, ||r_1||, ...]).  The error propagates with the
+    iteration matrix I - V A, so the residual ratios approach its spectral radius."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    hist = [float(np.linalg.norm(r))]
+    target = rtol * hist[0]
+    k = 0
+    while k < max_cycles and hist[-1] > target:
+        x = x + vc(r)
+        r = b - apply_A(x)
+        hist.append(float(np.linalg.norm(r)))
+        k += 1
+    return x, k, hist

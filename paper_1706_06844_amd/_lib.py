@@ -26,6 +26,7 @@ FDE_MIXED_FP32 = 1
 FDE_MIXED_BF16GEMM = 2
 FDE_MG_GEOMETRIC = 0
 FDE_MG_GALERKIN = 1
+FDE_MG_BAND = 2
 
 KFAM = ["outer_y", "outer_x", "mg0_y", "mg0_x", "mgc_y", "mgc_x", "cgs", "transfer", "coarse", "update",
         "cgs_finalize"]
@@ -72,6 +73,7 @@ SIGNATURES = {
     "fde_step_sources": (_I, [_P, _P, _I32, ctypes.POINTER(_D), ctypes.POINTER(_P), _P,
                               ctypes.POINTER(fde_stats)]),
     "fde_solve": (_I, [_P, _P, _P, ctypes.POINTER(fde_stats)]),
+    "fde_solve_mg": (_I, [_P, _P, _P, _I32, ctypes.POINTER(fde_stats)]),
     "fde_destroy": (None, [_P]),
     "fde_last_error": (ctypes.c_char_p, [_P]),
     "fde_num_levels": (_I, [_P]),

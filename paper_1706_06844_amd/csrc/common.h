@@ -127,6 +127,10 @@ hipError_t launch_coarse_invert(const CoarseView<R>& cv, const double* dense, do
 template <typename R>
 hipError_t launch_coarse_solve(int Nc, const double* inv, const R* b, R* x, const int* skip, hipStream_t st);
 
+// x += z elementwise (x FP64, z in precision R).
+template <typename R>
+hipError_t launch_add_to(size_t N, const R* z, double* x, hipStream_t st);
+
 // ---- Galerkin coarse operators (galerkin.hip) ----------------------------------------------------
 // Level l of the Galerkin hierarchy in factored form: coarse grid nlx x nly, fine grid n0x x n0y,
 // H = 2^logH.  cx0/cx1: [nly][n0x] pairs (c+_D, c-_D) for D = 0, 1; ey0/ey1: [n0y][nlx] pairs.

@@ -584,6 +584,20 @@ hipError_t launch_coarse_solve(int Nc, const double* inv, const R* b, R* x, cons
   return hipGetLastError();
 }
 
+// ---- x += z (FP64 x, z in the preconditioner precision) ---------------------------------------
+template <typename R>
+__global__ void add_to_kernel(size_t N, const R* __restrict__ z, double* __restrict__ x) {
+  for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < N; p += (size_t)gridDim.x * blockDim.x)
+    x[p] += (double)z[p];
+}
+template <typename R>
+hipError_t launch_add_to(size_t N, const R* z, double* x, hipStream_t st) {
+  hipLaunchKernelGGL((add_to_kernel<R>), dim3(grid_for(N)), dim3(kBlock), 0, st, N, z, x);
+  return hipGetLastError();
+}
+template hipError_t launch_add_to<float>(size_t, const float*, double*, hipStream_t);
+template hipError_t launch_add_to<double>(size_t, const double*, double*, hipStream_t);
+
 // ---- explicit instantiations ------------------------------------------------------------------
 #define FDE_INST_R(R)                                                                                   \
   template hipError_t launch_restrict<R>(int, int, const R*, R*, const R*, R*, const int*, hipStream_t); \

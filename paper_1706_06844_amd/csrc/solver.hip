@@ -195,6 +195,10 @@ struct fde_handle {
   size_t N = 0;
   double hx = 0, hy = 0, sx = 0, sy = 0;
   std::vector<double> wa, wb;  // WSGD weights for alpha and beta, k = 0..n
+  // weights and orders the preconditioner hierarchy is built from: (wa, wb, alpha, beta), or the
+  // order-2 (Laplacian) weights of the band preconditioner
+  std::vector<double> pwa, pwb;
+  double palpha = 0, pbeta = 0;
   DevAlloc mem;
   DevAlloc hier_mem;  // rebuilt on coefficient updates
   // outer FP64 operators: cur = left-hand side level t^(m), prev = explicit level t^(m-1)
@@ -341,7 +345,8 @@ int validate(const fde_problem* p, std::string* why) {
   if (!(p->b1 > p->a1) || !(p->b2 > p->a2)) return bad("domain needs a < b");
   if (!(p->tau > 0.0) || !std::isfinite(p->tau)) return bad("tau must be positive and finite");
   if (p->precision < FDE_FP64 || p->precision > FDE_MIXED_BF16GEMM) return bad("unknown precision");
-  if (p->mg_variant != FDE_MG_GEOMETRIC && p->mg_variant != FDE_MG_GALERKIN) return bad("unknown mg_variant");
+  if (p->mg_variant != FDE_MG_GEOMETRIC && p->mg_variant != FDE_MG_GALERKIN && p->mg_variant != FDE_MG_BAND)
+    return bad("unknown mg_variant");
   if (!(p->omega > 0.0 && p->omega <= 1.0)) return bad("omega must lie in (0,1]");
   if (p->nu_pre < 0 || p->nu_pre > 8 || p->nu_post < 0 || p->nu_post > 8) return bad("nu_pre/nu_post in 0..8");
   if (p->coarsest_n < 3) return bad("coarsest_n must be >= 3");
@@ -554,8 +559,8 @@ void build_gal_level(fde_handle* h, Hierarchy<R>& H, Level<R>& L, int l) {
   g.m1x = g.m1y = ((double)Hw * Hw - 1.0) / (6.0 * Hw);
   g.scale = std::ldexp(1.0, -2 * l);
   HIPCHECK(launch_gal_setup<R>(g, h->cur.dpm, h->cur.epm, st));
-  L.qx = upload<double>(m, gal_q(h->wa, F0.sx, Hw), st);
-  L.qy = upload<double>(m, gal_q(h->wb, F0.sy, Hw), st);
+  L.qx = upload<double>(m, gal_q(h->pwa, F0.sx, Hw), st);
+  L.qy = upload<double>(m, gal_q(h->pwb, F0.sy, Hw), st);
   L.dinv = dalloc<R>(m, L.N());
   HIPCHECK(launch_gal_diag<R>(g, L.qx, L.qy, h->p.omega, L.dinv, nullptr, st));
   g.dinv = L.dinv;
@@ -570,7 +575,8 @@ std::unique_ptr<Hierarchy<R>> build_hierarchy(fde_handle* h) {
   DevAlloc& m = h->hier_mem;
   hipStream_t st = h->stream;
   const fde_problem& p = h->p;
-  const bool galerkin = p.mg_variant == FDE_MG_GALERKIN && std::min(h->n1, h->n2) > p.coarsest_n;
+  const bool galerkin = (p.mg_variant == FDE_MG_GALERKIN || p.mg_variant == FDE_MG_BAND) &&
+                        std::min(h->n1, h->n2) > p.coarsest_n;
   H->galerkin = galerkin;
   int n1 = h->n1, n2 = h->n2, l = 0;
   while (true) {
@@ -580,8 +586,8 @@ std::unique_ptr<Hierarchy<R>> build_hierarchy(fde_handle* h) {
     L.L1 = 2 * (n1 + 1);
     L.L2 = 2 * (n2 + 1);
     const double hx = h->hx * (double)(1 << l), hy = h->hy * (double)(1 << l);
-    L.sx = p.tau / (2.0 * std::pow(hx, p.alpha));
-    L.sy = p.tau / (2.0 * std::pow(hy, p.beta));
+    L.sx = p.tau / (2.0 * std::pow(hx, h->palpha));
+    L.sy = p.tau / (2.0 * std::pow(hy, h->pbeta));
     const size_t N = L.N();
     if (galerkin && l > 0) {
       build_gal_level<R>(h, *H, L, l);
@@ -604,21 +610,21 @@ std::unique_ptr<Hierarchy<R>> build_hierarchy(fde_handle* h) {
         HIPCHECK(launch_inject_pairs<R>(F.n1, F.n2, F.epm, L.epm, st));
       }
       L.dinv = dalloc<R>(m, N);
-      HIPCHECK(launch_diag<R>((int)N, L.dpm, L.epm, L.sx * h->wa[1], L.sy * h->wb[1], p.omega, L.dinv, nullptr, st));
+      HIPCHECK(launch_diag<R>((int)N, L.dpm, L.epm, L.sx * h->pwa[1], L.sy * h->pwb[1], p.omega, L.dinv, nullptr, st));
       L.direct = std::max(n1, n2) <= kDirectOpMax;
       const bool tune = !galerkin && tune_level(n1, n2, (int)sizeof(R), &L.direct);
       if (L.direct || tune) {
         std::vector<double> sx(n1 + 1), sy(n2 + 1);
-        for (int k = 0; k <= n1; ++k) sx[k] = L.sx * h->wa[k];
-        for (int k = 0; k <= n2; ++k) sy[k] = L.sy * h->wb[k];
+        for (int k = 0; k <= n1; ++k) sx[k] = L.sx * h->pwa[k];
+        for (int k = 0; k <= n2; ++k) sy[k] = L.sy * h->pwb[k];
         L.swx = upload<R>(m, sx, st);
         L.swy = upload<R>(m, sy, st);
       }
       // FFT levels need symbols and twiddles; so does the fine level of a Galerkin hierarchy, whose
       // transforms every coarse level reuses
       if (!L.direct || tune || (galerkin && l == 0)) {
-        L.lam_x = upload<R>(m, symbol_host(h->wa, n1, L.L1, L.sx), st);
-        L.lam_y = upload<R>(m, symbol_host(h->wb, n2, L.L2, L.sy), st);
+        L.lam_x = upload<R>(m, symbol_host(h->pwa, n1, L.L1, L.sx), st);
+        L.lam_y = upload<R>(m, symbol_host(h->pwb, n2, L.L2, L.sy), st);
         L.tw_x = twiddles<R>(*H, m, L.L1, st);
         L.tw_y = twiddles<R>(*H, m, L.L2, st);
       }
@@ -630,8 +636,8 @@ std::unique_ptr<Hierarchy<R>> build_hierarchy(fde_handle* h) {
         L.mv.n2 = n2;
         const int ex = mfma_table_entries(n1), ey = mfma_table_entries(n2);
         std::vector<uint16_t> t1((size_t)ex * 512), t2((size_t)ex * 512), u1((size_t)ey * 512), u2((size_t)ey * 512);
-        mfma_tables(h->wa.data(), n1, L.sx, t1.data(), t2.data());
-        mfma_tables(h->wb.data(), n2, L.sy, u1.data(), u2.data());
+        mfma_tables(h->pwa.data(), n1, L.sx, t1.data(), t2.data());
+        mfma_tables(h->pwb.data(), n2, L.sy, u1.data(), u2.data());
         L.mv.tx1 = upload_raw(m, t1, st);
         L.mv.tx2 = upload_raw(m, t2, st);
         L.mv.ty1 = upload_raw(m, u1, st);
@@ -661,8 +667,8 @@ std::unique_ptr<Hierarchy<R>> build_hierarchy(fde_handle* h) {
     cv.n1[0] = C.n1;
     cv.n2[0] = C.n2;
     const int Hw = 1 << (nlev - 1);
-    std::vector<double> Qx = gal_Q(h->wa, H->lv[0].sx, Hw, C.n1, h->n1);
-    std::vector<double> Qy = gal_Q(h->wb, H->lv[0].sy, Hw, C.n2, h->n2);
+    std::vector<double> Qx = gal_Q(h->pwa, H->lv[0].sx, Hw, C.n1, h->n1);
+    std::vector<double> Qy = gal_Q(h->pwb, H->lv[0].sy, Hw, C.n2, h->n2);
     DevAlloc tmp;
     double* dQx = upload<double>(tmp, Qx, st);
     double* dQy = upload<double>(tmp, Qy, st);
@@ -908,6 +914,40 @@ int fgmres(fde_handle* h, Hierarchy<R>& H, const double* b, double* x, fde_stats
   return FDE_OK;
 }
 
+// Multigrid as a stand-alone solver: x_{k+1} = x_k + MG(b - A x_k) from x_0 = 0, with the FP64
+// true residual after every cycle, until ||b - A x|| <= rtol ||b|| or max_cycles.
+template <typename R>
+int mg_solve(fde_handle* h, Hierarchy<R>& H, const double* b, double* x, int max_cycles, fde_stats* stats) {
+  const size_t N = h->N;
+  HIPCHECK(launch_fill<double>(N, x, 0.0, h->stream));
+  cgs(h, CGS_INIT, 0, h->V, b, 2.0 * N * sizeof(double));  // r = b (column 0 of V), ||b||
+  read_state(h);
+  const OpView<double> op = h->cur.view(h->tw64_x, h->tw64_y, h->n1, h->n2, h->L1, h->L2);
+  R* z = static_cast<R*>(h->Z);
+  int k = 0;
+  while (!h->st_host->conv && k < max_cycles) {
+    vcycle_top<R>(h, H, h->V, nullptr, z, nullptr);
+    HIPCHECK(launch_add_to<R>(N, z, x, h->stream));
+    op_apply<double, double>(h, true, op, x, h->ay64, h->V, EP_RESID, b, nullptr, 0.0, nullptr);
+    cgs(h, CGS_RESNORM, 0, h->V, nullptr, (double)N * sizeof(double));
+    read_state(h);
+    ++k;
+    if (!std::isfinite(h->st_host->resnorm)) break;
+  }
+  const GmresState& s = *h->st_host;
+  if (stats) {
+    stats->iters = k;
+    stats->restarts = 0;
+    stats->converged = s.conv;
+    stats->reorth_steps = 0;
+    stats->relres_true = s.bnorm > 0 ? s.resnorm / s.bnorm : 0.0;
+    stats->relres_est = stats->relres_true;
+  }
+  if (!std::isfinite(s.resnorm)) return set_err(h, FDE_ENONFINITE, "the iterate became non-finite");
+  if (!s.conv) return set_err(h, FDE_ENOCONV, "cycle limit reached before the tolerance");
+  return FDE_OK;
+}
+
 int solve_impl(fde_handle* h, const double* b, double* x, fde_stats* stats) {
   if (h->fp32()) return fgmres<float>(h, *h->h32, b, x, stats);
   return fgmres<double>(h, *h->h64, b, x, stats);
@@ -1050,7 +1090,8 @@ size_t footprint_bytes(const fde_problem* pin) {
   b += (1 + 1 + 4 + 1) * N * 8;                     // ay64, rhs, scratch, async solution
   b += (p.restart + 1.0) * (double)basis_ld((size_t)N) * 8 + p.restart * N * R;
   b += (double)cgs_partials_len((size_t)N) * 8 + sizeof(GmresState) + 4096;
-  const bool gal = p.mg_variant == FDE_MG_GALERKIN && std::min(p.n1, p.n2) > p.coarsest_n;
+  const bool gal = (p.mg_variant == FDE_MG_GALERKIN || p.mg_variant == FDE_MG_BAND) &&
+                   std::min(p.n1, p.n2) > p.coarsest_n;
   int a1 = p.n1, a2 = p.n2, l = 0;
   double galscratch = 0;
   while (true) {
@@ -1156,6 +1197,17 @@ int fde_setup(const fde_problem* pin, const double* dp, const double* dm, const 
     h->sy = p.tau / (2.0 * std::pow(h->hy, p.beta));
     h->wa = wsgd_weights(p.alpha, p.n1 + 1);
     h->wb = wsgd_weights(p.beta, p.n2 + 1);
+    if (p.mg_variant == FDE_MG_BAND) {
+      // order 2: weights (1, -2, 1, 0, ...), T = tridiag(1, -2, 1), the Laplacian of Sec. 4.3
+      h->palpha = h->pbeta = 2.0;
+      h->pwa = wsgd_weights(2.0, p.n1 + 1);
+      h->pwb = wsgd_weights(2.0, p.n2 + 1);
+    } else {
+      h->palpha = p.alpha;
+      h->pbeta = p.beta;
+      h->pwa = h->wa;
+      h->pwb = h->wb;
+    }
     DevAlloc& m = h->mem;
     h->flags = dalloc<int>(m, 4);
     check_fields(h.get(), dp, dm, ep, em);
@@ -1245,6 +1297,17 @@ int fde_solve(fde_handle* h, const double* b, double* x, fde_stats* stats) {
   if (!b || !x) return set_err(h, FDE_EINVAL, "b or x is NULL");
   if (b == x) return set_err(h, FDE_EINVAL, "x may not alias b");
   return guarded(h, [&]() -> int { return solve_impl(h, b, x, stats); });
+}
+
+int fde_solve_mg(fde_handle* h, const double* b, double* x, int32_t max_cycles, fde_stats* stats) {
+  if (!h) return set_err(nullptr, FDE_EINVAL, "handle is NULL");
+  if (!b || !x) return set_err(h, FDE_EINVAL, "b or x is NULL");
+  if (b == x) return set_err(h, FDE_EINVAL, "x may not alias b");
+  if (max_cycles < 1) return set_err(h, FDE_EINVAL, "max_cycles must be >= 1");
+  return guarded(h, [&]() -> int {
+    if (h->fp32()) return mg_solve<float>(h, *h->h32, b, x, max_cycles, stats);
+    return mg_solve<double>(h, *h->h64, b, x, max_cycles, stats);
+  });
 }
 
 int fde_step_sources(fde_handle* h, const double* u_prev, int32_t nsrc, const double* phi, const double* const* S,
@@ -1421,7 +1484,7 @@ int fde_apply(fde_handle* h, int level, int prec, const double* x, double* y) {
   if (!h) return set_err(nullptr, FDE_EINVAL, "handle is NULL");
   if (!x || !y || x == y) return set_err(h, FDE_EINVAL, "bad x/y");
   return guarded(h, [&]() -> int {
-    if (level == 0 && prec == FDE_FP64) {
+    if (level == 0 && prec == FDE_FP64 && h->p.mg_variant != FDE_MG_BAND) {
       const OpView<double> op = h->cur.view(h->tw64_x, h->tw64_y, h->n1, h->n2, h->L1, h->L2);
       op_apply<double, double>(h, true, op, x, h->ay64, y, EP_APPLY, nullptr, nullptr, 0.0, nullptr);
       HIPCHECK(hipStreamSynchronize(h->stream));
@@ -1463,13 +1526,13 @@ int fde_level_diag(fde_handle* h, int level, double* diag) {
       auto& L = h->h64->lv.at(level);
       if (L.gal) HIPCHECK(launch_gal_diag<double>(L.gv, L.qx, L.qy, h->p.omega, nullptr, diag, h->stream));
       else
-        HIPCHECK(launch_diag<double>((int)L.N(), L.dpm, L.epm, L.sx * h->wa[1], L.sy * h->wb[1], h->p.omega,
+        HIPCHECK(launch_diag<double>((int)L.N(), L.dpm, L.epm, L.sx * h->pwa[1], L.sy * h->pwb[1], h->p.omega,
                                      nullptr, diag, h->stream));
     } else {
       auto& L = h->h32->lv.at(level);
       if (L.gal) HIPCHECK(launch_gal_diag<float>(L.gv, L.qx, L.qy, h->p.omega, nullptr, diag, h->stream));
       else
-        HIPCHECK(launch_diag<float>((int)L.N(), L.dpm, L.epm, L.sx * h->wa[1], L.sy * h->wb[1], h->p.omega,
+        HIPCHECK(launch_diag<float>((int)L.N(), L.dpm, L.epm, L.sx * h->pwa[1], L.sy * h->pwb[1], h->p.omega,
                                     nullptr, diag, h->stream));
     }
     HIPCHECK(hipStreamSynchronize(h->stream));

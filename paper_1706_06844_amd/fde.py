@@ -13,7 +13,8 @@ import torch
 
 from . import _lib as L
 from ._lib import (FDE_EAGAIN, FDE_EDEVICE, FDE_EINVAL, FDE_ENEGCOEF, FDE_ENOCONV, FDE_ENOMEM,  # noqa
-                   FDE_ENONFINITE, FDE_FP64, FDE_MG_GALERKIN, FDE_MG_GEOMETRIC, FDE_MIXED_BF16GEMM,
+                   FDE_ENONFINITE, FDE_FP64, FDE_MG_BAND, FDE_MG_GALERKIN, FDE_MG_GEOMETRIC,
+                   FDE_MIXED_BF16GEMM,
                    FDE_MIXED_FP32, FDE_OK, fde_problem, fde_stats)
 
 
@@ -127,6 +128,12 @@ def fde_step_sources(h: Handle, u_prev, phis: Sequence[float], fields: Sequence[
 def fde_solve(h: Handle, b, x) -> Dict:
     st = fde_stats()
     rc = _lib().fde_solve(h.ptr, _ptr(b, "b"), _ptr(x, "x"), ctypes.byref(st))
+    return _stats_result(rc, st, h)
+
+
+def fde_solve_mg(h: Handle, b, x, max_cycles: int = 200) -> Dict:
+    st = fde_stats()
+    rc = _lib().fde_solve_mg(h.ptr, _ptr(b, "b"), _ptr(x, "x"), int(max_cycles), ctypes.byref(st))
     return _stats_result(rc, st, h)
 
 

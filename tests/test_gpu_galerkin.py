@@ -133,3 +133,55 @@ def test_galerkin_c2_step_matches_oracle():
 
     ref = solve_step(op, rhs(op, u0, v), IterativeSolver(rtol=1e-12))
     assert rel(host(un), ref) <= 1e-9
+
+
+# ---- the band preconditioner P_2 (Sec. 4.3): the Laplacian in place of the fractional factors ----
+def _band_operator(p):
+    import copy
+
+    q = copy.copy(p)
+    q.alpha = q.beta = 2.0
+    return operator_from_problem(q, 0.0)
+
+
+@pytest.mark.parametrize("prec", [fde.FDE_FP64, fde.FDE_MIXED_FP32])
+def test_band_hierarchy_and_vcycle(prec):
+    n = 63
+    p = workloads.config_c2(n, 32)
+    h = make_handle(p, precision=prec, mg_variant=fde.FDE_MG_BAND)
+    opb = _band_operator(p)
+    lv = omg.galerkin_hierarchy_composed(opb)
+    assert fde.fde_num_levels(h) == len(lv)
+    tol = 1e-12 if prec == fde.FDE_FP64 else 3e-6
+    for l in range(len(lv)):
+        U = _rand((lv[l].n2, lv[l].n1), 500 + l)
+        y = dev(np.zeros_like(U))
+        fde.fde_apply(h, l, prec, dev(U), y)
+        assert rel(host(y), lv[l].apply(U)) <= tol, l
+    B = _rand((n, n), 17)
+    x = dev(np.zeros_like(B))
+    fde.fde_vcycle(h, dev(B), x)
+    assert rel(host(x), omg.VCycle(lv)(B)) <= (1e-11 if prec == fde.FDE_FP64 else 2e-5)
+
+
+@pytest.mark.parametrize("cfg", ["c1", "c2"])
+def test_band_preconditioned_solve(cfg):
+    from oracle.krylov import fgmres
+
+    n = 63 if cfg == "c1" else 127
+    p = workloads.config_c1(n) if cfg == "c1" else workloads.config_c2(n, 32)
+    op = operator_from_problem(p, 0.0)
+    b = rhs(op, workloads.sample_u0(p), workloads.sample_source(p, 0.5 * p.tau))
+    its = {}
+    for v in (fde.FDE_MG_GEOMETRIC, fde.FDE_MG_BAND):
+        h = make_handle(p, mg_variant=v, maxit=1000)
+        x = dev(np.zeros_like(b))
+        st = fde.fde_solve(h, dev(b), x)
+        assert st["converged"]
+        its[v] = st["iters"]
+        assert rel(host(x), solve_step(op, b)) <= 1e-9
+    ref = fgmres(op.apply, b, omg.VCycle(omg.galerkin_hierarchy_composed(_band_operator(p))), rtol=1e-10,
+                 restart=20, maxit=1000)
+    note(f"{cfg} n={n}: GMRES iterations with the multigrid preconditioner {its[fde.FDE_MG_GEOMETRIC]}, "
+         f"with the band preconditioner {its[fde.FDE_MG_BAND]} (oracle {ref.iters})")
+    assert abs(its[fde.FDE_MG_BAND] - ref.iters) <= 2

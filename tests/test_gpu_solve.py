@@ -175,3 +175,21 @@ def test_time_dependent_coefficients_example2(prec, variant):
     assert rel(host(u), ref) <= 1e-9
     X, Y = workloads.grid(p)
     note(f"example 2 error at T: {np.abs(host(u) - p.u_exact(X, Y, p.T)).max():.3e}")
+
+
+@pytest.mark.parametrize("prec", [fde.FDE_FP64, fde.FDE_MIXED_FP32])
+def test_multigrid_as_standalone_solver(prec):
+    # the V-cycle iteration without GMRES: same cycle count as the oracle's iteration, same solution
+    from oracle import multigrid as omg
+    from oracle.cn import rhs, solve_step
+
+    p = workloads.config_c1(63)
+    op = operator_from_problem(p, 0.0)
+    b = rhs(op, workloads.sample_u0(p), workloads.sample_source(p, 0.5 * p.tau))
+    _, k_ref, _ = omg.mg_solve(op.apply, b, omg.VCycle(omg.geometric_hierarchy(op)), 1e-10, 200)
+    h = make_handle(p, prec)
+    x = dev(np.zeros_like(b))
+    st = fde.fde_solve_mg(h, dev(b), x, 200)
+    note(f"stand-alone multigrid prec={prec}: {st['iters']} cycles (oracle {k_ref})")
+    assert st["converged"] and abs(st["iters"] - k_ref) <= 1
+    assert rel(host(x), solve_step(op, b)) <= 1e-9

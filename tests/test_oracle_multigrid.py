@@ -163,3 +163,33 @@ def test_geometric_hierarchy_shapes_and_injection():
     p = workloads.config_c2(31, 32)
     X, Y = np.meshgrid(np.arange(1, 32) / 32, np.arange(1, 32) / 32)
     np.testing.assert_allclose(lv[1].dp, p.dp(X, Y, 0.0), rtol=1e-15)
+
+
+def test_standalone_vcycle_iteration_contracts_at_the_spectral_radius():
+    # the stand-alone V-cycle iteration propagates the error with I - V A: the residual ratios
+    # settle near its spectral radius (in a norm-independent way, so within a margin) and the
+    # iteration converges, C1-like problem on a grid small enough for the dense matrix
+    import workloads
+    from oracle.cn import rhs
+    from oracle.operator import operator_from_problem
+
+    p = workloads.config_c1(31)
+    op = operator_from_problem(p, 0.0)
+    vc = mg.VCycle(mg.geometric_hierarchy(op))
+    rho = max(abs(np.linalg.eigvals(mg.vcycle_iteration_matrix(vc))))
+    b = rhs(op, workloads.sample_u0(p), workloads.sample_source(p, 0.5 * p.tau))
+    x, k, hist = mg.mg_solve(op.apply, b, vc, 1e-10, 200)
+    assert hist[-1] <= 1e-10 * hist[0]
+    ratios = np.array(hist[1:]) / np.array(hist[:-1])
+    tail = ratios[len(ratios) // 2:]
+    assert np.all(tail <= rho * 1.5 + 1e-3)
+    assert np.exp(np.mean(np.log(tail))) == pytest.approx(rho, rel=0.1)
+    # mesh independence of the cycle count (Sec. 4: the V-cycle is optimal for this class)
+    p2 = workloads.config_c1(63)
+    op2 = operator_from_problem(p2, 0.0)
+    b2 = rhs(op2, workloads.sample_u0(p2), workloads.sample_source(p2, 0.5 * p2.tau))
+    _, k2, _ = mg.mg_solve(op2.apply, b2, mg.VCycle(mg.geometric_hierarchy(op2)), 1e-10, 200)
+    assert abs(k2 - k) <= 2
+    # and it solves the system
+    from oracle.cn import solve_step
+    np.testing.assert_allclose(x, solve_step(op, b), rtol=0, atol=1e-8 * np.abs(x).max())
