@@ -190,6 +190,8 @@ int fde_level_diag(fde_handle* h, int level, double* diag);
 #define FDE_KFAM_COARSE 8    /* one-workgroup V-cycle of the small levels                        */
 #define FDE_KFAM_UPDATE 9    /* x += Z y                                                         */
 #define FDE_KFAM_CGS_FINALIZE 10 /* one-workgroup combination of the Gram-Schmidt partials, Givens  */
+                                 /* (problems of up to 32 * 2048 unknowns combine them inside the  */
+                                 /* pass, in its last workgroup, and never launch this family)     */
 #define FDE_KFAM_COUNT 11
 int fde_profile_enable(fde_handle* h, uint32_t family_mask);
 int fde_profile_read(fde_handle* h, int family, int64_t* launches, double* total_ms, double* bytes);

@@ -205,6 +205,8 @@ struct GmresState {
   int maxit, restart;
   int orth;       // Gram-Schmidt policy: 0 one pass, 1 always two passes, 2 second pass when needed
   int reorth;     // 1: the current Arnoldi step takes the second pass
+  unsigned ticket;  // workgroups of a small pass that have written their partials
+  int pad1_;
   double g[kMaxRestart + 1], cs[kMaxRestart], sn[kMaxRestart];
   double Rm[kMaxRestart * kMaxRestart];  // column j in Rm[j*kMaxRestart + i], i <= j
   double h1[kMaxRestart + 1], h2[kMaxRestart + 1];
@@ -223,7 +225,9 @@ hipError_t launch_cgs_pass(int kind, size_t N, int nv, double* V, size_t ldv, do
                            const double* src, GmresState* st, double* partials, int cap,
                            hipStream_t s);
 // Combines the partials of the preceding pass (same kind, nv, cap) and updates the solver state.
+// Not needed (and not launched) when cgs_fused(nv, cap): the pass then finalises itself.
 hipError_t launch_cgs_finalize(int kind, int nv, double* partials, GmresState* st, int cap, hipStream_t s);
+bool cgs_fused(int nv, int cap);
 int cgs_grid(size_t N);
 size_t cgs_partials_len(size_t N);
 // Column stride of the Krylov basis for N unknowns (multiple of 64 doubles).

@@ -75,10 +75,25 @@ __device__ void givens_step(GmresState* st, int j, double nrm) {
   if (est <= st->atol || st->iters >= st->maxit || breakdown || j + 1 >= st->restart) st->done = 1;
 }
 
+constexpr int kFusedMaxGrid = 32;  // passes with at most this many workgroups finalise themselves
+
+// LDS of the combination of a pass's partials: the solver state, the combined rows, and a staging
+// buffer of PL partials.
+template <int PL>
+struct FinLds {
+  GmresState ls;
+  double fin[kMaxRestart + 2];
+  double pl[PL];
+};
+
+template <int PL>
+__device__ void finalize_block(int kind, int nv, int G, const double* partials, GmresState* gst, FinLds<PL>& F);
+
 // One pass over the basis.  Each thread handles pairs of consecutive entries (16-byte loads); the
 // basis columns and w are padded to an even length, so the second entry of the last pair is
-// readable and is masked to zero.
-template <int MAXV>
+// readable and is masked to zero.  FUSED: the last workgroup to finish (counted on the state's
+// ticket) combines the partials itself, which saves small problems a launch per pass.
+template <int MAXV, bool FUSED>
 __global__ __launch_bounds__(kCgsBlock) void cgs_kernel(int kind, int N, int nv, const double* __restrict__ V,
                                                         size_t ldv, double* __restrict__ w,
                                                         const double* __restrict__ src, GmresState* st,
@@ -171,37 +186,50 @@ __global__ __launch_bounds__(kCgsBlock) void cgs_kernel(int kind, int N, int nv,
     for (int q = 0; q < kCgsWaves; ++q) s += red[q][threadIdx.x];
     partials[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = s;
   }
+  if constexpr (FUSED) {
+    __shared__ int last;
+    __threadfence();  // this workgroup's partials are visible before its ticket
+    __syncthreads();
+    if (threadIdx.x == 0) last = (atomicAdd(&st->ticket, 1u) == gridDim.x - 1);
+    __syncthreads();
+    if (!last) return;
+    __threadfence();  // and the other workgroups' partials are seen after it
+    if (threadIdx.x == 0) atomicExch(&st->ticket, 0u);
+    __shared__ FinLds<kFusedMaxGrid * (kMaxRestart + 2)> F;
+    finalize_block(kind, nv, (int)gridDim.x, partials, st, F);
+  }
 }
 
-// Combines the G per-block partials of a pass in block order (one workgroup) and updates the
-// solver state.  A separate launch instead of a last-block ticket: one counter hit by every block
-// of a wide grid serialises at the memory side.
-__global__ __launch_bounds__(kFinBlock) void cgs_finalize_kernel(int kind, int nv, int G,
-                                                                 const double* __restrict__ partials,
-                                                                 GmresState* gst) {
-  // The state is copied into LDS by the whole workgroup (one round of independent loads), updated
-  // there by one thread, and copied back: the update's many small dependent accesses then stay on
-  // chip instead of paying a device-memory round trip each.
+// Combination of a pass's partials and the state update, run by one whole workgroup.  The state is
+// copied into LDS by the workgroup (one round of independent loads), updated there by one thread,
+// and copied back: the update's many small dependent accesses then stay on chip instead of paying a
+// device-memory round trip each.  `partials` is read through volatile loads (the fused path reads
+// what other workgroups of the same launch wrote).
+template <int PL>
+__device__ void finalize_block(int kind, int nv, int G, const double* partials, GmresState* gst, FinLds<PL>& F) {
   constexpr int kWords = sizeof(GmresState) / 4;
   static_assert(sizeof(GmresState) % 4 == 0, "state is copied as 32-bit words");
-  __shared__ GmresState ls;
-  __shared__ double fin[kMaxRestart + 2];
-  __shared__ double pl[kFinLds];
+  GmresState& ls = F.ls;
+  double* fin = F.fin;
+  double* pl = F.pl;
+  const volatile double* vp = partials;
   {
     const unsigned* src = reinterpret_cast<const unsigned*>(gst);
     unsigned* dst = reinterpret_cast<unsigned*>(&ls);
     for (int k = threadIdx.x; k < kWords; k += blockDim.x) dst[k] = src[k];
   }
+  __syncthreads();
+  if (threadIdx.x == 0) ls.ticket = 0;
   const bool dots = (kind == CGS_DOTS || kind == CGS_UPDATE_DOTS);
   const bool norm = (kind != CGS_UPDATE_DOTS);
   const int nres = (dots ? nv : 0) + (norm ? 1 : 0);
   // the partials are fetched in rounds of independent loads (as many rows as fit the LDS buffer,
   // usually all of them), then summed from LDS in block order
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const int rows = kFinLds / G;
+  const int rows = PL / G;
   for (int r0 = 0; r0 < nres; r0 += rows) {
     const int nr = min(rows, nres - r0);
-    for (int e = threadIdx.x; e < nr * G; e += blockDim.x) pl[e] = partials[(size_t)r0 * G + e];
+    for (int e = threadIdx.x; e < nr * G; e += blockDim.x) pl[e] = vp[(size_t)r0 * G + e];
     __syncthreads();
     for (int r = wid; r < nr; r += nw) {
       double v = 0.0;
@@ -265,6 +293,16 @@ __global__ __launch_bounds__(kFinBlock) void cgs_finalize_kernel(int kind, int n
   }
 }
 
+// Combines the G per-block partials of a pass in block order and updates the solver state: a
+// launch of its own for wide passes, where one counter hit by every workgroup of the grid (the
+// last-workgroup ticket of the fused form) would serialise at the memory side.
+__global__ __launch_bounds__(kFinBlock) void cgs_finalize_kernel(int kind, int nv, int G,
+                                                                 const double* __restrict__ partials,
+                                                                 GmresState* gst) {
+  __shared__ FinLds<kFinLds> F;
+  finalize_block(kind, nv, G, partials, gst, F);
+}
+
 // Grid of a pass: wide passes (many columns) stream best with one workgroup per CU, narrow ones with
 // two; `cap` is the size-dependent maximum (cgs_grid).
 int cgs_pass_grid(int nv, int cap) {
@@ -280,21 +318,29 @@ hipError_t launch_cgs_pass(int kind, size_t N, int nv, double* V, size_t ldv, do
   if (kind == CGS_INIT && !src) return hipErrorInvalidValue;
   const int n = (int)N;
   const int grid = cgs_pass_grid(nv, cap);
-#define L_(M)                                                                                            \
-  hipLaunchKernelGGL((cgs_kernel<M>), dim3(grid), dim3(kCgsBlock), 0, s, kind, n, nv, V, ldv, w, src, st, \
-                     partials)
-  if (nv <= 4) L_(4);
-  else if (nv <= 8) L_(8);
-  else if (nv <= 12) L_(12);
-  else if (nv <= 16) L_(16);
-  else if (nv <= 24) L_(24);
-  else L_(kMaxRestart + 1);
+  const bool fused = grid <= kFusedMaxGrid;
+#define L_(M)                                                                                                   \
+  if (fused)                                                                                                    \
+    hipLaunchKernelGGL((cgs_kernel<M, true>), dim3(grid), dim3(kCgsBlock), 0, s, kind, n, nv, V, ldv, w, src, st, \
+                       partials);                                                                               \
+  else                                                                                                          \
+    hipLaunchKernelGGL((cgs_kernel<M, false>), dim3(grid), dim3(kCgsBlock), 0, s, kind, n, nv, V, ldv, w, src,    \
+                       st, partials)
+  if (nv <= 4) { L_(4); }
+  else if (nv <= 8) { L_(8); }
+  else if (nv <= 12) { L_(12); }
+  else if (nv <= 16) { L_(16); }
+  else if (nv <= 24) { L_(24); }
+  else { L_(kMaxRestart + 1); }
 #undef L_
   return hipGetLastError();
 }
 
+bool cgs_fused(int nv, int cap) { return cgs_pass_grid(nv, cap) <= kFusedMaxGrid; }
+
 hipError_t launch_cgs_finalize(int kind, int nv, double* partials, GmresState* st, int cap, hipStream_t s) {
   if (nv > kMaxRestart + 1 || cap < 1) return hipErrorInvalidValue;
+  if (cgs_fused(nv, cap)) return hipErrorInvalidValue;  // the pass has combined its partials itself
   hipLaunchKernelGGL(cgs_finalize_kernel, dim3(1), dim3(kFinBlock), 0, s, kind, nv, cgs_pass_grid(nv, cap), partials,
                      st);
   return hipGetLastError();

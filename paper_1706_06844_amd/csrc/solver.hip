@@ -833,11 +833,12 @@ void read_state(fde_handle* h) {
 }
 
 // One Gram-Schmidt pass (timed as the CGS family) and the combination of its partials (timed
-// separately).  Negative `bytes` mark the conditional second pass.
+// separately; small passes combine them in their last workgroup).  Negative `bytes` mark the conditional second pass.
 void cgs(fde_handle* h, int kind, int nv, double* w, const double* src, double bytes) {
   timed(h, FDE_KFAM_CGS, bytes, [&] {
     return launch_cgs_pass(kind, h->N, nv, h->V, h->ldv, w, src, h->st, h->partials, h->cgs_grid, h->stream);
   });
+  if (cgs_fused(nv, h->cgs_grid)) return;
   timed(h, FDE_KFAM_CGS_FINALIZE, bytes < 0 ? -1e-300 : 0.0,
         [&] { return launch_cgs_finalize(kind, nv, h->partials, h->st, h->cgs_grid, h->stream); });
 }
