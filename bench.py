@@ -7,10 +7,12 @@ coefficients d+ = 1+x+y^2, d- = 2-x+y, e+ = 1+xy, e- = 1.5+0.5 sin(pi x) y, tau 
 source = manufactured term + seeded N(0,1) field (seed 3), GMRES(20) to relative residual 1e-10,
 one geometric V(1,1) cycle per iteration.  A step is one CN step: right-hand side plus solve.
 
-Prints one JSON line: the mixed-precision (FP32 preconditioner, FP64 outer) throughput as `value`,
-the plain FP64 throughput beside it, per-step latency percentiles, iterations per step, the error of
-the mixed result against the FP64 GPU result, the live-timed roofline of the dominant kernel, and
-the FP64 CPU oracle timed on a bounded sample of the same workload.
+Prints one JSON line: the mixed-precision throughput as `value` (FP32 V-cycle and FP32 restart
+cycles refining the FP64 iterate from FP64 true residuals, to the same FP64 residual tolerance), the
+FP32-preconditioner-only (`mixed_*`) and plain FP64 (`fp64_*`) throughputs beside it, per-step
+latency percentiles, iterations per step, the errors against the FP64 GPU result, the live-timed
+roofline of the dominant kernel, and the FP64 CPU oracle timed on a bounded sample of the same
+workload.
 """
 from __future__ import annotations
 
@@ -62,7 +64,7 @@ def parse():
     ap.add_argument("--maxit", type=int, default=4000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=24)
-    ap.add_argument("--only", choices=["mixed", "fp64", "bf16"], default=None)
+    ap.add_argument("--only", choices=["cycle", "mixed", "fp64", "bf16"], default=None)
     ap.add_argument("--workload", choices=["c3", "c4", "c5"], default="c3",
                     help="c3: the single 2047^2 instance (default, the headline line); c4: 64 batched "
                          "instances; c5: served requests with Poisson arrivals")
@@ -80,6 +82,20 @@ def parse():
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_groups(prec):
+    """Profiling families grouped by the kernel they time (template variants of one kernel count as
+    one kernel).  With FP32 cycles the Arnoldi product runs the same FP32 fine-level FFT kernels as
+    the V-cycle's fine level."""
+    from paper_1706_06844_amd import fde
+
+    g = {f: [f] for f in fde.L.KFAM if f != "cgs_finalize"}
+    if prec == fde.FDE_MIXED_FP32_CYCLE:
+        for d in ("y", "x"):
+            g[f"fft_fine_{d}"] = [f"outer_{d}", f"mg0_{d}"]
+            del g[f"outer_{d}"], g[f"mg0_{d}"]
+    return g
 
 
 def run_precision(prec, p, dev_fields, S, phis, u0, steps, warmup, maxit, profile_family=None):
@@ -110,29 +126,39 @@ def run_precision(prec, p, dev_fields, S, phis, u0, steps, warmup, maxit, profil
         torch.cuda.synchronize()
         return time.perf_counter() - t0, lat, its, reo, a
 
-    # warmup, with every kernel family timed to find the dominant one
+    groups = kernel_groups(prec)
+
+    def group_sum(prof, g):
+        fams = groups[g]
+        return {k: sum(prof[f][k] for f in fams) for k in ("launches", "ms", "bytes")}
+
+    def dominant(prof):
+        cand = {g: group_sum(prof, g) for g in groups}
+        cand = {g: v for g, v in cand.items() if v["launches"] > 0}
+        return max(cand, key=lambda g: cand[g]["ms"]) if cand else None
+
+    # warmup, with every kernel family timed to find the dominant kernel
     fde.fde_profile_enable(h)
     run(warmup, "warmup")
     prof = fde.fde_profile_read(h)
-    fam = profile_family
-    cand = {k: v for k, v in prof.items() if v["launches"] > 0}
-    if fam is None and cand:
-        fam = max(cand, key=lambda k: cand[k]["ms"])
+    fam = profile_family or dominant(prof)
     fde.fde_profile_reset(h)
     # without warmup there is nothing to choose from: time every family in the timed run
     if fam is None:
         mask = (1 << len(fde.L.KFAM)) - 1
     else:
-        mask = 1 << fde.L.KFAM.index(fam)
-        if fam == "cgs":  # the passes' partials are combined by a separate one-workgroup kernel
+        mask = 0
+        for f in groups[fam]:
+            mask |= 1 << fde.L.KFAM.index(f)
+        if fam == "cgs":  # wide passes' partials are combined by a separate one-workgroup kernel
             mask |= 1 << fde.L.KFAM.index("cgs_finalize")
     fde.fde_profile_enable(h, mask)
     elapsed, lat, its, reo, u_final = run(steps, "timed")
     timed = fde.fde_profile_read(h)
     if fam is None:
         prof = timed
-        fam = max(timed, key=lambda k: timed[k]["ms"])
-    live = timed[fam]
+        fam = dominant(timed)
+    live = group_sum(timed, fam)
     fin = timed.get("cgs_finalize") if fam == "cgs" else None
     out = {"elapsed": elapsed, "lat": lat, "iters": its, "u": u_final.clone(), "family": fam,
            "live": live, "fin": fin, "warm_profile": prof, "reorth": reo}
@@ -410,7 +436,8 @@ def main():
         torch.cuda.synchronize()
         log(f"copy calibration: 3 copies of {u0.numel() * 8} bytes")
     res = {}
-    order = [("mixed", fde.FDE_MIXED_FP32), ("fp64", fde.FDE_FP64), ("bf16", fde.FDE_MIXED_BF16GEMM)]
+    order = [("cycle", fde.FDE_MIXED_FP32_CYCLE), ("mixed", fde.FDE_MIXED_FP32), ("fp64", fde.FDE_FP64),
+             ("bf16", fde.FDE_MIXED_BF16GEMM)]
     for name, prec in order:
         if args.only and args.only != name:
             continue
@@ -421,7 +448,7 @@ def main():
         r = res[name]
         log(f"{name}: {args.steps / r['elapsed']:.3f} steps/s, mean iters {np.mean(r['iters']):.1f}, "
             f"dominant {r['family']}")
-    main_name = "mixed" if "mixed" in res else ("fp64" if "fp64" in res else "bf16")
+    main_name = next(k for k in ("cycle", "mixed", "fp64", "bf16") if k in res)
     m = res[main_name]
     lat_ms = np.array(m["lat"]) * 1e3
     live = m["live"]
@@ -439,12 +466,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"mixed": "f64+f32", "fp64": "f64", "bf16": "f64+f32+bf16"}[main_name],
+        "dtype": {"cycle": "f64+f32", "mixed": "f64+f32", "fp64": "f64", "bf16": "f64+f32+bf16"}[main_name],
         "data": "synthetic",
         "config": {"workload": f"C3 anisotropic instance {args.n}x{args.n}, alpha=1.2, beta=1.9, "
                                "C2 variable coefficients, tau=1/16, manufactured + N(0,1) source "
                                "(seed 3)",
-                   "precision": {"mixed": "FP32 V-cycle in FP64 flexible GMRES", "fp64": "FP64",
+                   "precision": {"cycle": "FP32 V-cycle and FP32 restart cycles (basis, Arnoldi products) "
+                                          "refining the FP64 iterate from FP64 true residuals",
+                                 "mixed": "FP32 V-cycle in FP64 flexible GMRES", "fp64": "FP64",
                                  "bf16": "V-cycle with BF16 MFMA operator passes (FP32 accumulation) in FP64 "
                                          "flexible GMRES"}[main_name],
                    "gmres": "GMRES(20), rtol 1e-10, x0 = 0", "multigrid": "geometric V(1,1), damped Jacobi 0.7"},
@@ -464,24 +493,26 @@ def main():
         out["roofline"]["finalize_us_per_launch"] = us_fin
         # the whole Gram-Schmidt stage: pass plus the combination of its partials
         out["roofline"]["stage_achieved_with_finalize"] = bytes_per_launch / (stage_us * 1e-6) / 1e9
-    if "fp64" in res and main_name == "mixed":
-        f = res["fp64"]
-        out["fp64_value"] = args.steps / f["elapsed"]
-        out["fp64_ms_per_step"] = 1e3 * f["elapsed"] / args.steps
-        out["fp64_iters_per_step"] = float(np.mean(f["iters"]))
-        out["fp64_p50_ms"] = float(np.percentile(np.array(f["lat"]) * 1e3, 50))
-        out["fp64_p99_ms"] = float(np.percentile(np.array(f["lat"]) * 1e3, 99))
-        du = (m["u"] - f["u"]).double()
-        out["err_mixed_vs_fp64"] = float(torch.linalg.norm(du) / torch.linalg.norm(f["u"]))
-        out["mixed_speedup_vs_fp64"] = out["value"] / out["fp64_value"]
-    if "bf16" in res and main_name != "bf16":
-        g = res["bf16"]
-        ref = res["fp64"]["u"] if "fp64" in res else m["u"]
-        out["bf16_value"] = args.steps / g["elapsed"]
-        out["bf16_ms_per_step"] = 1e3 * g["elapsed"] / args.steps
-        out["bf16_iters_per_step"] = float(np.mean(g["iters"]))
-        out["err_bf16_vs_fp64"] = float(torch.linalg.norm((g["u"] - ref).double()) / torch.linalg.norm(ref))
-        out["bf16_warm_profile_ms"] = {k: round(v["ms"], 3) for k, v in g["warm_profile"].items()}
+    ref = res["fp64"]["u"] if "fp64" in res else None
+
+    def err_vs_fp64(r):
+        return float(torch.linalg.norm((r["u"] - ref).double()) / torch.linalg.norm(ref))
+
+    if ref is not None and main_name != "fp64":
+        out["err_vs_fp64"] = err_vs_fp64(m)
+    for name, r in res.items():
+        if name == main_name:
+            continue
+        out[f"{name}_value"] = args.steps / r["elapsed"]
+        out[f"{name}_ms_per_step"] = 1e3 * r["elapsed"] / args.steps
+        out[f"{name}_iters_per_step"] = float(np.mean(r["iters"]))
+        out[f"{name}_p50_ms"] = float(np.percentile(np.array(r["lat"]) * 1e3, 50))
+        out[f"{name}_p99_ms"] = float(np.percentile(np.array(r["lat"]) * 1e3, 99))
+        if ref is not None and name != "fp64":
+            out[f"err_{name}_vs_fp64"] = err_vs_fp64(r)
+        out[f"{name}_warm_profile_ms"] = {k: round(v["ms"], 3) for k, v in r["warm_profile"].items()}
+    if "fp64" in res and main_name != "fp64":
+        out["speedup_vs_fp64"] = out["value"] / out["fp64_value"]
     out["warm_profile_ms"] = {k: round(v["ms"], 3) for k, v in m["warm_profile"].items()}
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on a bounded sample")

@@ -54,6 +54,14 @@ extern "C" {
 #define FDE_MIXED_BF16GEMM 2   /* as FDE_MIXED_FP32; the rediscretised levels too large for the dense
                                   kernel (n > 255) apply their Toeplitz factors as BF16 MFMA products
                                   with FP32 accumulation instead of FP32 FFTs                        */
+#define FDE_MIXED_FP32_CYCLE 3 /* as FDE_MIXED_FP32, and each restart cycle in FP32 too: the Krylov
+                                  basis is stored in FP32 and A z_j is the preconditioner's FP32
+                                  fine-level operator (dot products, norms and the least-squares
+                                  problem stay FP64).  Every cycle starts from the FP64 true residual
+                                  b - A x and adds its correction to the FP64 iterate, so a restarted
+                                  solve is iterative refinement with FP32 inner solves and the
+                                  tolerance still holds for the FP64 residual.  Needs a rediscretised
+                                  fine level: not with FDE_MG_BAND                                 */
 
 #define FDE_MG_GEOMETRIC 0     /* rediscretised coarse operators, Sec. 4.2 (the paper's P_MGM)      */
 #define FDE_MG_GALERKIN 1      /* Galerkin coarse operators R A P, Sec. 4 TGM step 3 (tilde P_MGM)   */
@@ -69,7 +77,7 @@ typedef struct fde_problem {
   int32_t n1, n2;       /* interior points in x and y; multigrid needs 2^l - 1 with l >= 3         */
   double a1, b1, a2, b2;/* domain (a1,b1) x (a2,b2), a < b                                         */
   double tau;           /* time step, > 0                                                          */
-  int32_t precision;    /* FDE_FP64 | FDE_MIXED_FP32 | FDE_MIXED_BF16GEMM                          */
+  int32_t precision;    /* FDE_FP64 | FDE_MIXED_FP32 | FDE_MIXED_BF16GEMM | FDE_MIXED_FP32_CYCLE   */
   int32_t mg_variant;   /* FDE_MG_GEOMETRIC | FDE_MG_GALERKIN | FDE_MG_BAND                        */
   double omega;         /* Jacobi damping (Lemma lemsmo), 0 < omega <= 1; 0 selects 0.7             */
   int32_t nu_pre;       /* pre-smoothing steps per level, >= 0 (< 0 selects 1)                      */

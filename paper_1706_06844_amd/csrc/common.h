@@ -216,14 +216,16 @@ struct GmresState {
 
 // Passes of one Arnoldi step: DOTS (h1 = V^T w and ||w||^2, decides the second pass), UPDATE_DOTS
 // (second pass only: w -= V h1, h2 = V^T w), UPDATE_NORM (w -= V h, h = h2 or h1, then ||w|| and the
-// Givens update); INIT (w = src, ||src||) and RESNORM (||w||) start a solve and a cycle.
+// Givens update); INIT (w = src, ||src||) and RESNORM (||w||, or w = src and ||src|| when src is
+// given) start a solve and a cycle.
 enum CgsKind : int { CGS_DOTS = 0, CGS_UPDATE_DOTS = 1, CGS_UPDATE_NORM = 2, CGS_INIT = 3, CGS_RESNORM = 4 };
-// One fused pass over the basis V[0..nv) (FP64, column stride ldv: even, columns 16-byte aligned)
-// and w (16-byte aligned, readable up to N rounded up to even).
+// One fused pass over the basis V[0..nv) (FP64 or FP32 storage TV, column stride ldv a multiple of
+// 16 bytes' worth of entries, columns 16-byte aligned) and w (16-byte aligned, readable and
+// writable up to N rounded up to 16 bytes); src is FP64.
 // Streams the pass and writes per-workgroup partials; `cap` bounds the grid (cgs_grid(N)).
-hipError_t launch_cgs_pass(int kind, size_t N, int nv, double* V, size_t ldv, double* w,
-                           const double* src, GmresState* st, double* partials, int cap,
-                           hipStream_t s);
+template <typename TV>
+hipError_t launch_cgs_pass(int kind, size_t N, int nv, TV* V, size_t ldv, TV* w, const double* src,
+                           GmresState* st, double* partials, int cap, hipStream_t s);
 // Combines the partials of the preceding pass (same kind, nv, cap) and updates the solver state.
 // Not needed (and not launched) when cgs_fused(nv, cap): the pass then finalises itself.
 hipError_t launch_cgs_finalize(int kind, int nv, double* partials, GmresState* st, int cap, hipStream_t s);

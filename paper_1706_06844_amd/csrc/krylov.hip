@@ -89,15 +89,43 @@ struct FinLds {
 template <int PL>
 __device__ void finalize_block(int kind, int nv, int G, const double* partials, GmresState* gst, FinLds<PL>& F);
 
-// One pass over the basis.  Each thread handles pairs of consecutive entries (16-byte loads); the
-// basis columns and w are padded to an even length, so the second entry of the last pair is
-// readable and is masked to zero.  FUSED: the last workgroup to finish (counted on the state's
-// ticket) combines the partials itself, which saves small problems a launch per pass.
-template <int MAXV, bool FUSED>
-__global__ __launch_bounds__(kCgsBlock) void cgs_kernel(int kind, int N, int nv, const double* __restrict__ V,
-                                                        size_t ldv, double* __restrict__ w,
+// 16-byte vectors of the basis type: each thread streams VEC consecutive entries per load.
+template <typename TV>
+struct Vec16 {
+  static constexpr int VEC = 16 / (int)sizeof(TV);
+};
+template <typename TV>
+__device__ __forceinline__ void load16(const TV* p, TV (&v)[Vec16<TV>::VEC]) {
+  if constexpr (sizeof(TV) == 8) {
+    const double2 a = *reinterpret_cast<const double2*>(p);
+    v[0] = a.x;
+    v[1] = a.y;
+  } else {
+    const float4 a = *reinterpret_cast<const float4*>(p);
+    v[0] = a.x;
+    v[1] = a.y;
+    v[2] = a.z;
+    v[3] = a.w;
+  }
+}
+template <typename TV>
+__device__ __forceinline__ void store16(TV* p, const TV (&v)[Vec16<TV>::VEC]) {
+  if constexpr (sizeof(TV) == 8) *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
+  else *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+}
+
+// One pass over the basis (FP64 or FP32 storage; products, sums and coefficients in FP64).  Each
+// thread handles runs of VEC consecutive entries (16-byte loads); the basis columns and w are padded
+// to a multiple of VEC, so the last run is readable and its entries past N are masked to zero (and
+// written back as zero).  `src` (FP64) is copied into w by INIT, and by RESNORM when given: the
+// norm is then taken of the FP64 values.  FUSED: the last workgroup to finish (counted on the
+// state's ticket) combines the partials itself, which saves small problems a launch per pass.
+template <typename TV, int MAXV, bool FUSED>
+__global__ __launch_bounds__(kCgsBlock) void cgs_kernel(int kind, int N, int nv, const TV* __restrict__ V,
+                                                        size_t ldv, TV* __restrict__ w,
                                                         const double* __restrict__ src, GmresState* st,
                                                         double* __restrict__ partials) {
+  constexpr int VEC = Vec16<TV>::VEC;
   if (kind == CGS_DOTS || kind == CGS_UPDATE_DOTS || kind == CGS_UPDATE_NORM) {
     if (st->done) return;
     if (kind == CGS_UPDATE_DOTS && !st->reorth) return;
@@ -117,51 +145,79 @@ __global__ __launch_bounds__(kCgsBlock) void cgs_kernel(int kind, int N, int nv,
   const bool dots = (kind == CGS_DOTS || kind == CGS_UPDATE_DOTS);
   const bool upd = (kind == CGS_UPDATE_DOTS || kind == CGS_UPDATE_NORM);
   const bool norm = (kind != CGS_UPDATE_DOTS);
+  const bool copy = (kind == CGS_INIT) || (kind == CGS_RESNORM && src);
   double acc[MAXV];
 #pragma unroll
   for (int k = 0; k < MAXV; ++k) acc[k] = 0.0;
   double nacc = 0.0;
-  const int P = (N + 1) >> 1;
+  const int P = (N + VEC - 1) / VEC;
   const int stride = gridDim.x * kCgsBlock;
   for (int i = blockIdx.x * kCgsBlock + threadIdx.x; i < P; i += stride) {
-    const int p = 2 * i;
-    const bool two = p + 1 < N;
-    if (kind == CGS_INIT) {
-      const double b0 = src[p];
-      const double b1 = two ? src[p + 1] : 0.0;
-      w[p] = b0;
-      if (two) w[p + 1] = b1;
-      nacc += b0 * b0 + b1 * b1;
+    const int p = VEC * i;
+    const int nin = min(VEC, N - p);
+    TV wv[VEC];
+    if (copy) {
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        const double b = e < nin ? src[p + e] : 0.0;
+        wv[e] = (TV)b;
+        nacc += b * b;
+      }
+      store16(w + p, wv);
       continue;
     }
-    double2 wv = *reinterpret_cast<const double2*>(w + p);
-    if (!two) wv.y = 0.0;
+    load16(w + p, wv);
+#pragma unroll
+    for (int e = 0; e < VEC; ++e)
+      if (e >= nin) wv[e] = TV(0);
     if (kind == CGS_RESNORM) {
-      nacc += wv.x * wv.x + wv.y * wv.y;
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) nacc += (double)wv[e] * (double)wv[e];
       continue;
     }
-    double2 vk[MAXV];
+    TV vk[MAXV][VEC];
 #pragma unroll
     for (int k = 0; k < MAXV; ++k) {
-      vk[k] = (k < nv) ? *reinterpret_cast<const double2*>(V + (size_t)k * ldv + p) : make_double2(0.0, 0.0);
-      if (!two) vk[k].y = 0.0;
+      if (k < nv) {
+        load16(V + (size_t)k * ldv + p, vk[k]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) vk[k][e] = TV(0);
+      }
+    }
+    if (nin < VEC) {
+#pragma unroll
+      for (int k = 0; k < MAXV; ++k)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+          if (e >= nin) vk[k][e] = TV(0);
     }
     if (upd) {
+      double wd[VEC];
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) wd[e] = wv[e];
 #pragma unroll
       for (int k = 0; k < MAXV; ++k)
         if (k < nv) {
-          wv.x -= hc[k] * vk[k].x;
-          wv.y -= hc[k] * vk[k].y;
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) wd[e] -= hc[k] * (double)vk[k][e];
         }
-      if (two) *reinterpret_cast<double2*>(w + p) = wv;
-      else w[p] = wv.x;
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) wv[e] = (TV)wd[e];
+      store16(w + p, wv);
     }
     if (dots) {
 #pragma unroll
       for (int k = 0; k < MAXV; ++k)
-        if (k < nv) acc[k] += vk[k].x * wv.x + vk[k].y * wv.y;
+        if (k < nv) {
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) acc[k] += (double)vk[k][e] * (double)wv[e];
+        }
     }
-    if (norm) nacc += wv.x * wv.x + wv.y * wv.y;
+    if (norm) {
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) nacc += (double)wv[e] * (double)wv[e];
+    }
   }
   // rows of this pass: the nv dot products (DOTS, UPDATE_DOTS), then the squared norm (DOTS,
   // UPDATE_NORM, INIT, RESNORM)
@@ -311,20 +367,23 @@ int cgs_pass_grid(int nv, int cap) {
   return g;
 }
 
-hipError_t launch_cgs_pass(int kind, size_t N, int nv, double* V, size_t ldv, double* w, const double* src,
+template <typename TV>
+hipError_t launch_cgs_pass(int kind, size_t N, int nv, TV* V, size_t ldv, TV* w, const double* src,
                            GmresState* st, double* partials, int cap, hipStream_t s) {
+  constexpr int VEC = Vec16<TV>::VEC;
   if (nv > kMaxRestart + 1 || N > (size_t)0x7ffffffe || cap < 1) return hipErrorInvalidValue;
-  if (ldv % 2 || (reinterpret_cast<uintptr_t>(V) | reinterpret_cast<uintptr_t>(w)) % 16) return hipErrorInvalidValue;
+  if (ldv % VEC || (reinterpret_cast<uintptr_t>(V) | reinterpret_cast<uintptr_t>(w)) % 16)
+    return hipErrorInvalidValue;
   if (kind == CGS_INIT && !src) return hipErrorInvalidValue;
   const int n = (int)N;
   const int grid = cgs_pass_grid(nv, cap);
   const bool fused = grid <= kFusedMaxGrid;
-#define L_(M)                                                                                                   \
-  if (fused)                                                                                                    \
-    hipLaunchKernelGGL((cgs_kernel<M, true>), dim3(grid), dim3(kCgsBlock), 0, s, kind, n, nv, V, ldv, w, src, st, \
-                       partials);                                                                               \
-  else                                                                                                          \
-    hipLaunchKernelGGL((cgs_kernel<M, false>), dim3(grid), dim3(kCgsBlock), 0, s, kind, n, nv, V, ldv, w, src,    \
+#define L_(M)                                                                                                 \
+  if (fused)                                                                                                  \
+    hipLaunchKernelGGL((cgs_kernel<TV, M, true>), dim3(grid), dim3(kCgsBlock), 0, s, kind, n, nv, V, ldv, w, src, \
+                       st, partials);                                                                         \
+  else                                                                                                        \
+    hipLaunchKernelGGL((cgs_kernel<TV, M, false>), dim3(grid), dim3(kCgsBlock), 0, s, kind, n, nv, V, ldv, w, src, \
                        st, partials)
   if (nv <= 4) { L_(4); }
   else if (nv <= 8) { L_(8); }
@@ -335,6 +394,10 @@ hipError_t launch_cgs_pass(int kind, size_t N, int nv, double* V, size_t ldv, do
 #undef L_
   return hipGetLastError();
 }
+template hipError_t launch_cgs_pass<double>(int, size_t, int, double*, size_t, double*, const double*, GmresState*,
+                                            double*, int, hipStream_t);
+template hipError_t launch_cgs_pass<float>(int, size_t, int, float*, size_t, float*, const double*, GmresState*,
+                                           double*, int, hipStream_t);
 
 bool cgs_fused(int nv, int cap) { return cgs_pass_grid(nv, cap) <= kFusedMaxGrid; }
 

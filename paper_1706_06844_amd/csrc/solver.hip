@@ -212,7 +212,8 @@ struct fde_handle {
   std::unique_ptr<Hierarchy<double>> h64;
   std::unique_ptr<Hierarchy<float>> h32;
   // Krylov storage
-  double* V = nullptr;    // restart + 1 columns of N, column stride ldv
+  double* V = nullptr;    // restart + 1 columns of N, column stride ldv (one column with FP32 cycles)
+  float* V32 = nullptr;   // FP32 cycles: the basis, restart + 1 columns, column stride ldv
   size_t ldv = 0;
   void* Z = nullptr;      // restart x N, FP64 or FP32
   GmresState* st = nullptr;
@@ -235,6 +236,7 @@ struct fde_handle {
   Prof prof;
   std::string err;
   bool fp32() const { return p.precision != FDE_FP64; }
+  bool cyc32() const { return p.precision == FDE_MIXED_FP32_CYCLE; }
 };
 
 namespace {
@@ -344,9 +346,12 @@ int validate(const fde_problem* p, std::string* why) {
   if (p->n1 > 2047 || p->n2 > 2047) return bad("n1 and n2 are limited to 2047 (FFT length 4096)");
   if (!(p->b1 > p->a1) || !(p->b2 > p->a2)) return bad("domain needs a < b");
   if (!(p->tau > 0.0) || !std::isfinite(p->tau)) return bad("tau must be positive and finite");
-  if (p->precision < FDE_FP64 || p->precision > FDE_MIXED_BF16GEMM) return bad("unknown precision");
+  if (p->precision < FDE_FP64 || p->precision > FDE_MIXED_FP32_CYCLE) return bad("unknown precision");
   if (p->mg_variant != FDE_MG_GEOMETRIC && p->mg_variant != FDE_MG_GALERKIN && p->mg_variant != FDE_MG_BAND)
     return bad("unknown mg_variant");
+  if (p->precision == FDE_MIXED_FP32_CYCLE && p->mg_variant == FDE_MG_BAND)
+    return bad("FP32 cycles apply the operator on the preconditioner's fine level, which the band "
+               "preconditioner replaces");
   if (!(p->omega > 0.0 && p->omega <= 1.0)) return bad("omega must lie in (0,1]");
   if (p->nu_pre < 0 || p->nu_pre > 8 || p->nu_post < 0 || p->nu_post > 8) return bad("nu_pre/nu_post in 0..8");
   if (p->coarsest_n < 3) return bad("coarsest_n must be >= 3");
@@ -809,18 +814,19 @@ R* vcycle_from(fde_handle* h, Hierarchy<R>& H, int l, R* x, const int* skip, boo
   return cur;
 }
 
-// z = MG(s * v): v is FP64 (a basis column), s a device scalar (or NULL = 1).
-template <typename R>
-void vcycle_top(fde_handle* h, Hierarchy<R>& H, const double* v, const double* s, R* z, const int* skip) {
+// z = MG(s * v): v is a basis column (FP64, or FP32 with FP32 cycles), s a device scalar (or
+// NULL = 1).
+template <typename R, typename Tv = double>
+void vcycle_top(fde_handle* h, Hierarchy<R>& H, const Tv* v, const double* s, R* z, const int* skip) {
   Level<R>& L0 = H.lv[0];
   const int N = (int)L0.N();
-  const double pb = (double)N * (sizeof(double) + 3 * sizeof(R));
+  const double pb = (double)N * (sizeof(Tv) + 3 * sizeof(R));
   if (H.lc == 0) {
-    timed(h, FDE_KFAM_TRANSFER, pb, [&] { return launch_presmooth<R, double>(N, v, s, L0.dinv, L0.x, L0.b, skip, h->stream); });
+    timed(h, FDE_KFAM_TRANSFER, pb, [&] { return launch_presmooth<R, Tv>(N, v, s, L0.dinv, L0.x, L0.b, skip, h->stream); });
     timed(h, FDE_KFAM_COARSE, 2.0 * N * sizeof(R), [&] { return launch_coarse_vcycle<R>(H.cv, L0.b, z, skip, h->stream); });
     return;
   }
-  timed(h, FDE_KFAM_TRANSFER, pb, [&] { return launch_presmooth<R, double>(N, v, s, L0.dinv, z, L0.b, skip, h->stream); });
+  timed(h, FDE_KFAM_TRANSFER, pb, [&] { return launch_presmooth<R, Tv>(N, v, s, L0.dinv, z, L0.b, skip, h->stream); });
   if (h->p.nu_pre == 0) HIPCHECK(launch_fill<R>(L0.N(), z, R(0), h->stream));
   R* res = vcycle_from<R>(h, H, 0, z, skip, false);
   if (res != z) HIPCHECK(hipMemcpyAsync(z, res, L0.N() * sizeof(R), hipMemcpyDeviceToDevice, h->stream));
@@ -834,40 +840,72 @@ void read_state(fde_handle* h) {
 
 // One Gram-Schmidt pass (timed as the CGS family) and the combination of its partials (timed
 // separately; small passes combine them in their last workgroup).  Negative `bytes` mark the conditional second pass.
-void cgs(fde_handle* h, int kind, int nv, double* w, const double* src, double bytes) {
+template <typename TV>
+void cgs(fde_handle* h, int kind, int nv, TV* V, TV* w, const double* src, double bytes) {
   timed(h, FDE_KFAM_CGS, bytes, [&] {
-    return launch_cgs_pass(kind, h->N, nv, h->V, h->ldv, w, src, h->st, h->partials, h->cgs_grid, h->stream);
+    return launch_cgs_pass<TV>(kind, h->N, nv, V, h->ldv, w, src, h->st, h->partials, h->cgs_grid, h->stream);
   });
   if (cgs_fused(nv, h->cgs_grid)) return;
   timed(h, FDE_KFAM_CGS_FINALIZE, bytes < 0 ? -1e-300 : 0.0,
         [&] { return launch_cgs_finalize(kind, nv, h->partials, h->st, h->cgs_grid, h->stream); });
 }
 
-template <typename R>
-void arnoldi_step(fde_handle* h, Hierarchy<R>& H, int j) {
+// Step j of the Arnoldi process: z_j = MG(v_j), w = A z_j, and its orthogonalisation against
+// v_0..v_j.  With FP32 cycles the basis is FP32 and A z_j is the FP32 fine-level operator of the
+// preconditioner (the same discretisation as the FP64 one, Sec. 4.2).
+template <typename R, typename TV>
+void arnoldi_step(fde_handle* h, Hierarchy<R>& H, TV* V, int j) {
   const size_t N = h->N;
   const int* skip = &h->st->done;
   R* Z = static_cast<R*>(h->Z);
   const size_t ldv = h->ldv;
-  double* vj = h->V + (size_t)j * ldv;
-  double* w = h->V + (size_t)(j + 1) * ldv;
-  vcycle_top<R>(h, H, vj, &h->st->vscale[j], Z + (size_t)j * N, skip);
-  const OpView<double> op = h->cur.view(h->tw64_x, h->tw64_y, h->n1, h->n2, h->L1, h->L2);
-  op_apply<double, R>(h, true, op, Z + (size_t)j * N, h->ay64, w, EP_APPLY, nullptr, nullptr, 0.0, skip);
+  TV* vj = V + (size_t)j * ldv;
+  TV* w = V + (size_t)(j + 1) * ldv;
+  vcycle_top<R, TV>(h, H, vj, &h->st->vscale[j], Z + (size_t)j * N, skip);
+  if constexpr (std::is_same<TV, float>::value) {
+    Level<R>& L0 = H.lv[0];
+    if (L0.gal || L0.mfma) throw FdeError{FDE_EINVAL, "FP32 cycles need an FFT or dense fine level"};
+    op_apply<float, float>(h, true, L0.view(), Z + (size_t)j * N, L0.ay, w, EP_APPLY, nullptr, nullptr, 0.0, skip);
+  } else {
+    const OpView<double> op = h->cur.view(h->tw64_x, h->tw64_y, h->n1, h->n2, h->L1, h->L2);
+    op_apply<double, R>(h, true, op, Z + (size_t)j * N, h->ay64, w, EP_APPLY, nullptr, nullptr, 0.0, skip);
+  }
   // bytes of a pass: j + 1 basis columns and w read, w written by the update passes (a skipped
   // second pass is counted as a launch of zero bytes)
-  const double vb = (double)(j + 2) * N * sizeof(double);
-  cgs(h, CGS_DOTS, j + 1, w, nullptr, vb);
-  cgs(h, CGS_UPDATE_DOTS, j + 1, w, nullptr, -(vb + N * sizeof(double)));
-  cgs(h, CGS_UPDATE_NORM, j + 1, w, nullptr, vb + N * sizeof(double));
+  const double vb = (double)(j + 2) * N * sizeof(TV);
+  cgs<TV>(h, CGS_DOTS, j + 1, V, w, nullptr, vb);
+  cgs<TV>(h, CGS_UPDATE_DOTS, j + 1, V, w, nullptr, -(vb + N * sizeof(TV)));
+  cgs<TV>(h, CGS_UPDATE_NORM, j + 1, V, w, nullptr, vb + N * sizeof(TV));
+}
+
+// The start of a solve (w = b and ||b||) and of a cycle (the FP64 true residual and its norm).
+// With FP32 cycles the residual is formed in FP64 in the FP64 column and rounded into the basis by
+// the norm pass, whose norm is that of the FP64 values.
+void start_solve(fde_handle* h, const double* b) {
+  const size_t N = h->N;
+  if (h->cyc32()) cgs<float>(h, CGS_INIT, 0, h->V32, h->V32, b, N * (sizeof(double) + sizeof(float)));
+  else cgs<double>(h, CGS_INIT, 0, h->V, h->V, b, 2.0 * N * sizeof(double));
+}
+void restart_residual(fde_handle* h, const double* b, const double* x) {
+  const size_t N = h->N;
+  const OpView<double> op = h->cur.view(h->tw64_x, h->tw64_y, h->n1, h->n2, h->L1, h->L2);
+  op_apply<double, double>(h, true, op, x, h->ay64, h->V, EP_RESID, b, nullptr, 0.0, nullptr);
+  if (h->cyc32()) cgs<float>(h, CGS_RESNORM, 0, h->V32, h->V32, h->V, N * (sizeof(double) + sizeof(float)));
+  else cgs<double>(h, CGS_RESNORM, 0, h->V, h->V, nullptr, (double)N * sizeof(double));
+}
+template <typename R>
+void arnoldi(fde_handle* h, Hierarchy<R>& H, int j) {
+  if constexpr (std::is_same<R, float>::value) {
+    if (h->cyc32()) return arnoldi_step<R, float>(h, H, h->V32, j);
+  }
+  arnoldi_step<R, double>(h, H, h->V, j);
 }
 
 template <typename R>
 int fgmres(fde_handle* h, Hierarchy<R>& H, const double* b, double* x, fde_stats* stats) {
   const size_t N = h->N;
   const int restart = h->p.restart;
-  cgs(h, CGS_INIT, 0, h->V, b, 2.0 * N * sizeof(double));
-  const OpView<double> op = h->cur.view(h->tw64_x, h->tw64_y, h->n1, h->n2, h->L1, h->L2);
+  start_solve(h, b);
   int cycles = 0;
   // Arnoldi steps are issued without waiting; the host reads the device state only once the
   // previous solve's iteration count is reached (kernels after convergence return immediately).
@@ -878,7 +916,7 @@ int fgmres(fde_handle* h, Hierarchy<R>& H, const double* b, double* x, fde_stats
     h->prof.cur_cycle = cycles;
     for (; j < restart; ++j) {
       h->prof.cur_j = j;
-      arnoldi_step<R>(h, H, j);
+      arnoldi<R>(h, H, j);
       ++total_issued;
       if (total_issued >= hint - 1 || j + 1 == restart) {
         read_state(h);
@@ -892,8 +930,7 @@ int fgmres(fde_handle* h, Hierarchy<R>& H, const double* b, double* x, fde_stats
     timed(h, FDE_KFAM_UPDATE, (double)N * (nu * sizeof(R) + (cycles == 0 ? 1 : 2) * sizeof(double)), [&] {
       return launch_update_x<R>(N, static_cast<const R*>(h->Z), N, x, cycles == 0 ? 1 : 0, h->st, h->stream);
     });
-    op_apply<double, double>(h, true, op, x, h->ay64, h->V, EP_RESID, b, nullptr, 0.0, nullptr);
-    cgs(h, CGS_RESNORM, 0, h->V, nullptr, (double)N * sizeof(double));
+    restart_residual(h, b, x);
     read_state(h);
     ++cycles;
     if (h->st_host->conv || h->st_host->iters >= h->p.maxit) break;
@@ -921,7 +958,7 @@ template <typename R>
 int mg_solve(fde_handle* h, Hierarchy<R>& H, const double* b, double* x, int max_cycles, fde_stats* stats) {
   const size_t N = h->N;
   HIPCHECK(launch_fill<double>(N, x, 0.0, h->stream));
-  cgs(h, CGS_INIT, 0, h->V, b, 2.0 * N * sizeof(double));  // r = b (column 0 of V), ||b||
+  cgs<double>(h, CGS_INIT, 0, h->V, h->V, b, 2.0 * N * sizeof(double));  // r = b (FP64 column), ||b||
   read_state(h);
   const OpView<double> op = h->cur.view(h->tw64_x, h->tw64_y, h->n1, h->n2, h->L1, h->L2);
   R* z = static_cast<R*>(h->Z);
@@ -930,7 +967,7 @@ int mg_solve(fde_handle* h, Hierarchy<R>& H, const double* b, double* x, int max
     vcycle_top<R>(h, H, h->V, nullptr, z, nullptr);
     HIPCHECK(launch_add_to<R>(N, z, x, h->stream));
     op_apply<double, double>(h, true, op, x, h->ay64, h->V, EP_RESID, b, nullptr, 0.0, nullptr);
-    cgs(h, CGS_RESNORM, 0, h->V, nullptr, (double)N * sizeof(double));
+    cgs<double>(h, CGS_RESNORM, 0, h->V, h->V, nullptr, (double)N * sizeof(double));
     read_state(h);
     ++k;
     if (!std::isfinite(h->st_host->resnorm)) break;
@@ -965,11 +1002,9 @@ int guarded(fde_handle* h, F&& f);
 template <typename R>
 void cycle_body(fde_handle* h, Hierarchy<R>& H) {
   const size_t N = h->N;
-  for (int j = 0; j < h->p.restart; ++j) arnoldi_step<R>(h, H, j);
+  for (int j = 0; j < h->p.restart; ++j) arnoldi<R>(h, H, j);
   HIPCHECK(launch_update_x<R>(N, static_cast<const R*>(h->Z), N, h->as.xsol, 0, h->st, h->stream));
-  const OpView<double> op = h->cur.view(h->tw64_x, h->tw64_y, h->n1, h->n2, h->L1, h->L2);
-  op_apply<double, double>(h, true, op, h->as.xsol, h->ay64, h->V, EP_RESID, h->rhs, nullptr, 0.0, nullptr);
-  cgs(h, CGS_RESNORM, 0, h->V, nullptr, (double)N * sizeof(double));
+  restart_residual(h, h->rhs, h->as.xsol);
 }
 
 void issue_cycle(fde_handle* h) {
@@ -1029,7 +1064,7 @@ int async_step_start(fde_handle* h, const double* u_prev, int nsrc, const double
     const OpView<double> op = h->prev.view(h->tw64_x, h->tw64_y, h->n1, h->n2, h->L1, h->L2);
     op_apply<double, double>(h, true, op, u_prev, h->ay64, h->rhs, EP_RHS, nullptr, &src, h->p.tau, nullptr);
     HIPCHECK(launch_fill<double>(N, h->as.xsol, 0.0, h->stream));
-    cgs(h, CGS_INIT, 0, h->V, h->rhs, 2.0 * N * sizeof(double));
+    start_solve(h, h->rhs);
     h->as.cycles = 0;
     h->as.active = true;
     issue_cycle(h);
@@ -1089,7 +1124,9 @@ size_t footprint_bytes(const fde_problem* pin) {
   b += 4 * N * 8;                                   // outer coefficient pairs
   b += 2.0 * (L1 + L2) * 8 + 4.0 * (L1 + L2) * 8;   // symbols, twiddles
   b += (1 + 1 + 4 + 1) * N * 8;                     // ay64, rhs, scratch, async solution
-  b += (p.restart + 1.0) * (double)basis_ld((size_t)N) * 8 + p.restart * N * R;
+  const double ld = (double)basis_ld((size_t)N);
+  b += (p.precision == FDE_MIXED_FP32_CYCLE ? ld * 8 + (p.restart + 1.0) * ld * 4 : (p.restart + 1.0) * ld * 8);
+  b += p.restart * N * R;
   b += (double)cgs_partials_len((size_t)N) * 8 + sizeof(GmresState) + 4096;
   const bool gal = (p.mg_variant == FDE_MG_GALERKIN || p.mg_variant == FDE_MG_BAND) &&
                    std::min(p.n1, p.n2) > p.coarsest_n;
@@ -1239,7 +1276,12 @@ int fde_setup(const fde_problem* pin, const double* dp, const double* dm, const 
     h->rhs = dalloc<double>(m, N);
     h->scratch64 = dalloc<double>(m, 4 * N);
     h->ldv = basis_ld(N);
-    h->V = dalloc<double>(m, (size_t)(p.restart + 1) * h->ldv);
+    if (h->cyc32()) {
+      h->V = dalloc<double>(m, h->ldv);
+      h->V32 = dalloc<float>(m, (size_t)(p.restart + 1) * h->ldv);
+    } else {
+      h->V = dalloc<double>(m, (size_t)(p.restart + 1) * h->ldv);
+    }
     if (h->fp32()) h->Z = dalloc<float>(m, (size_t)p.restart * N);
     else h->Z = dalloc<double>(m, (size_t)p.restart * N);
     h->st = dalloc<GmresState>(m, 1);

@@ -45,7 +45,7 @@ def _drain(b, ids, shapes):
     return out
 
 
-@pytest.mark.parametrize("precision", [fde.FDE_FP64, fde.FDE_MIXED_FP32])
+@pytest.mark.parametrize("precision", [fde.FDE_FP64, fde.FDE_MIXED_FP32, fde.FDE_MIXED_FP32_CYCLE])
 def test_batch_results_equal_solo(precision):
     probs = _instances(6, (31, 63, 127), 41, 3)
     b = fde.fde_batch_create(8 << 30)
@@ -107,16 +107,17 @@ def test_budget_admission_and_release():
     b.close()
 
 
-def test_graph_replays_match_eager_over_many_cycles():
+@pytest.mark.parametrize("precision", [fde.FDE_MIXED_FP32, fde.FDE_MIXED_FP32_CYCLE])
+def test_graph_replays_match_eager_over_many_cycles(precision):
     # one anisotropic request needing many restart cycles per step: every cycle after the first is
     # a graph replay, with the host's own work in between
     p = workloads.config_c3(255, 16)
     p.M = 3
     b = fde.fde_batch_create(8 << 30)
     keep = []
-    rid = _admit(b, p, fde.FDE_MIXED_FP32, keep, maxit=4000)
+    rid = _admit(b, p, precision, keep, maxit=4000)
     res = _drain(b, [rid], {rid: (255, 255)})
-    ref, its = solo_run(p, 3, fde.FDE_MIXED_FP32, maxit=4000)
+    ref, its = solo_run(p, 3, precision, maxit=4000)
     note(f"C3-like 255: {res[rid][1]} iterations in 3 steps")
     assert res[rid][1] == its and its > 60
     assert rel(res[rid][0], ref) <= 1e-14

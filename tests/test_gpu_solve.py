@@ -16,7 +16,7 @@ from .gpu_util import dev, host, make_handle, note, rel
 
 pytestmark = pytest.mark.gpu
 
-PRECS = [fde.FDE_FP64, fde.FDE_MIXED_FP32]
+PRECS = [fde.FDE_FP64, fde.FDE_MIXED_FP32, fde.FDE_MIXED_FP32_CYCLE]
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -104,14 +104,20 @@ def test_fp64_and_mixed_agree_at_2047():
     u0 = dev(workloads.sample_u0(p))
     S = [dev(f) for f in fields]
     out = []
+    its = []
     for prec in PRECS:
         h = make_handle(p, precision=prec, maxit=4000)
         un = dev(np.zeros((p.n2, p.n1)))
         st = fde.fde_step_sources(h, u0, [f(0.5 * p.tau) for f in phis], S, un)
-        assert st["converged"]
+        assert st["converged"] and st["relres_true"] <= 1e-10
         out.append(host(un))
+        its.append(st["iters"])
         h.close()
+    note(f"C3 2047 iterations fp64 / mixed / fp32 cycles: {its}")
     assert rel(out[1], out[0]) <= 1e-9
+    assert rel(out[2], out[0]) <= 1e-9
+    # FP32 cycles refine from the FP64 residual: the iteration count stays that of the FP64 cycles
+    assert abs(its[2] - its[1]) <= 0.05 * its[1]
 
 
 def test_error_codes():
@@ -134,18 +140,29 @@ def test_error_codes():
     assert st["rc"] == fde.FDE_ENOCONV and not st["converged"] and st["iters"] == 1
 
 
-def test_zero_rhs_gives_zero():
+def test_fp32_cycles_reject_band_preconditioner():
     p = workloads.config_c2(31, 32)
-    h = make_handle(p)
+    fields = [dev(f) for f in workloads.sample(p, 0.0)]
+    from .gpu_util import problem_struct
+    with pytest.raises(fde.FdeError) as e:
+        fde.fde_setup(problem_struct(p, precision=fde.FDE_MIXED_FP32_CYCLE, mg_variant=fde.FDE_MG_BAND), *fields)
+    assert e.value.code == fde.FDE_EINVAL
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_zero_rhs_gives_zero(prec):
+    p = workloads.config_c2(31, 32)
+    h = make_handle(p, precision=prec)
     x = dev(np.ones((31, 31)))
     st = fde.fde_solve(h, dev(np.zeros((31, 31))), x)
     assert st["converged"] and st["iters"] == 0
     assert np.all(host(x) == 0.0)
 
 
-def test_solve_is_deterministic():
+@pytest.mark.parametrize("prec", [fde.FDE_MIXED_FP32, fde.FDE_MIXED_FP32_CYCLE])
+def test_solve_is_deterministic(prec):
     p = workloads.config_c2(255, 32)
-    h = make_handle(p, precision=fde.FDE_MIXED_FP32)
+    h = make_handle(p, precision=prec)
     b = dev(np.random.default_rng(4).standard_normal((255, 255)))
     xs = []
     for _ in range(2):
@@ -155,7 +172,8 @@ def test_solve_is_deterministic():
     assert np.array_equal(xs[0], xs[1])
 
 
-@pytest.mark.parametrize("prec,variant", [(fde.FDE_FP64, fde.FDE_MG_GEOMETRIC), (fde.FDE_MIXED_FP32, fde.FDE_MG_GALERKIN)])
+@pytest.mark.parametrize("prec,variant", [(fde.FDE_FP64, fde.FDE_MG_GEOMETRIC), (fde.FDE_MIXED_FP32, fde.FDE_MG_GALERKIN),
+                                          (fde.FDE_MIXED_FP32_CYCLE, fde.FDE_MG_GALERKIN)])
 def test_time_dependent_coefficients_example2(prec, variant):
     # Example 2 of Sec. 5: coefficients grow like (1+t); the left-hand side uses t^(m), the explicit
     # half t^(m-1), so every step refreshes the operators and the hierarchy (fde_update_coeffs)
@@ -177,7 +195,7 @@ def test_time_dependent_coefficients_example2(prec, variant):
     note(f"example 2 error at T: {np.abs(host(u) - p.u_exact(X, Y, p.T)).max():.3e}")
 
 
-@pytest.mark.parametrize("prec", [fde.FDE_FP64, fde.FDE_MIXED_FP32])
+@pytest.mark.parametrize("prec", PRECS)
 def test_multigrid_as_standalone_solver(prec):
     # the V-cycle iteration without GMRES: same cycle count as the oracle's iteration, same solution
     from oracle import multigrid as omg
