@@ -61,8 +61,8 @@ hipError_t launch_direct_op(int n1, int n2, const Tin* x, const R* dpm, const R*
                             const int* skip, hipStream_t st);
 
 bool fft_length_supported(int L);
-// FFT twiddle table for length L and the plan of the given element size (4 or 8 bytes),
-// interleaved complex, computed in double precision; count = 2 * entries.
+// FFT twiddle table for length L, shared by every transform plan and element size: exp(-2 pi i k/L),
+// k < L/2, interleaved complex, computed in extended precision; count = 2 * entries = L.
 void fft_twiddles(int L, int elem_bytes, double* out, int* count);
 int fft_twiddle_count(int L, int elem_bytes);
 // Symbol of one direction: out[k] = scale * lam[k] / L, lam = DFT of the circulant embedding of

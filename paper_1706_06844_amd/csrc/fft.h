@@ -11,8 +11,9 @@
 // position (b / NS) * NS * R + (b mod NS) + r * NS.  After the last stage (NS * R = L) that position
 // is again t + T*m, so the result stays in registers in natural order; earlier stages exchange data
 // through LDS.  Twiddles: a thread needs w^r, r = 1..R-1, with w = exp(sign 2 pi i (b mod NS)/(NS R));
-// it loads the single base value w of each stage (compact table [stage][b mod NS]) once per kernel
-// and forms the powers with a product tree of depth <= 4.
+// it loads the single base value w of each stage once per kernel from the table of exp(-2 pi i k/L),
+// k < L/2 (entry k = (b mod NS) L/(NS R), the same table for every plan), and forms the powers with a
+// product tree of depth <= 4.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -207,16 +208,14 @@ __host__ __device__ constexpr int emax_for(int bytes, int L) {
 }
 template <typename R, int L>
 using PlanFor = Plan<L, emax_for(sizeof(R), L)>;
-// The E elements a thread holds for a length-L transform in precision R.
-template <typename R, int L>
-using Reg = R[PlanFor<R, L>::E];
 
-// One Stockham stage.  `rr`/`ri` hold the thread's E elements (natural positions t + T*m).
+// One Stockham stage of plan P.  `rr`/`ri` hold the thread's E elements (natural positions t + T*m).
 // Every stage but the last has one butterfly per thread (radix E), computed in place; its outputs
-// are exchanged through `lds` (lds_exchange(L) reals) and read back at positions t + T*m.  The last stage (possibly of smaller radix, several butterflies per thread)
-// writes each butterfly's outputs over its own inputs, which are exactly positions t + T*m.
-template <int L, int S, int SIGN, typename R, typename P = PlanFor<R, L>>
-__device__ __forceinline__ void fft_stage(Reg<R, L>& rr, Reg<R, L>& ri, R* lds, const R* bw, int t) {
+// are exchanged through `lds` (lds_exchange(L) reals) and read back at positions t + T*m.  The last
+// stage (possibly of smaller radix, several butterflies per thread) writes each butterfly's outputs
+// over its own inputs, which are exactly positions t + T*m.
+template <int L, int S, int SIGN, typename R, typename P>
+__device__ __forceinline__ void fft_stage(R (&rr)[P::E], R (&ri)[P::E], R* lds, const R* bw, int t) {
   constexpr int E = P::E, T = P::T;
   constexpr int RADIX = P::radix(S);
   constexpr int NS = P::ns(S);
@@ -286,10 +285,10 @@ __device__ __forceinline__ void fft_stage(Reg<R, L>& rr, Reg<R, L>& ri, R* lds, 
 }
 
 // Base twiddles of every stage for this thread: bw[s][2q], bw[s][2q+1] = exp(-2 pi i j/(NS R)),
-// j = (t + T q) mod NS, loaded once per kernel from the compact table.
-template <typename R, int L>
+// j = (t + T q) mod NS, loaded once per kernel from the table of exp(-2 pi i k/L), k < L/2.
+template <typename R, int L, typename P_ = PlanFor<R, L>>
 struct Twiddles {
-  using P = PlanFor<R, L>;
+  using P = P_;
   static constexpr int NST = P::NSTAGES > 1 ? P::NSTAGES : 2;
   static constexpr int BPTMAX = P::E / P::radix(P::NSTAGES - 1);
   R w[NST][2 * BPTMAX];
@@ -298,10 +297,11 @@ struct Twiddles {
       constexpr int S = decltype(sc)::value;
       constexpr int NS = P::ns(S);
       constexpr int BPT = P::E / P::radix(S);
+      constexpr int STEP = L / (NS * P::radix(S));
       static_for<0, BPT>([&](auto qc) {
         const int j = (t + P::T * decltype(qc)::value) & (NS - 1);
-        w[S][2 * qc] = tab[2 * (P::tw_offset(S) + j)];
-        w[S][2 * qc + 1] = tab[2 * (P::tw_offset(S) + j) + 1];
+        w[S][2 * qc] = tab[2 * j * STEP];
+        w[S][2 * qc + 1] = tab[2 * j * STEP + 1];
       });
     });
   }
@@ -309,15 +309,15 @@ struct Twiddles {
 
 // Full length-L DFT (SIGN = -1 forward, +1 unnormalised inverse) of the thread group's data.
 // Every thread of the workgroup must call this (it contains barriers) even if its group is idle.
-template <int L, int SIGN, typename R>
-__device__ __forceinline__ void fft(Reg<R, L>& rr, Reg<R, L>& ri, R* lds, const Twiddles<R, L>& tw, int t_in) {
+template <int L, int SIGN, typename R, typename P>
+__device__ __forceinline__ void fft(R (&rr)[P::E], R (&ri)[P::E], R* lds, const Twiddles<R, L, P>& tw, int t_in) {
   // An opaque copy of the thread index: without it the compiler computes the LDS addresses of all
   // transforms of a kernel once and keeps them live throughout, which exhausts the registers.
   int t = t_in;
   __asm__ volatile("" : "+v"(t));
-  static_for<0, PlanFor<R, L>::NSTAGES>([&](auto s) {
+  static_for<0, P::NSTAGES>([&](auto s) {
     constexpr int S = decltype(s)::value;
-    fft_stage<L, S, SIGN>(rr, ri, lds, tw.w[S < Twiddles<R, L>::NST ? S : 0], t);
+    fft_stage<L, S, SIGN, R, P>(rr, ri, lds, tw.w[S < Twiddles<R, L, P>::NST ? S : 0], t);
   });
 }
 

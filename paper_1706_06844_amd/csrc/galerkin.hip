@@ -60,7 +60,7 @@ __global__ __launch_bounds__((XCfg<R, L>::THREADS), FDE_XW) void gal_row_kernel(
   const int t = threadIdx.x - slot * T;
   R* lds = lds_all + slot * SLOT;
   R* zs = lds + lds_exchange(L);
-  Twiddles<R, L> tw;
+  Twiddles<R, L, P> tw;
   tw.load(twtab, t);
   const int rowA = 2 * (blockIdx.x * S + slot);
   const bool hasA = rowA < nrows, hasB = rowA + 1 < nrows;
@@ -73,10 +73,10 @@ __global__ __launch_bounds__((XCfg<R, L>::THREADS), FDE_XW) void gal_row_kernel(
     zi[m] = (hasB && i < n0) ? interp(xb, 1, nl, i, logH) : R(0);
   });
   fft<L, -1>(zr, zi, lds, tw, t);
-  symbol_both<L>(zr, zi, zs, mu, t);
+  symbol_both<L, P>(zr, zi, zs, mu, t);
   fft<L, +1>(zr, zi, lds, tw, t);  // T u_A + i T u_B
   R pr[E], pi[E];
-  unstash<L>(pr, pi, zs, t);
+  unstash<L, P>(pr, pi, zs, t);
   static_for<0, E>([&](auto m) {  // the first products wait in LDS during the second transform
     const int i = t + T * m;
     zs[i] = zr[m];
@@ -110,7 +110,7 @@ __global__ __launch_bounds__((YCfg<R, L>::THREADS), FDE_YW) void gal_col_kernel(
   const int t = threadIdx.x / S;
   R* lds = lds_all + slot * SLOT;
   R* zs = lds + lds_exchange(L);
-  Twiddles<R, L> tw;
+  Twiddles<R, L, P> tw;
   tw.load(twtab, t);
   const int c0 = strip * 2 * S + 2 * slot;
   const bool v0 = c0 < nlx, v1 = c0 + 1 < nlx;
@@ -121,10 +121,10 @@ __global__ __launch_bounds__((YCfg<R, L>::THREADS), FDE_YW) void gal_col_kernel(
     zi[m] = (j < n0 && v1) ? interp(x + c0 + 1, nlx, nly, j, logH) : R(0);
   });
   fft<L, -1>(zr, zi, lds, tw, t);
-  symbol_both<L>(zr, zi, zs, mu, t);
+  symbol_both<L, P>(zr, zi, zs, mu, t);
   fft<L, +1>(zr, zi, lds, tw, t);
   R pr[E], pi[E];
-  unstash<L>(pr, pi, zs, t);
+  unstash<L, P>(pr, pi, zs, t);
   static_for<0, E>([&](auto m) {
     const int j = t + T * m;
     zs[j] = zr[m];

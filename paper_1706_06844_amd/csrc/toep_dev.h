@@ -27,10 +27,10 @@ namespace fde {
 // conj(lam) * Z goes to zs (real parts zs[0, L), imaginary parts zs[L, 2L)), each thread at its own
 // positions t + T*m, so no barrier is needed before it reads them back.  Between the two inverse
 // transforms the partial results of the first take the second product's place in zs.
-template <int L, typename R>
-__device__ __forceinline__ void symbol_both(Reg<R, L>& zr, Reg<R, L>& zi, R* zs, const R* __restrict__ lam,
+template <int L, typename P, typename R>
+__device__ __forceinline__ void symbol_both(R (&zr)[P::E], R (&zi)[P::E], R* zs, const R* __restrict__ lam,
                                             int t) {
-  constexpr int E = PlanFor<R, L>::E, T = PlanFor<R, L>::T;
+  constexpr int E = P::E, T = P::T;
   static_for<0, E>([&](auto m) {
     const int k = t + T * m;
     const R lr = lam[2 * k], li = lam[2 * k + 1];
@@ -42,9 +42,9 @@ __device__ __forceinline__ void symbol_both(Reg<R, L>& zr, Reg<R, L>& zi, R* zs,
   });
 }
 
-template <int L, typename R>
-__device__ __forceinline__ void unstash(Reg<R, L>& pr, Reg<R, L>& pi, const R* zs, int t) {
-  constexpr int E = PlanFor<R, L>::E, T = PlanFor<R, L>::T;
+template <int L, typename P, typename R>
+__device__ __forceinline__ void unstash(R (&pr)[P::E], R (&pi)[P::E], const R* zs, int t) {
+  constexpr int E = P::E, T = P::T;
   static_for<0, E>([&](auto m) {
     pr[m] = zs[t + T * m];
     pi[m] = zs[L + t + T * m];
@@ -77,11 +77,21 @@ __device__ __forceinline__ void chunked_for(F&& f) {
 #endif
 constexpr int kEpiGroup = FDE_EPI_GROUP;
 
+// Elements per thread of the row pass: at most 8 (more threads per transform and fewer registers
+// per thread than the column pass's plan; the row pass's six streams need the resident waves).
+#ifndef FDE_EMAX_X
+#define FDE_EMAX_X 8
+#endif
+template <typename R, int L>
+using XPlan = Plan<L, (emax_for(sizeof(R), L) < FDE_EMAX_X ? emax_for(sizeof(R), L) : FDE_EMAX_X)>;
+template <typename R, int L>
+using YPlan = PlanFor<R, L>;
+
 // Row pairs (transforms) per workgroup of the row pass: short transforms share a wavefront.
 template <typename R, int L>
 struct XCfg {
-  static constexpr int S = PlanFor<R, L>::T >= 64 ? 1 : 64 / PlanFor<R, L>::T;
-  static constexpr int THREADS = PlanFor<R, L>::T * S;
+  static constexpr int S = XPlan<R, L>::T >= 64 ? 1 : 64 / XPlan<R, L>::T;
+  static constexpr int THREADS = XPlan<R, L>::T * S;
 };
 
 #ifndef FDE_Y_THREADS
@@ -96,11 +106,11 @@ struct XCfg {
 // L = 1024..4096.
 template <typename R, int L>
 struct YCfg {
-  static constexpr int T_ = PlanFor<R, L>::T;
+  static constexpr int T_ = YPlan<R, L>::T;
   static constexpr int SW = L / FDE_Y_COLS_PER_SLOT_L > 1 ? L / FDE_Y_COLS_PER_SLOT_L : 1;
   static constexpr int S0 = SW > 64 / T_ ? SW : 64 / T_;
   static constexpr int S = T_ * S0 <= FDE_Y_THREADS ? S0 : (T_ >= FDE_Y_THREADS ? 1 : FDE_Y_THREADS / T_);
-  static constexpr int THREADS = PlanFor<R, L>::T * S;
+  static constexpr int THREADS = YPlan<R, L>::T * S;
 };
 
 }  // namespace fde

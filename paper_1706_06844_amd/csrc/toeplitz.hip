@@ -42,7 +42,7 @@ __global__ __launch_bounds__((XCfg<R, L>::THREADS), FDE_XW) void toep_x_kernel(
     const R* __restrict__ twtab, const R* __restrict__ ay, const R* __restrict__ b,
     const R* __restrict__ dinv, SrcTerms src, double tau, R* out, const int* __restrict__ skip) {
   if (skip && *skip) return;
-  using P = PlanFor<R, L>;
+  using P = XPlan<R, L>;
   constexpr int E = P::E, T = P::T, S = XCfg<R, L>::S;
   constexpr int SLOT = lds_exchange(L) + 2 * L;
   __shared__ R lds_all[S * SLOT];
@@ -50,7 +50,7 @@ __global__ __launch_bounds__((XCfg<R, L>::THREADS), FDE_XW) void toep_x_kernel(
   const int t = threadIdx.x - slot * T;
   R* lds = lds_all + slot * SLOT;
   R* zs = lds + lds_exchange(L);
-  Twiddles<R, L> tw;
+  Twiddles<R, L, P> tw;
   tw.load(twtab, t);
   const int rowA = 2 * (blockIdx.x * S + slot);
   const bool hasA = rowA < n2;
@@ -69,10 +69,10 @@ __global__ __launch_bounds__((XCfg<R, L>::THREADS), FDE_XW) void toep_x_kernel(
     zi[m] = (hasB && i < n1) ? (R)xb[i] : R(0);
   });
   fft<L, -1>(zr, zi, lds, tw, t);
-  symbol_both<L>(zr, zi, zs, mu, t);
+  symbol_both<L, P>(zr, zi, zs, mu, t);
   fft<L, +1>(zr, zi, lds, tw, t);  // real part: T xa, imaginary part: T xb
   R pr[E], pi[E];
-  unstash<L>(pr, pi, zs, t);
+  unstash<L, P>(pr, pi, zs, t);
   chunked_for<E, kEpiGroup>([&](auto m) {
     const int i = t + T * m;
     zs[i] = (hasA && i < n1) ? dA[2 * i] * zr[m] : R(0);
@@ -116,7 +116,7 @@ __global__ __launch_bounds__((YCfg<R, L>::THREADS), FDE_YW) void toep_y_kernel(
     int n1, int n2, const Tin* __restrict__ x, const R* __restrict__ epm, const R* __restrict__ mu,
     const R* __restrict__ twtab, R* __restrict__ ay, int nstrips, const int* __restrict__ skip) {
   if (skip && *skip) return;
-  using P = PlanFor<R, L>;
+  using P = YPlan<R, L>;
   constexpr int E = P::E, T = P::T, S = YCfg<R, L>::S;
   // Workgroups are dealt to the 8 XCDs round-robin; give each XCD a contiguous range of strips so
   // that neighbouring strips (which share cache lines) meet in the same L2.
@@ -129,7 +129,7 @@ __global__ __launch_bounds__((YCfg<R, L>::THREADS), FDE_YW) void toep_y_kernel(
   const int t = threadIdx.x / S;
   R* lds = lds_all + slot * SLOT;
   R* zs = lds + lds_exchange(L);
-  Twiddles<R, L> tw;
+  Twiddles<R, L, P> tw;
   tw.load(twtab, t);
   const int c0 = strip * 2 * S + 2 * slot;
   const bool v0 = c0 < n1, v1 = c0 + 1 < n1;
@@ -142,10 +142,10 @@ __global__ __launch_bounds__((YCfg<R, L>::THREADS), FDE_YW) void toep_y_kernel(
     zi[m] = (row < n2 && v1) ? (R)x[p + 1] : R(0);
   });
   fft<L, -1>(zr, zi, lds, tw, t);
-  symbol_both<L>(zr, zi, zs, mu, t);
+  symbol_both<L, P>(zr, zi, zs, mu, t);
   fft<L, +1>(zr, zi, lds, tw, t);  // T a + i T b along the columns
   R pr[E], pi[E];
-  unstash<L>(pr, pi, zs, t);
+  unstash<L, P>(pr, pi, zs, t);
   chunked_for<E, kEpiGroup>([&](auto m) {
     const int row = t + T * m;
     const unsigned p = (unsigned)row * (unsigned)n1 + (unsigned)c0;
@@ -390,33 +390,7 @@ template hipError_t launch_direct_op<float, float>(int, int, const float*, const
                                                    const float*, const SrcTerms*, double, const int*, hipStream_t);
 
 // ---- host side: twiddle tables and symbols ---------------------------------------------------
-struct RtPlan {
-  int E, T, nst;
-  int radix[16], ns[16];
-};
-static RtPlan rt_plan(int L, int emax) {
-  RtPlan p{};
-  p.E = L >= 2 * emax ? emax : L / 2;
-  p.T = L / p.E;
-  int logL = 0, logE = 0;
-  while ((1 << logL) < L) ++logL;
-  while ((1 << logE) < p.E) ++logE;
-  p.nst = (logL + logE - 1) / logE;
-  int ns = 1;
-  for (int s = 0; s < p.nst; ++s) {
-    p.radix[s] = (s < p.nst - 1 || logL % logE == 0) ? p.E : (1 << (logL % logE));
-    p.ns[s] = ns;
-    ns *= p.radix[s];
-  }
-  return p;
-}
-
-int fft_twiddle_count(int L, int elem_bytes) {
-  RtPlan p = rt_plan(L, emax_for(elem_bytes, L));
-  int c = 0;
-  for (int s = 1; s < p.nst; ++s) c += p.ns[s];
-  return 2 * c;
-}
+int fft_twiddle_count(int L, int) { return L; }
 
 // exp(-2 pi i k / M) accurate to the last bit via long double
 static void unit_root(long long k, long long M, double* re, double* im) {
@@ -425,17 +399,10 @@ static void unit_root(long long k, long long M, double* re, double* im) {
   *im = (double)sinl(a);
 }
 
-void fft_twiddles(int L, int elem_bytes, double* out, int* count) {
-  RtPlan p = rt_plan(L, emax_for(elem_bytes, L));
-  int o = 0;
-  for (int s = 1; s < p.nst; ++s) {
-    const int R = p.radix[s], NS = p.ns[s];
-    for (int j = 0; j < NS; ++j) {
-      unit_root((long long)j, (long long)NS * R, &out[o], &out[o + 1]);
-      o += 2;
-    }
-  }
-  if (count) *count = o;
+// The twiddle table of every transform plan of length L: exp(-2 pi i k/L), k < L/2.
+void fft_twiddles(int L, int, double* out, int* count) {
+  for (int k = 0; k < L / 2; ++k) unit_root(k, L, &out[2 * k], &out[2 * k + 1]);
+  if (count) *count = L;
 }
 
 // In-place radix-2 DFT (forward, sign -1) of length L (power of two), host side.
