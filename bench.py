@@ -30,6 +30,9 @@ if ROOT not in sys.path:
 
 METRIC = "MG-GMRES CN time-steps/s at 2047² + p50/p99 latency, mixed vs FP64 plain"
 HBM_PEAK_GBS = 8000.0
+# live timing of the dominant kernel samples every PROFILE_STRIDE-th launch (coprime to the three
+# Gram-Schmidt passes per step and to the restart length 20)
+PROFILE_STRIDE = 7
 
 # HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs of this workload
 # (scaled by a copy of known size), keyed by kernel family, with the hash of the source file the
@@ -87,10 +90,12 @@ def log(msg):
 def kernel_groups(prec):
     """Profiling families grouped by the kernel they time (template variants of one kernel count as
     one kernel).  With FP32 cycles the Arnoldi product runs the same FP32 fine-level FFT kernels as
-    the V-cycle's fine level."""
+    the V-cycle's fine level.  The coarser-level and transfer families hold several different
+    kernels at several sizes and are not candidates for the dominant kernel."""
     from paper_1706_06844_amd import fde
 
-    g = {f: [f] for f in fde.L.KFAM if f != "cgs_finalize"}
+    several = ("cgs_finalize", "mgc_y", "mgc_x", "transfer")
+    g = {f: [f] for f in fde.L.KFAM if f not in several}
     if prec == fde.FDE_MIXED_FP32_CYCLE:
         for d in ("y", "x"):
             g[f"fft_fine_{d}"] = [f"outer_{d}", f"mg0_{d}"]
@@ -153,6 +158,8 @@ def run_precision(prec, p, dev_fields, S, phis, u0, steps, warmup, maxit, profil
         if fam == "cgs":  # wide passes' partials are combined by a separate one-workgroup kernel
             mask |= 1 << fde.L.KFAM.index("cgs_finalize")
     fde.fde_profile_enable(h, mask)
+    # a sparse sample of the family's launches: every event pair costs the stream some microseconds
+    fde.fde_profile_stride(h, PROFILE_STRIDE)
     elapsed, lat, its, reo, u_final = run(steps, "timed")
     timed = fde.fde_profile_read(h)
     if fam is None:

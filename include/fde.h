@@ -202,6 +202,11 @@ int fde_level_diag(fde_handle* h, int level, double* diag);
                                  /* pass, in its last workgroup, and never launch this family)     */
 #define FDE_KFAM_COUNT 11
 int fde_profile_enable(fde_handle* h, uint32_t family_mask);
+/* Time only every `every`-th launch of each selected family (every >= 1; 1 after setup): each event
+ * pair costs the stream a few microseconds, so a sparse sample keeps a timed run close to an
+ * untimed one.  Pick a stride coprime to 3 and to the restart length so that the sample rotates
+ * over the pass kinds and basis sizes.  Resets the launch counters. */
+int fde_profile_stride(fde_handle* h, int every);
 int fde_profile_read(fde_handle* h, int family, int64_t* launches, double* total_ms, double* bytes);
 int fde_profile_reset(fde_handle* h);
 

@@ -88,6 +88,7 @@ SIGNATURES = {
     "fde_level_diag": (_I, [_P, _I, _P]),
     "fde_sync": (_I, [_P]),
     "fde_profile_enable": (_I, [_P, ctypes.c_uint32]),
+    "fde_profile_stride": (_I, [_P, _I]),
     "fde_profile_read": (_I, [_P, _I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "fde_profile_reset": (_I, [_P]),
     "fde_footprint": (ctypes.c_size_t, [ctypes.POINTER(fde_problem)]),

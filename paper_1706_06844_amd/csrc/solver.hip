@@ -169,6 +169,8 @@ struct ProfEntry {
 };
 struct Prof {
   unsigned mask = 0;
+  int stride = 1;                        // time every stride-th launch of a selected family
+  int64_t seen[FDE_KFAM_COUNT] = {};     // launches of each family issued while selected
   std::vector<hipEvent_t> freelist;
   std::vector<ProfEntry> pending;
   std::vector<int> cycle_nused;
@@ -262,7 +264,7 @@ hipEvent_t prof_event(fde_handle* h) {
 // mark the conditional second Gram-Schmidt pass (dropped from the totals when it did not run).
 template <typename F>
 void timed(fde_handle* h, int fam, double bytes, F&& launch) {
-  if (!(h->prof.mask & (1u << fam))) {
+  if (!(h->prof.mask & (1u << fam)) || (h->prof.seen[fam]++ % h->prof.stride) != 0) {
     HIPCHECK(launch());
     return;
   }
@@ -482,6 +484,10 @@ bool time_direct_vs_fft(fde_handle* h, Level<R>& L) {
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   const bool direct = best[1] < best[0];
+  const char* log = std::getenv("FDE_TUNE_LOG");
+  if (log && log[0] == '1')
+    std::fprintf(stderr, "fde: level %dx%d (%zu-byte) FFT %.1f us, dense %.1f us -> %s\n", L.n1, L.n2, sizeof(R),
+                 best[0] * 1e3, best[1] * 1e3, direct ? "dense" : "FFT");
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune_direct[{L.n1, L.n2, (int)sizeof(R)}] = direct;
   return direct;
@@ -1387,6 +1393,14 @@ int fde_profile_enable(fde_handle* h, uint32_t mask) {
     h->prof.mask = mask & ((1u << FDE_KFAM_COUNT) - 1);
     return FDE_OK;
   });
+}
+
+int fde_profile_stride(fde_handle* h, int every) {
+  if (!h) return set_err(nullptr, FDE_EINVAL, "handle is NULL");
+  if (every < 1) return set_err(h, FDE_EINVAL, "the stride must be >= 1");
+  h->prof.stride = every;
+  for (auto& c : h->prof.seen) c = 0;
+  return FDE_OK;
 }
 
 int fde_profile_read(fde_handle* h, int family, int64_t* launches, double* total_ms, double* bytes) {

@@ -73,10 +73,17 @@ __global__ __launch_bounds__((XCfg<R, L>::THREADS), FDE_XW) void toep_x_kernel(
   fft<L, +1>(zr, zi, lds, tw, t);  // real part: T xa, imaginary part: T xb
   R pr[E], pi[E];
   unstash<L, P>(pr, pi, zs, t);
+  using R2 = typename std::conditional<sizeof(R) == 4, float2, double2>::type;
+  R dmA[E], dmB[E];
   chunked_for<E, kEpiGroup>([&](auto m) {
     const int i = t + T * m;
-    zs[i] = (hasA && i < n1) ? dA[2 * i] * zr[m] : R(0);
-    zs[L + i] = (hasB && i < n1) ? dB[2 * i] * zi[m] : R(0);
+    R2 a{}, c{};
+    if (hasA && i < n1) a = *reinterpret_cast<const R2*>(dA + 2 * i);
+    if (hasB && i < n1) c = *reinterpret_cast<const R2*>(dB + 2 * i);
+    zs[i] = a.x * zr[m];
+    zs[L + i] = c.x * zi[m];
+    dmA[m] = a.y;
+    dmB[m] = c.y;
   });
   fft<L, +1>(pr, pi, lds, tw, t);  // real part: T^T xa, imaginary part: T^T xb
   const R* ayA = ay ? U(ay + oA) : nullptr;
@@ -87,9 +94,9 @@ __global__ __launch_bounds__((XCfg<R, L>::THREADS), FDE_XW) void toep_x_kernel(
   const R* diB = dinv ? U(dinv + oB) : nullptr;
   R* outA = U(out + oA);
   R* outB = U(out + oB);
-  auto finish = [&](const Tin* xr, const R* d, const R* ayr, const R* br, const R* dir, R* outr, size_t o,
+  auto finish = [&](const Tin* xr, R dm, const R* ayr, const R* br, const R* dir, R* outr, size_t o,
                     R lpart, R rpart, int i) {
-    R l = lpart + d[2 * i + 1] * rpart;
+    R l = lpart + dm * rpart;
     if (ayr) l += ayr[i];
     R bv = R(0), dv = R(0);
     double sv = 0.0;
@@ -105,8 +112,8 @@ __global__ __launch_bounds__((XCfg<R, L>::THREADS), FDE_XW) void toep_x_kernel(
   chunked_for<E, kEpiGroup>([&](auto m) {
     const int i = t + T * m;
     if (hasA && i < n1) {
-      finish(xa, dA, ayA, bA, diA, outA, oA, zs[i], pr[m], i);
-      if (hasB) finish(xb, dB, ayB, bB, diB, outB, oB, zs[L + i], pi[m], i);
+      finish(xa, dmA[m], ayA, bA, diA, outA, oA, zs[i], pr[m], i);
+      if (hasB) finish(xb, dmB[m], ayB, bB, diB, outB, oB, zs[L + i], pi[m], i);
     }
   });
 }
@@ -146,19 +153,27 @@ __global__ __launch_bounds__((YCfg<R, L>::THREADS), FDE_YW) void toep_y_kernel(
   fft<L, +1>(zr, zi, lds, tw, t);  // T a + i T b along the columns
   R pr[E], pi[E];
   unstash<L, P>(pr, pi, zs, t);
+  // (e+, e-) of both columns in one read: e+ weights the first product now, e- waits in registers
+  using R2 = typename std::conditional<sizeof(R) == 4, float2, double2>::type;
+  R em0[E], em1[E];
   chunked_for<E, kEpiGroup>([&](auto m) {
     const int row = t + T * m;
     const unsigned p = (unsigned)row * (unsigned)n1 + (unsigned)c0;
-    zs[row] = (row < n2 && v0) ? epm[2 * p] * zr[m] : R(0);
-    zs[L + row] = (row < n2 && v1) ? epm[2 * p + 2] * zi[m] : R(0);
+    R2 e0{}, e1{};
+    if (row < n2 && v0) e0 = *reinterpret_cast<const R2*>(epm + 2 * p);
+    if (row < n2 && v1) e1 = *reinterpret_cast<const R2*>(epm + 2 * p + 2);
+    zs[row] = e0.x * zr[m];
+    zs[L + row] = e1.x * zi[m];
+    em0[m] = e0.y;
+    em1[m] = e1.y;
   });
   fft<L, +1>(pr, pi, lds, tw, t);  // T^T a + i T^T b
   chunked_for<E, kEpiGroup>([&](auto m) {
     const int row = t + T * m;
     if (row < n2) {
       const unsigned p = (unsigned)row * (unsigned)n1 + (unsigned)c0;
-      if (v0) ay[p] = zs[row] + epm[2 * p + 1] * pr[m];
-      if (v1) ay[p + 1] = zs[L + row] + epm[2 * p + 3] * pi[m];
+      if (v0) ay[p] = zs[row] + em0[m] * pr[m];
+      if (v1) ay[p + 1] = zs[L + row] + em1[m] * pi[m];
     }
   });
 }

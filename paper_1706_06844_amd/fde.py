@@ -183,6 +183,10 @@ def fde_profile_enable(h: Handle, mask: int = (1 << len(L.KFAM)) - 1) -> None:
     _check(_lib().fde_profile_enable(h.ptr, mask), h)
 
 
+def fde_profile_stride(h: Handle, every: int) -> None:
+    _check(_lib().fde_profile_stride(h.ptr, every), h)
+
+
 def fde_profile_reset(h: Handle) -> None:
     _check(_lib().fde_profile_reset(h.ptr), h)
 

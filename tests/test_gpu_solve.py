@@ -211,3 +211,29 @@ def test_multigrid_as_standalone_solver(prec):
     note(f"stand-alone multigrid prec={prec}: {st['iters']} cycles (oracle {k_ref})")
     assert st["converged"] and abs(st["iters"] - k_ref) <= 1
     assert rel(host(x), solve_step(op, b)) <= 1e-9
+
+
+def test_kernel_timing_counts_and_stride():
+    # every launch of the timed families is counted once; a stride of 3 keeps one launch in three
+    n = 1023  # FFT fine level
+    p = workloads.config_c2(n, 32)
+    h = make_handle(p, precision=fde.FDE_MIXED_FP32_CYCLE)
+    b = dev(np.random.default_rng(6).standard_normal((n, n)))
+    counts = {}
+    for every in (1, 3):
+        fde.fde_profile_enable(h)
+        fde.fde_profile_stride(h, every)
+        fde.fde_profile_reset(h)
+        x = dev(np.zeros((n, n)))
+        st = fde.fde_solve(h, b, x)
+        assert st["converged"]
+        prof = fde.fde_profile_read(h)
+        counts[every] = prof
+        fde.fde_profile_enable(h, 0)
+    its = st["iters"]
+    # two fine-level column passes per V-cycle, one per Arnoldi product
+    assert counts[1]["mg0_y"]["launches"] == 2 * its
+    assert abs(counts[3]["mg0_y"]["launches"] - 2 * its / 3) <= 2
+    assert counts[3]["mg0_y"]["ms"] > 0
+    with pytest.raises(fde.FdeError):
+        fde.fde_profile_stride(h, 0)
