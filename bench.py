@@ -67,7 +67,7 @@ def parse():
     ap.add_argument("--maxit", type=int, default=4000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=24)
-    ap.add_argument("--only", choices=["cycle", "mixed", "fp64", "bf16"], default=None)
+    ap.add_argument("--only", choices=["cycle16", "cycle", "mixed", "fp64", "bf16"], default=None)
     ap.add_argument("--workload", choices=["c3", "c4", "c5"], default="c3",
                     help="c3: the single 2047^2 instance (default, the headline line); c4: 64 batched "
                          "instances; c5: served requests with Poisson arrivals")
@@ -96,7 +96,7 @@ def kernel_groups(prec):
 
     several = ("cgs_finalize", "mgc_y", "mgc_x", "transfer")
     g = {f: [f] for f in fde.L.KFAM if f not in several}
-    if prec == fde.FDE_MIXED_FP32_CYCLE:
+    if prec in (fde.FDE_MIXED_FP32_CYCLE, fde.FDE_MIXED_CYCLE_BF16):
         for d in ("y", "x"):
             g[f"fft_fine_{d}"] = [f"outer_{d}", f"mg0_{d}"]
             del g[f"outer_{d}"], g[f"mg0_{d}"]
@@ -443,8 +443,8 @@ def main():
         torch.cuda.synchronize()
         log(f"copy calibration: 3 copies of {u0.numel() * 8} bytes")
     res = {}
-    order = [("cycle", fde.FDE_MIXED_FP32_CYCLE), ("mixed", fde.FDE_MIXED_FP32), ("fp64", fde.FDE_FP64),
-             ("bf16", fde.FDE_MIXED_BF16GEMM)]
+    order = [("cycle16", fde.FDE_MIXED_CYCLE_BF16), ("cycle", fde.FDE_MIXED_FP32_CYCLE), ("mixed", fde.FDE_MIXED_FP32),
+             ("fp64", fde.FDE_FP64), ("bf16", fde.FDE_MIXED_BF16GEMM)]
     for name, prec in order:
         if args.only and args.only != name:
             continue
@@ -455,7 +455,7 @@ def main():
         r = res[name]
         log(f"{name}: {args.steps / r['elapsed']:.3f} steps/s, mean iters {np.mean(r['iters']):.1f}, "
             f"dominant {r['family']}")
-    main_name = next(k for k in ("cycle", "mixed", "fp64", "bf16") if k in res)
+    main_name = next(k for k in ("cycle16", "cycle", "mixed", "fp64", "bf16") if k in res)
     m = res[main_name]
     lat_ms = np.array(m["lat"]) * 1e3
     live = m["live"]
@@ -473,12 +473,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"cycle": "f64+f32", "mixed": "f64+f32", "fp64": "f64", "bf16": "f64+f32+bf16"}[main_name],
+        "dtype": {"cycle16": "f64+f32+bf16", "cycle": "f64+f32", "mixed": "f64+f32", "fp64": "f64",
+                  "bf16": "f64+f32+bf16"}[main_name],
         "data": "synthetic",
         "config": {"workload": f"C3 anisotropic instance {args.n}x{args.n}, alpha=1.2, beta=1.9, "
                                "C2 variable coefficients, tau=1/16, manufactured + N(0,1) source "
                                "(seed 3)",
-                   "precision": {"cycle": "FP32 V-cycle and FP32 restart cycles (basis, Arnoldi products) "
+                   "precision": {"cycle16": "FP32 V-cycle and FP32 restart cycles (Arnoldi products, "
+                                            "orthogonalisation; basis stored in BF16) refining the FP64 iterate "
+                                            "from FP64 true residuals",
+                                 "cycle": "FP32 V-cycle and FP32 restart cycles (basis, Arnoldi products) "
                                           "refining the FP64 iterate from FP64 true residuals",
                                  "mixed": "FP32 V-cycle in FP64 flexible GMRES", "fp64": "FP64",
                                  "bf16": "V-cycle with BF16 MFMA operator passes (FP32 accumulation) in FP64 "

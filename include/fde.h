@@ -62,6 +62,13 @@ extern "C" {
                                   solve is iterative refinement with FP32 inner solves and the
                                   tolerance still holds for the FP64 residual.  Needs a rediscretised
                                   fine level: not with FDE_MG_BAND                                 */
+#define FDE_MIXED_CYCLE_BF16 4 /* as FDE_MIXED_FP32_CYCLE with the Krylov basis stored in BF16: each
+                                  new direction is orthogonalised in FP32 and stored rounded to BF16
+                                  (a basis orthonormal to about 3 digits, enough for the modest
+                                  reduction each restart cycle delivers on solves that take many
+                                  cycles; a solve that would end inside its first cycle takes a
+                                  second one); half the Gram-Schmidt traffic again.  Not with
+                                  FDE_MG_BAND                                                       */
 
 #define FDE_MG_GEOMETRIC 0     /* rediscretised coarse operators, Sec. 4.2 (the paper's P_MGM)      */
 #define FDE_MG_GALERKIN 1      /* Galerkin coarse operators R A P, Sec. 4 TGM step 3 (tilde P_MGM)   */
@@ -77,7 +84,8 @@ typedef struct fde_problem {
   int32_t n1, n2;       /* interior points in x and y; multigrid needs 2^l - 1 with l >= 3         */
   double a1, b1, a2, b2;/* domain (a1,b1) x (a2,b2), a < b                                         */
   double tau;           /* time step, > 0                                                          */
-  int32_t precision;    /* FDE_FP64 | FDE_MIXED_FP32 | FDE_MIXED_BF16GEMM | FDE_MIXED_FP32_CYCLE   */
+  int32_t precision;    /* FDE_FP64 | FDE_MIXED_FP32 | FDE_MIXED_BF16GEMM | FDE_MIXED_FP32_CYCLE |
+                           FDE_MIXED_CYCLE_BF16                                                     */
   int32_t mg_variant;   /* FDE_MG_GEOMETRIC | FDE_MG_GALERKIN | FDE_MG_BAND                        */
   double omega;         /* Jacobi damping (Lemma lemsmo), 0 < omega <= 1; 0 selects 0.7             */
   int32_t nu_pre;       /* pre-smoothing steps per level, >= 0 (< 0 selects 1)                      */

@@ -25,6 +25,7 @@ FDE_FP64 = 0
 FDE_MIXED_FP32 = 1
 FDE_MIXED_BF16GEMM = 2
 FDE_MIXED_FP32_CYCLE = 3
+FDE_MIXED_CYCLE_BF16 = 4
 FDE_MG_GEOMETRIC = 0
 FDE_MG_GALERKIN = 1
 FDE_MG_BAND = 2

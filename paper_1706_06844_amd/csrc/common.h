@@ -219,12 +219,19 @@ struct GmresState {
 // Givens update); INIT (w = src, ||src||) and RESNORM (||w||, or w = src and ||src|| when src is
 // given) start a solve and a cycle.
 enum CgsKind : int { CGS_DOTS = 0, CGS_UPDATE_DOTS = 1, CGS_UPDATE_NORM = 2, CGS_INIT = 3, CGS_RESNORM = 4 };
-// One fused pass over the basis V[0..nv) (FP64 or FP32 storage TV, column stride ldv a multiple of
-// 16 bytes' worth of entries, columns 16-byte aligned) and w (16-byte aligned, readable and
-// writable up to N rounded up to 16 bytes); src is FP64.
-// Streams the pass and writes per-workgroup partials; `cap` bounds the grid (cgs_grid(N)).
-template <typename TV>
-hipError_t launch_cgs_pass(int kind, size_t N, int nv, TV* V, size_t ldv, TV* w, const double* src,
+// BF16 storage of a Krylov basis entry (the upper half of the FP32 bit pattern).
+struct bf16_t {
+  uint16_t bits;
+};
+// One fused pass over the basis V[0..nv) (storage TB: FP64, FP32 or BF16; column stride ldv a
+// multiple of the run length, 16 / sizeof(TW) entries; columns aligned to a run) and the work vector
+// w (storage TW: FP64 or FP32, 16-byte aligned, readable and writable up to N rounded up to a run);
+// src is FP64.  With TB = TW, w is itself a basis column and vout is unused; with BF16 storage the
+// passes that finish a vector (UPDATE_NORM, INIT, RESNORM with src) also write its BF16 rounding
+// to the basis column vout.  Streams the pass and writes per-workgroup partials; `cap` bounds the
+// grid (cgs_grid(N)).
+template <typename TB, typename TW>
+hipError_t launch_cgs_pass(int kind, size_t N, int nv, TB* V, size_t ldv, TW* w, TB* vout, const double* src,
                            GmresState* st, double* partials, int cap, hipStream_t s);
 // Combines the partials of the preceding pass (same kind, nv, cap) and updates the solver state.
 // Not needed (and not launched) when cgs_fused(nv, cap): the pass then finalises itself.

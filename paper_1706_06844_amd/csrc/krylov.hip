@@ -14,6 +14,7 @@
 // order.  The result does not depend on scheduling, so runs are bitwise
 // reproducible for a given launch shape.
 #include "common.h"
+#include "fft.h"  // static_for
 
 namespace fde {
 
@@ -89,43 +90,122 @@ struct FinLds {
 template <int PL>
 __device__ void finalize_block(int kind, int nv, int G, const double* partials, GmresState* gst, FinLds<PL>& F);
 
-// 16-byte vectors of the basis type: each thread streams VEC consecutive entries per load.
-template <typename TV>
-struct Vec16 {
-  static constexpr int VEC = 16 / (int)sizeof(TV);
+// Runs of VEC consecutive entries per thread: 16-byte loads of the work vector w (FP64: 2 entries,
+// FP32: 4) and the matching entries of the basis columns (FP64, FP32 or BF16 storage).  Basis
+// entries are held in registers as `reg` (FP64, or FP32 for FP32 and BF16 storage).
+template <typename TB>
+struct BasisT {
+  using reg = TB;
 };
-template <typename TV>
-__device__ __forceinline__ void load16(const TV* p, TV (&v)[Vec16<TV>::VEC]) {
-  if constexpr (sizeof(TV) == 8) {
+template <>
+struct BasisT<bf16_t> {
+  using reg = float;
+};
+
+template <typename T, int VEC>
+__device__ __forceinline__ void load_vec(const T* p, typename BasisT<T>::reg (&v)[VEC]) {
+  if constexpr (std::is_same<T, double>::value) {
+    static_assert(VEC == 2, "FP64 runs are 2 entries");
     const double2 a = *reinterpret_cast<const double2*>(p);
     v[0] = a.x;
     v[1] = a.y;
-  } else {
+  } else if constexpr (std::is_same<T, float>::value) {
+    static_assert(VEC == 4, "FP32 runs are 4 entries");
     const float4 a = *reinterpret_cast<const float4*>(p);
     v[0] = a.x;
     v[1] = a.y;
     v[2] = a.z;
     v[3] = a.w;
+  } else {
+    static_assert(VEC == 4, "BF16 runs are 4 entries");
+    const uint2 a = *reinterpret_cast<const uint2*>(p);
+    v[0] = __uint_as_float(a.x << 16);
+    v[1] = __uint_as_float(a.x & 0xffff0000u);
+    v[2] = __uint_as_float(a.y << 16);
+    v[3] = __uint_as_float(a.y & 0xffff0000u);
   }
 }
-template <typename TV>
-__device__ __forceinline__ void store16(TV* p, const TV (&v)[Vec16<TV>::VEC]) {
-  if constexpr (sizeof(TV) == 8) *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
-  else *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+// A run of basis entries as loaded (16 bytes of FP64 or FP32, 8 bytes of BF16), unpacked entry by
+// entry where it is used, so that the loads of all columns are issued before any result is needed.
+template <typename TB>
+struct RawT;
+template <>
+struct RawT<double> {
+  using type = double2;
+};
+template <>
+struct RawT<float> {
+  using type = float4;
+};
+template <>
+struct RawT<bf16_t> {
+  using type = uint2;
+};
+template <typename TB>
+__device__ __forceinline__ typename RawT<TB>::type load_raw(const TB* p) {
+  return *reinterpret_cast<const typename RawT<TB>::type*>(p);
+}
+template <typename TB>
+__device__ __forceinline__ typename RawT<TB>::type zero_raw() {
+  return typename RawT<TB>::type{};
+}
+template <typename TB, int E>
+__device__ __forceinline__ typename BasisT<TB>::reg raw_elem(const typename RawT<TB>::type& r) {
+  if constexpr (std::is_same<TB, double>::value) return E == 0 ? r.x : r.y;
+  else if constexpr (std::is_same<TB, float>::value) return E == 0 ? r.x : E == 1 ? r.y : E == 2 ? r.z : r.w;
+  else if constexpr (E == 0) return __uint_as_float(r.x << 16);
+  else if constexpr (E == 1) return __uint_as_float(r.x & 0xffff0000u);
+  else if constexpr (E == 2) return __uint_as_float(r.y << 16);
+  else return __uint_as_float(r.y & 0xffff0000u);
+}
+// zero the entries of a run at positions >= nin (the padding past N)
+template <typename TB>
+__device__ __forceinline__ void raw_mask(typename RawT<TB>::type& r, int nin) {
+  if constexpr (std::is_same<TB, double>::value) {
+    if (nin < 2) r.y = 0.0;
+  } else if constexpr (std::is_same<TB, float>::value) {
+    if (nin < 2) r.y = 0.f;
+    if (nin < 3) r.z = 0.f;
+    if (nin < 4) r.w = 0.f;
+  } else {
+    if (nin < 2) r.x &= 0xffffu;
+    if (nin < 3) r.y = 0u;
+    else if (nin < 4) r.y &= 0xffffu;
+  }
 }
 
-// One pass over the basis (FP64 or FP32 storage; products, sums and coefficients in FP64).  Each
-// thread handles runs of VEC consecutive entries (16-byte loads); the basis columns and w are padded
-// to a multiple of VEC, so the last run is readable and its entries past N are masked to zero (and
-// written back as zero).  `src` (FP64) is copied into w by INIT, and by RESNORM when given: the
-// norm is then taken of the FP64 values.  FUSED: the last workgroup to finish (counted on the
-// state's ticket) combines the partials itself, which saves small problems a launch per pass.
-template <typename TV, int MAXV, bool FUSED>
-__global__ __launch_bounds__(kCgsBlock) void cgs_kernel(int kind, int N, int nv, const TV* __restrict__ V,
-                                                        size_t ldv, TV* __restrict__ w,
+template <typename T, int VEC>
+__device__ __forceinline__ void store_vec(T* p, const T (&v)[VEC]) {
+  if constexpr (std::is_same<T, double>::value) *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
+  else *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+}
+// FP32 to BF16, rounded to nearest even (NaN and infinity stay what they are).
+__device__ __forceinline__ unsigned bf16_bits(float f) {
+  const unsigned u = __float_as_uint(f);
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ void store_bf16x4(bf16_t* p, const float (&v)[4]) {
+  *reinterpret_cast<uint2*>(p) = make_uint2(bf16_bits(v[0]) | (bf16_bits(v[1]) << 16),
+                                            bf16_bits(v[2]) | (bf16_bits(v[3]) << 16));
+}
+
+// One pass over the basis (products, sums and coefficients in FP64).  TW is the storage of the work
+// vector w (FP64 or FP32), TB that of the basis: the same type, w then being a basis column, or BF16
+// with an FP32 w, the final pass then also writing the BF16 rounding of w into the basis column
+// `vout` (INIT and RESNORM too).  Each thread handles runs of VEC consecutive entries; the basis
+// columns and w are padded to a multiple of VEC, so the last run is readable and its entries past N
+// are masked to zero (and written back as zero).  `src` (FP64) is copied into w by INIT, and by
+// RESNORM when given: the norm is then taken of the FP64 values.  FUSED: the last workgroup to
+// finish (counted on the state's ticket) combines the partials itself, which saves small problems a
+// launch per pass.
+template <typename TB, typename TW, int MAXV, bool FUSED>
+__global__ __launch_bounds__(kCgsBlock) void cgs_kernel(int kind, int N, int nv, const TB* __restrict__ V,
+                                                        size_t ldv, TW* __restrict__ w, TB* __restrict__ vout,
                                                         const double* __restrict__ src, GmresState* st,
                                                         double* __restrict__ partials) {
-  constexpr int VEC = Vec16<TV>::VEC;
+  constexpr int VEC = 16 / (int)sizeof(TW);
+  using RB = typename BasisT<TB>::reg;
+  constexpr bool kSplit = std::is_same<TB, bf16_t>::value;
   if (kind == CGS_DOTS || kind == CGS_UPDATE_DOTS || kind == CGS_UPDATE_NORM) {
     if (st->done) return;
     if (kind == CGS_UPDATE_DOTS && !st->reorth) return;
@@ -155,43 +235,61 @@ __global__ __launch_bounds__(kCgsBlock) void cgs_kernel(int kind, int N, int nv,
   for (int i = blockIdx.x * kCgsBlock + threadIdx.x; i < P; i += stride) {
     const int p = VEC * i;
     const int nin = min(VEC, N - p);
-    TV wv[VEC];
+    TW wv[VEC];
     if (copy) {
 #pragma unroll
       for (int e = 0; e < VEC; ++e) {
         const double b = e < nin ? src[p + e] : 0.0;
-        wv[e] = (TV)b;
+        wv[e] = (TW)b;
         nacc += b * b;
       }
-      store16(w + p, wv);
+      store_vec(w + p, wv);
+      if constexpr (kSplit) store_bf16x4(vout + p, wv);
       continue;
     }
-    load16(w + p, wv);
+    load_vec<TW, VEC>(w + p, wv);
 #pragma unroll
     for (int e = 0; e < VEC; ++e)
-      if (e >= nin) wv[e] = TV(0);
+      if (e >= nin) wv[e] = TW(0);
     if (kind == CGS_RESNORM) {
 #pragma unroll
       for (int e = 0; e < VEC; ++e) nacc += (double)wv[e] * (double)wv[e];
       continue;
     }
-    TV vk[MAXV][VEC];
+    // basis entries: FP64 and FP32 runs unpacked at load; BF16 runs kept packed until used (with
+    // the unpacking next to the loads the compiler waits for each load before issuing the next)
+    RB vu[kSplit ? 1 : MAXV][VEC];
+    typename RawT<TB>::type vk[kSplit ? MAXV : 1];
+    if constexpr (kSplit) {
 #pragma unroll
-    for (int k = 0; k < MAXV; ++k) {
-      if (k < nv) {
-        load16(V + (size_t)k * ldv + p, vk[k]);
-      } else {
+      for (int k = 0; k < MAXV; ++k) vk[k] = (k < nv) ? load_raw(V + (size_t)k * ldv + p) : zero_raw<TB>();
+      if (nin < VEC) {
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) vk[k][e] = TV(0);
+        for (int k = 0; k < MAXV; ++k) raw_mask<TB>(vk[k], nin);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < MAXV; ++k) {
+        if (k < nv) {
+          load_vec<TB, VEC>(V + (size_t)k * ldv + p, vu[k]);
+        } else {
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) vu[k][e] = RB(0);
+        }
+      }
+      if (nin < VEC) {
+#pragma unroll
+        for (int k = 0; k < MAXV; ++k)
+#pragma unroll
+          for (int e = 0; e < VEC; ++e)
+            if (e >= nin) vu[k][e] = RB(0);
       }
     }
-    if (nin < VEC) {
-#pragma unroll
-      for (int k = 0; k < MAXV; ++k)
-#pragma unroll
-        for (int e = 0; e < VEC; ++e)
-          if (e >= nin) vk[k][e] = TV(0);
-    }
+    auto basis = [&](int k, auto ec) -> RB {
+      constexpr int e = decltype(ec)::value;
+      if constexpr (kSplit) return raw_elem<TB, e>(vk[k]);
+      else return vu[k][e];
+    };
     if (upd) {
       double wd[VEC];
 #pragma unroll
@@ -199,19 +297,26 @@ __global__ __launch_bounds__(kCgsBlock) void cgs_kernel(int kind, int N, int nv,
 #pragma unroll
       for (int k = 0; k < MAXV; ++k)
         if (k < nv) {
-#pragma unroll
-          for (int e = 0; e < VEC; ++e) wd[e] -= hc[k] * (double)vk[k][e];
+          static_for<0, VEC>([&](auto ec) {
+            constexpr int e = decltype(ec)::value;
+            wd[e] -= hc[k] * (double)basis(k, ec);
+          });
         }
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) wv[e] = (TV)wd[e];
-      store16(w + p, wv);
+      for (int e = 0; e < VEC; ++e) wv[e] = (TW)wd[e];
+      store_vec(w + p, wv);
+      if constexpr (kSplit) {
+        if (kind == CGS_UPDATE_NORM) store_bf16x4(vout + p, wv);
+      }
     }
     if (dots) {
 #pragma unroll
       for (int k = 0; k < MAXV; ++k)
         if (k < nv) {
-#pragma unroll
-          for (int e = 0; e < VEC; ++e) acc[k] += (double)vk[k][e] * (double)wv[e];
+          static_for<0, VEC>([&](auto ec) {
+            constexpr int e = decltype(ec)::value;
+            acc[k] += (double)basis(k, ec) * (double)wv[e];
+          });
         }
     }
     if (norm) {
@@ -367,24 +472,27 @@ int cgs_pass_grid(int nv, int cap) {
   return g;
 }
 
-template <typename TV>
-hipError_t launch_cgs_pass(int kind, size_t N, int nv, TV* V, size_t ldv, TV* w, const double* src,
+template <typename TB, typename TW>
+hipError_t launch_cgs_pass(int kind, size_t N, int nv, TB* V, size_t ldv, TW* w, TB* vout, const double* src,
                            GmresState* st, double* partials, int cap, hipStream_t s) {
-  constexpr int VEC = Vec16<TV>::VEC;
+  constexpr int VEC = 16 / (int)sizeof(TW);
+  constexpr bool split = std::is_same<TB, bf16_t>::value;
   if (nv > kMaxRestart + 1 || N > (size_t)0x7ffffffe || cap < 1) return hipErrorInvalidValue;
-  if (ldv % VEC || (reinterpret_cast<uintptr_t>(V) | reinterpret_cast<uintptr_t>(w)) % 16)
-    return hipErrorInvalidValue;
+  if (ldv % VEC || (reinterpret_cast<uintptr_t>(V) | reinterpret_cast<uintptr_t>(w)) % 16) return hipErrorInvalidValue;
   if (kind == CGS_INIT && !src) return hipErrorInvalidValue;
+  // the BF16 column is written by the passes that finish a vector
+  const bool writes = kind == CGS_UPDATE_NORM || kind == CGS_INIT || (kind == CGS_RESNORM && src);
+  if (split && writes && (!vout || reinterpret_cast<uintptr_t>(vout) % 8)) return hipErrorInvalidValue;
   const int n = (int)N;
   const int grid = cgs_pass_grid(nv, cap);
   const bool fused = grid <= kFusedMaxGrid;
-#define L_(M)                                                                                                 \
-  if (fused)                                                                                                  \
-    hipLaunchKernelGGL((cgs_kernel<TV, M, true>), dim3(grid), dim3(kCgsBlock), 0, s, kind, n, nv, V, ldv, w, src, \
-                       st, partials);                                                                         \
-  else                                                                                                        \
-    hipLaunchKernelGGL((cgs_kernel<TV, M, false>), dim3(grid), dim3(kCgsBlock), 0, s, kind, n, nv, V, ldv, w, src, \
-                       st, partials)
+#define L_(M)                                                                                              \
+  if (fused)                                                                                               \
+    hipLaunchKernelGGL((cgs_kernel<TB, TW, M, true>), dim3(grid), dim3(kCgsBlock), 0, s, kind, n, nv, V, ldv, \
+                       w, vout, src, st, partials);                                                        \
+  else                                                                                                     \
+    hipLaunchKernelGGL((cgs_kernel<TB, TW, M, false>), dim3(grid), dim3(kCgsBlock), 0, s, kind, n, nv, V, ldv, \
+                       w, vout, src, st, partials)
   if (nv <= 4) { L_(4); }
   else if (nv <= 8) { L_(8); }
   else if (nv <= 12) { L_(12); }
@@ -394,10 +502,12 @@ hipError_t launch_cgs_pass(int kind, size_t N, int nv, TV* V, size_t ldv, TV* w,
 #undef L_
   return hipGetLastError();
 }
-template hipError_t launch_cgs_pass<double>(int, size_t, int, double*, size_t, double*, const double*, GmresState*,
-                                            double*, int, hipStream_t);
-template hipError_t launch_cgs_pass<float>(int, size_t, int, float*, size_t, float*, const double*, GmresState*,
-                                           double*, int, hipStream_t);
+template hipError_t launch_cgs_pass<double, double>(int, size_t, int, double*, size_t, double*, double*,
+                                                    const double*, GmresState*, double*, int, hipStream_t);
+template hipError_t launch_cgs_pass<float, float>(int, size_t, int, float*, size_t, float*, float*, const double*,
+                                                  GmresState*, double*, int, hipStream_t);
+template hipError_t launch_cgs_pass<bf16_t, float>(int, size_t, int, bf16_t*, size_t, float*, bf16_t*,
+                                                   const double*, GmresState*, double*, int, hipStream_t);
 
 bool cgs_fused(int nv, int cap) { return cgs_pass_grid(nv, cap) <= kFusedMaxGrid; }
 

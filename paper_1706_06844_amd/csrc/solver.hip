@@ -216,6 +216,8 @@ struct fde_handle {
   // Krylov storage
   double* V = nullptr;    // restart + 1 columns of N, column stride ldv (one column with FP32 cycles)
   float* V32 = nullptr;   // FP32 cycles: the basis, restart + 1 columns, column stride ldv
+  bf16_t* V16 = nullptr;  // BF16 basis: restart + 1 columns, column stride ldv
+  float* W32 = nullptr;   // BF16 basis: the FP32 vector being orthogonalised (ldv entries)
   size_t ldv = 0;
   void* Z = nullptr;      // restart x N, FP64 or FP32
   GmresState* st = nullptr;
@@ -238,7 +240,8 @@ struct fde_handle {
   Prof prof;
   std::string err;
   bool fp32() const { return p.precision != FDE_FP64; }
-  bool cyc32() const { return p.precision == FDE_MIXED_FP32_CYCLE; }
+  bool cyc32() const { return p.precision == FDE_MIXED_FP32_CYCLE || p.precision == FDE_MIXED_CYCLE_BF16; }
+  bool basis16() const { return p.precision == FDE_MIXED_CYCLE_BF16; }
 };
 
 namespace {
@@ -348,10 +351,10 @@ int validate(const fde_problem* p, std::string* why) {
   if (p->n1 > 2047 || p->n2 > 2047) return bad("n1 and n2 are limited to 2047 (FFT length 4096)");
   if (!(p->b1 > p->a1) || !(p->b2 > p->a2)) return bad("domain needs a < b");
   if (!(p->tau > 0.0) || !std::isfinite(p->tau)) return bad("tau must be positive and finite");
-  if (p->precision < FDE_FP64 || p->precision > FDE_MIXED_FP32_CYCLE) return bad("unknown precision");
+  if (p->precision < FDE_FP64 || p->precision > FDE_MIXED_CYCLE_BF16) return bad("unknown precision");
   if (p->mg_variant != FDE_MG_GEOMETRIC && p->mg_variant != FDE_MG_GALERKIN && p->mg_variant != FDE_MG_BAND)
     return bad("unknown mg_variant");
-  if (p->precision == FDE_MIXED_FP32_CYCLE && p->mg_variant == FDE_MG_BAND)
+  if ((p->precision == FDE_MIXED_FP32_CYCLE || p->precision == FDE_MIXED_CYCLE_BF16) && p->mg_variant == FDE_MG_BAND)
     return bad("FP32 cycles apply the operator on the preconditioner's fine level, which the band "
                "preconditioner replaces");
   if (!(p->omega > 0.0 && p->omega <= 1.0)) return bad("omega must lie in (0,1]");
@@ -846,10 +849,11 @@ void read_state(fde_handle* h) {
 
 // One Gram-Schmidt pass (timed as the CGS family) and the combination of its partials (timed
 // separately; small passes combine them in their last workgroup).  Negative `bytes` mark the conditional second pass.
-template <typename TV>
-void cgs(fde_handle* h, int kind, int nv, TV* V, TV* w, const double* src, double bytes) {
+template <typename TB, typename TW>
+void cgs(fde_handle* h, int kind, int nv, TB* V, TW* w, TB* vout, const double* src, double bytes) {
   timed(h, FDE_KFAM_CGS, bytes, [&] {
-    return launch_cgs_pass<TV>(kind, h->N, nv, V, h->ldv, w, src, h->st, h->partials, h->cgs_grid, h->stream);
+    return launch_cgs_pass<TB, TW>(kind, h->N, nv, V, h->ldv, w, vout, src, h->st, h->partials, h->cgs_grid,
+                                   h->stream);
   });
   if (cgs_fused(nv, h->cgs_grid)) return;
   timed(h, FDE_KFAM_CGS_FINALIZE, bytes < 0 ? -1e-300 : 0.0,
@@ -857,18 +861,30 @@ void cgs(fde_handle* h, int kind, int nv, TV* V, TV* w, const double* src, doubl
 }
 
 // Step j of the Arnoldi process: z_j = MG(v_j), w = A z_j, and its orthogonalisation against
-// v_0..v_j.  With FP32 cycles the basis is FP32 and A z_j is the FP32 fine-level operator of the
-// preconditioner (the same discretisation as the FP64 one, Sec. 4.2).
-template <typename R, typename TV>
-void arnoldi_step(fde_handle* h, Hierarchy<R>& H, TV* V, int j) {
+// v_0..v_j.  With FP32 cycles A z_j is the FP32 fine-level operator of the preconditioner (the same
+// discretisation as the FP64 one, Sec. 4.2) and the basis is FP32 (TB = TW = float: w is column
+// j + 1) or BF16 (w is a separate FP32 vector, which also carries v_j into the V-cycle, and the
+// final pass writes its BF16 rounding to column j + 1).
+template <typename R, typename TB, typename TW>
+void arnoldi_step(fde_handle* h, Hierarchy<R>& H, TB* V, TW* wsep, int j) {
+  constexpr bool split = !std::is_same<TB, TW>::value;
   const size_t N = h->N;
   const int* skip = &h->st->done;
   R* Z = static_cast<R*>(h->Z);
   const size_t ldv = h->ldv;
-  TV* vj = V + (size_t)j * ldv;
-  TV* w = V + (size_t)(j + 1) * ldv;
-  vcycle_top<R, TV>(h, H, vj, &h->st->vscale[j], Z + (size_t)j * N, skip);
-  if constexpr (std::is_same<TV, float>::value) {
+  TW* vj;
+  TW* w;
+  TB* vout = nullptr;
+  if constexpr (split) {
+    vj = wsep;
+    w = wsep;
+    vout = V + (size_t)(j + 1) * ldv;
+  } else {
+    vj = V + (size_t)j * ldv;
+    w = V + (size_t)(j + 1) * ldv;
+  }
+  vcycle_top<R, TW>(h, H, vj, &h->st->vscale[j], Z + (size_t)j * N, skip);
+  if constexpr (std::is_same<TW, float>::value) {
     Level<R>& L0 = H.lv[0];
     if (L0.gal || L0.mfma) throw FdeError{FDE_EINVAL, "FP32 cycles need an FFT or dense fine level"};
     op_apply<float, float>(h, true, L0.view(), Z + (size_t)j * N, L0.ay, w, EP_APPLY, nullptr, nullptr, 0.0, skip);
@@ -876,12 +892,12 @@ void arnoldi_step(fde_handle* h, Hierarchy<R>& H, TV* V, int j) {
     const OpView<double> op = h->cur.view(h->tw64_x, h->tw64_y, h->n1, h->n2, h->L1, h->L2);
     op_apply<double, R>(h, true, op, Z + (size_t)j * N, h->ay64, w, EP_APPLY, nullptr, nullptr, 0.0, skip);
   }
-  // bytes of a pass: j + 1 basis columns and w read, w written by the update passes (a skipped
-  // second pass is counted as a launch of zero bytes)
-  const double vb = (double)(j + 2) * N * sizeof(TV);
-  cgs<TV>(h, CGS_DOTS, j + 1, V, w, nullptr, vb);
-  cgs<TV>(h, CGS_UPDATE_DOTS, j + 1, V, w, nullptr, -(vb + N * sizeof(TV)));
-  cgs<TV>(h, CGS_UPDATE_NORM, j + 1, V, w, nullptr, vb + N * sizeof(TV));
+  // bytes of a pass: j + 1 basis columns and w read, w written by the update passes, the BF16
+  // column by the final one (a skipped second pass is counted as a launch of zero bytes)
+  const double vb = (double)(j + 1) * N * sizeof(TB) + (double)N * sizeof(TW);
+  cgs<TB, TW>(h, CGS_DOTS, j + 1, V, w, vout, nullptr, vb);
+  cgs<TB, TW>(h, CGS_UPDATE_DOTS, j + 1, V, w, vout, nullptr, -(vb + N * sizeof(TW)));
+  cgs<TB, TW>(h, CGS_UPDATE_NORM, j + 1, V, w, vout, nullptr, vb + N * sizeof(TW) + (split ? N * sizeof(TB) : 0.0));
 }
 
 // The start of a solve (w = b and ||b||) and of a cycle (the FP64 true residual and its norm).
@@ -889,22 +905,29 @@ void arnoldi_step(fde_handle* h, Hierarchy<R>& H, TV* V, int j) {
 // the norm pass, whose norm is that of the FP64 values.
 void start_solve(fde_handle* h, const double* b) {
   const size_t N = h->N;
-  if (h->cyc32()) cgs<float>(h, CGS_INIT, 0, h->V32, h->V32, b, N * (sizeof(double) + sizeof(float)));
-  else cgs<double>(h, CGS_INIT, 0, h->V, h->V, b, 2.0 * N * sizeof(double));
+  if (h->basis16())
+    cgs<bf16_t, float>(h, CGS_INIT, 0, h->V16, h->W32, h->V16, b, N * (sizeof(double) + sizeof(float) + 2.0));
+  else if (h->cyc32())
+    cgs<float, float>(h, CGS_INIT, 0, h->V32, h->V32, nullptr, b, N * (sizeof(double) + sizeof(float)));
+  else cgs<double, double>(h, CGS_INIT, 0, h->V, h->V, nullptr, b, 2.0 * N * sizeof(double));
 }
 void restart_residual(fde_handle* h, const double* b, const double* x) {
   const size_t N = h->N;
   const OpView<double> op = h->cur.view(h->tw64_x, h->tw64_y, h->n1, h->n2, h->L1, h->L2);
   op_apply<double, double>(h, true, op, x, h->ay64, h->V, EP_RESID, b, nullptr, 0.0, nullptr);
-  if (h->cyc32()) cgs<float>(h, CGS_RESNORM, 0, h->V32, h->V32, h->V, N * (sizeof(double) + sizeof(float)));
-  else cgs<double>(h, CGS_RESNORM, 0, h->V, h->V, nullptr, (double)N * sizeof(double));
+  if (h->basis16())
+    cgs<bf16_t, float>(h, CGS_RESNORM, 0, h->V16, h->W32, h->V16, h->V, N * (sizeof(double) + sizeof(float) + 2.0));
+  else if (h->cyc32())
+    cgs<float, float>(h, CGS_RESNORM, 0, h->V32, h->V32, nullptr, h->V, N * (sizeof(double) + sizeof(float)));
+  else cgs<double, double>(h, CGS_RESNORM, 0, h->V, h->V, nullptr, nullptr, (double)N * sizeof(double));
 }
 template <typename R>
 void arnoldi(fde_handle* h, Hierarchy<R>& H, int j) {
   if constexpr (std::is_same<R, float>::value) {
-    if (h->cyc32()) return arnoldi_step<R, float>(h, H, h->V32, j);
+    if (h->basis16()) return arnoldi_step<R, bf16_t, float>(h, H, h->V16, h->W32, j);
+    if (h->cyc32()) return arnoldi_step<R, float, float>(h, H, h->V32, nullptr, j);
   }
-  arnoldi_step<R, double>(h, H, h->V, j);
+  arnoldi_step<R, double, double>(h, H, h->V, nullptr, j);
 }
 
 template <typename R>
@@ -964,7 +987,7 @@ template <typename R>
 int mg_solve(fde_handle* h, Hierarchy<R>& H, const double* b, double* x, int max_cycles, fde_stats* stats) {
   const size_t N = h->N;
   HIPCHECK(launch_fill<double>(N, x, 0.0, h->stream));
-  cgs<double>(h, CGS_INIT, 0, h->V, h->V, b, 2.0 * N * sizeof(double));  // r = b (FP64 column), ||b||
+  cgs<double, double>(h, CGS_INIT, 0, h->V, h->V, nullptr, b, 2.0 * N * sizeof(double));  // r = b, ||b||
   read_state(h);
   const OpView<double> op = h->cur.view(h->tw64_x, h->tw64_y, h->n1, h->n2, h->L1, h->L2);
   R* z = static_cast<R*>(h->Z);
@@ -973,7 +996,7 @@ int mg_solve(fde_handle* h, Hierarchy<R>& H, const double* b, double* x, int max
     vcycle_top<R>(h, H, h->V, nullptr, z, nullptr);
     HIPCHECK(launch_add_to<R>(N, z, x, h->stream));
     op_apply<double, double>(h, true, op, x, h->ay64, h->V, EP_RESID, b, nullptr, 0.0, nullptr);
-    cgs<double>(h, CGS_RESNORM, 0, h->V, h->V, nullptr, (double)N * sizeof(double));
+    cgs<double, double>(h, CGS_RESNORM, 0, h->V, h->V, nullptr, nullptr, (double)N * sizeof(double));
     read_state(h);
     ++k;
     if (!std::isfinite(h->st_host->resnorm)) break;
@@ -1131,7 +1154,9 @@ size_t footprint_bytes(const fde_problem* pin) {
   b += 2.0 * (L1 + L2) * 8 + 4.0 * (L1 + L2) * 8;   // symbols, twiddles
   b += (1 + 1 + 4 + 1) * N * 8;                     // ay64, rhs, scratch, async solution
   const double ld = (double)basis_ld((size_t)N);
-  b += (p.precision == FDE_MIXED_FP32_CYCLE ? ld * 8 + (p.restart + 1.0) * ld * 4 : (p.restart + 1.0) * ld * 8);
+  if (p.precision == FDE_MIXED_CYCLE_BF16) b += ld * 8 + ld * 4 + (p.restart + 1.0) * ld * 2;
+  else if (p.precision == FDE_MIXED_FP32_CYCLE) b += ld * 8 + (p.restart + 1.0) * ld * 4;
+  else b += (p.restart + 1.0) * ld * 8;
   b += p.restart * N * R;
   b += (double)cgs_partials_len((size_t)N) * 8 + sizeof(GmresState) + 4096;
   const bool gal = (p.mg_variant == FDE_MG_GALERKIN || p.mg_variant == FDE_MG_BAND) &&
@@ -1282,7 +1307,11 @@ int fde_setup(const fde_problem* pin, const double* dp, const double* dm, const 
     h->rhs = dalloc<double>(m, N);
     h->scratch64 = dalloc<double>(m, 4 * N);
     h->ldv = basis_ld(N);
-    if (h->cyc32()) {
+    if (h->basis16()) {
+      h->V = dalloc<double>(m, h->ldv);
+      h->V16 = dalloc<bf16_t>(m, (size_t)(p.restart + 1) * h->ldv);
+      h->W32 = dalloc<float>(m, h->ldv);
+    } else if (h->cyc32()) {
       h->V = dalloc<double>(m, h->ldv);
       h->V32 = dalloc<float>(m, (size_t)(p.restart + 1) * h->ldv);
     } else {

@@ -14,7 +14,7 @@ import torch
 from . import _lib as L
 from ._lib import (FDE_EAGAIN, FDE_EDEVICE, FDE_EINVAL, FDE_ENEGCOEF, FDE_ENOCONV, FDE_ENOMEM,  # noqa
                    FDE_ENONFINITE, FDE_FP64, FDE_MG_BAND, FDE_MG_GALERKIN, FDE_MG_GEOMETRIC,
-                   FDE_MIXED_BF16GEMM, FDE_MIXED_FP32_CYCLE,
+                   FDE_MIXED_BF16GEMM, FDE_MIXED_CYCLE_BF16, FDE_MIXED_FP32_CYCLE,
                    FDE_MIXED_FP32, FDE_OK, fde_problem, fde_stats)
 
 

@@ -62,7 +62,7 @@ def test_problem_default(lib):
     ("n1", 10, "2^l - 1"), ("n2", 3, "2^l - 1"), ("n1", 4095, "2047"),
     ("tau", 0.0, "tau"), ("tau", -1.0, "tau"), ("restart", 40, "restart"),
     ("omega", 1.5, "omega"), ("b1", -1.0, "a < b"), ("precision", 7, "precision"),
-    ("precision", 4, "precision"),
+    ("precision", 5, "precision"),
 ])
 def test_setup_rejects_invalid_problems(lib, field, value, needle):
     p = L.fde_problem()
@@ -75,10 +75,11 @@ def test_setup_rejects_invalid_problems(lib, field, value, needle):
     assert needle in lib.fde_last_error(None).decode()
 
 
-def test_fp32_cycles_need_a_rediscretised_fine_level(lib):
+@pytest.mark.parametrize("prec", [L.FDE_MIXED_FP32_CYCLE, L.FDE_MIXED_CYCLE_BF16])
+def test_fp32_cycles_need_a_rediscretised_fine_level(lib, prec):
     p = L.fde_problem()
     lib.fde_problem_default(ctypes.byref(p), 1.5, 1.5, 63, 63, 0.01)
-    p.precision = L.FDE_MIXED_FP32_CYCLE
+    p.precision = prec
     p.mg_variant = L.FDE_MG_BAND
     out = ctypes.c_void_p()
     fake = ctypes.c_void_p(0x1000)
@@ -91,7 +92,7 @@ def test_fp32_cycles_halve_the_basis_footprint():
     from paper_1706_06844_amd import fde
 
     q = {}
-    for prec in (L.FDE_MIXED_FP32, L.FDE_MIXED_FP32_CYCLE):
+    for prec in (L.FDE_MIXED_FP32, L.FDE_MIXED_FP32_CYCLE, L.FDE_MIXED_CYCLE_BF16):
         p = fde.fde_problem_default(1.5, 1.5, 2047, 2047, 0.01)
         p.precision = prec
         q[prec] = fde.fde_footprint(p)
@@ -100,6 +101,9 @@ def test_fp32_cycles_halve_the_basis_footprint():
     # 5% margin)
     saved = 21 * ld * 8 - (ld * 8 + 21 * ld * 4)
     assert q[L.FDE_MIXED_FP32] - q[L.FDE_MIXED_FP32_CYCLE] == pytest.approx(1.05 * saved, abs=2)
+    # BF16 storage: 21 BF16 columns plus one FP32 work vector in place of 21 FP32 columns
+    saved16 = 21 * ld * 4 - (ld * 4 + 21 * ld * 2)
+    assert q[L.FDE_MIXED_FP32_CYCLE] - q[L.FDE_MIXED_CYCLE_BF16] == pytest.approx(1.05 * saved16, abs=2)
 
 
 def test_setup_rejects_null_arguments(lib):

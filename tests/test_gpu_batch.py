@@ -45,7 +45,8 @@ def _drain(b, ids, shapes):
     return out
 
 
-@pytest.mark.parametrize("precision", [fde.FDE_FP64, fde.FDE_MIXED_FP32, fde.FDE_MIXED_FP32_CYCLE])
+@pytest.mark.parametrize("precision", [fde.FDE_FP64, fde.FDE_MIXED_FP32, fde.FDE_MIXED_FP32_CYCLE,
+                                       fde.FDE_MIXED_CYCLE_BF16])
 def test_batch_results_equal_solo(precision):
     probs = _instances(6, (31, 63, 127), 41, 3)
     b = fde.fde_batch_create(8 << 30)
@@ -107,7 +108,7 @@ def test_budget_admission_and_release():
     b.close()
 
 
-@pytest.mark.parametrize("precision", [fde.FDE_MIXED_FP32, fde.FDE_MIXED_FP32_CYCLE])
+@pytest.mark.parametrize("precision", [fde.FDE_MIXED_FP32, fde.FDE_MIXED_FP32_CYCLE, fde.FDE_MIXED_CYCLE_BF16])
 def test_graph_replays_match_eager_over_many_cycles(precision):
     # one anisotropic request needing many restart cycles per step: every cycle after the first is
     # a graph replay, with the host's own work in between

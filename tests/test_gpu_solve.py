@@ -16,7 +16,7 @@ from .gpu_util import dev, host, make_handle, note, rel
 
 pytestmark = pytest.mark.gpu
 
-PRECS = [fde.FDE_FP64, fde.FDE_MIXED_FP32, fde.FDE_MIXED_FP32_CYCLE]
+PRECS = [fde.FDE_FP64, fde.FDE_MIXED_FP32, fde.FDE_MIXED_FP32_CYCLE, fde.FDE_MIXED_CYCLE_BF16]
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -60,7 +60,9 @@ def test_c1_full_run_matches_oracle(prec):
     X, Y = workloads.grid(p)
     err = np.abs(u - p.u_exact(X, Y, p.T)).max()
     assert err == pytest.approx(np.abs(ref - p.u_exact(X, Y, p.T)).max(), rel=1e-6)
-    assert max(iters) <= 20
+    # a solve that fits in one restart cycle needs the cycle to reach the tolerance; a BF16 basis
+    # holds about 3 digits, so it finishes in a second cycle
+    assert max(iters) <= (30 if prec == fde.FDE_MIXED_CYCLE_BF16 else 20)
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -113,11 +115,13 @@ def test_fp64_and_mixed_agree_at_2047():
         out.append(host(un))
         its.append(st["iters"])
         h.close()
-    note(f"C3 2047 iterations fp64 / mixed / fp32 cycles: {its}")
-    assert rel(out[1], out[0]) <= 1e-9
-    assert rel(out[2], out[0]) <= 1e-9
-    # FP32 cycles refine from the FP64 residual: the iteration count stays that of the FP64 cycles
+    note(f"C3 2047 iterations fp64 / mixed / fp32 cycles / bf16 basis: {its}")
+    for k in (1, 2, 3):
+        assert rel(out[k], out[0]) <= 1e-9
+    # FP32 cycles refine from the FP64 residual: the iteration count stays that of the FP64 cycles;
+    # a BF16 basis costs a few iterations
     assert abs(its[2] - its[1]) <= 0.05 * its[1]
+    assert abs(its[3] - its[1]) <= 0.05 * its[1]
 
 
 def test_error_codes():
@@ -144,9 +148,10 @@ def test_fp32_cycles_reject_band_preconditioner():
     p = workloads.config_c2(31, 32)
     fields = [dev(f) for f in workloads.sample(p, 0.0)]
     from .gpu_util import problem_struct
-    with pytest.raises(fde.FdeError) as e:
-        fde.fde_setup(problem_struct(p, precision=fde.FDE_MIXED_FP32_CYCLE, mg_variant=fde.FDE_MG_BAND), *fields)
-    assert e.value.code == fde.FDE_EINVAL
+    for prec in (fde.FDE_MIXED_FP32_CYCLE, fde.FDE_MIXED_CYCLE_BF16):
+        with pytest.raises(fde.FdeError) as e:
+            fde.fde_setup(problem_struct(p, precision=prec, mg_variant=fde.FDE_MG_BAND), *fields)
+        assert e.value.code == fde.FDE_EINVAL
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -159,7 +164,7 @@ def test_zero_rhs_gives_zero(prec):
     assert np.all(host(x) == 0.0)
 
 
-@pytest.mark.parametrize("prec", [fde.FDE_MIXED_FP32, fde.FDE_MIXED_FP32_CYCLE])
+@pytest.mark.parametrize("prec", [fde.FDE_MIXED_FP32, fde.FDE_MIXED_FP32_CYCLE, fde.FDE_MIXED_CYCLE_BF16])
 def test_solve_is_deterministic(prec):
     p = workloads.config_c2(255, 32)
     h = make_handle(p, precision=prec)
@@ -173,7 +178,8 @@ def test_solve_is_deterministic(prec):
 
 
 @pytest.mark.parametrize("prec,variant", [(fde.FDE_FP64, fde.FDE_MG_GEOMETRIC), (fde.FDE_MIXED_FP32, fde.FDE_MG_GALERKIN),
-                                          (fde.FDE_MIXED_FP32_CYCLE, fde.FDE_MG_GALERKIN)])
+                                          (fde.FDE_MIXED_FP32_CYCLE, fde.FDE_MG_GALERKIN),
+                                          (fde.FDE_MIXED_CYCLE_BF16, fde.FDE_MG_GEOMETRIC)])
 def test_time_dependent_coefficients_example2(prec, variant):
     # Example 2 of Sec. 5: coefficients grow like (1+t); the left-hand side uses t^(m), the explicit
     # half t^(m-1), so every step refreshes the operators and the hierarchy (fde_update_coeffs)
