@@ -224,7 +224,7 @@ struct bf16_t {
   uint16_t bits;
 };
 // One fused pass over the basis V[0..nv) (storage TB: FP64, FP32 or BF16; column stride ldv a
-// multiple of the run length, 16 / sizeof(TW) entries; columns aligned to a run) and the work vector
+// multiple of the run length, 16 bytes of basis entries; columns 16-byte aligned) and the work vector
 // w (storage TW: FP64 or FP32, 16-byte aligned, readable and writable up to N rounded up to a run);
 // src is FP64.  With TB = TW, w is itself a basis column and vout is unused; with BF16 storage the
 // passes that finish a vector (UPDATE_NORM, INIT, RESNORM with src) also write its BF16 rounding

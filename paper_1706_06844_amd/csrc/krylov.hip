@@ -90,9 +90,9 @@ struct FinLds {
 template <int PL>
 __device__ void finalize_block(int kind, int nv, int G, const double* partials, GmresState* gst, FinLds<PL>& F);
 
-// Runs of VEC consecutive entries per thread: 16-byte loads of the work vector w (FP64: 2 entries,
-// FP32: 4) and the matching entries of the basis columns (FP64, FP32 or BF16 storage).  Basis
-// entries are held in registers as `reg` (FP64, or FP32 for FP32 and BF16 storage).
+// Runs of VEC consecutive entries per thread: 16-byte loads of the basis columns (FP64: 2 entries,
+// FP32: 4, BF16: 8) and the matching entries of the work vector w (FP64 or FP32).  Basis entries
+// are used as `reg` (FP64, or FP32 for FP32 and BF16 storage).
 template <typename TB>
 struct BasisT {
   using reg = TB;
@@ -110,22 +110,20 @@ __device__ __forceinline__ void load_vec(const T* p, typename BasisT<T>::reg (&v
     v[0] = a.x;
     v[1] = a.y;
   } else if constexpr (std::is_same<T, float>::value) {
-    static_assert(VEC == 4, "FP32 runs are 4 entries");
-    const float4 a = *reinterpret_cast<const float4*>(p);
-    v[0] = a.x;
-    v[1] = a.y;
-    v[2] = a.z;
-    v[3] = a.w;
+    static_assert(VEC == 4 || VEC == 8, "FP32 runs are 4 or 8 entries");
+#pragma unroll
+    for (int q = 0; q < VEC / 4; ++q) {
+      const float4 a = *reinterpret_cast<const float4*>(p + 4 * q);
+      v[4 * q] = a.x;
+      v[4 * q + 1] = a.y;
+      v[4 * q + 2] = a.z;
+      v[4 * q + 3] = a.w;
+    }
   } else {
-    static_assert(VEC == 4, "BF16 runs are 4 entries");
-    const uint2 a = *reinterpret_cast<const uint2*>(p);
-    v[0] = __uint_as_float(a.x << 16);
-    v[1] = __uint_as_float(a.x & 0xffff0000u);
-    v[2] = __uint_as_float(a.y << 16);
-    v[3] = __uint_as_float(a.y & 0xffff0000u);
+    static_assert(std::is_same<T, double>::value || std::is_same<T, float>::value, "FP64 or FP32 runs");
   }
 }
-// A run of basis entries as loaded (16 bytes of FP64 or FP32, 8 bytes of BF16), unpacked entry by
+// A run of basis entries as loaded (16 bytes: 2 FP64, 4 FP32 or 8 BF16 entries), unpacked entry by
 // entry where it is used, so that the loads of all columns are issued before any result is needed.
 template <typename TB>
 struct RawT;
@@ -139,7 +137,7 @@ struct RawT<float> {
 };
 template <>
 struct RawT<bf16_t> {
-  using type = uint2;
+  using type = uint4;  // 8 entries
 };
 template <typename TB>
 __device__ __forceinline__ typename RawT<TB>::type load_raw(const TB* p) {
@@ -153,10 +151,10 @@ template <typename TB, int E>
 __device__ __forceinline__ typename BasisT<TB>::reg raw_elem(const typename RawT<TB>::type& r) {
   if constexpr (std::is_same<TB, double>::value) return E == 0 ? r.x : r.y;
   else if constexpr (std::is_same<TB, float>::value) return E == 0 ? r.x : E == 1 ? r.y : E == 2 ? r.z : r.w;
-  else if constexpr (E == 0) return __uint_as_float(r.x << 16);
-  else if constexpr (E == 1) return __uint_as_float(r.x & 0xffff0000u);
-  else if constexpr (E == 2) return __uint_as_float(r.y << 16);
-  else return __uint_as_float(r.y & 0xffff0000u);
+  else {
+    const unsigned u = E < 2 ? r.x : E < 4 ? r.y : E < 6 ? r.z : r.w;
+    return __uint_as_float((E & 1) ? (u & 0xffff0000u) : (u << 16));
+  }
 }
 // zero the entries of a run at positions >= nin (the padding past N)
 template <typename TB>
@@ -168,25 +166,34 @@ __device__ __forceinline__ void raw_mask(typename RawT<TB>::type& r, int nin) {
     if (nin < 3) r.z = 0.f;
     if (nin < 4) r.w = 0.f;
   } else {
-    if (nin < 2) r.x &= 0xffffu;
-    if (nin < 3) r.y = 0u;
-    else if (nin < 4) r.y &= 0xffffu;
+    unsigned* u = &r.x;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (nin <= 2 * q) u[q] = 0u;
+      else if (nin == 2 * q + 1) u[q] &= 0xffffu;
+    }
   }
 }
 
 template <typename T, int VEC>
 __device__ __forceinline__ void store_vec(T* p, const T (&v)[VEC]) {
-  if constexpr (std::is_same<T, double>::value) *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
-  else *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+  if constexpr (std::is_same<T, double>::value) {
+    *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
+  } else {
+#pragma unroll
+    for (int q = 0; q < VEC / 4; ++q)
+      *reinterpret_cast<float4*>(p + 4 * q) = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+  }
 }
 // FP32 to BF16, rounded to nearest even (NaN and infinity stay what they are).
 __device__ __forceinline__ unsigned bf16_bits(float f) {
   const unsigned u = __float_as_uint(f);
   return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
 }
-__device__ __forceinline__ void store_bf16x4(bf16_t* p, const float (&v)[4]) {
-  *reinterpret_cast<uint2*>(p) = make_uint2(bf16_bits(v[0]) | (bf16_bits(v[1]) << 16),
-                                            bf16_bits(v[2]) | (bf16_bits(v[3]) << 16));
+__device__ __forceinline__ void store_bf16x8(bf16_t* p, const float (&v)[8]) {
+  *reinterpret_cast<uint4*>(p) =
+      make_uint4(bf16_bits(v[0]) | (bf16_bits(v[1]) << 16), bf16_bits(v[2]) | (bf16_bits(v[3]) << 16),
+                 bf16_bits(v[4]) | (bf16_bits(v[5]) << 16), bf16_bits(v[6]) | (bf16_bits(v[7]) << 16));
 }
 
 // One pass over the basis (products, sums and coefficients in FP64).  TW is the storage of the work
@@ -203,9 +210,9 @@ __global__ __launch_bounds__(kCgsBlock) void cgs_kernel(int kind, int N, int nv,
                                                         size_t ldv, TW* __restrict__ w, TB* __restrict__ vout,
                                                         const double* __restrict__ src, GmresState* st,
                                                         double* __restrict__ partials) {
-  constexpr int VEC = 16 / (int)sizeof(TW);
-  using RB = typename BasisT<TB>::reg;
   constexpr bool kSplit = std::is_same<TB, bf16_t>::value;
+  constexpr int VEC = kSplit ? 8 : 16 / (int)sizeof(TW);  // 16-byte loads of the basis
+  using RB = typename BasisT<TB>::reg;
   if (kind == CGS_DOTS || kind == CGS_UPDATE_DOTS || kind == CGS_UPDATE_NORM) {
     if (st->done) return;
     if (kind == CGS_UPDATE_DOTS && !st->reorth) return;
@@ -244,7 +251,7 @@ __global__ __launch_bounds__(kCgsBlock) void cgs_kernel(int kind, int N, int nv,
         nacc += b * b;
       }
       store_vec(w + p, wv);
-      if constexpr (kSplit) store_bf16x4(vout + p, wv);
+      if constexpr (kSplit) store_bf16x8(vout + p, wv);
       continue;
     }
     load_vec<TW, VEC>(w + p, wv);
@@ -306,7 +313,7 @@ __global__ __launch_bounds__(kCgsBlock) void cgs_kernel(int kind, int N, int nv,
       for (int e = 0; e < VEC; ++e) wv[e] = (TW)wd[e];
       store_vec(w + p, wv);
       if constexpr (kSplit) {
-        if (kind == CGS_UPDATE_NORM) store_bf16x4(vout + p, wv);
+        if (kind == CGS_UPDATE_NORM) store_bf16x8(vout + p, wv);
       }
     }
     if (dots) {
@@ -475,14 +482,14 @@ int cgs_pass_grid(int nv, int cap) {
 template <typename TB, typename TW>
 hipError_t launch_cgs_pass(int kind, size_t N, int nv, TB* V, size_t ldv, TW* w, TB* vout, const double* src,
                            GmresState* st, double* partials, int cap, hipStream_t s) {
-  constexpr int VEC = 16 / (int)sizeof(TW);
   constexpr bool split = std::is_same<TB, bf16_t>::value;
+  constexpr int VEC = split ? 8 : 16 / (int)sizeof(TW);
   if (nv > kMaxRestart + 1 || N > (size_t)0x7ffffffe || cap < 1) return hipErrorInvalidValue;
   if (ldv % VEC || (reinterpret_cast<uintptr_t>(V) | reinterpret_cast<uintptr_t>(w)) % 16) return hipErrorInvalidValue;
   if (kind == CGS_INIT && !src) return hipErrorInvalidValue;
   // the BF16 column is written by the passes that finish a vector
   const bool writes = kind == CGS_UPDATE_NORM || kind == CGS_INIT || (kind == CGS_RESNORM && src);
-  if (split && writes && (!vout || reinterpret_cast<uintptr_t>(vout) % 8)) return hipErrorInvalidValue;
+  if (split && writes && (!vout || reinterpret_cast<uintptr_t>(vout) % 16)) return hipErrorInvalidValue;
   const int n = (int)N;
   const int grid = cgs_pass_grid(nv, cap);
   const bool fused = grid <= kFusedMaxGrid;
