@@ -38,8 +38,10 @@ PROFILE_STRIDE = 7
 # (scaled by a copy of known size), keyed by kernel family, with the hash of the source file the
 # kernels were built from: the figure is reported only while that source is unchanged.
 PMC_TRAFFIC = {
-    "cgs": {"bytes_per_launch": 396.98e6, "source": "paper_1706_06844_amd/csrc/krylov.hip",
-            "sha256": "30ed1c7dd8db1a5f9ae70a84a55906ba20b0655fef489e8df2eb1f4f302baef9", "summary": "profiles/cgs_pass_c3_2047_mixed.md"},
+    # toep_y_kernel<float, float, 4096>: 1596 dispatches of one C3 step (FP32 cycles, BF16 basis)
+    "mg0_y": {"bytes_per_launch": 75.593e6, "source": "paper_1706_06844_amd/csrc/toeplitz.hip",
+              "sha256": "ed0db88acf3f8e938ee8c5473bc4e8c04141702e82f6177a42b72f3285cb6505",
+              "summary": "profiles/fft_column_pass_c3_2047.md"},
 }
 
 
@@ -88,19 +90,14 @@ def log(msg):
 
 
 def kernel_groups(prec):
-    """Profiling families grouped by the kernel they time (template variants of one kernel count as
-    one kernel).  With FP32 cycles the Arnoldi product runs the same FP32 fine-level FFT kernels as
-    the V-cycle's fine level.  The coarser-level and transfer families hold several different
-    kernels at several sizes and are not candidates for the dominant kernel."""
+    """Profiling families that time a single kernel (template variants of one kernel count as one):
+    the candidates for the dominant kernel.  The coarser-level and transfer families hold several
+    different kernels at several sizes.  (With FP32 cycles the Arnoldi product runs the fine-level
+    FP32 FFT kernels and is timed in the mg0 families.)"""
     from paper_1706_06844_amd import fde
 
     several = ("cgs_finalize", "mgc_y", "mgc_x", "transfer")
-    g = {f: [f] for f in fde.L.KFAM if f not in several}
-    if prec in (fde.FDE_MIXED_FP32_CYCLE, fde.FDE_MIXED_CYCLE_BF16):
-        for d in ("y", "x"):
-            g[f"fft_fine_{d}"] = [f"outer_{d}", f"mg0_{d}"]
-            del g[f"outer_{d}"], g[f"mg0_{d}"]
-    return g
+    return {f: [f] for f in fde.L.KFAM if f not in several}
 
 
 def run_precision(prec, p, dev_fields, S, phis, u0, steps, warmup, maxit, profile_family=None):

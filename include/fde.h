@@ -195,10 +195,13 @@ int fde_level_diag(fde_handle* h, int level, double* diag);
  * the handle's stream.  Launches issued for Arnoldi steps that the device skipped (after
  * convergence) are not counted.  bytes: the algorithmic bytes of the counted launches (every input
  * and output field once). */
-#define FDE_KFAM_OUTER_Y 0   /* FP64 system operator, column (y) pass                            */
+#define FDE_KFAM_OUTER_Y 0   /* FP64 system operator, column (y) pass: Arnoldi products of FP64  */
+                             /* cycles, true residuals, right-hand sides                        */
 #define FDE_KFAM_OUTER_X 1   /* FP64 system operator, row (x) pass with epilogue                 */
-#define FDE_KFAM_MG0_Y 2     /* fine-level preconditioner operator, FFT column pass               */
-#define FDE_KFAM_MG0_X 3     /* fine level: FFT row pass (residual / Jacobi), dense or MFMA passes */
+#define FDE_KFAM_MG0_Y 2     /* fine-level FP32/FP64 preconditioner operator, FFT column pass    */
+                             /* (with FP32 cycles also the Arnoldi products)                     */
+#define FDE_KFAM_MG0_X 3     /* fine level: FFT row pass (residual / Jacobi; Arnoldi product with */
+                             /* FP32 cycles), dense or MFMA passes                               */
 #define FDE_KFAM_MGC_Y 4     /* coarser levels, FFT column pass                                  */
 #define FDE_KFAM_MGC_X 5     /* coarser levels: FFT row pass, dense, Galerkin or MFMA kernels    */
 #define FDE_KFAM_CGS 6       /* Gram-Schmidt passes, norms (the streaming kernels)               */

@@ -887,7 +887,8 @@ void arnoldi_step(fde_handle* h, Hierarchy<R>& H, TB* V, TW* wsep, int j) {
   if constexpr (std::is_same<TW, float>::value) {
     Level<R>& L0 = H.lv[0];
     if (L0.gal || L0.mfma) throw FdeError{FDE_EINVAL, "FP32 cycles need an FFT or dense fine level"};
-    op_apply<float, float>(h, true, L0.view(), Z + (size_t)j * N, L0.ay, w, EP_APPLY, nullptr, nullptr, 0.0, skip);
+    // the fine-level FFT kernels of the V-cycle: timed with them (MG0 families)
+    op_apply<float, float>(h, false, L0.view(), Z + (size_t)j * N, L0.ay, w, EP_APPLY, nullptr, nullptr, 0.0, skip);
   } else {
     const OpView<double> op = h->cur.view(h->tw64_x, h->tw64_y, h->n1, h->n2, h->L1, h->L2);
     op_apply<double, R>(h, true, op, Z + (size_t)j * N, h->ay64, w, EP_APPLY, nullptr, nullptr, 0.0, skip);
