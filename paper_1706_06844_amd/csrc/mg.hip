@@ -32,9 +32,41 @@ __global__ void presmooth_kernel(int N, const Tin* __restrict__ b, const double*
   }
 }
 
+// FP32 in and out, all arrays 16-byte aligned: runs of 4 (the tail of N mod 4 elementwise).
+__global__ void presmooth4_kernel(int N, const float* __restrict__ b, const double* __restrict__ bscale,
+                                  const float* __restrict__ dinv, float* __restrict__ x, float* __restrict__ bcopy,
+                                  const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const double s = bscale ? *bscale : 1.0;
+  const int N4 = N >> 2;
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < N4; q += gridDim.x * blockDim.x) {
+    const float4 bv4 = reinterpret_cast<const float4*>(b)[q];
+    const float4 d4 = reinterpret_cast<const float4*>(dinv)[q];
+    const float4 v = make_float4((float)(s * (double)bv4.x), (float)(s * (double)bv4.y), (float)(s * (double)bv4.z),
+                                 (float)(s * (double)bv4.w));
+    if (bcopy) reinterpret_cast<float4*>(bcopy)[q] = v;
+    reinterpret_cast<float4*>(x)[q] = make_float4(d4.x * v.x, d4.y * v.y, d4.z * v.z, d4.w * v.w);
+  }
+  if (blockIdx.x == 0 && (int)threadIdx.x < N - 4 * N4) {
+    const int p = 4 * N4 + threadIdx.x;
+    const float bv = (float)(s * (double)b[p]);
+    if (bcopy) bcopy[p] = bv;
+    x[p] = dinv[p] * bv;
+  }
+}
+
 template <typename R, typename Tin>
 hipError_t launch_presmooth(int N, const Tin* b, const double* bscale, const R* dinv, R* x, R* bcopy,
                             const int* skip, hipStream_t st) {
+  if constexpr (std::is_same<R, float>::value && std::is_same<Tin, float>::value) {
+    const uintptr_t a = reinterpret_cast<uintptr_t>(b) | reinterpret_cast<uintptr_t>(dinv) |
+                        reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(bcopy);
+    if (a % 16 == 0) {
+      hipLaunchKernelGGL(presmooth4_kernel, dim3(grid_for((size_t)(N + 3) / 4)), dim3(kBlock), 0, st, N, b, bscale,
+                         dinv, x, bcopy, skip);
+      return hipGetLastError();
+    }
+  }
   hipLaunchKernelGGL((presmooth_kernel<R, Tin>), dim3(grid_for(N)), dim3(kBlock), 0, st, N, b, bscale,
                      dinv, x, bcopy, skip);
   return hipGetLastError();
@@ -43,40 +75,42 @@ hipError_t launch_presmooth(int N, const Tin* b, const double* bscale, const R* 
 // ---- restriction rc = P^T r / 4 ---------------------------------------------------------------
 // With xc given, also the coarse level's first Jacobi sweep from zero: xc = dinv_c .* rc (the same
 // product the pre-smoothing kernel forms, fused to save a launch).
+// One coarse row J per blockIdx.y; coarse point I reads fine rows 2J..2J+2, columns 2I..2I+2.
 template <typename R>
 __global__ void restrict_kernel(int n1, int n2, const R* __restrict__ r, R* __restrict__ rc,
                                 const R* __restrict__ dinv_c, R* __restrict__ xc, const int* __restrict__ skip) {
   if (skip && *skip) return;
-  const int k1 = (n1 - 1) / 2, k2 = (n2 - 1) / 2;
-  const int Kc = k1 * k2;
-  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < Kc; q += gridDim.x * blockDim.x) {
-    const int J = q / k1, I = q - J * k1;
-    const int fj = 2 * J + 1, fi = 2 * I + 1;
-    const R* r0 = r + (size_t)(fj - 1) * n1 + fi;
-    const R* r1 = r0 + n1;
-    const R* r2 = r1 + n1;
-    const R a0 = r0[-1] + 2 * r0[0] + r0[1];
-    const R a1 = r1[-1] + 2 * r1[0] + r1[1];
-    const R a2 = r2[-1] + 2 * r2[0] + r2[1];
-    const R v = (a0 + 2 * a1 + a2) * R(0.0625);
-    rc[q] = v;
-    if (xc) xc[q] = dinv_c[q] * v;
-  }
+  const int k1 = (n1 - 1) / 2;
+  const int J = blockIdx.y;
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= k1) return;
+  const R* r0 = r + (size_t)(2 * J) * n1 + 2 * I + 1;
+  const R* r1 = r0 + n1;
+  const R* r2 = r1 + n1;
+  const R a0 = r0[-1] + 2 * r0[0] + r0[1];
+  const R a1 = r1[-1] + 2 * r1[0] + r1[1];
+  const R a2 = r2[-1] + 2 * r2[0] + r2[1];
+  const R v = (a0 + 2 * a1 + a2) * R(0.0625);
+  const size_t q = (size_t)J * k1 + I;
+  rc[q] = v;
+  if (xc) xc[q] = dinv_c[q] * v;
 }
 
 template <typename R>
 hipError_t launch_restrict(int n1, int n2, const R* r, R* rc, const R* dinv_c, R* xc, const int* skip,
                            hipStream_t st) {
   if (xc && !dinv_c) return hipErrorInvalidValue;
-  const int Kc = ((n1 - 1) / 2) * ((n2 - 1) / 2);
-  hipLaunchKernelGGL((restrict_kernel<R>), dim3(grid_for(Kc)), dim3(kBlock), 0, st, n1, n2, r, rc, dinv_c, xc,
-                     skip);
+  const int k1 = (n1 - 1) / 2, k2 = (n2 - 1) / 2;
+  if (k1 < 1 || k2 < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((restrict_kernel<R>), dim3(ceil_div(k1, kBlock), k2), dim3(kBlock), 0, st, n1, n2, r, rc,
+                     dinv_c, xc, skip);
   return hipGetLastError();
 }
 
 // ---- prolongation and correction x += P e -----------------------------------------------------
 // Coarse neighbours of fine index f (0-based) on a coarse grid of size k: odd f = 2c+1 -> (c, 1);
-// even f = 2c -> (c-1, 1/2), (c, 1/2), dropping indices outside [0, k).
+// even f = 2c -> (c-1, 1/2), (c, 1/2), dropping indices outside [0, k).  (Used by the one-workgroup
+// V-cycle.)
 __device__ __forceinline__ void coarse_nbrs(int f, int k, int* c, float* w, int* cnt) {
   if (f & 1) {
     c[0] = (f - 1) >> 1;
@@ -97,32 +131,31 @@ __device__ __forceinline__ void coarse_nbrs(int f, int k, int* c, float* w, int*
   }
 }
 
+// Fine index f (0-based) takes (e[(f-1)>>1] + e[f>>1]) / 2 from its coarse neighbours, entries
+// outside [0, k) being zero: an odd f = 2c+1 gets e[c] (both indices equal), an even f = 2c the mean
+// of e[c-1] and e[c].  One fine row per blockIdx.y, so the row weights are uniform per workgroup.
 template <typename R>
 __global__ void prolong_kernel(int n1, int n2, const R* __restrict__ e, R* __restrict__ x,
                                const int* __restrict__ skip) {
   if (skip && *skip) return;
   const int k1 = (n1 - 1) / 2, k2 = (n2 - 1) / 2;
-  const int N = n1 * n2;
-  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < N; p += gridDim.x * blockDim.x) {
-    const int j = p / n1, i = p - j * n1;
-    int cy[2], cx[2], ny, nx;
-    float wy[2], wx[2];
-    coarse_nbrs(j, k2, cy, wy, &ny);
-    coarse_nbrs(i, k1, cx, wx, &nx);
-    R v = 0;
-    for (int a = 0; a < ny; ++a) {
-      R s = 0;
-      for (int c = 0; c < nx; ++c) s += (R)wx[c] * e[(size_t)cy[a] * k1 + cx[c]];
-      v += (R)wy[a] * s;
-    }
-    x[p] += v;
-  }
+  const int j = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n1) return;
+  const int ya = (j - 1) >> 1, yb = j >> 1;  // coarse rows (equal for odd j)
+  const int xa = (i - 1) >> 1, xb = i >> 1;
+  auto E = [&](int cy, int cx) -> R {
+    return (cy >= 0 && cy < k2 && cx >= 0 && cx < k1) ? e[(size_t)cy * k1 + cx] : R(0);
+  };
+  const R v = R(0.25) * ((E(ya, xa) + E(ya, xb)) + (E(yb, xa) + E(yb, xb)));
+  x[(size_t)j * n1 + i] += v;
 }
 
 template <typename R>
 hipError_t launch_prolong(int n1, int n2, const R* e, R* x, const int* skip, hipStream_t st) {
-  hipLaunchKernelGGL((prolong_kernel<R>), dim3(grid_for((size_t)n1 * n2)), dim3(kBlock), 0, st, n1, n2,
-                     e, x, skip);
+  if (n1 < 3 || n2 < 3) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((prolong_kernel<R>), dim3(ceil_div(n1, kBlock), n2), dim3(kBlock), 0, st, n1, n2, e, x,
+                     skip);
   return hipGetLastError();
 }
 
