@@ -264,7 +264,8 @@ def run_c4(args):
     unknown_steps = sum(p.n1 * p.n2 * p.M for p in probs)
     steps = sum(p.M for p in probs)
     out = {}
-    for prec_name, prec in (("mixed", fde.FDE_MIXED_FP32), ("fp64", fde.FDE_FP64)):
+    for prec_name, prec in (("mixed", fde.FDE_MIXED_FP32), ("fp64", fde.FDE_FP64),
+                            ("cycle", fde.FDE_MIXED_FP32_CYCLE)):
         # batched: admission (resident setup) outside the timed region
         b = fde.fde_batch_create(200 << 30)
         ids = [admit(b, r, prec, 1e-9, 2000) for r in reqs]
@@ -314,7 +315,10 @@ def run_c4(args):
         "fp64_value": steps / out["fp64"]["batched_s"],
         "fp64_one_at_a_time_steps_per_s": steps / out["fp64"]["sequential_s"],
         "iters_mixed": m["iters"], "iters_fp64": out["fp64"]["iters"],
-        "max_abs_diff_alone_vs_mix": max(m["max_diff_alone_vs_mix"], out["fp64"]["max_diff_alone_vs_mix"]),
+        "fp32_cycles_value": steps / out["cycle"]["batched_s"],
+        "fp32_cycles_one_at_a_time_steps_per_s": steps / out["cycle"]["sequential_s"],
+        "iters_fp32_cycles": out["cycle"]["iters"],
+        "max_abs_diff_alone_vs_mix": max(v["max_diff_alone_vs_mix"] for v in out.values()),
     }
     print(json.dumps(line), flush=True)
 
