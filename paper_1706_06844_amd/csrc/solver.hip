@@ -883,15 +883,15 @@ void arnoldi_step(fde_handle* h, Hierarchy<R>& H, TB* V, TW* wsep, int j) {
     vj = V + (size_t)j * ldv;
     w = V + (size_t)(j + 1) * ldv;
   }
-  vcycle_top<R, TW>(h, H, vj, &h->st->vscale[j], Z + (size_t)j * N, skip);
+  vcycle_top<R, TW>(h, H, vj, &h->st->vscale[j], Z + (size_t)j * ldv, skip);
   if constexpr (std::is_same<TW, float>::value) {
     Level<R>& L0 = H.lv[0];
     if (L0.gal || L0.mfma) throw FdeError{FDE_EINVAL, "FP32 cycles need an FFT or dense fine level"};
     // the fine-level FFT kernels of the V-cycle: timed with them (MG0 families)
-    op_apply<float, float>(h, false, L0.view(), Z + (size_t)j * N, L0.ay, w, EP_APPLY, nullptr, nullptr, 0.0, skip);
+    op_apply<float, float>(h, false, L0.view(), Z + (size_t)j * ldv, L0.ay, w, EP_APPLY, nullptr, nullptr, 0.0, skip);
   } else {
     const OpView<double> op = h->cur.view(h->tw64_x, h->tw64_y, h->n1, h->n2, h->L1, h->L2);
-    op_apply<double, R>(h, true, op, Z + (size_t)j * N, h->ay64, w, EP_APPLY, nullptr, nullptr, 0.0, skip);
+    op_apply<double, R>(h, true, op, Z + (size_t)j * ldv, h->ay64, w, EP_APPLY, nullptr, nullptr, 0.0, skip);
   }
   // bytes of a pass: j + 1 basis columns and w read, w written by the update passes, the BF16
   // column by the final one (a skipped second pass is counted as a launch of zero bytes)
@@ -958,7 +958,7 @@ int fgmres(fde_handle* h, Hierarchy<R>& H, const double* b, double* x, fde_stats
     h->prof.cur_j = -1;
     const int nu = h->st_host->nused;
     timed(h, FDE_KFAM_UPDATE, (double)N * (nu * sizeof(R) + (cycles == 0 ? 1 : 2) * sizeof(double)), [&] {
-      return launch_update_x<R>(N, static_cast<const R*>(h->Z), N, x, cycles == 0 ? 1 : 0, h->st, h->stream);
+      return launch_update_x<R>(N, static_cast<const R*>(h->Z), h->ldv, x, cycles == 0 ? 1 : 0, h->st, h->stream);
     });
     restart_residual(h, b, x);
     read_state(h);
@@ -1033,7 +1033,7 @@ template <typename R>
 void cycle_body(fde_handle* h, Hierarchy<R>& H) {
   const size_t N = h->N;
   for (int j = 0; j < h->p.restart; ++j) arnoldi<R>(h, H, j);
-  HIPCHECK(launch_update_x<R>(N, static_cast<const R*>(h->Z), N, h->as.xsol, 0, h->st, h->stream));
+  HIPCHECK(launch_update_x<R>(N, static_cast<const R*>(h->Z), h->ldv, h->as.xsol, 0, h->st, h->stream));
   restart_residual(h, h->rhs, h->as.xsol);
 }
 
@@ -1158,7 +1158,7 @@ size_t footprint_bytes(const fde_problem* pin) {
   if (p.precision == FDE_MIXED_CYCLE_BF16) b += ld * 8 + ld * 4 + (p.restart + 1.0) * ld * 2;
   else if (p.precision == FDE_MIXED_FP32_CYCLE) b += ld * 8 + (p.restart + 1.0) * ld * 4;
   else b += (p.restart + 1.0) * ld * 8;
-  b += p.restart * N * R;
+  b += p.restart * ld * R;
   b += (double)cgs_partials_len((size_t)N) * 8 + sizeof(GmresState) + 4096;
   const bool gal = (p.mg_variant == FDE_MG_GALERKIN || p.mg_variant == FDE_MG_BAND) &&
                    std::min(p.n1, p.n2) > p.coarsest_n;
@@ -1318,8 +1318,9 @@ int fde_setup(const fde_problem* pin, const double* dp, const double* dm, const 
     } else {
       h->V = dalloc<double>(m, (size_t)(p.restart + 1) * h->ldv);
     }
-    if (h->fp32()) h->Z = dalloc<float>(m, (size_t)p.restart * N);
-    else h->Z = dalloc<double>(m, (size_t)p.restart * N);
+    // preconditioned vectors at the basis column stride: every column starts 16-byte aligned
+    if (h->fp32()) h->Z = dalloc<float>(m, (size_t)p.restart * h->ldv);
+    else h->Z = dalloc<double>(m, (size_t)p.restart * h->ldv);
     h->st = dalloc<GmresState>(m, 1);
     h->cgs_grid = cgs_grid(N);
     h->partials = dalloc<double>(m, cgs_partials_len(N));
