@@ -35,12 +35,14 @@ HBM_PEAK_GBS = 8000.0
 PROFILE_STRIDE = 7
 
 # HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs of this workload
-# (scaled by a copy of known size), keyed by kernel family, with the hash of the source file the
-# kernels were built from: the figure is reported only while that source is unchanged.
+# (scaled by a copy of known size), keyed by kernel family, with the hash of the source files the
+# kernel is built from: the figure is reported only while those sources are unchanged.
 PMC_TRAFFIC = {
     # toep_y_kernel<float, float, 4096>: 1596 dispatches of one C3 step (FP32 cycles, BF16 basis)
-    "mg0_y": {"bytes_per_launch": 75.593e6, "source": "paper_1706_06844_amd/csrc/toeplitz.hip",
-              "sha256": "ed0db88acf3f8e938ee8c5473bc4e8c04141702e82f6177a42b72f3285cb6505",
+    "mg0_y": {"bytes_per_launch": 75.593e6,
+              "sources": ["paper_1706_06844_amd/csrc/toeplitz.hip", "paper_1706_06844_amd/csrc/toep_dev.h",
+                          "paper_1706_06844_amd/csrc/fft.h", "paper_1706_06844_amd/csrc/common.h"],
+              "sha256": "f6b0241b1ac4cb88c7039c14ebe1d78c835f956065262580ba2549d27d767015",
               "summary": "profiles/fft_column_pass_c3_2047.md"},
 }
 
@@ -51,13 +53,14 @@ def measured_traffic(family):
     e = PMC_TRAFFIC.get(family)
     if not e:
         return None
+    h = hashlib.sha256()
     try:
-        with open(os.path.join(ROOT, e["source"]), "rb") as f:
-            if hashlib.sha256(f.read()).hexdigest() != e["sha256"]:
-                return None
+        for src in e["sources"]:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
     except OSError:
         return None
-    return e["bytes_per_launch"]
+    return e["bytes_per_launch"] if h.hexdigest() == e["sha256"] else None
 
 
 def parse():

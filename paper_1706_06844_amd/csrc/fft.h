@@ -200,11 +200,19 @@ struct Plan {
 #ifndef FDE_SHORT_L
 #define FDE_SHORT_L 2048
 #endif
+#ifndef FDE_EMAX_F32_TINY
+#define FDE_EMAX_F32_TINY 4
+#endif
+#ifndef FDE_TINY_L
+#define FDE_TINY_L 1024
+#endif
 // Elements per thread for a length-L transform with elements of `bytes` bytes.  Measured on gfx950:
-// FP32 transforms of length 4096 run fastest with 16 elements (three radix-16 stages), shorter ones
-// with 8 (more threads per transform, more waves resident); FP64 with 8.
+// FP32 transforms of length 4096 run fastest with 16 elements (three radix-16 stages), length 2048
+// with 8 and length 1024 and below with 4 (more threads per transform, more waves resident on the
+// smaller grids); FP64 with 8.
 __host__ __device__ constexpr int emax_for(int bytes, int L) {
-  return bytes == 8 ? FDE_EMAX_F64 : (L <= FDE_SHORT_L ? FDE_EMAX_F32_SHORT : FDE_EMAX_F32);
+  return bytes == 8 ? FDE_EMAX_F64
+                    : (L <= FDE_TINY_L ? FDE_EMAX_F32_TINY : (L <= FDE_SHORT_L ? FDE_EMAX_F32_SHORT : FDE_EMAX_F32));
 }
 template <typename R, int L>
 using PlanFor = Plan<L, emax_for(sizeof(R), L)>;

@@ -101,6 +101,22 @@ def test_level_operators_match_geometric_hierarchy(prec):
         np.testing.assert_allclose(host(d), L.diag(), rtol=1e-14 if prec == fde.FDE_FP64 else 1e-6)
 
 
+def test_fp32_fft_levels_match_geometric_hierarchy():
+    # the FFT passes of the FP32 levels 1023^2 (length 2048) and 511^2 (length 1024): each length
+    # has its own elements-per-thread plan
+    n = 1023
+    p = workloads.config_c2(n, 32)
+    h = make_handle(p, precision=fde.FDE_MIXED_FP32)
+    lv = omg.geometric_hierarchy(operator_from_problem(p, 0.0))
+    for l in (0, 1):
+        L = lv[l]
+        note(f"FP32 FFT level {l} ({L.n1}^2)")
+        U = _rand((L.n2, L.n1), 200 + l)
+        y = dev(np.zeros_like(U))
+        fde.fde_apply(h, l, fde.FDE_MIXED_FP32, dev(U), y)
+        assert rel(host(y), L.apply(U)) <= 2e-6, l
+
+
 @pytest.mark.parametrize("prec", [fde.FDE_FP64, fde.FDE_MIXED_FP32])
 def test_smoother_and_transfers_match_oracle(prec):
     n = 127
