@@ -70,6 +70,7 @@ std::vector<double> wsgd_weights(double g, int K) {
 constexpr int kDirectMaxN = 31;    // the coarsest level may have up to this many points per side
 constexpr int kOneWgMaxN = 15;     // levels with max(n1, n2) <= this run in the one-workgroup kernel
 constexpr int kDirectOpMax = 255;  // levels with max(n1, n2) <= this use the direct operator kernel
+constexpr int kDirectOpMaxF32 = 127;  // the same for FP32 levels (whose short FFTs are cheaper)
 
 template <typename R>
 struct Level {
@@ -625,7 +626,7 @@ std::unique_ptr<Hierarchy<R>> build_hierarchy(fde_handle* h) {
       }
       L.dinv = dalloc<R>(m, N);
       HIPCHECK(launch_diag<R>((int)N, L.dpm, L.epm, L.sx * h->pwa[1], L.sy * h->pwb[1], p.omega, L.dinv, nullptr, st));
-      L.direct = std::max(n1, n2) <= kDirectOpMax;
+      L.direct = std::max(n1, n2) <= (sizeof(R) == 4 ? kDirectOpMaxF32 : kDirectOpMax);
       const bool tune = !galerkin && tune_level(n1, n2, (int)sizeof(R), &L.direct);
       if (L.direct || tune) {
         std::vector<double> sx(n1 + 1), sy(n2 + 1);
@@ -1166,7 +1167,7 @@ size_t footprint_bytes(const fde_problem* pin) {
   double galscratch = 0;
   while (true) {
     const double Nl = (double)a1 * a2;
-    const bool direct = std::max(a1, a2) <= kDirectOpMax;
+    const bool direct = std::max(a1, a2) <= (f32 ? kDirectOpMaxF32 : kDirectOpMax);
     const bool one_wg = !gal && std::max(a1, a2) <= kOneWgMaxN;
     if (gal && l > 0) {
       b += 4.0 * a2 * p.n1 * R + 4.0 * p.n2 * a1 * R + 2.0 * Nl * R;  // fields, dinv, qx/qy (small)
