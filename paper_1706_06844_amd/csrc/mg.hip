@@ -257,20 +257,39 @@ hipError_t launch_scan_fields(size_t N, const double* const* f, int nf, int* fla
 // ---- direct (dense Toeplitz sum) operator on small levels -------------------------------------
 // l(j,i) = d+ sum_k swx[i-k+1] X[j][k] + d- sum_k swx[k-i+1] X[j][k]
 //        + e+ sum_k swy[j-k+1] X[k][i] + e- sum_k swy[k-j+1] X[k][i]   (only indices >= 0)
+// l = (tau/2 L x)(j, i) on a small level held in LDS.  wx, wy: the scaled weights zero-extended,
+// w[n + m] = s w_m for 0 <= m <= n and 0 below (2n + 2 entries), so that every sum runs over the
+// whole row or column without bounds (fixed trip counts the compiler can pipeline).
 template <typename R>
-__device__ __forceinline__ R direct_l(int n1, int n2, int j, int i, const R* X, const R* swx,
-                                      const R* swy, const R* __restrict__ dpm,
+__device__ __forceinline__ R direct_l(int n1, int n2, int j, int i, const R* X, const R* wx,
+                                      const R* wy, const R* __restrict__ dpm,
                                       const R* __restrict__ epm) {
   R lx = 0, rx = 0, ly = 0, ry = 0;
   const R* row = X + j * n1;
-  const int kl = min(i + 1, n1 - 1);
-  for (int k = 0; k <= kl; ++k) lx += swx[i - k + 1] * row[k];
-  for (int k = max(i - 1, 0); k < n1; ++k) rx += swx[k - i + 1] * row[k];
-  const int kt = min(j + 1, n2 - 1);
-  for (int k = 0; k <= kt; ++k) ly += swy[j - k + 1] * X[k * n1 + i];
-  for (int k = max(j - 1, 0); k < n2; ++k) ry += swy[k - j + 1] * X[k * n1 + i];
+  const R* wl = wx + n1 + i + 1;  // wl[-k] = s w_{i-k+1}
+  const R* wr = wx + n1 - i + 1;  // wr[k]  = s w_{k-i+1}
+#pragma unroll 4
+  for (int k = 0; k < n1; ++k) {
+    const R v = row[k];
+    lx += wl[-k] * v;
+    rx += wr[k] * v;
+  }
+  const R* vl = wy + n2 + j + 1;
+  const R* vr = wy + n2 - j + 1;
+#pragma unroll 4
+  for (int k = 0; k < n2; ++k) {
+    const R v = X[k * n1 + i];
+    ly += vl[-k] * v;
+    ry += vr[k] * v;
+  }
   const int p = j * n1 + i;
   return dpm[2 * p] * lx + dpm[2 * p + 1] * rx + epm[2 * p] * ly + epm[2 * p + 1] * ry;
+}
+
+// Fills the zero-extended weight table w[0, 2n + 2) from sw[0..n] (see direct_l).
+template <typename R>
+__device__ __forceinline__ void fill_wext(R* w, const R* __restrict__ sw, int n, int tid, int nt) {
+  for (int m = tid; m < 2 * n + 2; m += nt) w[m] = (m >= n && m - n <= n) ? sw[m - n] : R(0);
 }
 
 template <typename R>
@@ -293,7 +312,7 @@ __host__ __device__ size_t coarse_lds_elems(const CoarseView<R>& cv) {
   size_t n = 0, mx = 0;
   for (int l = 0; l < cv.nlev; ++l) {
     const size_t N = (size_t)cv.n1[l] * cv.n2[l];
-    n += 2 * N + (cv.n1[l] + 1) + (cv.n2[l] + 1) + 5 * N;
+    n += 2 * N + (2 * cv.n1[l] + 2) + (2 * cv.n2[l] + 2) + 5 * N;
     if (N > mx) mx = N;
   }
   n += mx;
@@ -318,10 +337,10 @@ __device__ CoarseLds<R> coarse_carve(const CoarseView<R>& cv, R* base) {
     q += N;
     s.X[l] = q;
     q += N;
-    s.swx[l] = q;
-    q += cv.n1[l] + 1;
+    s.swx[l] = q;  // zero-extended tables (direct_l)
+    q += 2 * cv.n1[l] + 2;
     s.swy[l] = q;
-    q += cv.n2[l] + 1;
+    q += 2 * cv.n2[l] + 2;
     s.dpm[l] = q;
     q += 2 * N;
     s.epm[l] = q;
@@ -365,8 +384,8 @@ __global__ __launch_bounds__(1024) void coarse_vcycle_kernel(CoarseView<R> cv, c
   // everything the cycle reads is copied into LDS once, with independent loads
   for (int l = 0; l < cv.nlev; ++l) {
     const int N = cv.n1[l] * cv.n2[l];
-    for (int k = tid; k <= cv.n1[l]; k += nt) s.swx[l][k] = cv.swx[l][k];
-    for (int k = tid; k <= cv.n2[l]; k += nt) s.swy[l][k] = cv.swy[l][k];
+    fill_wext(s.swx[l], cv.swx[l], cv.n1[l], tid, nt);
+    fill_wext(s.swy[l], cv.swy[l], cv.n2[l], tid, nt);
     for (int k = tid; k < 2 * N; k += nt) {
       s.dpm[l][k] = cv.dpm[l][k];
       s.epm[l][k] = cv.epm[l][k];
@@ -467,10 +486,10 @@ __global__ void direct_apply_kernel(CoarseView<R> cv, int l, const R* __restrict
   R* X = reinterpret_cast<R*>(smem_raw);
   const int n1 = cv.n1[l], n2 = cv.n2[l], N = n1 * n2;
   R* swx = X + N;
-  R* swy = swx + n1 + 1;
+  R* swy = swx + 2 * n1 + 2;
   for (int p = threadIdx.x; p < N; p += blockDim.x) X[p] = x[p];
-  for (int k = threadIdx.x; k <= n1; k += blockDim.x) swx[k] = cv.swx[l][k];
-  for (int k = threadIdx.x; k <= n2; k += blockDim.x) swy[k] = cv.swy[l][k];
+  fill_wext(swx, cv.swx[l], n1, threadIdx.x, blockDim.x);
+  fill_wext(swy, cv.swy[l], n2, threadIdx.x, blockDim.x);
   __syncthreads();
   for (int p = threadIdx.x; p < N; p += blockDim.x) {
     const int j = p / n1, i = p - j * n1;
@@ -488,7 +507,7 @@ template <typename R>
 hipError_t launch_direct_apply(const CoarseView<R>& cv, int level, const R* x, R* out, int mode, const R* b,
                                hipStream_t st) {
   const size_t N = (size_t)cv.n1[level] * cv.n2[level];
-  const size_t bytes = (N + cv.n1[level] + cv.n2[level] + 2) * sizeof(R);
+  const size_t bytes = (N + 2 * cv.n1[level] + 2 * cv.n2[level] + 4) * sizeof(R);
   hipLaunchKernelGGL((direct_apply_kernel<R>), dim3(1), dim3(1024), bytes, st, cv, level, x, out, mode, b);
   return hipGetLastError();
 }
