@@ -47,7 +47,7 @@ def test_outer_apply_rectangular(n1, n2):
 
 
 def test_outer_apply_smooth_input_relative_to_abs_operator():
-    # On smooth inputs the weights' zero sum cancels; judge against |A||x| as well.
+    # On smooth inputs the weights' zero sum cancels; compare against |A||x| as well.
     n = 255
     p = workloads.config_c3(n, 16)
     h = make_handle(p)
