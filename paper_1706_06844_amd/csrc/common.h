@@ -207,6 +207,7 @@ struct GmresState {
   int reorth;     // 1: the current Arnoldi step takes the second pass
   unsigned ticket;  // workgroups of a small pass that have written their partials
   int pad1_;
+  double keep_min;  // policy 2: second pass when the first leaves less than this fraction of ||w||^2
   double g[kMaxRestart + 1], cs[kMaxRestart], sn[kMaxRestart];
   double Rm[kMaxRestart * kMaxRestart];  // column j in Rm[j*kMaxRestart + i], i <= j
   double h1[kMaxRestart + 1], h2[kMaxRestart + 1];

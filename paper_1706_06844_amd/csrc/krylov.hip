@@ -421,9 +421,10 @@ __device__ void finalize_block(int kind, int nv, int G, const double* partials, 
         hh += h * h;
       }
       // After one projection ||w - V h||^2 = ||w||^2 - ||h||^2 (orthonormal V).  A second pass is
-      // needed when the projection removed more than half of ||w||^2 (norm ratio below 1/sqrt 2).
+      // needed when the projection removed more than the fraction 1 - keep_min of ||w||^2 (the
+      // classical criterion takes keep_min = 1/2, a norm ratio below 1/sqrt 2).
       const double ww = fin[nv];
-      st->reorth = st->orth == 1 ? 1 : st->orth == 0 ? 0 : (hh > 0.5 * ww ? 1 : 0);
+      st->reorth = st->orth == 1 ? 1 : st->orth == 0 ? 0 : (ww - hh < st->keep_min * ww ? 1 : 0);
     } else if (kind == CGS_UPDATE_DOTS) {
       for (int k = 0; k < nv; ++k) st->h2[k] = fin[k] * st->vscale[k];
     } else if (kind == CGS_UPDATE_NORM) {
