@@ -387,6 +387,12 @@ __device__ void finalize_block(int kind, int nv, int G, const double* partials, 
     for (int k = threadIdx.x; k < kWords; k += blockDim.x) dst[k] = src[k];
   }
   __syncthreads();
+  // nothing to combine after convergence, or for a second pass that was not taken (decided from the
+  // state before any partial is read)
+  if (kind == CGS_DOTS || kind == CGS_UPDATE_DOTS || kind == CGS_UPDATE_NORM) {
+    if (ls.done) return;
+    if (kind == CGS_UPDATE_DOTS && !ls.reorth) return;
+  }
   if (threadIdx.x == 0) ls.ticket = 0;
   const bool dots = (kind == CGS_DOTS || kind == CGS_UPDATE_DOTS);
   const bool norm = (kind != CGS_UPDATE_DOTS);
@@ -406,10 +412,6 @@ __device__ void finalize_block(int kind, int nv, int G, const double* partials, 
       if (lane == 0) fin[r0 + r] = v;
     }
     __syncthreads();
-  }
-  if (kind == CGS_DOTS || kind == CGS_UPDATE_DOTS || kind == CGS_UPDATE_NORM) {
-    if (ls.done) return;
-    if (kind == CGS_UPDATE_DOTS && !ls.reorth) return;
   }
   GmresState* st = &ls;
   if (threadIdx.x == 0) {
