@@ -421,7 +421,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); independent instances "
-              "would be sharded across GPUs without communication, which this build does not "
+              "would be sharded across GPUs without communication, which this benchmark does not "
               "measure.", file=sys.stderr)
         sys.exit(2)
     import torch
