@@ -1330,13 +1330,14 @@ int fde_setup(const fde_problem* pin, const double* dp, const double* dm, const 
     init.rtol = p.rtol;
     init.maxit = p.maxit;
     init.restart = p.restart;
-    // A second Gram-Schmidt pass when the first cancels more than half of ||w||^2.  With a BF16
-    // basis (orthonormal to about 3 digits) a single pass leaves components of about 4e-3 ||w||
-    // along the basis, harmless unless the cancellation is large: the second pass is taken only
-    // when less than a tenth of ||w||^2 remains.  Slowly converging solves (many cycles, each with a
-    // modest reduction) then almost never take it; fast ones still reach the tolerance in a cycle.
+    // A second Gram-Schmidt pass when the first cancels more than half of ||w||^2.  In FP32 cycles
+    // (a basis stored in FP32, or in BF16 and orthonormal to about 3 digits) a single pass leaves
+    // components along the basis of the order of the storage rounding times the cancellation, which
+    // matter only when the cancellation is large: the second pass is taken only when less than a
+    // tenth of ||w||^2 remains.  Slowly converging solves (many cycles, each with a modest
+    // reduction) then almost never take it; fast ones still reach the tolerance in a cycle.
     init.orth = 2;
-    init.keep_min = h->basis16() ? 0.1 : 0.5;
+    init.keep_min = h->cyc32() ? 0.1 : 0.5;
     HIPCHECK(hipMemcpyAsync(h->st, &init, sizeof(init), hipMemcpyHostToDevice, h->stream));
     build_preconditioner(h.get());
     HIPCHECK(hipStreamSynchronize(h->stream));
