@@ -255,8 +255,9 @@ def admit(b, hr, precision, rtol, maxit):
 
 
 def run_c4(args):
-    """64 uneven instances (n in {127,255,511}, 8 CN steps, mixed precision, rtol 1e-9) resident
-    together and stepped as one batch, against the same instances run one after another."""
+    """64 uneven instances (n in {127,255,511}, 8 CN steps, rtol 1e-9) resident together and stepped
+    as one batch, against the same instances run one after another; FP32 restart cycles as the
+    value, the FP32 preconditioner in FP64 cycles and plain FP64 beside it."""
     import torch
 
     import workloads
@@ -305,22 +306,25 @@ def run_c4(args):
             b1.close()
         out[prec_name] = {"batched_s": tb, "sequential_s": ts, "iters": iters, "max_diff_alone_vs_mix": maxdiff}
         log(f"c4 {prec_name}: batched {tb:.2f} s, one at a time {ts:.2f} s, {iters} iterations")
-    m = out["mixed"]
+    m = out["cycle"]
     line = {
         "metric": "C4 batched CN steps/s (64 uneven instances, mixed precision)",
         "value": steps / m["batched_s"], "unit": "CN steps/s", "n_gpus": 1, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
         "config": {"workload": "C4: 64 instances (seed 4), n in {127,255,511}, alpha,beta ~ U[1.1,1.9], "
-                               "c(1+ax+by^2) coefficients, tau=1/8, 8 CN steps, rtol 1e-9"},
+                               "c(1+ax+by^2) coefficients, tau=1/8, 8 CN steps, rtol 1e-9",
+                   "precision": "FP32 V-cycle and FP32 restart cycles (FP32 basis) refining the FP64 "
+                                "iterate from FP64 true residuals"},
         "unknown_updates_per_s": unknown_steps / m["batched_s"],
         "one_at_a_time_steps_per_s": steps / m["sequential_s"],
         "batching_speedup": m["sequential_s"] / m["batched_s"],
+        "iters": m["iters"],
+        "fp32_preconditioner_value": steps / out["mixed"]["batched_s"],
+        "fp32_preconditioner_one_at_a_time_steps_per_s": steps / out["mixed"]["sequential_s"],
+        "iters_fp32_preconditioner": out["mixed"]["iters"],
         "fp64_value": steps / out["fp64"]["batched_s"],
         "fp64_one_at_a_time_steps_per_s": steps / out["fp64"]["sequential_s"],
-        "iters_mixed": m["iters"], "iters_fp64": out["fp64"]["iters"],
-        "fp32_cycles_value": steps / out["cycle"]["batched_s"],
-        "fp32_cycles_one_at_a_time_steps_per_s": steps / out["cycle"]["sequential_s"],
-        "iters_fp32_cycles": out["cycle"]["iters"],
+        "iters_fp64": out["fp64"]["iters"],
         "max_abs_diff_alone_vs_mix": max(v["max_diff_alone_vs_mix"] for v in out.values()),
     }
     print(json.dumps(line), flush=True)
