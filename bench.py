@@ -30,9 +30,9 @@ if ROOT not in sys.path:
 
 METRIC = "MG-GMRES CN time-steps/s at 2047² + p50/p99 latency, mixed vs FP64 plain"
 HBM_PEAK_GBS = 8000.0
-# live timing of the dominant kernel samples every PROFILE_STRIDE-th launch (coprime to the three
+# live timing of the dominant kernel samples every PROFILE_STRIDE-th launch (coprime to the two or three
 # Gram-Schmidt passes per step and to the restart length 20)
-PROFILE_STRIDE = 7
+PROFILE_STRIDE = 17
 
 # HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs of this workload
 # (scaled by a copy of known size), keyed by kernel family, with the hash of the source files the
