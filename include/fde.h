@@ -72,9 +72,12 @@ extern "C" {
 
 #define FDE_MG_GEOMETRIC 0     /* rediscretised coarse operators, Sec. 4.2 (the paper's P_MGM)      */
 #define FDE_MG_GALERKIN 1      /* Galerkin coarse operators R A P, Sec. 4 TGM step 3 (tilde P_MGM)   */
-#define FDE_MG_BAND 2          /* the band preconditioner P_2 of Sec. 4.3: the same system with the
-                                  Laplacian (order 2) in place of both fractional factors, applied
-                                  as one Galerkin V-cycle; the outer operator stays fractional      */
+#define FDE_MG_BAND 2          /* the band preconditioner P_2 = (1/r) I - (P_x + (s/r) P_y) of
+                                  Sec. 4.3: the system matrix with the Laplacian matrix
+                                  tridiag(1, -2, 1) in place of both fractional factors and the
+                                  same scalings r = tau/(2 hx^alpha), s = tau/(2 hy^beta), applied
+                                  (as r P_2) through one Galerkin V-cycle; the outer operator stays
+                                  fractional                                                       */
 
 typedef struct fde_handle fde_handle;
 
@@ -92,7 +95,8 @@ typedef struct fde_problem {
   int32_t nu_post;      /* post-smoothing steps per level, >= 0 (< 0 selects 1)                     */
   int32_t coarsest_n;   /* coarsen while min(n1,n2) > coarsest_n; 0 selects 7 (the 8x8-cell grid)   */
   int32_t restart;      /* GMRES restart length, 1..32; 0 selects 20 (Sec. 5)                      */
-  int32_t maxit;        /* total iteration limit per solve; 0 selects 200                           */
+  int32_t maxit;        /* total iteration limit per solve; 0 selects 5000 (enough for the
+                           strongly anisotropic 2047^2 instances, which take ~530)              */
   double rtol;          /* stop when ||b - A x||_2 <= rtol ||b||_2; 0 selects 1e-10                */
 } fde_problem;
 
@@ -101,7 +105,9 @@ typedef struct fde_stats {
   int32_t iters;        /* GMRES iterations (preconditioner applications) in this solve           */
   int32_t restarts;     /* completed restart cycles beyond the first                               */
   int32_t converged;    /* 1 if the true relative residual met rtol                                */
-  int32_t reorth_steps;  /* Arnoldi steps that needed a second Gram-Schmidt pass                   */
+  int32_t reorth_steps;  /* Arnoldi steps that took a second Gram-Schmidt pass: with an FP64
+                           basis when the first pass removed more than 1/2 of ||w||^2, with FP32
+                           restart cycles (FP32 or BF16 basis) more than 9/10                    */
   double relres_true;   /* ||b - A x|| / ||b|| computed in FP64 from the returned x               */
   double relres_est;    /* the Arnoldi (Givens) estimate at exit                                   */
 } fde_stats;

@@ -133,3 +133,46 @@ def operator_from_problem(p, t: float) -> Operator:
 
     dp, dm, ep, em = sample(p, t)
     return Operator(p.alpha, p.beta, p.n1, p.n2, p.hx, p.hy, p.tau, dp, dm, ep, em)
+
+
+# ----------------------------------------------------------------------------------------------
+# The band (Laplacian) preconditioner of Sec. 4.3
+# ----------------------------------------------------------------------------------------------
+def laplacian_matrix(n: int) -> np.ndarray:
+    """The second-difference matrix tridiag(1, -2, 1) of order n (the Laplacian matrix A^2)."""
+    return -2.0 * np.eye(n) + np.eye(n, k=1) + np.eye(n, k=-1)
+
+
+def band_P2_scaled_dense(op: "Operator") -> np.ndarray:
+    """The band preconditioner of Sec. 4.3 assembled as the paper writes it:
+    P_x = D+ (I kron A^2) + D- (I kron (A^2)^T), P_y = E+ (A^2 kron I) + E- ((A^2)^T kron I),
+    P_2 = (1/r) I - (P_x + (s/r) P_y), with r = tau/(2 hx^alpha), s = tau/(2 hy^beta) the same
+    scalings as the system matrix of eq. (M).  Reading: A^2 is the second-difference matrix
+    tridiag(1, -2, 1); with that sign P_2 is the alpha = beta = 2 member of the family of eq. (M)
+    (whose A^g = -T_g has the positive diagonal -w_1), so it is positive definite like M."""
+    r = op.tau / (2.0 * op.hx ** op.alpha)
+    s = op.tau / (2.0 * op.hy ** op.beta)
+    I1, I2 = np.eye(op.n1), np.eye(op.n2)
+    A2x, A2y = laplacian_matrix(op.n1), laplacian_matrix(op.n2)
+    Px = np.diag(op.dp.ravel()) @ np.kron(I2, A2x) + np.diag(op.dm.ravel()) @ np.kron(I2, A2x.T)
+    Py = np.diag(op.ep.ravel()) @ np.kron(A2y, I1) + np.diag(op.em.ravel()) @ np.kron(A2y.T, I1)
+    return np.eye(op.n1 * op.n2) / r - (Px + (s / r) * Py)
+
+
+class BandOperator(Operator):
+    """r P_2 in the unscaled form of the per-step system: I - tau/2 L_2 with L_2 built like L but
+    with the Laplacian matrix in place of T_alpha and T_beta and the fractional scalings kept,
+    L_2 u = D+ (I kron A^2) u/hx^alpha + D- (I kron (A^2)^T) u/hx^alpha + E+ (A^2 kron I) u/hy^beta
+            + E- ((A^2)^T kron I) u/hy^beta.
+    Multiplying by r = tau/(2 hx^alpha) turns the paper's P_2 into this matrix, exactly as the
+    scaled system matrix M becomes I - tau/2 L (Sec. 4.3, eq. (M))."""
+
+    def __post_init__(self):
+        self.Tx = laplacian_matrix(self.n1) / self.hx ** self.alpha
+        self.Ty = laplacian_matrix(self.n2) / self.hy ** self.beta
+
+
+def band_operator(op: "Operator") -> BandOperator:
+    """The band preconditioner (unscaled) on the grid and coefficient fields of `op`."""
+    return BandOperator(op.alpha, op.beta, op.n1, op.n2, op.hx, op.hy, op.tau,
+                        op.dp, op.dm, op.ep, op.em)

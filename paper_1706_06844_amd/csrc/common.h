@@ -208,6 +208,7 @@ struct GmresState {
   unsigned ticket;  // workgroups of a small pass that have written their partials
   int pad1_;
   double keep_min;  // policy 2: second pass when the first leaves less than this fraction of ||w||^2
+  double brk_tol;   // breakdown: the new direction's norm below brk_tol times its column's
   double g[kMaxRestart + 1], cs[kMaxRestart], sn[kMaxRestart];
   double Rm[kMaxRestart * kMaxRestart];  // column j in Rm[j*kMaxRestart + i], i <= j
   double h1[kMaxRestart + 1], h2[kMaxRestart + 1];

@@ -5,9 +5,14 @@
 // The basis V is stored unnormalised: column k holds a multiple of v_k and vscale[k] turns it into
 // v_k.  This saves the separate normalisation pass; every consumer applies the scale.
 //
-// Orthogonalisation is classical Gram-Schmidt with a second pass only when the first one cancelled
-// more than half of the squared norm (the criterion of Daniel, Gragg, Kaufman and Stewart, 1976):
-// usually two passes over the basis per step instead of three.
+// Orthogonalisation is classical Gram-Schmidt with a second pass only when the first one removed
+// more than the fraction 1 - keep_min of the squared norm (the criterion of Daniel, Gragg, Kaufman
+// and Stewart, 1976).  keep_min is set per basis storage: 1/2 (the classical value) for an FP64
+// basis; 1/10 for FP32 restart cycles (FP32 or BF16 basis), whose stored columns are orthonormal
+// only to their storage rounding, so that the second pass pays off only when the first cancels
+// most of w.  A direction whose norm after orthogonalisation falls below brk_tol times the
+// projected column is a breakdown (the Krylov space is invariant to the basis' precision): 1e-14
+// for FP64 storage, 1e-6 for FP32 and 4e-3 for BF16, a few units of the storage rounding.
 //
 // Reductions: every thread accumulates a fixed strided subset, a fixed tree combines the block's
 // values, each block writes its partials, and a one-workgroup kernel combines the partials in block
@@ -72,7 +77,7 @@ __device__ void givens_step(GmresState* st, int j, double nrm) {
   if (st->reorth) st->reorth_mask |= 1u << j;
   st->vscale[j + 1] = nrm > 0.0 ? 1.0 / nrm : 0.0;
   // breakdown: the new direction vanished relative to the column (the Krylov space is invariant)
-  const bool breakdown = !(nrm > 1e-14 * r);
+  const bool breakdown = !(nrm > st->brk_tol * r);
   if (est <= st->atol || st->iters >= st->maxit || breakdown || j + 1 >= st->restart) st->done = 1;
 }
 

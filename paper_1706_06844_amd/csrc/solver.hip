@@ -198,8 +198,8 @@ struct fde_handle {
   size_t N = 0;
   double hx = 0, hy = 0, sx = 0, sy = 0;
   std::vector<double> wa, wb;  // WSGD weights for alpha and beta, k = 0..n
-  // weights and orders the preconditioner hierarchy is built from: (wa, wb, alpha, beta), or the
-  // order-2 (Laplacian) weights of the band preconditioner
+  // weights the preconditioner hierarchy is built from (wa, wb, or the order-2 Laplacian weights of
+  // the band preconditioner) and the exponents of its scalings tau/(2 h^alpha), tau/(2 h^beta)
   std::vector<double> pwa, pwb;
   double palpha = 0, pbeta = 0;
   DevAlloc mem;
@@ -381,7 +381,7 @@ void fill_defaults(fde_problem* q) {
   if (q->nu_post < 0) q->nu_post = 1;
   if (q->coarsest_n == 0) q->coarsest_n = 7;
   if (q->restart == 0) q->restart = 20;
-  if (q->maxit == 0) q->maxit = 200;
+  if (q->maxit == 0) q->maxit = 5000;
   if (q->rtol == 0.0) q->rtol = 1e-10;
 }
 
@@ -1237,7 +1237,7 @@ void fde_problem_default(fde_problem* p, double alpha, double beta, int32_t n1, 
   p->nu_post = 1;
   p->coarsest_n = 7;
   p->restart = 20;
-  p->maxit = 200;
+  p->maxit = 5000;
   p->rtol = 1e-10;
 }
 
@@ -1268,14 +1268,15 @@ int fde_setup(const fde_problem* pin, const double* dp, const double* dm, const 
     h->sy = p.tau / (2.0 * std::pow(h->hy, p.beta));
     h->wa = wsgd_weights(p.alpha, p.n1 + 1);
     h->wb = wsgd_weights(p.beta, p.n2 + 1);
+    // The band preconditioner of Sec. 4.3 replaces both fractional factors by the Laplacian matrix
+    // tridiag(1, -2, 1) (the order-2 weights (1, -2, 1, 0, ...)) and keeps the scalings
+    // r = tau/(2 hx^alpha), s = tau/(2 hy^beta) of the system matrix: r P_2 = I - tau/2 L_2.
+    h->palpha = p.alpha;
+    h->pbeta = p.beta;
     if (p.mg_variant == FDE_MG_BAND) {
-      // order 2: weights (1, -2, 1, 0, ...), T = tridiag(1, -2, 1), the Laplacian of Sec. 4.3
-      h->palpha = h->pbeta = 2.0;
       h->pwa = wsgd_weights(2.0, p.n1 + 1);
       h->pwb = wsgd_weights(2.0, p.n2 + 1);
     } else {
-      h->palpha = p.alpha;
-      h->pbeta = p.beta;
       h->pwa = h->wa;
       h->pwb = h->wb;
     }
@@ -1338,6 +1339,8 @@ int fde_setup(const fde_problem* pin, const double* dp, const double* dm, const 
     // reduction) then almost never take it; fast ones still reach the tolerance in a cycle.
     init.orth = 2;
     init.keep_min = h->cyc32() ? 0.1 : 0.5;
+    // breakdown threshold: a few units of the rounding of the basis storage
+    init.brk_tol = h->basis16() ? 4e-3 : h->cyc32() ? 1e-6 : 1e-14;
     HIPCHECK(hipMemcpyAsync(h->st, &init, sizeof(init), hipMemcpyHostToDevice, h->stream));
     build_preconditioner(h.get());
     HIPCHECK(hipStreamSynchronize(h->stream));

@@ -54,7 +54,7 @@ def test_problem_default(lib):
     assert (p.alpha, p.beta, p.n1, p.n2, p.tau) == (1.5, 1.6, 63, 31, 0.01)
     assert (p.a1, p.b1, p.a2, p.b2) == (0.0, 1.0, 0.0, 1.0)
     assert p.omega == 0.7 and p.nu_pre == 1 and p.nu_post == 1 and p.coarsest_n == 7
-    assert p.restart == 20 and p.maxit == 200 and p.rtol == 1e-10
+    assert p.restart == 20 and p.maxit == 5000 and p.rtol == 1e-10
 
 
 @pytest.mark.parametrize("field,value,needle", [

@@ -137,11 +137,11 @@ def test_galerkin_c2_step_matches_oracle():
 
 # ---- the band preconditioner P_2 (Sec. 4.3): the Laplacian in place of the fractional factors ----
 def _band_operator(p):
-    import copy
+    # r P_2 of Sec. 4.3: the Laplacian matrix in place of the fractional factors, with the system's
+    # scalings tau/(2 hx^alpha), tau/(2 hy^beta)
+    from oracle.operator import band_operator
 
-    q = copy.copy(p)
-    q.alpha = q.beta = 2.0
-    return operator_from_problem(q, 0.0)
+    return band_operator(operator_from_problem(p, 0.0))
 
 
 @pytest.mark.parametrize("prec", [fde.FDE_FP64, fde.FDE_MIXED_FP32])

@@ -90,8 +90,7 @@ def test_c3_step_residual_sampled_by_oracle():
     rng = np.random.default_rng(1)
     js, is_ = rng.integers(0, 2047, 40), rng.integers(0, 2047, 40)
     x = host(un)
-    b_pts = (op.rhs(u0)[js, is_] if False else
-             u0[js, is_] + 0.5 * p.tau * op.L_points(u0, js, is_)
+    b_pts = (u0[js, is_] + 0.5 * p.tau * op.L_points(u0, js, is_)
              + p.tau * workloads.sample_source(p, 0.5 * p.tau)[js, is_])
     r_pts = b_pts - op.apply_points(x, js, is_)
     # the true relative residual is <= 1e-10 in 2-norm; sampled entries are far below ||b||

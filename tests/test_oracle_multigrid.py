@@ -193,3 +193,63 @@ def test_standalone_vcycle_iteration_contracts_at_the_spectral_radius():
     # and it solves the system
     from oracle.cn import solve_step
     np.testing.assert_allclose(x, solve_step(op, b), rtol=0, atol=1e-8 * np.abs(x).max())
+
+
+# ---- the V-cycle against its iteration matrix written out densely (Sec. 4) ----
+def _smoother(A, omega):
+    return np.eye(A.shape[0]) - omega * (A / np.diag(A)[:, None])
+
+
+def _cycle_matrix(vc):
+    """x = V b for every unit b: the V-cycle as a matrix (it is linear in b)."""
+    L0 = vc.levels[0]
+    N = L0.n1 * L0.n2
+    V = np.empty((N, N))
+    for c in range(N):
+        e = np.zeros(N)
+        e[c] = 1.0
+        V[:, c] = vc(e.reshape(L0.n2, L0.n1)).ravel()
+    return V
+
+
+@pytest.mark.parametrize("variant", ["geometric", "galerkin"])
+def test_two_level_vcycle_equals_two_grid_formula(variant):
+    # Two levels (15 -> 7, exact coarse solve), one pre- and one post-sweep from a zero guess:
+    # the error propagates with S (I - P A_c^-1 R A) S, R = P^T/4, S = I - omega D^-1 A (the two-grid
+    # method of Sec. 4 with the pre-smoothing step of the V-cycle paragraph added).  For Galerkin
+    # A_c = R A P, which turns the coarse correction into the paper's I - P (P^T A P)^-1 P^T A.
+    op = _c2_op(15)
+    levels = (mg.geometric_hierarchy(op) if variant == "geometric"
+              else mg.galerkin_hierarchy_dense(op))
+    assert len(levels) == 2
+    vc = mg.VCycle(levels, omega=0.7)
+    A = op.dense()
+    P = mg.prolong_2d_dense(15, 15)
+    Ac = levels[1].dense()
+    S = _smoother(A, 0.7)
+    expect = S @ (np.eye(A.shape[0]) - P @ np.linalg.solve(Ac, 0.25 * P.T @ A)) @ S
+    got = np.eye(A.shape[0]) - _cycle_matrix(vc) @ A
+    np.testing.assert_allclose(got, expect, rtol=0, atol=1e-12)
+    if variant == "galerkin":
+        tgm = mg.tgm_iteration_matrix(A, P, 0.7, 1) @ S
+        np.testing.assert_allclose(got, tgm, rtol=0, atol=1e-12)
+
+
+def test_three_level_vcycle_follows_the_recursion():
+    # Three levels (31 -> 15 -> 7) with two pre- and one post-sweep and omega = 0.6: the coarse
+    # problem is solved by the next cycle, whose map is B_1 = (I - E_1) A_1^-1, so
+    # E_0 = S^1 (I - P B_1 R A_0) S^2 and E_1 = S_1 (I - P A_2^-1 R A_1) S_1^2.  A dropped or extra
+    # smoothing step, a missing correction or a wrong transfer scaling breaks the equality.
+    op = _c2_op(31)
+    levels = mg.geometric_hierarchy(op)
+    assert [L.n1 for L in levels] == [31, 15, 7]
+    vc = mg.VCycle(levels, omega=0.6, nu_pre=2, nu_post=1)
+    A0, A1, A2 = levels[0].dense(), levels[1].dense(), levels[2].dense()
+    P0, P1 = mg.prolong_2d_dense(31, 31), mg.prolong_2d_dense(15, 15)
+    S0, S1 = _smoother(A0, 0.6), _smoother(A1, 0.6)
+    I0, I1 = np.eye(A0.shape[0]), np.eye(A1.shape[0])
+    E1 = S1 @ (I1 - P1 @ np.linalg.solve(A2, 0.25 * P1.T @ A1)) @ S1 @ S1
+    B1 = (I1 - E1) @ np.linalg.inv(A1)
+    E0 = S0 @ (I0 - P0 @ B1 @ (0.25 * P0.T @ A0)) @ S0 @ S0
+    got = I0 - _cycle_matrix(vc) @ A0
+    np.testing.assert_allclose(got, E0, rtol=0, atol=1e-11)

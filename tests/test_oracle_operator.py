@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import workloads
-from oracle.operator import Operator, paper_A, toeplitz_T
+from oracle.operator import Operator, operator_from_problem, paper_A, toeplitz_T
 from oracle.weights import wsgd
 
 
@@ -122,3 +122,77 @@ def test_wsgd_second_order_consistency(alpha, beta):
     errs = [_consistency_error(n, alpha, beta) for n in (31, 63, 127, 255)]
     ratios = [errs[i] / errs[i + 1] for i in range(3)]
     assert all(3.7 < r < 4.3 for r in ratios[1:]), ratios
+
+
+# ---- the point-sampled application used at sizes where the full product is too slow ----
+@pytest.mark.parametrize("n1,n2", [(63, 63), (31, 63)])
+def test_L_points_equal_full_application(n1, n2):
+    p = workloads.config_c2(n1, 32)
+    p.n2 = n2
+    op = operator_from_problem(p, 0.0)
+    U = np.random.default_rng(5).standard_normal((n2, n1))
+    rng = np.random.default_rng(6)
+    js = np.concatenate([[0, 0, n2 - 1, n2 - 1], rng.integers(0, n2, 40)])
+    is_ = np.concatenate([[0, n1 - 1, 0, n1 - 1], rng.integers(0, n1, 40)])
+    full_L, full_A = op.L(U), op.apply(U)
+    np.testing.assert_allclose(op.L_points(U, js, is_), full_L[js, is_], rtol=0,
+                               atol=1e-12 * np.abs(full_L).max())
+    np.testing.assert_allclose(op.apply_points(U, js, is_), full_A[js, is_], rtol=0,
+                               atol=1e-12 * np.abs(full_A).max())
+    # and against the dense matrix of eq. (AxAy), row by row
+    Ld = op.L_dense()
+    rows = js * n1 + is_
+    np.testing.assert_allclose(op.L_points(U, js, is_), Ld[rows] @ U.ravel(), rtol=0,
+                               atol=1e-12 * np.abs(full_L).max())
+
+
+# ---- the band (Laplacian) preconditioner P_2 of Sec. 4.3 ----
+def test_band_operator_is_r_times_paper_P2():
+    from oracle.operator import band_operator, band_P2_scaled_dense
+
+    p = workloads.config_c2(15, 32)
+    op = operator_from_problem(p, 0.0)
+    r = op.tau / (2.0 * op.hx ** op.alpha)
+    B = band_operator(op)
+    np.testing.assert_allclose(B.dense(), r * band_P2_scaled_dense(op), rtol=0, atol=1e-13)
+    # the field-form application and the pointwise diagonal agree with the assembled matrix
+    U = np.random.default_rng(1).standard_normal((15, 15))
+    np.testing.assert_allclose(B.apply(U).ravel(), B.dense() @ U.ravel(), atol=1e-12)
+    np.testing.assert_allclose(B.diag().ravel(), np.diag(B.dense()), atol=1e-13)
+
+
+def test_band_P2_has_five_diagonals():
+    # Sec. 4.3: "only five nonzero diagonals" (offsets 0, +-1, +-n1 in the lexicographic order)
+    from oracle.operator import band_P2_scaled_dense
+
+    n = 15
+    op = operator_from_problem(workloads.config_c2(n, 32), 0.0)
+    P2 = band_P2_scaled_dense(op)
+    offs = {j - i for i, j in zip(*np.nonzero(P2))}
+    assert offs == {0, 1, -1, n, -n}
+
+
+def test_band_P2_equals_system_matrix_at_order_two():
+    # With alpha = beta = 2 the WSGD weights are (1, -2, 1) and the system matrix M of eq. (M) is
+    # the band preconditioner itself (the "Laplacian preconditioner (alpha = beta = 2)", Sec. 4.3).
+    from oracle.operator import band_P2_scaled_dense
+
+    n = 15
+    p = workloads.config_c2(n, 32)
+    dp, dm, ep, em = workloads.sample(p, 0.0)
+    h = 1.0 / (n + 1)
+    op2 = Operator(2.0, 2.0, n, n, h, h, p.tau, dp, dm, ep, em)
+    np.testing.assert_allclose(band_P2_scaled_dense(op2), op2.paper_scaled_dense(), rtol=1e-13,
+                               atol=1e-13 * np.abs(op2.paper_scaled_dense()).max())
+
+
+def test_band_P2_spd_for_constant_equal_coefficients():
+    from oracle.operator import band_P2_scaled_dense
+
+    n = 15
+    h = 1.0 / (n + 1)
+    one = np.ones((n, n))
+    op = Operator(1.6, 1.8, n, n, h, h, 1.0 / 32, one, one, 2 * one, 2 * one)
+    P2 = band_P2_scaled_dense(op)
+    np.testing.assert_allclose(P2, P2.T, atol=1e-12)
+    assert np.linalg.eigvalsh(P2).min() > 0
