@@ -7,12 +7,13 @@ coefficients d+ = 1+x+y^2, d- = 2-x+y, e+ = 1+xy, e- = 1.5+0.5 sin(pi x) y, tau 
 source = manufactured term + seeded N(0,1) field (seed 3), GMRES(20) to relative residual 1e-10,
 one geometric V(1,1) cycle per iteration.  A step is one CN step: right-hand side plus solve.
 
-Prints one JSON line: the mixed-precision throughput as `value` (FP32 V-cycle and FP32 restart
-cycles refining the FP64 iterate from FP64 true residuals, to the same FP64 residual tolerance), the
-FP32-preconditioner-only (`mixed_*`) and plain FP64 (`fp64_*`) throughputs beside it, per-step
-latency percentiles, iterations per step, the errors against the FP64 GPU result, the live-timed
-roofline of the dominant kernel, and the FP64 CPU oracle timed on a bounded sample of the same
-workload.
+Prints one JSON line: the mixed-precision throughput as `value` (the FP32 V-cycle as the
+preconditioner of FP64 flexible GMRES: FP64 basis, Arnoldi products, inner products, Givens
+rotations and true residuals), plain FP64 (`fp64_*`) and the FP32-restart-cycle modes (`cycle_*`,
+`cycle16_*`) beside it, per-step latency percentiles, iterations per step, the errors against the
+FP64 GPU result, the live-timed roofline of the dominant kernel, the FP64 CPU oracle timed on a
+bounded sample of the same workload, and the 511^2 C2 workload run in full by the GPU and by the
+oracle (all host cores and one thread).
 """
 from __future__ import annotations
 
@@ -71,6 +72,7 @@ def parse():
     ap.add_argument("--n", type=int, default=2047)
     ap.add_argument("--maxit", type=int, default=4000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c2", action="store_true", help="skip the C2 (511^2) GPU and oracle comparison")
     ap.add_argument("--cpu-sample-iters", type=int, default=24)
     ap.add_argument("--only", choices=["cycle16", "cycle", "mixed", "fp64", "bf16"], default=None)
     ap.add_argument("--workload", choices=["c3", "c4", "c5"], default="c3",
@@ -183,13 +185,7 @@ def cpu_baseline(p, iters_per_step, sample_iters):
     from oracle.krylov import fgmres
     from oracle.operator import operator_from_problem
 
-    threads = None
-    try:
-        from threadpoolctl import threadpool_info
-
-        threads = max((i.get("num_threads", 0) for i in threadpool_info()), default=None)
-    except Exception:
-        pass
+    threads = blas_threads()
     t_setup = time.perf_counter()
     op = operator_from_problem(p, 0.0)
     vc = omg.VCycle(omg.geometric_hierarchy(op))
@@ -216,6 +212,74 @@ def cpu_baseline(p, iters_per_step, sample_iters):
                        f"iterations ({t_rhs + t_it:.1f} s, setup {t_setup:.1f} s excluded), scaled by "
                        f"{iters_per_step:.1f} iterations/step"),
             "host_cpus": os.cpu_count(), "cpu_model": model}
+
+
+def blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+
+        return max((i.get("num_threads", 0) for i in threadpool_info()), default=None)
+    except Exception:
+        return None
+
+
+def c2_comparison(steps_gpu=32, steps_cpu=2):
+    """The C2 workload (511^2, alpha = 1.8, beta = 1.6, variable coefficients, 32 CN steps, seed 2)
+    on the GPU in full (FP32 V-cycle in FP64 GMRES, and plain FP64), and the oracle (its FGMRES(50)
+    with its V-cycle to 1e-12) on the first steps with all host cores and with one thread; the GPU's
+    state after those steps is compared with the oracle's."""
+    import torch
+
+    import workloads
+    from oracle.cn import IterativeSolver, cn_run
+    from paper_1706_06844_amd import fde
+
+    p = workloads.config_c2(511, 32)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda:0")
+    F = [d(f) for f in workloads.sample(p, 0.0)]
+    phis, fields = workloads.source_terms(p)
+    S = [d(f) for f in fields]
+    u0 = d(workloads.sample_u0(p))
+    gpu = {}
+    for name, prec in (("mixed", fde.FDE_MIXED_FP32), ("fp64", fde.FDE_FP64)):
+        h = fde.fde_setup(fde.fde_problem_default(p.alpha, p.beta, p.n1, p.n2, p.tau, precision=prec), *F)
+        a, b = u0.clone(), torch.empty_like(u0)
+        fde.fde_step_sources(h, a, [f(0.5 * p.tau) for f in phis], S, b)  # warm-up
+        a.copy_(u0)
+        its, early = [], None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for m in range(1, steps_gpu + 1):
+            st = fde.fde_step_sources(h, a, [f((m - 0.5) * p.tau) for f in phis], S, b)
+            its.append(st["iters"])
+            a, b = b, a
+            if m == steps_cpu:
+                early = a.clone()
+        torch.cuda.synchronize()
+        gpu[name] = {"steps_per_s": steps_gpu / (time.perf_counter() - t0), "iters_per_step": float(np.mean(its)),
+                     "early": early.cpu().numpy()}
+        h.close()
+    from threadpoolctl import threadpool_limits
+
+    t0 = time.perf_counter()
+    ref = cn_run(p, steps=steps_cpu, solver=IterativeSolver(rtol=1e-12)).u
+    t_all = (time.perf_counter() - t0) / steps_cpu
+    cores = blas_threads()
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        cn_run(p, steps=1, solver=IterativeSolver(rtol=1e-12))
+        t_one = time.perf_counter() - t0
+    err = {k: float(np.linalg.norm(v["early"] - ref) / np.linalg.norm(ref)) for k, v in gpu.items()}
+    return {"workload": "C2 511x511, alpha=1.8, beta=1.6, variable coefficients, tau=1/32, 32 CN steps, "
+                        "manufactured + N(0,1) source (seed 2), rtol 1e-10",
+            "gpu_mixed_steps_per_s": gpu["mixed"]["steps_per_s"], "gpu_fp64_steps_per_s": gpu["fp64"]["steps_per_s"],
+            "gpu_mixed_iters_per_step": gpu["mixed"]["iters_per_step"],
+            "gpu_fp64_iters_per_step": gpu["fp64"]["iters_per_step"],
+            "oracle_steps_per_s": 1.0 / t_all, "oracle_cores": cores,
+            "oracle_steps_per_s_1_thread": 1.0 / t_one,
+            "oracle_sample": f"first {steps_cpu} steps with all cores, the first step with one thread",
+            f"err_mixed_vs_oracle_after_{steps_cpu}_steps": err["mixed"],
+            f"err_fp64_vs_oracle_after_{steps_cpu}_steps": err["fp64"]}
 
 
 def exp_terms(p):
@@ -463,7 +527,9 @@ def main():
         r = res[name]
         log(f"{name}: {args.steps / r['elapsed']:.3f} steps/s, mean iters {np.mean(r['iters']):.1f}, "
             f"dominant {r['family']}")
-    main_name = next(k for k in ("cycle16", "cycle", "mixed", "fp64", "bf16") if k in res)
+    # the value: the FP32 V-cycle inside FP64 flexible GMRES (FP64 basis, Arnoldi products, inner
+    # products, Givens and true residuals); the FP32-cycle modes are reported beside it
+    main_name = next(k for k in ("mixed", "cycle16", "cycle", "fp64", "bf16") if k in res)
     m = res[main_name]
     lat_ms = np.array(m["lat"]) * 1e3
     live = m["live"]
@@ -536,6 +602,9 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(p, out["iters_per_step"], args.cpu_sample_iters)
+    if not args.no_c2:
+        log("c2: 511^2 on the GPU (32 steps) and the oracle (2 steps all cores, 1 step one thread)")
+        out["c2"] = c2_comparison()
     print(json.dumps(out), flush=True)
 
 

@@ -106,8 +106,10 @@ typedef struct fde_stats {
   int32_t restarts;     /* completed restart cycles beyond the first                               */
   int32_t converged;    /* 1 if the true relative residual met rtol                                */
   int32_t reorth_steps;  /* Arnoldi steps that took a second Gram-Schmidt pass: with an FP64
-                           basis when the first pass removed more than 1/2 of ||w||^2, with FP32
-                           restart cycles (FP32 or BF16 basis) more than 9/10                    */
+                           basis when the first pass left less than 1e-6 of ||w||^2, with FP32
+                           restart cycles (FP32 or BF16 basis) less than 1/10.  The environment
+                           variable FDE_REORTH_KEEP (a fraction in [0, 1], read by fde_setup)
+                           overrides the threshold for measurements                             */
   double relres_true;   /* ||b - A x|| / ||b|| computed in FP64 from the returned x               */
   double relres_est;    /* the Arnoldi (Givens) estimate at exit                                   */
 } fde_stats;
@@ -175,6 +177,11 @@ int fde_level_size(const fde_handle* h, int level, int32_t* n1, int32_t* n2);
  * to FP64; BF16 levels use their MFMA products).  For level 0 and prec = FDE_FP64 this is the outer
  * FP64 operator of the solver, available on every handle. */
 int fde_apply(fde_handle* h, int level, int prec, const double* x, double* y);
+
+/* r = b - A_level x (the residual epilogue of the operator passes, as the V-cycle forms it before
+ * restricting, Sec. 4 V-cycle), same levels, precisions and layout as fde_apply.  r may alias
+ * neither x nor b. */
+int fde_residual(fde_handle* h, int level, int prec, const double* b, const double* x, double* r);
 
 /* One damped-Jacobi step on a level (Lemma lemsmo): x <- x + omega D^-1 (b - A x), D = diag(A).
  * With zero_guess != 0 the incoming x is ignored and treated as 0. */

@@ -81,6 +81,7 @@ SIGNATURES = {
     "fde_num_levels": (_I, [_P]),
     "fde_level_size": (_I, [_P, _I, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "fde_apply": (_I, [_P, _I, _I, _P, _P]),
+    "fde_residual": (_I, [_P, _I, _I, _P, _P, _P]),
     "fde_smooth": (_I, [_P, _I, _I, _P, _P, _I]),
     "fde_restrict": (_I, [_P, _I, _I, _P, _P]),
     "fde_prolong": (_I, [_P, _I, _I, _P, _P]),

@@ -7,10 +7,10 @@
 //
 // Orthogonalisation is classical Gram-Schmidt with a second pass only when the first one removed
 // more than the fraction 1 - keep_min of the squared norm (the criterion of Daniel, Gragg, Kaufman
-// and Stewart, 1976).  keep_min is set per basis storage: 1/2 (the classical value) for an FP64
-// basis; 1/10 for FP32 restart cycles (FP32 or BF16 basis), whose stored columns are orthonormal
-// only to their storage rounding, so that the second pass pays off only when the first cancels
-// most of w.  A direction whose norm after orthogonalisation falls below brk_tol times the
+// and Stewart, 1976, who take 1/2).  keep_min is set per basis storage: 1e-6 for an FP64 basis (a
+// single pass then loses at most about 1e3 rounding units of orthogonality); 1/10 for FP32 restart
+// cycles (FP32 or BF16 basis), whose stored columns are orthonormal only to their storage rounding,
+// so that the second pass pays off only when the first cancels most of w.  A direction whose norm after orthogonalisation falls below brk_tol times the
 // projected column is a breakdown (the Krylov space is invariant to the basis' precision): 1e-14
 // for FP64 storage, 1e-6 for FP32 and 4e-3 for BF16, a few units of the storage rounding.
 //

@@ -1331,14 +1331,22 @@ int fde_setup(const fde_problem* pin, const double* dp, const double* dm, const 
     init.rtol = p.rtol;
     init.maxit = p.maxit;
     init.restart = p.restart;
-    // A second Gram-Schmidt pass when the first cancels more than half of ||w||^2.  In FP32 cycles
-    // (a basis stored in FP32, or in BF16 and orthonormal to about 3 digits) a single pass leaves
-    // components along the basis of the order of the storage rounding times the cancellation, which
-    // matter only when the cancellation is large: the second pass is taken only when less than a
-    // tenth of ||w||^2 remains.  Slowly converging solves (many cycles, each with a modest
-    // reduction) then almost never take it; fast ones still reach the tolerance in a cycle.
+    // A second Gram-Schmidt pass only when the first one cancelled most of w.  One classical pass
+    // over an orthonormal basis leaves components along it of about u ||w|| / ||w - V h|| (u the
+    // rounding unit of the basis storage), so the pass is repeated when the norm ratio would make
+    // that loss of orthogonality felt.  FP64 basis: when less than 1e-6 of ||w||^2 remains (ratio
+    // above 1000, loss above ~1e-13).  FP32 cycles (a basis stored in FP32, or in BF16 and
+    // orthonormal to about 3 digits): when less than a tenth remains.  The anisotropic 2047^2
+    // instances cancel between 1/2 and 1/100 of ||w||^2 per step and take the second pass almost
+    // never, at unchanged iteration counts; fast solves, whose last directions cancel almost all
+    // of w, still take it.
     init.orth = 2;
-    init.keep_min = h->cyc32() ? 0.1 : 0.5;
+    init.keep_min = h->cyc32() ? 0.1 : 1e-6;
+    // measurement override of the criterion (a fraction in [0, 1]; 0 never repeats the pass)
+    if (const char* e = std::getenv("FDE_REORTH_KEEP")) {
+      const double v = std::atof(e);
+      if (v >= 0.0 && v <= 1.0) init.keep_min = v;
+    }
     // breakdown threshold: a few units of the rounding of the basis storage
     init.brk_tol = h->basis16() ? 4e-3 : h->cyc32() ? 1e-6 : 1e-14;
     HIPCHECK(hipMemcpyAsync(h->st, &init, sizeof(init), hipMemcpyHostToDevice, h->stream));
@@ -1592,6 +1600,22 @@ int fde_apply(fde_handle* h, int level, int prec, const double* x, double* y) {
     if (prec == FDE_FP64) return apply_hook<double>(h, level, x, y, EP_APPLY, nullptr);
     if (prec == FDE_MIXED_FP32) return apply_hook<float>(h, level, x, y, EP_APPLY, nullptr);
     throw FdeError{FDE_EINVAL, "unsupported precision for fde_apply"};
+  });
+}
+
+int fde_residual(fde_handle* h, int level, int prec, const double* b, const double* x, double* r) {
+  if (!h) return set_err(nullptr, FDE_EINVAL, "handle is NULL");
+  if (!b || !x || !r || r == x || r == b) return set_err(h, FDE_EINVAL, "bad b/x/r");
+  return guarded(h, [&]() -> int {
+    if (level == 0 && prec == FDE_FP64 && h->p.mg_variant != FDE_MG_BAND) {
+      const OpView<double> op = h->cur.view(h->tw64_x, h->tw64_y, h->n1, h->n2, h->L1, h->L2);
+      op_apply<double, double>(h, true, op, x, h->ay64, r, EP_RESID, b, nullptr, 0.0, nullptr);
+      HIPCHECK(hipStreamSynchronize(h->stream));
+      return FDE_OK;
+    }
+    if (prec == FDE_FP64) return apply_hook<double>(h, level, x, r, EP_RESID, b);
+    if (prec == FDE_MIXED_FP32) return apply_hook<float>(h, level, x, r, EP_RESID, b);
+    throw FdeError{FDE_EINVAL, "unsupported precision for fde_residual"};
   });
 }
 

@@ -151,6 +151,10 @@ def fde_apply(h: Handle, level: int, prec: int, x, y) -> None:
     _check(_lib().fde_apply(h.ptr, level, prec, _ptr(x, "x"), _ptr(y, "y")), h)
 
 
+def fde_residual(h: Handle, level: int, prec: int, b, x, r) -> None:
+    _check(_lib().fde_residual(h.ptr, level, prec, _ptr(b, "b"), _ptr(x, "x"), _ptr(r, "r")), h)
+
+
 def fde_smooth(h: Handle, level: int, prec: int, b, x, zero_guess: bool) -> None:
     _check(_lib().fde_smooth(h.ptr, level, prec, _ptr(b, "b"), _ptr(x, "x"), int(zero_guess)), h)
 
