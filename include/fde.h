@@ -285,6 +285,24 @@ int fde_batch_cancel(fde_batch* b, int id);
 /* Number of requests still stepping and the budgeted bytes in use. */
 int fde_batch_info(const fde_batch* b, int32_t* active, size_t* bytes_in_use);
 
+/* ---- an entry point that allocates nothing ----------------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  y = (I - tau/2 L) x, the FP64 system operator of
+ * fde_apply (level 0, FDE_FP64) for the problem *p (alpha, beta, n1, n2, domain and tau are read;
+ * the solver settings are ignored), without a handle.  dp, dm, ep, em, x, y: device FP64 fields
+ * [n2][n1] owned by the caller (coefficients are not scanned for sign or finiteness); y may not alias
+ * x.  All work is issued on `stream` (NULL: the default stream) and the call returns without
+ * waiting.  The weights, symbols, twiddles, coefficient pairs and the intermediate field are kept in
+ * a fixed library-owned device array of about 42 MB (5 * 1023^2 doubles plus tables), one per GPU
+ * the library runs on, held until the process ends: n1 and n2 are limited to FDE_NOALLOC_MAX_N
+ * (FDE_EINVAL beyond).  The call performs no device allocation and no host-device copy.  Every call
+ * on one GPU uses the same array, so calls that overlap on one GPU (different streams or host
+ * threads) race; order them on one stream.  Returns 0 or FDE_EINVAL / FDE_EDEVICE (message in
+ * fde_last_error(NULL)). */
+#define FDE_NOALLOC_MAX_N 1023
+int fde_apply_noalloc(const fde_problem* p, const double* dp, const double* dm, const double* ep,
+                      const double* em, const double* x, double* y, void* stream);
+
 
 #ifdef __cplusplus
 }

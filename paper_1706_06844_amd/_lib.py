@@ -67,6 +67,8 @@ _D = ctypes.c_double
 _I32 = ctypes.c_int32
 
 # name -> (restype, argtypes)
+FDE_NOALLOC_MAX_N = 1023  # largest n1, n2 of fde_apply_noalloc
+
 SIGNATURES = {
     "fde_problem_default": (None, [ctypes.POINTER(fde_problem), _D, _D, _I32, _I32, _D]),
     "fde_setup": (_I, [ctypes.POINTER(fde_problem), _P, _P, _P, _P, _P, ctypes.POINTER(_P)]),
@@ -102,6 +104,7 @@ SIGNATURES = {
     "fde_batch_poll": (_I, [_P, _I, _P, ctypes.POINTER(ctypes.c_int64)]),
     "fde_batch_cancel": (_I, [_P, _I]),
     "fde_batch_info": (_I, [_P, ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_size_t)]),
+    "fde_apply_noalloc": (_I, [ctypes.POINTER(fde_problem), _P, _P, _P, _P, _P, _P, _P]),
 }
 
 _lib: Optional[ctypes.CDLL] = None

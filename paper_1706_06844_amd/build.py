@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfde.so")
-SOURCES = ["toeplitz.hip", "galerkin.hip", "mfma.hip", "mg.hip", "krylov.hip", "solver.hip", "batch.hip"]
+SOURCES = ["toeplitz.hip", "galerkin.hip", "mfma.hip", "mg.hip", "krylov.hip", "solver.hip", "batch.hip", "noalloc.hip"]
 ARCH = os.environ.get("FDE_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

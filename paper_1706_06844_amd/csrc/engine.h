@@ -19,5 +19,7 @@ hipStream_t handle_stream(const fde_handle* h);
 void async_use_graph(fde_handle* h, bool on);
 // Device bytes a handle for problem p needs (0 if p is invalid).
 size_t footprint_bytes(const fde_problem* p);
+// Sets the message fde_last_error(NULL) returns on this thread.
+void set_global_error(const char* msg);
 
 }  // namespace fde

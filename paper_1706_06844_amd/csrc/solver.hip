@@ -1192,6 +1192,7 @@ size_t footprint_bytes(const fde_problem* pin) {
   return (size_t)(b * 1.05) + ((size_t)8 << 20);
 }
 hipStream_t handle_stream(const fde_handle* h) { return h ? h->stream : nullptr; }
+void set_global_error(const char* msg) { g_global_error = msg; }
 void async_use_graph(fde_handle* h, bool on) {
   if (h) h->as.use_graph = on;
 }

@@ -284,3 +284,9 @@ def fde_batch_info(b: Batch):
     a, by = ctypes.c_int32(), ctypes.c_size_t()
     _check(_lib().fde_batch_info(b.ptr, ctypes.byref(a), ctypes.byref(by)))
     return a.value, by.value
+
+
+def fde_apply_noalloc(problem: fde_problem, dp, dm, ep, em, x, y, stream=None) -> None:
+    """y = (I - tau/2 L) x without a handle and without device allocation (asynchronous on stream)."""
+    _check(_lib().fde_apply_noalloc(ctypes.byref(problem), _ptr(dp, "dp"), _ptr(dm, "dm"), _ptr(ep, "ep"),
+                                    _ptr(em, "em"), _ptr(x, "x"), _ptr(y, "y"), _stream_ptr(stream)))
