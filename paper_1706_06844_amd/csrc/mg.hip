@@ -7,6 +7,7 @@
 // [1 2 1; 2 4 2; 1 2 1] / 16.  Coarse geometric levels rediscretise the operator with h doubled and
 // the coefficient fields injected at the coarse points (Sec. 4.2).
 #include "common.h"
+#include "fft.h"  // static_for
 
 namespace fde {
 
@@ -326,13 +327,16 @@ size_t coarse_lds_bytes(const CoarseView<R>& cv) {
   return coarse_lds_elems(cv) * sizeof(R) + Nc * Nc * sizeof(double);
 }
 
-template <typename R>
+// The level loops of the one-workgroup V-cycle run over compile-time level indices (NL levels), so
+// that the per-level pointers stay in registers instead of a private array in scratch memory.
+template <typename R, int NL>
 __device__ CoarseLds<R> coarse_carve(const CoarseView<R>& cv, R* base) {
   CoarseLds<R> s;
   R* q = base;
-  size_t mx = 0;
-  for (int l = 0; l < cv.nlev; ++l) {
-    const size_t N = (size_t)cv.n1[l] * cv.n2[l];
+  int mx = 0;
+  static_for<0, NL>([&](auto lc) {
+    constexpr int l = decltype(lc)::value;
+    const int N = cv.n1[l] * cv.n2[l];
     s.B[l] = q;
     q += N;
     s.X[l] = q;
@@ -348,7 +352,7 @@ __device__ CoarseLds<R> coarse_carve(const CoarseView<R>& cv, R* base) {
     s.dinv[l] = q;
     q += N;
     if (N > mx) mx = N;
-  }
+  });
   s.T = q;
   q += mx;
   uintptr_t a = reinterpret_cast<uintptr_t>(q);
@@ -357,32 +361,34 @@ __device__ CoarseLds<R> coarse_carve(const CoarseView<R>& cv, R* base) {
   return s;
 }
 
-// One Jacobi step on level l: X <- X + dinv (B - X + l(X)), through the scratch T.
-template <typename R>
-__device__ void coarse_jacobi(const CoarseView<R>& cv, const CoarseLds<R>& s, int l) {
-  const int n1 = cv.n1[l], n2 = cv.n2[l], N = n1 * n2;
+// One Jacobi step on level L: X <- X + dinv (B - X + l(X)), through the scratch T.
+template <typename R, int L>
+__device__ void coarse_jacobi(const CoarseView<R>& cv, const CoarseLds<R>& s) {
+  const int n1 = cv.n1[L], n2 = cv.n2[L], N = n1 * n2;
   for (int p = threadIdx.x; p < N; p += blockDim.x) {
     const int j = p / n1, i = p - j * n1;
-    const R xv = s.X[l][p];
-    const R lv = direct_l(n1, n2, j, i, s.X[l], s.swx[l], s.swy[l], s.dpm[l], s.epm[l]);
-    s.T[p] = xv + s.dinv[l][p] * (s.B[l][p] - xv + lv);
+    const R xv = s.X[L][p];
+    const R lv = direct_l(n1, n2, j, i, s.X[L], s.swx[L], s.swy[L], s.dpm[L], s.epm[L]);
+    s.T[p] = xv + s.dinv[L][p] * (s.B[L][p] - xv + lv);
   }
   __syncthreads();
-  for (int p = threadIdx.x; p < N; p += blockDim.x) s.X[l][p] = s.T[p];
+  for (int p = threadIdx.x; p < N; p += blockDim.x) s.X[L][p] = s.T[p];
   __syncthreads();
 }
 
-template <typename R>
+template <typename R, int NL>
 __global__ __launch_bounds__(1024) void coarse_vcycle_kernel(CoarseView<R> cv, const R* __restrict__ b_in,
                                                              R* __restrict__ x_out,
                                                              const int* __restrict__ skip) {
   if (skip && *skip) return;
   extern __shared__ unsigned char smem_raw[];
   R* base = reinterpret_cast<R*>(smem_raw);
-  const CoarseLds<R> s = coarse_carve(cv, base);
+  const CoarseLds<R> s = coarse_carve<R, NL>(cv, base);
   const int tid = threadIdx.x, nt = blockDim.x;
+  constexpr int last = NL - 1;
   // everything the cycle reads is copied into LDS once, with independent loads
-  for (int l = 0; l < cv.nlev; ++l) {
+  static_for<0, NL>([&](auto lc) {
+    constexpr int l = decltype(lc)::value;
     const int N = cv.n1[l] * cv.n2[l];
     fill_wext(s.swx[l], cv.swx[l], cv.n1[l], tid, nt);
     fill_wext(s.swy[l], cv.swy[l], cv.n2[l], tid, nt);
@@ -391,9 +397,9 @@ __global__ __launch_bounds__(1024) void coarse_vcycle_kernel(CoarseView<R> cv, c
       s.epm[l][k] = cv.epm[l][k];
     }
     for (int k = tid; k < N; k += nt) s.dinv[l][k] = cv.dinv[l][k];
-  }
+  });
   {
-    const int Nc = cv.n1[cv.nlev - 1] * cv.n2[cv.nlev - 1];
+    const int Nc = cv.n1[last] * cv.n2[last];
     for (int k = tid; k < Nc * Nc; k += nt) s.inv[k] = cv.inv[k];
   }
   {
@@ -401,13 +407,13 @@ __global__ __launch_bounds__(1024) void coarse_vcycle_kernel(CoarseView<R> cv, c
     for (int p = tid; p < N0; p += nt) s.B[0][p] = b_in[p];
   }
   __syncthreads();
-  const int last = cv.nlev - 1;
   // descend: pre-smooth, residual, restrict
-  for (int l = 0; l < last; ++l) {
+  static_for<0, last>([&](auto lc) {
+    constexpr int l = decltype(lc)::value;
     const int n1 = cv.n1[l], n2 = cv.n2[l], N = n1 * n2;
     for (int p = tid; p < N; p += nt) s.X[l][p] = cv.nu_pre > 0 ? s.dinv[l][p] * s.B[l][p] : R(0);
     __syncthreads();
-    for (int it = 1; it < cv.nu_pre; ++it) coarse_jacobi(cv, s, l);
+    for (int it = 1; it < cv.nu_pre; ++it) coarse_jacobi<R, l>(cv, s);
     for (int p = tid; p < N; p += nt) {
       const int j = p / n1, i = p - j * n1;
       const R xv = s.X[l][p];
@@ -426,7 +432,7 @@ __global__ __launch_bounds__(1024) void coarse_vcycle_kernel(CoarseView<R> cv, c
       s.B[l + 1][q] = (a0 + 2 * a1 + a2) * R(0.0625);
     }
     __syncthreads();
-  }
+  });
   // coarsest: X = inv B (FP64 inverse from Gauss-Jordan elimination with partial pivoting)
   {
     const int Nc = cv.n1[last] * cv.n2[last];
@@ -439,7 +445,8 @@ __global__ __launch_bounds__(1024) void coarse_vcycle_kernel(CoarseView<R> cv, c
     __syncthreads();
   }
   // ascend: prolongate, correct, post-smooth
-  for (int l = last - 1; l >= 0; --l) {
+  static_for<0, last>([&](auto kc) {
+    constexpr int l = last - 1 - decltype(kc)::value;
     const int n1 = cv.n1[l], n2 = cv.n2[l], N = n1 * n2;
     const int k1 = (n1 - 1) / 2, k2 = (n2 - 1) / 2;
     const R* E = s.X[l + 1];
@@ -458,25 +465,42 @@ __global__ __launch_bounds__(1024) void coarse_vcycle_kernel(CoarseView<R> cv, c
       s.X[l][p] += v;
     }
     __syncthreads();
-    for (int it = 0; it < cv.nu_post; ++it) coarse_jacobi(cv, s, l);
-  }
+    for (int it = 0; it < cv.nu_post; ++it) coarse_jacobi<R, l>(cv, s);
+  });
   {
     const int N0 = cv.n1[0] * cv.n2[0];
     for (int p = tid; p < N0; p += nt) x_out[p] = s.X[0][p];
   }
 }
 
+template <typename R, int NL>
+static hipError_t launch_coarse_vcycle_n(const CoarseView<R>& cv, const R* b, R* x, const int* skip, size_t bytes,
+                                         hipStream_t st) {
+  if (bytes > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&coarse_vcycle_kernel<R, NL>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((coarse_vcycle_kernel<R, NL>), dim3(1), dim3(1024), bytes, st, cv, b, x, skip);
+  return hipGetLastError();
+}
+
 template <typename R>
 hipError_t launch_coarse_vcycle(const CoarseView<R>& cv, const R* b, R* x, const int* skip, hipStream_t st) {
   const size_t bytes = coarse_lds_bytes(cv);
   if (bytes > 160 * 1024 || !cv.inv) return hipErrorInvalidValue;
-  if (bytes > 65536) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&coarse_vcycle_kernel<R>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (e != hipSuccess) return e;
+  switch (cv.nlev) {
+    case 1:
+      return launch_coarse_vcycle_n<R, 1>(cv, b, x, skip, bytes, st);
+    case 2:
+      return launch_coarse_vcycle_n<R, 2>(cv, b, x, skip, bytes, st);
+    case 3:
+      return launch_coarse_vcycle_n<R, 3>(cv, b, x, skip, bytes, st);
+    case 4:
+      return launch_coarse_vcycle_n<R, 4>(cv, b, x, skip, bytes, st);
+    default:
+      return hipErrorInvalidValue;
   }
-  hipLaunchKernelGGL((coarse_vcycle_kernel<R>), dim3(1), dim3(1024), bytes, st, cv, b, x, skip);
-  return hipGetLastError();
 }
 
 template <typename R>

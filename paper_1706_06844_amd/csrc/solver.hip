@@ -68,7 +68,16 @@ std::vector<double> wsgd_weights(double g, int K) {
 }
 
 constexpr int kDirectMaxN = 31;    // the coarsest level may have up to this many points per side
-constexpr int kOneWgMaxN = 15;     // levels with max(n1, n2) <= this run in the one-workgroup kernel
+// Levels with max(n1, n2) <= one_wg_max() run in the one-workgroup coarse kernel (31 by default; the
+// environment variable FDE_ONEWG_MAX = 15 or 31 overrides it for measurements).
+int one_wg_max() {
+  static const int v = [] {
+    const char* e = std::getenv("FDE_ONEWG_MAX");
+    const int x = e ? std::atoi(e) : 31;
+    return (x == 15 || x == 31) ? x : 31;
+  }();
+  return v;
+}
 constexpr int kDirectOpMax = 255;  // levels with max(n1, n2) <= this use the direct operator kernel
 constexpr int kDirectOpMaxF32 = 127;  // the same for FP32 levels (whose short FFTs are cheaper)
 
@@ -433,7 +442,7 @@ std::vector<double> symbol_host(const std::vector<double>& w, int n, int L, doub
 // ---- autotuner -------------------------------------------------------------------------------
 // The operator of a level can run as the dense-Toeplitz kernel (one launch, O(n) work per point) or
 // as the two FFT passes (O(log n) per point, more launches and transform overhead).  Which is faster
-// depends on the size and the precision, so levels whose larger side lies in (kOneWgMaxN,
+// depends on the size and the precision, so levels whose larger side lies in (one_wg_max(),
 // kDirectTuneMax] are timed both ways the first time their shape occurs in the process, and the
 // faster one is kept for every later hierarchy (FDE_AUTOTUNE=0 keeps the static size rule).
 constexpr int kDirectTuneMax = 511;
@@ -443,7 +452,7 @@ std::map<std::tuple<int, int, int>, bool> g_tune_direct;
 // True if the level has to be timed now; otherwise *direct holds the cached or static choice.
 bool tune_level(int n1, int n2, int bytes, bool* direct) {
   const int mx = std::max(n1, n2);
-  if (mx <= kOneWgMaxN || mx > kDirectTuneMax) return false;
+  if (mx <= one_wg_max() || mx > kDirectTuneMax) return false;
   const char* e = std::getenv("FDE_AUTOTUNE");
   if (e && e[0] == '0') return false;
   std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -659,7 +668,7 @@ std::unique_ptr<Hierarchy<R>> build_hierarchy(fde_handle* h) {
         L.mv.ty2 = upload_raw(m, u2, st);
       }
     }
-    const bool coarse_one_wg = !galerkin && std::max(n1, n2) <= kOneWgMaxN;
+    const bool coarse_one_wg = !galerkin && std::max(n1, n2) <= one_wg_max();
     if (!coarse_one_wg) L.r = dalloc<R>(m, N);
     if (!L.in_place() && !coarse_one_wg) L.x2 = dalloc<R>(m, N);
     L.b = dalloc<R>(m, N);
@@ -693,7 +702,7 @@ std::unique_ptr<Hierarchy<R>> build_hierarchy(fde_handle* h) {
     HIPCHECK(hipStreamSynchronize(st));  // tmp is freed on return
   } else {
     H->lc = nlev - 1;
-    while (H->lc > 0 && std::max(H->lv[H->lc - 1].n1, H->lv[H->lc - 1].n2) <= kOneWgMaxN) --H->lc;
+    while (H->lc > 0 && std::max(H->lv[H->lc - 1].n1, H->lv[H->lc - 1].n2) <= one_wg_max()) --H->lc;
     if (nlev - H->lc > kMaxCoarseLevels) throw FdeError{FDE_EINVAL, "too many direct coarse levels"};
     cv.nlev = nlev - H->lc;
     for (int k = 0; k < cv.nlev; ++k) {
@@ -1168,7 +1177,7 @@ size_t footprint_bytes(const fde_problem* pin) {
   while (true) {
     const double Nl = (double)a1 * a2;
     const bool direct = std::max(a1, a2) <= (f32 ? kDirectOpMaxF32 : kDirectOpMax);
-    const bool one_wg = !gal && std::max(a1, a2) <= kOneWgMaxN;
+    const bool one_wg = !gal && std::max(a1, a2) <= one_wg_max();
     if (gal && l > 0) {
       b += 4.0 * a2 * p.n1 * R + 4.0 * p.n2 * a1 * R + 2.0 * Nl * R;  // fields, dinv, qx/qy (small)
       if (galscratch == 0) galscratch = (2.0 * a2 * p.n1 + 2.0 * p.n2 * a1) * R;
