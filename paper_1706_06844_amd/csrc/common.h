@@ -78,6 +78,21 @@ hipError_t launch_restrict(int n1, int n2, const R* r, R* rc, const R* dinv_c, R
                            hipStream_t st);
 template <typename R>
 hipError_t launch_prolong(int n1, int n2, const R* e, R* x, const int* skip, hipStream_t st);
+// Direct (dense-Toeplitz) levels, tiled with LDS-staged rows and columns:
+// residual b - A x fused with the full-weighting restriction rc = P^T r / 4 (and, with xc given,
+// the coarse level's first Jacobi sweep from zero, xc = dinv_c .* rc); the residual stays on chip.
+template <typename R>
+hipError_t launch_tile_resid_restrict(int n1, int n2, const R* x, const R* b, const R* dpm, const R* epm,
+                                      const R* swx, const R* swy, R* rc, const R* dinv_c, R* xc, const int* skip,
+                                      hipStream_t st);
+// True if both tiled kernels' LDS staging fits a workgroup for an n1 x n2 level.
+template <typename R>
+bool tile_lds_fits(int n1, int n2);
+// One damped-Jacobi sweep xout = xn + dinv (b - A xn) with xn = x + P e (prolongation and
+// correction fused into the staging; e = NULL: xn = x).  xout may not alias x.
+template <typename R>
+hipError_t launch_tile_jacobi(int n1, int n2, const R* x, const R* e, const R* b, const R* dpm, const R* epm,
+                              const R* dinv, const R* swx, const R* swy, R* xout, const int* skip, hipStream_t st);
 template <typename Tout, typename Tin>
 hipError_t launch_convert(size_t N, const Tin* in, Tout* out, hipStream_t st);
 template <typename R>
@@ -249,6 +264,17 @@ hipError_t launch_update_x(size_t N, const Tz* Z, size_t ldz, double* x, int fir
 
 // ---- small helpers -----------------------------------------------------------------------------
 inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
+// Reads a device flag (the skip flag of speculatively issued Arnoldi steps) with a vector load: the
+// index is an opaque zero in a vector register, so that waiting for the flag does not also wait for
+// the kernel's scalar argument loads, and a kernel can issue its other loads before it needs the flag.
+__device__ const int kZeroFlag = 0;
+__device__ __forceinline__ int load_flag(const int* p) {
+  int z = 0;
+  __asm__ volatile("" : "+v"(z));
+  const int* q = p ? p : &kZeroFlag;
+  return q[z];
+}
+
 inline bool is_pow2m1(int n) { return n >= 1 && ((n + 1) & n) == 0; }
 
 }  // namespace fde

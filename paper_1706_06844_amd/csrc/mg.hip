@@ -24,7 +24,7 @@ template <typename R, typename Tin>
 __global__ void presmooth_kernel(int N, const Tin* __restrict__ b, const double* __restrict__ bscale,
                                  const R* __restrict__ dinv, R* __restrict__ x, R* __restrict__ bcopy,
                                  const int* __restrict__ skip) {
-  if (skip && *skip) return;
+  if (load_flag(skip)) return;
   const double s = bscale ? *bscale : 1.0;
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < N; p += gridDim.x * blockDim.x) {
     const R bv = (R)(s * (double)b[p]);
@@ -37,7 +37,7 @@ __global__ void presmooth_kernel(int N, const Tin* __restrict__ b, const double*
 __global__ void presmooth4_kernel(int N, const float* __restrict__ b, const double* __restrict__ bscale,
                                   const float* __restrict__ dinv, float* __restrict__ x, float* __restrict__ bcopy,
                                   const int* __restrict__ skip) {
-  if (skip && *skip) return;
+  if (load_flag(skip)) return;
   const double s = bscale ? *bscale : 1.0;
   const int N4 = N >> 2;
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < N4; q += gridDim.x * blockDim.x) {
@@ -80,7 +80,7 @@ hipError_t launch_presmooth(int N, const Tin* b, const double* bscale, const R* 
 template <typename R>
 __global__ void restrict_kernel(int n1, int n2, const R* __restrict__ r, R* __restrict__ rc,
                                 const R* __restrict__ dinv_c, R* __restrict__ xc, const int* __restrict__ skip) {
-  if (skip && *skip) return;
+  const int skipv = load_flag(skip);  // waited for after the loads below are issued
   const int k1 = (n1 - 1) / 2;
   const int J = blockIdx.y;
   const int I = blockIdx.x * blockDim.x + threadIdx.x;
@@ -88,13 +88,15 @@ __global__ void restrict_kernel(int n1, int n2, const R* __restrict__ r, R* __re
   const R* r0 = r + (size_t)(2 * J) * n1 + 2 * I + 1;
   const R* r1 = r0 + n1;
   const R* r2 = r1 + n1;
+  const size_t q = (size_t)J * k1 + I;
   const R a0 = r0[-1] + 2 * r0[0] + r0[1];
   const R a1 = r1[-1] + 2 * r1[0] + r1[1];
   const R a2 = r2[-1] + 2 * r2[0] + r2[1];
+  const R dc = xc ? dinv_c[q] : R(0);
+  if (skipv) return;
   const R v = (a0 + 2 * a1 + a2) * R(0.0625);
-  const size_t q = (size_t)J * k1 + I;
   rc[q] = v;
-  if (xc) xc[q] = dinv_c[q] * v;
+  if (xc) xc[q] = dc * v;
 }
 
 template <typename R>
@@ -138,7 +140,7 @@ __device__ __forceinline__ void coarse_nbrs(int f, int k, int* c, float* w, int*
 template <typename R>
 __global__ void prolong_kernel(int n1, int n2, const R* __restrict__ e, R* __restrict__ x,
                                const int* __restrict__ skip) {
-  if (skip && *skip) return;
+  const int skipv = load_flag(skip);  // waited for after the loads below are issued
   const int k1 = (n1 - 1) / 2, k2 = (n2 - 1) / 2;
   const int j = blockIdx.y;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -149,7 +151,9 @@ __global__ void prolong_kernel(int n1, int n2, const R* __restrict__ e, R* __res
     return (cy >= 0 && cy < k2 && cx >= 0 && cx < k1) ? e[(size_t)cy * k1 + cx] : R(0);
   };
   const R v = R(0.25) * ((E(ya, xa) + E(ya, xb)) + (E(yb, xa) + E(yb, xb)));
-  x[(size_t)j * n1 + i] += v;
+  const R xv = x[(size_t)j * n1 + i];
+  if (skipv) return;
+  x[(size_t)j * n1 + i] = xv + v;
 }
 
 template <typename R>
@@ -293,6 +297,321 @@ __device__ __forceinline__ void fill_wext(R* w, const R* __restrict__ sw, int n,
   for (int m = tid; m < 2 * n + 2; m += nt) w[m] = (m >= n && m - n <= n) ? sw[m - n] : R(0);
 }
 
+// ---- tiled operator kernels of the direct (dense-Toeplitz) levels, fused with the transfers -------
+// A workgroup owns a tile of output points and stages in LDS what its Toeplitz sums read: the tile's
+// rows over the whole row length and its columns over the whole column length (as x, or as the
+// prolongated-and-corrected x + P e), plus the zero-extended weight tables.  Two fusions of the
+// V-cycle's transfer steps (Sec. 4.1, Lemma lemapp) follow:
+//   * residual + restriction: the residual b - A x of a 15 x 15 fine block, then the 9-point
+//     full weighting P^T r / 4 onto the 7 x 7 coarse points whose stencils the block covers (coarse
+//     J, I <-> fine 2J+1, 2I+1), and the coarse level's first Jacobi sweep from zero; the residual
+//     never leaves LDS (blocks overlap by one fine row and column);
+//   * prolongation + Jacobi: x_new = x + P e formed while staging, then one damped-Jacobi sweep
+//     x_new + dinv (b - A x_new) on a 16 x 16 tile, written to a second buffer (neighbouring tiles
+//     still read x).
+// These levels are small (at most 255 points per side), so a kernel's time is mostly the latency of
+// its global loads: every thread issues all of its loads (the skip flag included) in one round
+// before it waits for any of them.
+constexpr int kTileJ = 16;            // Jacobi tile side (fine points)
+constexpr int kTileRC = 7;            // restriction tile side (coarse points)
+constexpr int kTileRF = 2 * kTileRC + 1;  // fine rows and columns it covers
+constexpr int kTileThreads = 256;
+constexpr int kTileMaxN = 255;        // largest side of a tiled level (one staged row per thread)
+constexpr int kTileCS = kTileJ / 2 + 1;   // coarse rows (columns) under the 16 fine rows of a tile
+
+template <typename R>
+struct Pair {
+  R a, b;
+};
+template <typename R>
+__device__ __forceinline__ Pair<R> load_pair(const R* p) {
+  using R2 = typename std::conditional<sizeof(R) == 4, float2, double2>::type;
+  const R2 v = *reinterpret_cast<const R2*>(p);
+  return {v.x, v.y};
+}
+
+// Entry m of the zero-extended weight table (w[n + k] = sw[k] for 0 <= k <= n, 0 below).
+template <typename R>
+__device__ __forceinline__ R wext_value(const R* __restrict__ sw, int n, int m) {
+  return (m >= n && m - n <= n && m < 2 * n + 2) ? sw[m - n] : R(0);
+}
+
+// tau/2 (L x)(j, i) from the staged row xrow (whole length n1), the staged column xcol (stride nc)
+// and the point's coefficient pairs.
+template <typename R>
+__device__ __forceinline__ R tile_l(int n1, int n2, int j, int i, const R* xrow, const R* xcol, int nc, const R* wx,
+                                    const R* wy, Pair<R> d, Pair<R> e) {
+  R lx = 0, rx = 0, ly = 0, ry = 0;
+  const R* wl = wx + n1 + i + 1;  // wl[-k] = swx[i-k+1]
+  const R* wr = wx + n1 - i + 1;  // wr[k]  = swx[k-i+1]
+#pragma unroll 4
+  for (int k = 0; k < n1; ++k) {
+    const R v = xrow[k];
+    lx += wl[-k] * v;
+    rx += wr[k] * v;
+  }
+  const R* vl = wy + n2 + j + 1;
+  const R* vr = wy + n2 - j + 1;
+#pragma unroll 4
+  for (int k = 0; k < n2; ++k) {
+    const R v = xcol[k * nc];
+    ly += vl[-k] * v;
+    ry += vr[k] * v;
+  }
+  return d.a * lx + d.b * rx + e.a * ly + e.b * ry;
+}
+
+template <typename R>
+__host__ __device__ constexpr size_t tile_rr_lds(int n1, int n2) {
+  return ((size_t)kTileRF * n1 + (size_t)n2 * kTileRF + 2 * n1 + 2 + 2 * n2 + 2 + kTileRF * kTileRF) * sizeof(R);
+}
+template <typename R>
+__host__ __device__ constexpr size_t tile_j_lds(int n1, int n2) {
+  return ((size_t)kTileJ * n1 + (size_t)n2 * kTileJ + 2 * n1 + 2 + 2 * n2 + 2 +
+          (size_t)kTileCS * ((n1 - 1) / 2) + (size_t)((n2 - 1) / 2) * kTileCS) *
+         sizeof(R);
+}
+
+// Staged values of a tile: its NR rows at column tid of each, and its NC columns (column tid % NC,
+// rows tid / NC + u * (256 / NC)), loaded into registers in one round.
+template <typename R, int NR, int NC>
+struct TileLoads {
+  static constexpr int KSTEP = kTileThreads / NC;
+  static constexpr int NU = (kTileMaxN + KSTEP - 1) / KSTEP;
+  R xrv[NR], xcv[NU], wxv[2], wyv[2];
+  __device__ __forceinline__ void load(int n1, int n2, const R* __restrict__ x, int r0, int c0,
+                                       const R* __restrict__ swx, const R* __restrict__ swy) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) xrv[r] = (tid < n1 && r0 + r < n2) ? x[(size_t)(r0 + r) * n1 + tid] : R(0);
+    const int cc = tid % NC, i = c0 + cc;
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const int k = tid / NC + u * KSTEP;
+      xcv[u] = (tid < KSTEP * NC && k < n2 && i < n1) ? x[(size_t)k * n1 + i] : R(0);
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      wxv[q] = wext_value(swx, n1, tid + q * kTileThreads);
+      wyv[q] = wext_value(swy, n2, tid + q * kTileThreads);
+    }
+  }
+  __device__ __forceinline__ void store_weights(int n1, int n2, R* wx, R* wy) const {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int m = tid + q * kTileThreads;
+      if (m < 2 * n1 + 2) wx[m] = wxv[q];
+      if (m < 2 * n2 + 2) wy[m] = wyv[q];
+    }
+  }
+  // stage x (+ f(row, col) when given) into xr[NR][n1] and xc[n2][NC]
+  template <class F>
+  __device__ __forceinline__ void store_x(int n1, int n2, int r0, int c0, R* xr, R* xc, F&& add) const {
+    const int tid = threadIdx.x;
+    if (tid < n1) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) xr[r * n1 + tid] = (r0 + r < n2) ? xrv[r] + add(r0 + r, tid) : R(0);
+    }
+    const int cc = tid % NC, i = c0 + cc;
+    if (tid < KSTEP * NC) {
+#pragma unroll
+      for (int u = 0; u < NU; ++u) {
+        const int k = tid / NC + u * KSTEP;
+        if (k < n2) xc[k * NC + cc] = i < n1 ? xcv[u] + add(k, i) : R(0);
+      }
+    }
+  }
+};
+
+template <typename R>
+__global__ __launch_bounds__(kTileThreads) void tile_resid_restrict_kernel(
+    int n1, int n2, const R* __restrict__ x, const R* __restrict__ b, const R* __restrict__ dpm,
+    const R* __restrict__ epm, const R* __restrict__ swx, const R* __restrict__ swy, R* __restrict__ bc,
+    const R* __restrict__ dinv_c, R* __restrict__ xcout, const int* __restrict__ skip) {
+  extern __shared__ unsigned char smem_raw[];
+  R* xr = reinterpret_cast<R*>(smem_raw);  // kTileRF x n1
+  R* xc = xr + kTileRF * n1;               // n2 x kTileRF
+  R* wx = xc + n2 * kTileRF;
+  R* wy = wx + 2 * n1 + 2;
+  R* rt = wy + 2 * n2 + 2;                 // kTileRF x kTileRF residual block
+  const int tid = threadIdx.x;
+  const int k1 = (n1 - 1) / 2, k2 = (n2 - 1) / 2;
+  const int I0 = blockIdx.x * kTileRC, J0 = blockIdx.y * kTileRC;
+  const int r0 = 2 * J0, c0 = 2 * I0;
+  // one round of loads: skip flag, staged rows and columns, weights, this thread's point and coarse point
+  const int skipv = load_flag(skip);
+  TileLoads<R, kTileRF, kTileRF> ld;
+  ld.load(n1, n2, x, r0, c0, swx, swy);
+  const int rr = tid / kTileRF, cc = tid - rr * kTileRF;
+  const int j = r0 + rr, i = c0 + cc;
+  const bool own = tid < kTileRF * kTileRF && j < n2 && i < n1;
+  const size_t p = own ? (size_t)j * n1 + i : 0;
+  const Pair<R> dpv = own ? load_pair(dpm + 2 * p) : Pair<R>{0, 0};
+  const Pair<R> epv = own ? load_pair(epm + 2 * p) : Pair<R>{0, 0};
+  const R bv = own ? b[p] : R(0);
+  const int JJ = tid / kTileRC, II = tid - JJ * kTileRC;
+  const int J = J0 + JJ, I = I0 + II;
+  const bool cown = tid < kTileRC * kTileRC && J < k2 && I < k1;
+  const size_t q = cown ? (size_t)J * k1 + I : 0;
+  const R dcv = (cown && xcout) ? dinv_c[q] : R(0);
+  if (skipv) return;
+  ld.store_weights(n1, n2, wx, wy);
+  ld.store_x(n1, n2, r0, c0, xr, xc, [](int, int) { return R(0); });
+  __syncthreads();
+  if (tid < kTileRF * kTileRF) {
+    R r = R(0);
+    if (own) r = bv - xr[rr * n1 + i] + tile_l(n1, n2, j, i, xr + rr * n1, xc + cc, kTileRF, wx, wy, dpv, epv);
+    rt[tid] = r;
+  }
+  __syncthreads();
+  if (cown) {
+    const R* q0 = rt + (2 * JJ) * kTileRF + 2 * II + 1;
+    const R* q1 = q0 + kTileRF;
+    const R* q2 = q1 + kTileRF;
+    const R a0 = q0[-1] + 2 * q0[0] + q0[1];
+    const R a1 = q1[-1] + 2 * q1[0] + q1[1];
+    const R a2 = q2[-1] + 2 * q2[0] + q2[1];
+    const R v = (a0 + 2 * a1 + a2) * R(0.0625);
+    bc[q] = v;
+    if (xcout) xcout[q] = dcv * v;
+  }
+}
+
+template <typename R, bool PRO>
+__global__ __launch_bounds__(kTileThreads) void tile_jacobi_kernel(
+    int n1, int n2, const R* __restrict__ x, const R* __restrict__ e, const R* __restrict__ b,
+    const R* __restrict__ dpm, const R* __restrict__ epm, const R* __restrict__ dinv, const R* __restrict__ swx,
+    const R* __restrict__ swy, R* __restrict__ xout, const int* __restrict__ skip) {
+  extern __shared__ unsigned char smem_raw[];
+  const int k1 = (n1 - 1) / 2, k2 = (n2 - 1) / 2;
+  R* xr = reinterpret_cast<R*>(smem_raw);  // kTileJ x n1
+  R* xc = xr + kTileJ * n1;                // n2 x kTileJ
+  R* wx = xc + n2 * kTileJ;
+  R* wy = wx + 2 * n1 + 2;
+  R* er = wy + 2 * n2 + 2;                 // coarse rows cr0 .. cr0 + kTileCS - 1 (all k1 columns)
+  R* ec = er + kTileCS * k1;               // coarse columns cc0 .. cc0 + kTileCS - 1 (all k2 rows)
+  const int tid = threadIdx.x;
+  const int r0 = blockIdx.y * kTileJ, c0 = blockIdx.x * kTileJ;
+  const int cr0 = (r0 >> 1) - 1, cc0 = (c0 >> 1) - 1;  // first coarse row/column under the tile
+  // one round of loads
+  const int skipv = load_flag(skip);
+  TileLoads<R, kTileJ, kTileJ> ld;
+  ld.load(n1, n2, x, r0, c0, swx, swy);
+  const int rr = tid / kTileJ, cc = tid - rr * kTileJ;
+  const int j = r0 + rr, i = c0 + cc;
+  const bool own = j < n2 && i < n1;
+  const size_t p = own ? (size_t)j * n1 + i : 0;
+  const Pair<R> dpv = own ? load_pair(dpm + 2 * p) : Pair<R>{0, 0};
+  const Pair<R> epv = own ? load_pair(epm + 2 * p) : Pair<R>{0, 0};
+  const R bv = own ? b[p] : R(0);
+  const R dv = own ? dinv[p] : R(0);
+  constexpr int NE = PRO ? (kTileCS * ((kTileMaxN - 1) / 2) + kTileThreads - 1) / kTileThreads : 1;
+  R erv[NE], ecv[NE];
+  if constexpr (PRO) {
+#pragma unroll
+    for (int t = 0; t < NE; ++t) {
+      const int qr = tid + t * kTileThreads;
+      const int cr = qr / k1, ci = qr - cr * k1, y = cr0 + cr;
+      erv[t] = (qr < kTileCS * k1 && y >= 0 && y < k2) ? e[(size_t)y * k1 + ci] : R(0);
+      const int ck = qr / kTileCS, cj = qr - ck * kTileCS, xcol = cc0 + cj;
+      ecv[t] = (qr < k2 * kTileCS && xcol >= 0 && xcol < k1) ? e[(size_t)ck * k1 + xcol] : R(0);
+    }
+  }
+  if (skipv) return;
+  ld.store_weights(n1, n2, wx, wy);
+  if constexpr (PRO) {
+#pragma unroll
+    for (int t = 0; t < NE; ++t) {
+      const int qr = tid + t * kTileThreads;
+      if (qr < kTileCS * k1) er[qr] = erv[t];
+      if (qr < k2 * kTileCS) ec[qr] = ecv[t];
+    }
+    __syncthreads();
+    // (P e)(j, i): a quarter of the sum of the up to four coarse neighbours, read from the row strip
+    // (staged rows) or the column strip (staged columns)
+    auto pe_row = [&](int jj, int ii) -> R {
+      const int ya = ((jj - 1) >> 1) - cr0, yb = (jj >> 1) - cr0, xa = (ii - 1) >> 1, xb = ii >> 1;
+      const R a = xa >= 0 ? er[ya * k1 + xa] + er[yb * k1 + xa] : R(0);
+      const R c = xb < k1 ? er[ya * k1 + xb] + er[yb * k1 + xb] : R(0);
+      return R(0.25) * (a + c);
+    };
+    auto pe_col = [&](int jj, int ii) -> R {
+      const int ya = (jj - 1) >> 1, yb = jj >> 1, xa = ((ii - 1) >> 1) - cc0, xb = (ii >> 1) - cc0;
+      const R a = ya >= 0 ? ec[ya * kTileCS + xa] + ec[ya * kTileCS + xb] : R(0);
+      const R c = yb < k2 ? ec[yb * kTileCS + xa] + ec[yb * kTileCS + xb] : R(0);
+      return R(0.25) * (a + c);
+    };
+    if (tid < n1) {
+#pragma unroll
+      for (int r = 0; r < kTileJ; ++r)
+        xr[r * n1 + tid] = (r0 + r < n2) ? ld.xrv[r] + pe_row(r0 + r, tid) : R(0);
+    }
+    {
+      constexpr int KS = TileLoads<R, kTileJ, kTileJ>::KSTEP, NU = TileLoads<R, kTileJ, kTileJ>::NU;
+      const int ci = c0 + tid % kTileJ;
+#pragma unroll
+      for (int u = 0; u < NU; ++u) {
+        const int k = tid / kTileJ + u * KS;
+        if (k < n2) xc[k * kTileJ + tid % kTileJ] = ci < n1 ? ld.xcv[u] + pe_col(k, ci) : R(0);
+      }
+    }
+  } else {
+    ld.store_x(n1, n2, r0, c0, xr, xc, [](int, int) { return R(0); });
+  }
+  __syncthreads();
+  if (!own) return;
+  const R xv = xr[rr * n1 + i];
+  const R l = tile_l(n1, n2, j, i, xr + rr * n1, xc + cc, kTileJ, wx, wy, dpv, epv);
+  xout[p] = xv + dv * (bv - xv + l);
+}
+
+template <typename R>
+bool tile_lds_fits(int n1, int n2) {
+  return n1 <= kTileMaxN && n2 <= kTileMaxN && tile_rr_lds<R>(n1, n2) <= 160 * 1024 &&
+         tile_j_lds<R>(n1, n2) <= 160 * 1024;
+}
+
+template <typename R>
+hipError_t launch_tile_resid_restrict(int n1, int n2, const R* x, const R* b, const R* dpm, const R* epm,
+                                      const R* swx, const R* swy, R* bc, const R* dinv_c, R* xc, const int* skip,
+                                      hipStream_t st) {
+  const int k1 = (n1 - 1) / 2, k2 = (n2 - 1) / 2;
+  if (k1 < 1 || k2 < 1 || (xc && !dinv_c) || !tile_lds_fits<R>(n1, n2)) return hipErrorInvalidValue;
+  const size_t bytes = tile_rr_lds<R>(n1, n2);
+  if (bytes > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&tile_resid_restrict_kernel<R>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((tile_resid_restrict_kernel<R>), dim3(ceil_div(k1, kTileRC), ceil_div(k2, kTileRC)),
+                     dim3(kTileThreads), bytes, st, n1, n2, x, b, dpm, epm, swx, swy, bc, dinv_c, xc, skip);
+  return hipGetLastError();
+}
+
+template <typename R, bool PRO>
+static hipError_t launch_tile_jacobi_t(int n1, int n2, const R* x, const R* e, const R* b, const R* dpm,
+                                       const R* epm, const R* dinv, const R* swx, const R* swy, R* xout,
+                                       const int* skip, size_t bytes, hipStream_t st) {
+  if (bytes > 65536) {
+    hipError_t er = hipFuncSetAttribute(reinterpret_cast<const void*>(&tile_jacobi_kernel<R, PRO>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (er != hipSuccess) return er;
+  }
+  hipLaunchKernelGGL((tile_jacobi_kernel<R, PRO>), dim3(ceil_div(n1, kTileJ), ceil_div(n2, kTileJ)),
+                     dim3(kTileThreads), bytes, st, n1, n2, x, e, b, dpm, epm, dinv, swx, swy, xout, skip);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_tile_jacobi(int n1, int n2, const R* x, const R* e, const R* b, const R* dpm, const R* epm,
+                              const R* dinv, const R* swx, const R* swy, R* xout, const int* skip, hipStream_t st) {
+  if (n1 < 3 || n2 < 3 || x == xout || !tile_lds_fits<R>(n1, n2)) return hipErrorInvalidValue;
+  const size_t bytes = tile_j_lds<R>(n1, n2);
+  if (e) return launch_tile_jacobi_t<R, true>(n1, n2, x, e, b, dpm, epm, dinv, swx, swy, xout, skip, bytes, st);
+  return launch_tile_jacobi_t<R, false>(n1, n2, x, e, b, dpm, epm, dinv, swx, swy, xout, skip, bytes, st);
+}
+
 template <typename R>
 struct CoarseLds {
   R* B[kMaxCoarseLevels];
@@ -326,6 +645,9 @@ size_t coarse_lds_bytes(const CoarseView<R>& cv) {
   const size_t Nc = (size_t)cv.n1[l] * cv.n2[l];
   return coarse_lds_elems(cv) * sizeof(R) + Nc * Nc * sizeof(double);
 }
+
+constexpr int kCoarseMaxN = 1024;  // points per level of the one-workgroup V-cycle (31^2 = 961)
+constexpr int kCoarseInvPer = 16;  // entries of the coarsest inverse per thread (128^2 / 1024)
 
 // The level loops of the one-workgroup V-cycle run over compile-time level indices (NL levels), so
 // that the per-level pointers stay in registers instead of a private array in scratch memory.
@@ -380,32 +702,61 @@ template <typename R, int NL>
 __global__ __launch_bounds__(1024) void coarse_vcycle_kernel(CoarseView<R> cv, const R* __restrict__ b_in,
                                                              R* __restrict__ x_out,
                                                              const int* __restrict__ skip) {
-  if (skip && *skip) return;
   extern __shared__ unsigned char smem_raw[];
   R* base = reinterpret_cast<R*>(smem_raw);
   const CoarseLds<R> s = coarse_carve<R, NL>(cv, base);
   const int tid = threadIdx.x, nt = blockDim.x;
   constexpr int last = NL - 1;
-  // everything the cycle reads is copied into LDS once, with independent loads
+  // Everything the cycle reads is copied into LDS once.  All loads (the skip flag included) are
+  // issued before the first of them is waited for: one round of memory latency instead of one per
+  // array.  Per thread: at most 2 pair entries and 1 entry of each level field (levels of at most
+  // kCoarseMaxN points), 1 weight-table entry, kCoarseInvPer entries of the FP64 inverse.
+  const int skipv = load_flag(skip);
+  R gd[NL][2], ge[NL][2], gi[NL], gwx[NL], gwy[NL];
   static_for<0, NL>([&](auto lc) {
     constexpr int l = decltype(lc)::value;
     const int N = cv.n1[l] * cv.n2[l];
-    fill_wext(s.swx[l], cv.swx[l], cv.n1[l], tid, nt);
-    fill_wext(s.swy[l], cv.swy[l], cv.n2[l], tid, nt);
-    for (int k = tid; k < 2 * N; k += nt) {
-      s.dpm[l][k] = cv.dpm[l][k];
-      s.epm[l][k] = cv.epm[l][k];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int k = tid + u * nt;
+      gd[l][u] = k < 2 * N ? cv.dpm[l][k] : R(0);
+      ge[l][u] = k < 2 * N ? cv.epm[l][k] : R(0);
     }
-    for (int k = tid; k < N; k += nt) s.dinv[l][k] = cv.dinv[l][k];
+    gi[l] = tid < N ? cv.dinv[l][tid] : R(0);
+    gwx[l] = wext_value(cv.swx[l], cv.n1[l], tid);
+    gwy[l] = wext_value(cv.swy[l], cv.n2[l], tid);
   });
-  {
-    const int Nc = cv.n1[last] * cv.n2[last];
-    for (int k = tid; k < Nc * Nc; k += nt) s.inv[k] = cv.inv[k];
+  const int Nc = cv.n1[last] * cv.n2[last];
+  double ginv[kCoarseInvPer];
+#pragma unroll
+  for (int u = 0; u < kCoarseInvPer; ++u) {
+    const int k = tid + u * nt;
+    ginv[u] = k < Nc * Nc ? cv.inv[k] : 0.0;
   }
-  {
-    const int N0 = cv.n1[0] * cv.n2[0];
-    for (int p = tid; p < N0; p += nt) s.B[0][p] = b_in[p];
+  const int N0 = cv.n1[0] * cv.n2[0];
+  const R gb = tid < N0 ? b_in[tid] : R(0);
+  if (skipv) return;
+  static_for<0, NL>([&](auto lc) {
+    constexpr int l = decltype(lc)::value;
+    const int N = cv.n1[l] * cv.n2[l];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int k = tid + u * nt;
+      if (k < 2 * N) {
+        s.dpm[l][k] = gd[l][u];
+        s.epm[l][k] = ge[l][u];
+      }
+    }
+    if (tid < N) s.dinv[l][tid] = gi[l];
+    if (tid < 2 * cv.n1[l] + 2) s.swx[l][tid] = gwx[l];
+    if (tid < 2 * cv.n2[l] + 2) s.swy[l][tid] = gwy[l];
+  });
+#pragma unroll
+  for (int u = 0; u < kCoarseInvPer; ++u) {
+    const int k = tid + u * nt;
+    if (k < Nc * Nc) s.inv[k] = ginv[u];
   }
+  if (tid < N0) s.B[0][tid] = gb;
   __syncthreads();
   // descend: pre-smooth, residual, restrict
   static_for<0, last>([&](auto lc) {
@@ -489,6 +840,15 @@ template <typename R>
 hipError_t launch_coarse_vcycle(const CoarseView<R>& cv, const R* b, R* x, const int* skip, hipStream_t st) {
   const size_t bytes = coarse_lds_bytes(cv);
   if (bytes > 160 * 1024 || !cv.inv) return hipErrorInvalidValue;
+  // the single-round load phase holds at most kCoarseMaxN points per level and kCoarseInvPer * 1024
+  // entries of the inverse per thread
+  for (int l = 0; l < cv.nlev; ++l)
+    if (cv.n1[l] * cv.n2[l] > kCoarseMaxN || 2 * cv.n1[l] + 2 > 1024 || 2 * cv.n2[l] + 2 > 1024)
+      return hipErrorInvalidValue;
+  {
+    const int Nc = cv.n1[cv.nlev - 1] * cv.n2[cv.nlev - 1];
+    if (Nc * Nc > kCoarseInvPer * 1024) return hipErrorInvalidValue;
+  }
   switch (cv.nlev) {
     case 1:
       return launch_coarse_vcycle_n<R, 1>(cv, b, x, skip, bytes, st);
@@ -680,6 +1040,12 @@ template hipError_t launch_add_to<double>(size_t, const double*, double*, hipStr
   template hipError_t launch_prolong<R>(int, int, const R*, R*, const int*, hipStream_t);              \
   template hipError_t launch_fill<R>(size_t, R*, R, hipStream_t);                                      \
   template hipError_t launch_interleave<R>(size_t, const double*, const double*, R*, hipStream_t);     \
+  template hipError_t launch_tile_resid_restrict<R>(int, int, const R*, const R*, const R*, const R*,    \
+                                                    const R*, const R*, R*, const R*, R*, const int*,     \
+                                                    hipStream_t);                                         \
+  template bool tile_lds_fits<R>(int, int);                                                            \
+  template hipError_t launch_tile_jacobi<R>(int, int, const R*, const R*, const R*, const R*, const R*,  \
+                                            const R*, const R*, const R*, R*, const int*, hipStream_t);   \
   template hipError_t launch_inject_pairs<R>(int, int, const R*, R*, hipStream_t);                     \
   template hipError_t launch_diag<R>(int, const R*, const R*, double, double, double, R*, double*,      \
                                      hipStream_t);                                                      \

@@ -78,8 +78,23 @@ int one_wg_max() {
   }();
   return v;
 }
-constexpr int kDirectOpMax = 255;  // levels with max(n1, n2) <= this use the direct operator kernel
-constexpr int kDirectOpMaxF32 = 127;  // the same for FP32 levels (whose short FFTs are cheaper)
+// The outer FP64 operator of grids with max(n1, n2) <= kOuterDirectMax uses the direct kernel.
+constexpr int kOuterDirectMax = 255;
+// Levels with max(n1, n2) <= direct_op_max() use the direct (dense-Toeplitz) kernels: 255 in FP64, 127
+// in FP32 (at 255^2 the FP32 transforms and the tiled direct kernels cost the same; at 511^2 the
+// transforms win by 20 %).  The environment variables FDE_DIRECT_MAX_F64 / FDE_DIRECT_MAX_F32 override
+// the limits for measurements.
+int direct_op_max(size_t bytes) {
+  static const int v64 = [] {
+    const char* e = std::getenv("FDE_DIRECT_MAX_F64");
+    return e ? std::atoi(e) : 255;
+  }();
+  static const int v32 = [] {
+    const char* e = std::getenv("FDE_DIRECT_MAX_F32");
+    return e ? std::atoi(e) : 127;
+  }();
+  return bytes == 8 ? v64 : v32;
+}
 
 template <typename R>
 struct Level {
@@ -100,6 +115,7 @@ struct Level {
   R* x2 = nullptr;  // second iterate buffer of levels that cannot smooth in place
   R* ay = nullptr;
   bool direct = false;
+  bool tiled = false;        // direct level whose V-cycle legs run the tiled kernels with fused transfers
   bool gal = false;          // Galerkin level (factored form)
   bool mfma = false;         // operator passes as BF16 MFMA products
   MfmaView mv{};
@@ -164,7 +180,7 @@ struct Outer {
     v.tw_y = twy;
     v.swx = swx;
     v.swy = swy;
-    v.direct = std::max(n1, n2) <= kDirectOpMax ? 1 : 0;
+    v.direct = std::max(n1, n2) <= kOuterDirectMax ? 1 : 0;
     return v;
   }
 };
@@ -635,7 +651,7 @@ std::unique_ptr<Hierarchy<R>> build_hierarchy(fde_handle* h) {
       }
       L.dinv = dalloc<R>(m, N);
       HIPCHECK(launch_diag<R>((int)N, L.dpm, L.epm, L.sx * h->pwa[1], L.sy * h->pwb[1], p.omega, L.dinv, nullptr, st));
-      L.direct = std::max(n1, n2) <= (sizeof(R) == 4 ? kDirectOpMaxF32 : kDirectOpMax);
+      L.direct = std::max(n1, n2) <= direct_op_max(sizeof(R));
       const bool tune = !galerkin && tune_level(n1, n2, (int)sizeof(R), &L.direct);
       if (L.direct || tune) {
         std::vector<double> sx(n1 + 1), sy(n2 + 1);
@@ -654,6 +670,7 @@ std::unique_ptr<Hierarchy<R>> build_hierarchy(fde_handle* h) {
       }
       if (!L.direct || tune) L.ay = dalloc<R>(m, N);
       if (tune) L.direct = time_direct_vs_fft<R>(h, L);
+      L.tiled = L.direct && !L.mfma && std::min(n1, n2) > p.coarsest_n && tile_lds_fits<R>(n1, n2);
       if (std::is_same<R, float>::value && p.precision == FDE_MIXED_BF16GEMM && !L.direct) {
         L.mfma = true;
         L.mv.n1 = n1;
@@ -818,11 +835,36 @@ R* vcycle_from(fde_handle* h, Hierarchy<R>& H, int l, R* x, const int* skip, boo
       cur = nxt;
     }
   };
+  Level<R>& C = H.lv[l + 1];
+  // the restriction also takes the coarse level's first sweep when that level smooths
+  const bool fuse = (l + 1 < H.lc) && h->p.nu_pre > 0;
+  if (L.tiled) {
+    // direct level: residual and restriction in one kernel, prolongation inside the post-smoothing
+    const double fb = (double)(sizeof(R)) * (double)N;
+    auto tile_sweep = [&](const R* e) {
+      R* nxt = (cur == x) ? L.x2 : x;
+      timed(h, l == 0 ? FDE_KFAM_MG0_X : FDE_KFAM_MGC_X, fb * 8.0 + (e ? (double)Nc * sizeof(R) : 0.0), [&] {
+        return launch_tile_jacobi<R>(L.n1, L.n2, cur, e, L.b, L.dpm, L.epm, L.dinv, L.swx, L.swy, nxt, skip, st);
+      });
+      cur = nxt;
+    };
+    for (int it = 1; it < h->p.nu_pre; ++it) tile_sweep(nullptr);
+    timed(h, l == 0 ? FDE_KFAM_MG0_X : FDE_KFAM_MGC_X, fb * 6.0 + (double)(fuse ? 3 : 1) * Nc * sizeof(R), [&] {
+      return launch_tile_resid_restrict<R>(L.n1, L.n2, cur, L.b, L.dpm, L.epm, L.swx, L.swy, C.b,
+                                           fuse ? C.dinv : nullptr, fuse ? C.x : nullptr, skip, st);
+    });
+    const R* ec = vcycle_from<R>(h, H, l + 1, C.x, skip, fuse);
+    if (h->p.nu_post == 0) {
+      timed(h, FDE_KFAM_TRANSFER, (double)(2 * N + Nc) * sizeof(R),
+            [&] { return launch_prolong<R>(L.n1, L.n2, ec, cur, skip, st); });
+    } else {
+      tile_sweep(ec);
+      for (int it = 1; it < h->p.nu_post; ++it) tile_sweep(nullptr);
+    }
+    return cur;
+  }
   for (int it = 1; it < h->p.nu_pre; ++it) jacobi_sweep();
   level_apply<R>(h, L, cur, L.r, EP_RESID, skip);
-  // the restriction also takes the coarse level's first sweep when that level smooths
-  Level<R>& C = H.lv[l + 1];
-  const bool fuse = (l + 1 < H.lc) && h->p.nu_pre > 0;
   timed(h, FDE_KFAM_TRANSFER, (double)(N + (fuse ? 3 : 1) * Nc) * sizeof(R), [&] {
     return launch_restrict<R>(L.n1, L.n2, L.r, C.b, fuse ? C.dinv : nullptr, fuse ? C.x : nullptr, skip, st);
   });
@@ -1176,7 +1218,7 @@ size_t footprint_bytes(const fde_problem* pin) {
   double galscratch = 0;
   while (true) {
     const double Nl = (double)a1 * a2;
-    const bool direct = std::max(a1, a2) <= (f32 ? kDirectOpMaxF32 : kDirectOpMax);
+    const bool direct = std::max(a1, a2) <= direct_op_max(f32 ? 4 : 8);
     const bool one_wg = !gal && std::max(a1, a2) <= one_wg_max();
     if (gal && l > 0) {
       b += 4.0 * a2 * p.n1 * R + 4.0 * p.n2 * a1 * R + 2.0 * Nl * R;  // fields, dinv, qx/qy (small)

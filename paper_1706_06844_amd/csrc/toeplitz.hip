@@ -41,7 +41,7 @@ __global__ __launch_bounds__((XCfg<R, L>::THREADS), FDE_XW) void toep_x_kernel(
     int n1, int n2, const Tin* x, const R* __restrict__ dpm, const R* __restrict__ mu,
     const R* __restrict__ twtab, const R* __restrict__ ay, const R* __restrict__ b,
     const R* __restrict__ dinv, SrcTerms src, double tau, R* out, const int* __restrict__ skip) {
-  if (skip && *skip) return;
+  const int skipv = load_flag(skip);  // waited for after the row loads are issued
   using P = XPlan<R, L>;
   constexpr int E = P::E, T = P::T, S = XCfg<R, L>::S;
   constexpr int SLOT = lds_exchange(L) + 2 * L;
@@ -68,6 +68,7 @@ __global__ __launch_bounds__((XCfg<R, L>::THREADS), FDE_XW) void toep_x_kernel(
     zr[m] = (hasA && i < n1) ? (R)xa[i] : R(0);
     zi[m] = (hasB && i < n1) ? (R)xb[i] : R(0);
   });
+  if (skipv) return;
   fft<L, -1>(zr, zi, lds, tw, t);
   symbol_both<L, P>(zr, zi, zs, mu, t);
   fft<L, +1>(zr, zi, lds, tw, t);  // real part: T xa, imaginary part: T xb
@@ -122,7 +123,7 @@ template <typename R, typename Tin, int L>
 __global__ __launch_bounds__((YCfg<R, L>::THREADS), FDE_YW) void toep_y_kernel(
     int n1, int n2, const Tin* __restrict__ x, const R* __restrict__ epm, const R* __restrict__ mu,
     const R* __restrict__ twtab, R* __restrict__ ay, int nstrips, const int* __restrict__ skip) {
-  if (skip && *skip) return;
+  const int skipv = load_flag(skip);  // waited for after the column loads are issued
   using P = YPlan<R, L>;
   constexpr int E = P::E, T = P::T, S = YCfg<R, L>::S;
   // Workgroups are dealt to the 8 XCDs round-robin; give each XCD a contiguous range of strips so
@@ -148,6 +149,7 @@ __global__ __launch_bounds__((YCfg<R, L>::THREADS), FDE_YW) void toep_y_kernel(
     zr[m] = (row < n2 && v0) ? (R)x[p] : R(0);
     zi[m] = (row < n2 && v1) ? (R)x[p + 1] : R(0);
   });
+  if (skipv) return;
   fft<L, -1>(zr, zi, lds, tw, t);
   symbol_both<L, P>(zr, zi, zs, mu, t);
   fft<L, +1>(zr, zi, lds, tw, t);  // T a + i T b along the columns
