@@ -39,11 +39,16 @@ PROFILE_STRIDE = 17
 # (scaled by a copy of known size), keyed by kernel family, with the hash of the source files the
 # kernel is built from: the figure is reported only while those sources are unchanged.
 PMC_TRAFFIC = {
-    # toep_y_kernel<float, float, 4096>: 1599 dispatches of one C3 step (FP32 cycles, BF16 basis)
-    "mg0_y": {"bytes_per_launch": 75.59e6,
-              "sources": ["paper_1706_06844_amd/csrc/toeplitz.hip", "paper_1706_06844_amd/csrc/toep_dev.h",
-                          "paper_1706_06844_amd/csrc/fft.h", "paper_1706_06844_amd/csrc/common.h"],
-              "sha256": "37d0afd537c92a918002b8fc3f3934d33834b8ad492105414582c673f596fbf1",
+    # cgs_kernel<double, double, *> (FP64 Gram-Schmidt passes): per executed pass of one C3 step with
+    # the FP32 V-cycle in FP64 GMRES (1080 executed of 1606 dispatches)
+    "cgs": {"bytes_per_launch": 390.01e6,
+             "sources": ['paper_1706_06844_amd/csrc/krylov.hip', 'paper_1706_06844_amd/csrc/common.h', 'paper_1706_06844_amd/csrc/fft.h'],
+             "sha256": "44f68dea1ba3cab87f431a0e8f991c237cfd4a11034b6679c816adfe50f73970",
+             "summary": "profiles/gram_schmidt_fp64_c3_2047.md"},
+    # toep_y_kernel<float, float, 4096>: 1052 dispatches of the same step
+    "mg0_y": {"bytes_per_launch": 71.13e6,
+              "sources": ['paper_1706_06844_amd/csrc/toeplitz.hip', 'paper_1706_06844_amd/csrc/toep_dev.h', 'paper_1706_06844_amd/csrc/fft.h', 'paper_1706_06844_amd/csrc/common.h'],
+              "sha256": "c339191e7f7891beda39fbc7aabc8c732de3811d95048165aa358443854aab3f",
               "summary": "profiles/fft_column_pass_c3_2047.md"},
 }
 

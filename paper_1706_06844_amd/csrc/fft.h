@@ -148,9 +148,15 @@ __device__ __forceinline__ void dft(R (&re)[N], R (&im)[N]) {
   }
 }
 
-// LDS index padding: one spare slot every 16 elements keeps strided stage writes conflict-free.
-__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
-__host__ __device__ constexpr int lds_len(int L) { return L + L / 16 + 1; }
+// LDS index padding: one spare slot every 2^FDE_LPAD_SHIFT elements spreads the strided stage writes
+// over the banks.  Measured on gfx950 (SQ_LDS_BANK_CONFLICT): one slot in 32 halves the conflict
+// cycles of the FP32 row pass against one in 16 and takes 1-3 % off the FP64 passes; the transforms
+// are not bound by LDS conflicts (the FP32 passes' times moved by 1 %).
+#ifndef FDE_LPAD_SHIFT
+#define FDE_LPAD_SHIFT 5
+#endif
+__device__ __forceinline__ int lpad(int i) { return i + (i >> FDE_LPAD_SHIFT); }
+__host__ __device__ constexpr int lds_len(int L) { return L + (L >> FDE_LPAD_SHIFT) + 1; }
 // Exchange of a stage: real and imaginary parts together (one barrier pair per stage) or one after
 // the other through a single buffer (half the LDS, two barrier pairs).
 #ifndef FDE_EXCH_SPLIT

@@ -456,14 +456,49 @@ std::vector<double> symbol_host(const std::vector<double>& w, int n, int L, doub
 }
 
 // ---- autotuner -------------------------------------------------------------------------------
-// The operator of a level can run as the dense-Toeplitz kernel (one launch, O(n) work per point) or
-// as the two FFT passes (O(log n) per point, more launches and transform overhead).  Which is faster
-// depends on the size and the precision, so levels whose larger side lies in (one_wg_max(),
-// kDirectTuneMax] are timed both ways the first time their shape occurs in the process, and the
-// faster one is kept for every later hierarchy (FDE_AUTOTUNE=0 keeps the static size rule).
+// A level whose larger side lies in (one_wg_max(), kDirectTuneMax] can run its V-cycle legs either as
+// the tiled direct kernels (residual with restriction, prolongation with Jacobi: two launches of
+// O(n) work per point) or as the FFT passes with separate transfers (residual passes, restriction,
+// prolongation, Jacobi passes: six launches of O(log n) work per point).  Which is faster depends on
+// the size and the precision, so the first hierarchy of a shape times one leg both ways and keeps
+// the faster.  The choice is appended to a cache file (FDE_TUNE_CACHE, default
+// $HOME/.cache/fde_tune_v1.txt) that every process reads before tuning: processes that find an entry
+// run the same kernels and so produce bitwise identical results.  FDE_AUTOTUNE=0 keeps the static
+// size rule (direct_op_max).
 constexpr int kDirectTuneMax = 511;
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int>, bool> g_tune_direct;
+bool g_tune_loaded = false;
+
+std::string tune_cache_path() {
+  if (const char* e = std::getenv("FDE_TUNE_CACHE")) return e;
+  if (const char* home = std::getenv("HOME")) return std::string(home) + "/.cache/fde_tune_v1.txt";
+  return "";
+}
+
+// Reads the cache file once per process (caller holds g_tune_mu); the first entry of a key wins.
+void tune_cache_load() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const std::string path = tune_cache_path();
+  if (path.empty()) return;
+  FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return;
+  int a, b, c, d;
+  while (std::fscanf(f, "%d %d %d %d", &a, &b, &c, &d) == 4) g_tune_direct.emplace(std::make_tuple(a, b, c), d != 0);
+  std::fclose(f);
+}
+
+void tune_cache_append(int n1, int n2, int bytes, bool direct) {
+  const std::string path = tune_cache_path();
+  if (path.empty()) return;
+  const size_t slash = path.rfind('/');
+  if (slash != std::string::npos) (void)std::system(("mkdir -p '" + path.substr(0, slash) + "' 2>/dev/null").c_str());
+  if (FILE* f = std::fopen(path.c_str(), "a")) {
+    std::fprintf(f, "%d %d %d %d\n", n1, n2, bytes, direct ? 1 : 0);
+    std::fclose(f);
+  }
+}
 
 // True if the level has to be timed now; otherwise *direct holds the cached or static choice.
 bool tune_level(int n1, int n2, int bytes, bool* direct) {
@@ -472,54 +507,68 @@ bool tune_level(int n1, int n2, int bytes, bool* direct) {
   const char* e = std::getenv("FDE_AUTOTUNE");
   if (e && e[0] == '0') return false;
   std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_cache_load();
   auto it = g_tune_direct.find({n1, n2, bytes});
   if (it == g_tune_direct.end()) return true;
   *direct = it->second;
   return false;
 }
 
+// Times one V-cycle leg of level L (restriction side and prolongation side) both ways on the
+// handle's scratch fields (their contents do not matter for the timing).
 template <typename R>
 bool time_direct_vs_fft(fde_handle* h, Level<R>& L) {
   hipStream_t st = h->stream;
-  const size_t N = L.N();
-  R* x = reinterpret_cast<R*>(h->scratch64);  // the fine-level scratch holds 4 fine FP64 fields
+  const size_t N = L.N(), Nc = (size_t)((L.n1 - 1) / 2) * ((L.n2 - 1) / 2);
+  R* x = reinterpret_cast<R*>(h->scratch64);  // 4 fine FP64 fields: x, y, b and the coarse fields
   R* y = x + N;
-  HIPCHECK(launch_fill<R>(N, x, R(0.5), st));
-  hipEvent_t a, b;
+  R* b = y + N;
+  R* bc = b + N;
+  R* xc = bc + Nc;
+  R* dc = xc + Nc;
+  HIPCHECK(launch_fill<R>(3 * N + 3 * Nc, x, R(0.5), st));
+  hipEvent_t a, e;
   HIPCHECK(hipEventCreate(&a));
-  HIPCHECK(hipEventCreate(&b));
-  auto run = [&](bool direct) {
-    L.direct = direct;
-    const OpView<R> v = L.view();
-    if (direct)
-      HIPCHECK((launch_direct_op<R, R>(L.n1, L.n2, x, L.dpm, L.epm, L.swx, L.swy, y, EP_APPLY, nullptr, L.dinv,
-                                       nullptr, 0.0, nullptr, st)));
-    else
-      HIPCHECK((launch_operator<R, R>(v, x, L.ay, y, EP_APPLY, nullptr, nullptr, 0.0, nullptr, st)));
+  HIPCHECK(hipEventCreate(&e));
+  auto leg = [&](bool direct) {
+    if (direct) {
+      HIPCHECK(launch_tile_resid_restrict<R>(L.n1, L.n2, x, b, L.dpm, L.epm, L.swx, L.swy, bc, dc, xc, nullptr, st));
+      HIPCHECK(launch_tile_jacobi<R>(L.n1, L.n2, x, xc, b, L.dpm, L.epm, L.dinv, L.swx, L.swy, y, nullptr, st));
+    } else {
+      L.direct = false;
+      const OpView<R> v = L.view();
+      HIPCHECK((launch_operator<R, R>(v, x, L.ay, y, EP_RESID, b, nullptr, 0.0, nullptr, st)));
+      HIPCHECK(launch_restrict<R>(L.n1, L.n2, y, bc, dc, xc, nullptr, st));
+      HIPCHECK(launch_prolong<R>(L.n1, L.n2, xc, x, nullptr, st));
+      HIPCHECK((launch_operator<R, R>(v, x, L.ay, x, EP_JACOBI, b, nullptr, 0.0, nullptr, st)));
+    }
   };
+  const bool can_direct = tile_lds_fits<R>(L.n1, L.n2);
   float best[2] = {1e30f, 1e30f};
-  for (int d = 0; d < 2; ++d) {
-    run(d == 1);  // warm-up
+  for (int d = 0; d < (can_direct ? 2 : 1); ++d) {
+    leg(d == 1);  // warm-up
     for (int r = 0; r < 5; ++r) {
       HIPCHECK(hipEventRecord(a, st));
-      run(d == 1);
-      HIPCHECK(hipEventRecord(b, st));
-      HIPCHECK(hipEventSynchronize(b));
+      leg(d == 1);
+      HIPCHECK(hipEventRecord(e, st));
+      HIPCHECK(hipEventSynchronize(e));
       float ms = 0.f;
-      HIPCHECK(hipEventElapsedTime(&ms, a, b));
+      HIPCHECK(hipEventElapsedTime(&ms, a, e));
       best[d] = std::min(best[d], ms);
     }
   }
   (void)hipEventDestroy(a);
-  (void)hipEventDestroy(b);
+  (void)hipEventDestroy(e);
   const bool direct = best[1] < best[0];
+  L.direct = direct;
   const char* log = std::getenv("FDE_TUNE_LOG");
   if (log && log[0] == '1')
-    std::fprintf(stderr, "fde: level %dx%d (%zu-byte) FFT %.1f us, dense %.1f us -> %s\n", L.n1, L.n2, sizeof(R),
-                 best[0] * 1e3, best[1] * 1e3, direct ? "dense" : "FFT");
+    std::fprintf(stderr, "fde: level %dx%d (%zu-byte) leg: FFT %.1f us, tiled direct %.1f us -> %s\n", L.n1, L.n2,
+                 sizeof(R), best[0] * 1e3, best[1] * 1e3, direct ? "direct" : "FFT");
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tune_direct[{L.n1, L.n2, (int)sizeof(R)}] = direct;
-  return direct;
+  if (g_tune_direct.emplace(std::make_tuple(L.n1, L.n2, (int)sizeof(R)), direct).second)
+    tune_cache_append(L.n1, L.n2, (int)sizeof(R), direct);
+  return g_tune_direct[{L.n1, L.n2, (int)sizeof(R)}];
 }
 
 // Composite hat of half-width H at offset d (the 1-D factor of P_1 ... P_l, bilinear).
