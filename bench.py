@@ -336,11 +336,15 @@ def run_c4(args):
     reqs = [host_request(p) for p in probs]
     unknown_steps = sum(p.n1 * p.n2 * p.M for p in probs)
     steps = sum(p.M for p in probs)
+    # grouped mode: one group per size, as many slots as instances of the most frequent size
+    slots = max(sum(1 for p in probs if p.n1 == n) for n in {p.n1 for p in probs})
     out = {}
-    for prec_name, prec in (("mixed", fde.FDE_MIXED_FP32), ("fp64", fde.FDE_FP64),
-                            ("cycle", fde.FDE_MIXED_FP32_CYCLE)):
-        # batched: admission (resident setup) outside the timed region
+
+    def batched(prec, grouped):
+        # admission (resident setup, graph capture) outside the timed region
         b = fde.fde_batch_create(200 << 30)
+        if grouped:
+            fde.fde_batch_set_grouping(b, 511, slots)
         ids = [admit(b, r, prec, 1e-9, 2000) for r in reqs]
         assert min(ids) >= 0
         torch.cuda.synchronize()
@@ -349,14 +353,24 @@ def run_c4(args):
             pass
         torch.cuda.synchronize()
         tb = time.perf_counter() - t0
-        finals, iters = {}, 0
+        finals, iters = [], 0
         for rid, p in zip(ids, probs):
             u = torch.empty((p.n2, p.n1), dtype=torch.float64, device="cuda:0")
             st, it = fde.fde_batch_poll(b, rid, u)
             assert st == 1, (rid, st)
-            finals[rid] = u
+            finals.append(u)
             iters += it
         b.close()
+        return tb, finals, iters
+
+    for prec_name, prec in (("mixed", fde.FDE_MIXED_FP32), ("fp64", fde.FDE_FP64),
+                            ("cycle", fde.FDE_MIXED_FP32_CYCLE)):
+        tb, finals, iters = batched(prec, False)
+        tg, gfinals, giters = batched(prec, True)
+        gdiff = max(float((a - c).abs().max()) for a, c in zip(finals, gfinals))
+        log(f"c4 {prec_name}: grouped vs ungrouped max diff {gdiff:.3e}, iterations {giters} vs {iters}")
+        finals = dict(zip(range(len(probs)), finals))
+        ids = list(range(len(probs)))
         # sequential: one resident instance at a time, same steps (setup outside the timed region)
         ts = 0.0
         maxdiff = 0.0
@@ -373,8 +387,11 @@ def run_c4(args):
             fde.fde_batch_poll(b1, i1, u)
             maxdiff = max(maxdiff, float((u - finals[rid]).abs().max()))
             b1.close()
-        out[prec_name] = {"batched_s": tb, "sequential_s": ts, "iters": iters, "max_diff_alone_vs_mix": maxdiff}
-        log(f"c4 {prec_name}: batched {tb:.2f} s, one at a time {ts:.2f} s, {iters} iterations")
+        out[prec_name] = {"batched_s": tb, "grouped_s": tg, "sequential_s": ts, "iters": iters,
+                          "max_diff_alone_vs_mix": maxdiff, "grouped_max_diff": gdiff,
+                          "grouped_iters_equal": giters == iters}
+        log(f"c4 {prec_name}: batched {tb:.2f} s, grouped ({slots} slots) {tg:.2f} s, one at a time {ts:.2f} s, "
+            f"{iters} iterations")
     m = out["cycle"]
     line = {
         "metric": "C4 batched CN steps/s (64 uneven instances, mixed precision)",
@@ -385,6 +402,12 @@ def run_c4(args):
                    "precision": "FP32 V-cycle and FP32 restart cycles (FP32 basis) refining the FP64 "
                                 "iterate from FP64 true residuals"},
         "unknown_updates_per_s": unknown_steps / m["batched_s"],
+        "grouped_steps_per_s": steps / m["grouped_s"],
+        "grouped_slots": slots,
+        "fp32_preconditioner_grouped_steps_per_s": steps / out["mixed"]["grouped_s"],
+        "fp64_grouped_steps_per_s": steps / out["fp64"]["grouped_s"],
+        "grouped_max_abs_diff_vs_ungrouped": max(v["grouped_max_diff"] for v in out.values()),
+        "grouped_iters_equal": all(v["grouped_iters_equal"] for v in out.values()),
         "one_at_a_time_steps_per_s": steps / m["sequential_s"],
         "batching_speedup": m["sequential_s"] / m["batched_s"],
         "iters": m["iters"],

@@ -257,6 +257,19 @@ size_t fde_footprint(const fde_problem* p);
 int fde_batch_create(size_t budget_bytes, void* stream, fde_batch** out);
 void fde_batch_destroy(fde_batch* b);
 
+/* Grouped mode: requests with equal shape (n1, n2, precision, multigrid settings, restart; the
+ * geometric hierarchy, any precision but FDE_MIXED_BF16GEMM) and max(n1, n2) <= max_n share a
+ * group of `slots` equal slots of one device region and one stream.  A group's restart cycle is one
+ * captured HIP graph whose every kernel covers all slots (one launch per kernel for the whole
+ * group instead of one per request), issued while any member solves; empty slots and members whose
+ * solve has stopped are skipped by every kernel, so each member computes exactly what it computes
+ * alone.  A group is created when the first request of its shape is admitted and charges
+ * slots * (fde_footprint rounded up to 4 KiB) to the budget until the batch is destroyed; its members
+ * are charged (2 + nsrc) * n1 * n2 * 8 bytes each.  max_n = 0 turns grouping off (the default).
+ * Only on an empty batch; FDE_EINVAL for slots outside 1..1024 (with max_n > 0) or a batch that
+ * holds requests. */
+int fde_batch_set_grouping(fde_batch* b, int32_t max_n, int32_t slots);
+
 /* Admits a request: problem *p (as for fde_setup), coefficient fields (copied), initial field u0
  * (device, copied), nsteps CN steps from t0, and a separable source sum_k phi_k(t) S_k with
  * phi_k(t) = coef[k] * exp(rate[k] * t) evaluated at the half steps (nsrc <= 4; coef, rate host

@@ -9,9 +9,18 @@
 // Requests are admitted against a device-memory budget and may join or leave between calls to
 // fde_batch_step (continuous batching).  The kernels a request runs, and their order, do not depend
 // on the other requests, so its result is the same alone and in the mix.
+//
+// Grouped mode (fde_batch_set_grouping): requests of one shape (sizes, precision, multigrid settings)
+// up to a size limit share a group: one device region cut into equal slots, one stream, and one
+// captured restart cycle whose every launch covers all slots (grid z = slot; the kernels shift their
+// pointers by the slot size).  A group cycle is issued while any member has a solve in flight; each
+// member starts its CN steps on its own (right-hand side, norm of b) between cycles.  A member whose
+// solve is finished, and an empty slot, are skipped by every kernel of the cycle (done / idle flags),
+// so each member runs exactly the arithmetic it runs alone.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstring>
 #include <map>
 #include <string>
 #include <thread>
@@ -30,6 +39,9 @@ enum ReqState { RS_START = 0, RS_RUNNING = 1, RS_DONE = 2, RS_FAILED = 3 };
 struct Request {
   fde_handle* h = nullptr;
   hipStream_t stream = nullptr;
+  int group = -1;  // index of its group in grouped mode (the stream then belongs to the group)
+  int slot = -1;
+  int cycles = 0;  // restart cycles of the solve in flight (grouped mode)
   fde_problem p{};
   size_t N = 0;
   double* u[2] = {nullptr, nullptr};
@@ -53,8 +65,52 @@ void release(Request& r) {
     if (p) (void)hipFree(p);
   for (int k = 0; k < kMaxSrc; ++k)
     if (r.S[k]) (void)hipFree(r.S[k]);
-  if (r.stream) (void)hipStreamDestroy(r.stream);
+  if (r.stream && r.group < 0) (void)hipStreamDestroy(r.stream);
   r = Request{};
+}
+
+// A group: `nslots` slots of `slot_bytes` in one allocation, members by slot, the captured cycle.
+struct Group {
+  fde_problem shape{};
+  int nslots = 0;
+  size_t slot_bytes = 0;
+  char* arena = nullptr;
+  hipStream_t stream = nullptr;
+  std::vector<int> member;  // request id per slot, -1 if empty
+  long long st_off = 0;     // offset of the solver state within a slot
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipEvent_t ev = nullptr;
+  GmresState* hst = nullptr;  // pinned: the states' host-read prefix of every slot after a cycle
+  GmresState* idle = nullptr;  // pinned: the state written into an empty slot
+  bool inflight = false;
+};
+
+// The part of the state the host reads after a cycle (the configuration fields follow it).
+constexpr size_t kStatePrefix = offsetof(GmresState, rtol);
+
+bool same_shape(const fde_problem& a, const fde_problem& b) {
+  return a.n1 == b.n1 && a.n2 == b.n2 && a.precision == b.precision && a.mg_variant == b.mg_variant &&
+         a.nu_pre == b.nu_pre && a.nu_post == b.nu_post && a.coarsest_n == b.coarsest_n && a.restart == b.restart &&
+         a.omega == b.omega;
+}
+
+void destroy_group(Group& g) {
+  if (g.stream) (void)hipStreamSynchronize(g.stream);
+  if (g.gexec) (void)hipGraphExecDestroy(g.gexec);
+  if (g.graph) (void)hipGraphDestroy(g.graph);
+  if (g.ev) (void)hipEventDestroy(g.ev);
+  if (g.hst) (void)hipHostFree(g.hst);
+  if (g.idle) (void)hipHostFree(g.idle);
+  if (g.arena) (void)hipFree(g.arena);
+  if (g.stream) (void)hipStreamDestroy(g.stream);
+  g = Group{};
+}
+
+// Marks slot `s` empty on the device: every kernel of the group cycle skips it from now on.
+hipError_t mark_idle(Group& g, int s) {
+  return hipMemcpyAsync(g.arena + (size_t)s * g.slot_bytes + g.st_off, g.idle, sizeof(GmresState),
+                        hipMemcpyHostToDevice, g.stream);
 }
 
 }  // namespace
@@ -65,6 +121,9 @@ struct fde_batch {
   int next_id = 0;
   std::map<int, Request> reqs;
   std::string err;
+  int group_max_n = 0;  // 0: grouping off
+  int group_slots = 0;
+  std::vector<Group> groups;
 };
 
 extern "C" {
@@ -81,8 +140,19 @@ int fde_batch_create(size_t budget_bytes, void* stream, fde_batch** out) {
 
 void fde_batch_destroy(fde_batch* b) {
   if (!b) return;
+  for (Group& g : b->groups)
+    if (g.stream) (void)hipStreamSynchronize(g.stream);
   for (auto& kv : b->reqs) release(kv.second);
+  for (Group& g : b->groups) destroy_group(g);
   delete b;
+}
+
+int fde_batch_set_grouping(fde_batch* b, int32_t max_n, int32_t slots) {
+  if (!b || max_n < 0 || slots < 0 || (max_n > 0 && slots < 1) || slots > 1024) return FDE_EINVAL;
+  if (!b->reqs.empty()) return FDE_EINVAL;
+  b->group_max_n = slots > 0 ? max_n : 0;
+  b->group_slots = slots;
+  return FDE_OK;
 }
 
 int fde_batch_admit(fde_batch* b, const fde_problem* p, const double* dp, const double* dm, const double* ep,
@@ -107,13 +177,89 @@ int fde_batch_admit(fde_batch* b, const fde_problem* p, const double* dp, const 
     release(r);
     return code;
   };
-  if (hipStreamCreateWithFlags(&r.stream, hipStreamNonBlocking) != hipSuccess)
-    return fail(FDE_EDEVICE, "stream creation failed");
-  const int rc = fde_setup(p, dp, dm, ep, em, r.stream, &r.h);
-  if (rc != FDE_OK) {
-    b->err = fde_last_error(nullptr);
-    release(r);
-    return rc;
+  fde_problem pf = *p;  // the defaults filled in, so that equal shapes compare equal
+  {
+    fde_problem q{};
+    fde_problem_default(&q, p->alpha, p->beta, p->n1, p->n2, p->tau);
+    if (pf.nu_pre < 0) pf.nu_pre = q.nu_pre;
+    if (pf.nu_post < 0) pf.nu_post = q.nu_post;
+    if (pf.coarsest_n == 0) pf.coarsest_n = q.coarsest_n;
+    if (pf.restart == 0) pf.restart = q.restart;
+  }
+  if (b->group_max_n > 0 && group_eligible(&pf, b->group_max_n)) {
+    // a free slot of a group of this shape, or a new group
+    int gi = -1, si = -1;
+    for (int k = 0; k < (int)b->groups.size() && gi < 0; ++k) {
+      Group& g = b->groups[k];
+      if (!g.arena || !same_shape(g.shape, pf)) continue;
+      for (int s = 0; s < g.nslots; ++s)
+        if (g.member[s] < 0) {
+          gi = k;
+          si = s;
+          break;
+        }
+    }
+    const size_t extra = (2 + (size_t)nsrc) * N * sizeof(double);
+    if (gi < 0) {
+      Group g;
+      g.shape = pf;
+      g.nslots = b->group_slots;
+      g.slot_bytes = (core + 4095) / 4096 * 4096;
+      const size_t gbytes = g.slot_bytes * (size_t)g.nslots;
+      if (b->used + gbytes + extra > b->budget) return FDE_EAGAIN;
+      g.member.assign(g.nslots, -1);
+      if (hipMalloc(&g.arena, gbytes) != hipSuccess) return FDE_ENOMEM;
+      if (hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&g.ev, hipEventDisableTiming) != hipSuccess ||
+          hipHostMalloc((void**)&g.hst, sizeof(GmresState) * g.nslots, hipHostMallocDefault) != hipSuccess ||
+          hipHostMalloc((void**)&g.idle, sizeof(GmresState), hipHostMallocDefault) != hipSuccess) {
+        destroy_group(g);
+        return FDE_EDEVICE;
+      }
+      std::memset(g.idle, 0, sizeof(GmresState));
+      g.idle->done = 1;
+      g.idle->conv = 1;
+      g.idle->idle = 1;
+      b->used += gbytes;
+      b->groups.push_back(g);
+      gi = (int)b->groups.size() - 1;
+      si = 0;
+    } else if (b->used + extra > b->budget) {
+      return FDE_EAGAIN;
+    }
+    Group& g = b->groups[gi];
+    r.group = gi;
+    r.slot = si;
+    r.stream = g.stream;
+    r.bytes = extra;
+    const int rc = group_setup(&pf, dp, dm, ep, em, g.stream, g.arena + (size_t)si * g.slot_bytes, g.slot_bytes, &r.h);
+    if (rc != FDE_OK) {
+      b->err = fde_last_error(nullptr);
+      release(r);
+      return rc;
+    }
+    if (!g.gexec) {
+      // the first member (slot 0) lays out the slots: empty ones get the idle state, and the cycle of
+      // all slots is captured once
+      g.st_off = group_state_offset(r.h);
+      for (int s = 1; s < g.nslots; ++s)
+        if (mark_idle(g, s) != hipSuccess) return fail(FDE_EDEVICE, "initialising the slots failed");
+      const int cr = group_capture_cycle(r.h, g.nslots, (long long)g.slot_bytes, &g.graph, &g.gexec);
+      if (cr != FDE_OK) {
+        b->err = fde_last_error(r.h);
+        release(r);
+        return cr;
+      }
+    }
+  } else {
+    if (hipStreamCreateWithFlags(&r.stream, hipStreamNonBlocking) != hipSuccess)
+      return fail(FDE_EDEVICE, "stream creation failed");
+    const int rc = fde_setup(p, dp, dm, ep, em, r.stream, &r.h);
+    if (rc != FDE_OK) {
+      b->err = fde_last_error(nullptr);
+      release(r);
+      return rc;
+    }
   }
   for (double*& q : r.u)
     if (hipMalloc(&q, N * sizeof(double)) != hipSuccess) return fail(FDE_ENOMEM, "device allocation failed");
@@ -130,18 +276,122 @@ int fde_batch_admit(fde_batch* b, const fde_problem* p, const double* dp, const 
   // the caller may free or reuse its arrays once this returns
   if (hipStreamSynchronize(r.stream) != hipSuccess) return fail(FDE_EDEVICE, "stream synchronisation failed");
   const int id = b->next_id++;
-  b->used += need;
+  b->used += r.bytes;
+  if (r.group >= 0) b->groups[r.group].member[r.slot] = id;
   b->reqs.emplace(id, r);
   return id;
 }
+
+namespace {
+
+// Advances the grouped requests: a finished group cycle is read out (members whose solve stopped
+// complete their step), members waiting for a step start it, and the next cycle is issued.  Returns
+// the number of steps completed; *active counts the groups with work in flight.
+int step_groups(fde_batch* b, int* active) {
+  int completed = 0;
+  for (int gi = 0; gi < (int)b->groups.size(); ++gi) {
+    Group& g = b->groups[gi];
+    if (!g.arena || !g.gexec) continue;
+    if (g.inflight) {
+      const hipError_t q = hipEventQuery(g.ev);
+      if (q == hipErrorNotReady) {
+        ++*active;
+        continue;
+      }
+      g.inflight = false;
+      for (int s = 0; s < g.nslots; ++s) {
+        if (g.member[s] < 0) continue;
+        Request& r = b->reqs.at(g.member[s]);
+        if (r.state != RS_RUNNING) continue;
+        if (q != hipSuccess) {
+          r.state = RS_FAILED;
+          r.err = FDE_EDEVICE;
+          ++completed;
+          continue;
+        }
+        ++r.cycles;
+        int fin = 0;
+        fde_stats st{};
+        const int rc = group_step_result(r.h, g.hst[s], r.cycles, &fin, &st);
+        if (!fin && rc == FDE_OK) continue;
+        ++completed;
+        r.iters += st.iters;
+        if (rc == FDE_ENOCONV) {
+          ++r.noconv;
+        } else if (rc != FDE_OK) {
+          r.state = RS_FAILED;
+          r.err = rc;
+          (void)mark_idle(g, s);
+          continue;
+        }
+        const int nxt = 1 - r.cur;
+        if (hipMemcpyAsync(r.u[nxt], async_result(r.h), r.N * sizeof(double), hipMemcpyDeviceToDevice, g.stream) !=
+            hipSuccess) {
+          r.state = RS_FAILED;
+          r.err = FDE_EDEVICE;
+          continue;
+        }
+        r.cur = nxt;
+        ++r.steps_done;
+        r.state = (r.steps_done >= r.nsteps) ? RS_DONE : RS_START;
+        if (r.state == RS_DONE) (void)mark_idle(g, s);
+      }
+    }
+    // start the steps of members that wait for one, then issue a cycle if any member solves
+    bool any = false;
+    for (int s = 0; s < g.nslots; ++s) {
+      if (g.member[s] < 0) continue;
+      Request& r = b->reqs.at(g.member[s]);
+      if (r.state == RS_START) {
+        const double t = r.t0 + (r.steps_done + 0.5) * r.p.tau;
+        double phi[kMaxSrc];
+        for (int k = 0; k < r.nsrc; ++k) phi[k] = r.coef[k] * std::exp(r.rate[k] * t);
+        const int rc = group_step_start(r.h, r.u[r.cur], r.nsrc, phi, r.S);
+        if (rc != FDE_OK) {
+          r.state = RS_FAILED;
+          r.err = rc;
+          (void)mark_idle(g, s);
+          ++completed;
+          continue;
+        }
+        r.state = RS_RUNNING;
+        r.cycles = 0;
+      }
+      if (r.state == RS_RUNNING) any = true;
+    }
+    if (!any) continue;
+    if (hipGraphLaunch(g.gexec, g.stream) != hipSuccess ||
+        hipMemcpy2DAsync(g.hst, sizeof(GmresState), g.arena + g.st_off, g.slot_bytes, kStatePrefix, g.nslots,
+                         hipMemcpyDeviceToHost, g.stream) != hipSuccess ||
+        hipEventRecord(g.ev, g.stream) != hipSuccess) {
+      for (int s = 0; s < g.nslots; ++s) {
+        if (g.member[s] < 0) continue;
+        Request& r = b->reqs.at(g.member[s]);
+        if (r.state == RS_RUNNING) {
+          r.state = RS_FAILED;
+          r.err = FDE_EDEVICE;
+          ++completed;
+        }
+      }
+      continue;
+    }
+    g.inflight = true;
+    ++*active;
+  }
+  return completed;
+}
+
+}  // namespace
 
 int fde_batch_step(fde_batch* b) {
   if (!b) return FDE_EINVAL;
   int completed = 0;
   while (true) {
     int active = 0;
+    completed += step_groups(b, &active);
     for (auto& kv : b->reqs) {
       Request& r = kv.second;
+      if (r.group >= 0) continue;
       if (r.state == RS_START) {
         // source amplitudes at the half step t^(m-1/2), m = steps_done + 1
         const double t = r.t0 + (r.steps_done + 0.5) * r.p.tau;
@@ -191,6 +441,22 @@ int fde_batch_step(fde_batch* b) {
   return running;
 }
 
+}  // extern "C"
+
+namespace {
+// Frees the request's slot: it is marked idle (ordered after the group's work) before the handle goes.
+// A cycle still counted in flight is read out by the next fde_batch_step for the other members.
+void leave_group(fde_batch* b, Request& r) {
+  if (r.group < 0) return;
+  Group& g = b->groups[r.group];
+  (void)mark_idle(g, r.slot);
+  if (g.stream) (void)hipStreamSynchronize(g.stream);
+  g.member[r.slot] = -1;
+}
+}  // namespace
+
+extern "C" {
+
 int fde_batch_poll(fde_batch* b, int id, double* u_out, int64_t* iters_out) {
   if (!b) return FDE_EINVAL;
   auto it = b->reqs.find(id);
@@ -200,6 +466,7 @@ int fde_batch_poll(fde_batch* b, int id, double* u_out, int64_t* iters_out) {
   if (r.state == RS_FAILED) {
     const int e = r.err;
     b->used -= r.bytes;
+    leave_group(b, r);
     release(r);
     b->reqs.erase(it);
     return e;
@@ -211,6 +478,7 @@ int fde_batch_poll(fde_batch* b, int id, double* u_out, int64_t* iters_out) {
         hipStreamSynchronize(r.stream) != hipSuccess)
       return FDE_EDEVICE;
     b->used -= r.bytes;
+    leave_group(b, r);
     release(r);
     b->reqs.erase(it);
   }
@@ -222,6 +490,7 @@ int fde_batch_cancel(fde_batch* b, int id) {
   auto it = b->reqs.find(id);
   if (it == b->reqs.end()) return FDE_EINVAL;
   b->used -= it->second.bytes;
+  leave_group(b, it->second);
   release(it->second);
   b->reqs.erase(it);
   return FDE_OK;

@@ -221,7 +221,7 @@ struct GmresState {
   int orth;       // Gram-Schmidt policy: 0 one pass, 1 always two passes, 2 second pass when needed
   int reorth;     // 1: the current Arnoldi step takes the second pass
   unsigned ticket;  // workgroups of a small pass that have written their partials
-  int pad1_;
+  int idle;         // 1: a slot of a batched group without a solve in flight: the cycle's kernels skip it
   double keep_min;  // policy 2: second pass when the first leaves less than this fraction of ||w||^2
   double brk_tol;   // breakdown: the new direction's norm below brk_tol times its column's
   double g[kMaxRestart + 1], cs[kMaxRestart], sn[kMaxRestart];
@@ -264,6 +264,31 @@ hipError_t launch_update_x(size_t N, const Tz* Z, size_t ldz, double* x, int fir
 
 // ---- small helpers -----------------------------------------------------------------------------
 inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
+// ---- batched launches ---------------------------------------------------------------------------
+// Instances of one shape whose device buffers are laid out identically, `zoff` bytes apart, can be
+// advanced by one launch: the grid's z dimension runs over the instances and every kernel of the
+// solve shifts each of its pointer arguments by blockIdx.z * zoff.  The launchers read the current
+// batch from this thread's context (1 instance, offset 0 outside a batched section).
+struct BatchCtx {
+  int nz = 1;
+  long long zoff = 0;
+};
+inline thread_local BatchCtx g_batch;
+inline int batch_nz() { return g_batch.nz; }
+inline long long batch_zoff() { return g_batch.zoff; }
+// Sets the batch for the lifetime of the object (restores the previous one).
+struct BatchScope {
+  BatchCtx saved;
+  BatchScope(int nz, long long zoff) : saved(g_batch) { g_batch = BatchCtx{nz, zoff}; }
+  ~BatchScope() { g_batch = saved; }
+};
+template <typename T>
+__device__ __forceinline__ T* zshift(T* p, long long zoff) {
+  return (p && zoff) ? reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(p) + (uintptr_t)((long long)blockIdx.z * zoff))
+                     : p;
+}
+#define FDE_ZSHIFT(p) (p = zshift(p, zoff))
+
 // Reads a device flag (the skip flag of speculatively issued Arnoldi steps) with a vector load: the
 // index is an opaque zero in a vector register, so that waiting for the flag does not also wait for
 // the kernel's scalar argument loads, and a kernel can issue its other loads before it needs the flag.

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include "../../include/fde.h"
+#include "common.h"
 
 namespace fde {
 
@@ -21,5 +22,22 @@ void async_use_graph(fde_handle* h, bool on);
 size_t footprint_bytes(const fde_problem* p);
 // Sets the message fde_last_error(NULL) returns on this thread.
 void set_global_error(const char* msg);
+
+// ---- batched groups (batch.hip): handles of one shape in equal slots of one device region ----------
+// fde_setup with every buffer carved, in a fixed order, from [base, base + cap): handles of the same
+// shape built in equal slots have identical layouts, `cap` bytes apart.
+int group_setup(const fde_problem* p, const double* dp, const double* dm, const double* ep, const double* em,
+                hipStream_t stream, void* base, size_t cap, fde_handle** out);
+// Byte offset of the handle's solver state within its slot.
+long long group_state_offset(const fde_handle* h);
+// Starts a CN step of one member on its stream: right-hand side, x = 0 and the norm of b (no cycle).
+int group_step_start(fde_handle* h, const double* u_prev, int nsrc, const double* phi, const double* const* S);
+// Captures one restart cycle of every slot as a graph: the handle of slot 0 issues the launches, each
+// with nz instances zoff bytes apart.
+int group_capture_cycle(fde_handle* h, int nz, long long zoff, hipGraph_t* graph, hipGraphExec_t* gexec);
+// After a cycle: *finished = 1 if the member's solve stopped (stats filled, fde_step's return code).
+int group_step_result(fde_handle* h, const GmresState& s, int cycles, int* finished, fde_stats* stats);
+// Whether problems of this shape can be advanced by batched launches.
+bool group_eligible(const fde_problem* p, int max_n);
 
 }  // namespace fde

@@ -214,7 +214,14 @@ template <typename TB, typename TW, int MAXV, bool FUSED>
 __global__ __launch_bounds__(kCgsBlock) void cgs_kernel(int kind, int N, int nv, const TB* __restrict__ V,
                                                         size_t ldv, TW* __restrict__ w, TB* __restrict__ vout,
                                                         const double* __restrict__ src, GmresState* st,
-                                                        double* __restrict__ partials) {
+                                                        double* __restrict__ partials, long long zoff) {
+  FDE_ZSHIFT(V);
+  FDE_ZSHIFT(w);
+  FDE_ZSHIFT(vout);
+  FDE_ZSHIFT(src);
+  FDE_ZSHIFT(st);
+  FDE_ZSHIFT(partials);
+  if (st->idle) return;
   constexpr bool kSplit = std::is_same<TB, bf16_t>::value;
   constexpr int VEC = kSplit ? 8 : 16 / (int)sizeof(TW);  // 16-byte loads of the basis
   using RB = typename BasisT<TB>::reg;
@@ -392,8 +399,9 @@ __device__ void finalize_block(int kind, int nv, int G, const double* partials, 
     for (int k = threadIdx.x; k < kWords; k += blockDim.x) dst[k] = src[k];
   }
   __syncthreads();
-  // nothing to combine after convergence, or for a second pass that was not taken (decided from the
-  // state before any partial is read)
+  // nothing to combine for an idle slot of a batched group, after convergence, or for a second pass
+  // that was not taken (decided from the state before any partial is read)
+  if (ls.idle) return;
   if (kind == CGS_DOTS || kind == CGS_UPDATE_DOTS || kind == CGS_UPDATE_NORM) {
     if (ls.done) return;
     if (kind == CGS_UPDATE_DOTS && !ls.reorth) return;
@@ -474,7 +482,9 @@ __device__ void finalize_block(int kind, int nv, int G, const double* partials, 
 // last-workgroup ticket of the fused form) would serialise at the memory side.
 __global__ __launch_bounds__(kFinBlock) void cgs_finalize_kernel(int kind, int nv, int G,
                                                                  const double* __restrict__ partials,
-                                                                 GmresState* gst) {
+                                                                 GmresState* gst, long long zoff) {
+  FDE_ZSHIFT(partials);
+  FDE_ZSHIFT(gst);
   __shared__ FinLds<kFinLds> F;
   finalize_block(kind, nv, G, partials, gst, F);
 }
@@ -503,11 +513,11 @@ hipError_t launch_cgs_pass(int kind, size_t N, int nv, TB* V, size_t ldv, TW* w,
   const bool fused = grid <= kFusedMaxGrid;
 #define L_(M)                                                                                              \
   if (fused)                                                                                               \
-    hipLaunchKernelGGL((cgs_kernel<TB, TW, M, true>), dim3(grid), dim3(kCgsBlock), 0, s, kind, n, nv, V, ldv, \
-                       w, vout, src, st, partials);                                                        \
+    hipLaunchKernelGGL((cgs_kernel<TB, TW, M, true>), dim3(grid, 1, batch_nz()), dim3(kCgsBlock), 0, s, kind, n, nv, \
+                       V, ldv, w, vout, src, st, partials, batch_zoff());                                   \
   else                                                                                                     \
-    hipLaunchKernelGGL((cgs_kernel<TB, TW, M, false>), dim3(grid), dim3(kCgsBlock), 0, s, kind, n, nv, V, ldv, \
-                       w, vout, src, st, partials)
+    hipLaunchKernelGGL((cgs_kernel<TB, TW, M, false>), dim3(grid, 1, batch_nz()), dim3(kCgsBlock), 0, s, kind, n, nv, \
+                       V, ldv, w, vout, src, st, partials, batch_zoff())
   if (nv <= 4) { L_(4); }
   else if (nv <= 8) { L_(8); }
   else if (nv <= 12) { L_(12); }
@@ -529,15 +539,20 @@ bool cgs_fused(int nv, int cap) { return cgs_pass_grid(nv, cap) <= kFusedMaxGrid
 hipError_t launch_cgs_finalize(int kind, int nv, double* partials, GmresState* st, int cap, hipStream_t s) {
   if (nv > kMaxRestart + 1 || cap < 1) return hipErrorInvalidValue;
   if (cgs_fused(nv, cap)) return hipErrorInvalidValue;  // the pass has combined its partials itself
-  hipLaunchKernelGGL(cgs_finalize_kernel, dim3(1), dim3(kFinBlock), 0, s, kind, nv, cgs_pass_grid(nv, cap), partials,
-                     st);
+  hipLaunchKernelGGL(cgs_finalize_kernel, dim3(1, 1, batch_nz()), dim3(kFinBlock), 0, s, kind, nv, cgs_pass_grid(nv, cap),
+                     partials, st, batch_zoff());
   return hipGetLastError();
 }
 
 // x = (first ? 0 : x) + Z y, with y solving the nused x nused triangular system R y = g.
 template <typename Tz>
 __global__ __launch_bounds__(256) void update_x_kernel(size_t N, const Tz* __restrict__ Z, size_t ldz,
-                                                       double* __restrict__ x, int first, GmresState* st) {
+                                                       double* __restrict__ x, int first, GmresState* st,
+                                                       long long zoff) {
+  FDE_ZSHIFT(Z);
+  FDE_ZSHIFT(x);
+  FDE_ZSHIFT(st);
+  if (st->idle) return;
   __shared__ double y[kMaxRestart];
   __shared__ int m_s;
   if (threadIdx.x == 0) {
@@ -568,7 +583,8 @@ hipError_t launch_update_x(size_t N, const Tz* Z, size_t ldz, double* x, int fir
   size_t g = (N + 256 * 4 - 1) / (256 * 4);
   if (g > 2048) g = 2048;
   if (g < 1) g = 1;
-  hipLaunchKernelGGL((update_x_kernel<Tz>), dim3((int)g), dim3(256), 0, s, N, Z, ldz, x, first, st);
+  hipLaunchKernelGGL((update_x_kernel<Tz>), dim3((int)g, 1, batch_nz()), dim3(256), 0, s, N, Z, ldz, x, first, st,
+                     batch_zoff());
   return hipGetLastError();
 }
 template hipError_t launch_update_x<double>(size_t, const double*, size_t, double*, int, GmresState*,

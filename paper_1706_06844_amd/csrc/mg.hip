@@ -23,7 +23,13 @@ static inline int grid_for(size_t n, int per_block = kBlock) {
 template <typename R, typename Tin>
 __global__ void presmooth_kernel(int N, const Tin* __restrict__ b, const double* __restrict__ bscale,
                                  const R* __restrict__ dinv, R* __restrict__ x, R* __restrict__ bcopy,
-                                 const int* __restrict__ skip) {
+                                 const int* __restrict__ skip, long long zoff) {
+  FDE_ZSHIFT(b);
+  FDE_ZSHIFT(bscale);
+  FDE_ZSHIFT(dinv);
+  FDE_ZSHIFT(x);
+  FDE_ZSHIFT(bcopy);
+  FDE_ZSHIFT(skip);
   if (load_flag(skip)) return;
   const double s = bscale ? *bscale : 1.0;
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < N; p += gridDim.x * blockDim.x) {
@@ -36,7 +42,13 @@ __global__ void presmooth_kernel(int N, const Tin* __restrict__ b, const double*
 // FP32 in and out, all arrays 16-byte aligned: runs of 4 (the tail of N mod 4 elementwise).
 __global__ void presmooth4_kernel(int N, const float* __restrict__ b, const double* __restrict__ bscale,
                                   const float* __restrict__ dinv, float* __restrict__ x, float* __restrict__ bcopy,
-                                  const int* __restrict__ skip) {
+                                  const int* __restrict__ skip, long long zoff) {
+  FDE_ZSHIFT(b);
+  FDE_ZSHIFT(bscale);
+  FDE_ZSHIFT(dinv);
+  FDE_ZSHIFT(x);
+  FDE_ZSHIFT(bcopy);
+  FDE_ZSHIFT(skip);
   if (load_flag(skip)) return;
   const double s = bscale ? *bscale : 1.0;
   const int N4 = N >> 2;
@@ -63,13 +75,13 @@ hipError_t launch_presmooth(int N, const Tin* b, const double* bscale, const R* 
     const uintptr_t a = reinterpret_cast<uintptr_t>(b) | reinterpret_cast<uintptr_t>(dinv) |
                         reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(bcopy);
     if (a % 16 == 0) {
-      hipLaunchKernelGGL(presmooth4_kernel, dim3(grid_for((size_t)(N + 3) / 4)), dim3(kBlock), 0, st, N, b, bscale,
-                         dinv, x, bcopy, skip);
+      hipLaunchKernelGGL(presmooth4_kernel, dim3(grid_for((size_t)(N + 3) / 4), 1, batch_nz()), dim3(kBlock), 0, st, N,
+                         b, bscale, dinv, x, bcopy, skip, batch_zoff());
       return hipGetLastError();
     }
   }
-  hipLaunchKernelGGL((presmooth_kernel<R, Tin>), dim3(grid_for(N)), dim3(kBlock), 0, st, N, b, bscale,
-                     dinv, x, bcopy, skip);
+  hipLaunchKernelGGL((presmooth_kernel<R, Tin>), dim3(grid_for(N), 1, batch_nz()), dim3(kBlock), 0, st, N, b, bscale,
+                     dinv, x, bcopy, skip, batch_zoff());
   return hipGetLastError();
 }
 
@@ -79,7 +91,13 @@ hipError_t launch_presmooth(int N, const Tin* b, const double* bscale, const R* 
 // One coarse row J per blockIdx.y; coarse point I reads fine rows 2J..2J+2, columns 2I..2I+2.
 template <typename R>
 __global__ void restrict_kernel(int n1, int n2, const R* __restrict__ r, R* __restrict__ rc,
-                                const R* __restrict__ dinv_c, R* __restrict__ xc, const int* __restrict__ skip) {
+                                const R* __restrict__ dinv_c, R* __restrict__ xc, const int* __restrict__ skip,
+                                long long zoff) {
+  FDE_ZSHIFT(r);
+  FDE_ZSHIFT(rc);
+  FDE_ZSHIFT(dinv_c);
+  FDE_ZSHIFT(xc);
+  FDE_ZSHIFT(skip);
   const int skipv = load_flag(skip);  // waited for after the loads below are issued
   const int k1 = (n1 - 1) / 2;
   const int J = blockIdx.y;
@@ -105,8 +123,9 @@ hipError_t launch_restrict(int n1, int n2, const R* r, R* rc, const R* dinv_c, R
   if (xc && !dinv_c) return hipErrorInvalidValue;
   const int k1 = (n1 - 1) / 2, k2 = (n2 - 1) / 2;
   if (k1 < 1 || k2 < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((restrict_kernel<R>), dim3(ceil_div(k1, kBlock), k2), dim3(kBlock), 0, st, n1, n2, r, rc,
-                     dinv_c, xc, skip);
+  if (k2 > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((restrict_kernel<R>), dim3(ceil_div(k1, kBlock), k2, batch_nz()), dim3(kBlock), 0, st, n1, n2, r,
+                     rc, dinv_c, xc, skip, batch_zoff());
   return hipGetLastError();
 }
 
@@ -139,7 +158,10 @@ __device__ __forceinline__ void coarse_nbrs(int f, int k, int* c, float* w, int*
 // of e[c-1] and e[c].  One fine row per blockIdx.y, so the row weights are uniform per workgroup.
 template <typename R>
 __global__ void prolong_kernel(int n1, int n2, const R* __restrict__ e, R* __restrict__ x,
-                               const int* __restrict__ skip) {
+                               const int* __restrict__ skip, long long zoff) {
+  FDE_ZSHIFT(e);
+  FDE_ZSHIFT(x);
+  FDE_ZSHIFT(skip);
   const int skipv = load_flag(skip);  // waited for after the loads below are issued
   const int k1 = (n1 - 1) / 2, k2 = (n2 - 1) / 2;
   const int j = blockIdx.y;
@@ -159,31 +181,36 @@ __global__ void prolong_kernel(int n1, int n2, const R* __restrict__ e, R* __res
 template <typename R>
 hipError_t launch_prolong(int n1, int n2, const R* e, R* x, const int* skip, hipStream_t st) {
   if (n1 < 3 || n2 < 3) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((prolong_kernel<R>), dim3(ceil_div(n1, kBlock), n2), dim3(kBlock), 0, st, n1, n2, e, x,
-                     skip);
+  if (n2 > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((prolong_kernel<R>), dim3(ceil_div(n1, kBlock), n2, batch_nz()), dim3(kBlock), 0, st, n1, n2, e, x,
+                     skip, batch_zoff());
   return hipGetLastError();
 }
 
 // ---- elementwise helpers ----------------------------------------------------------------------
 template <typename Tout, typename Tin>
-__global__ void convert_kernel(size_t N, const Tin* __restrict__ in, Tout* __restrict__ out) {
+__global__ void convert_kernel(size_t N, const Tin* __restrict__ in, Tout* __restrict__ out, long long zoff) {
+  FDE_ZSHIFT(in);
+  FDE_ZSHIFT(out);
   for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < N; p += (size_t)gridDim.x * blockDim.x)
     out[p] = (Tout)in[p];
 }
 template <typename Tout, typename Tin>
 hipError_t launch_convert(size_t N, const Tin* in, Tout* out, hipStream_t st) {
-  hipLaunchKernelGGL((convert_kernel<Tout, Tin>), dim3(grid_for(N)), dim3(kBlock), 0, st, N, in, out);
+  hipLaunchKernelGGL((convert_kernel<Tout, Tin>), dim3(grid_for(N), 1, batch_nz()), dim3(kBlock), 0, st, N, in, out,
+                     batch_zoff());
   return hipGetLastError();
 }
 
 template <typename R>
-__global__ void fill_kernel(size_t N, R* __restrict__ out, R v) {
+__global__ void fill_kernel(size_t N, R* __restrict__ out, R v, long long zoff) {
+  FDE_ZSHIFT(out);
   for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < N; p += (size_t)gridDim.x * blockDim.x)
     out[p] = v;
 }
 template <typename R>
 hipError_t launch_fill(size_t N, R* out, R v, hipStream_t st) {
-  hipLaunchKernelGGL((fill_kernel<R>), dim3(grid_for(N)), dim3(kBlock), 0, st, N, out, v);
+  hipLaunchKernelGGL((fill_kernel<R>), dim3(grid_for(N), 1, batch_nz()), dim3(kBlock), 0, st, N, out, v, batch_zoff());
   return hipGetLastError();
 }
 
@@ -428,7 +455,17 @@ template <typename R>
 __global__ __launch_bounds__(kTileThreads) void tile_resid_restrict_kernel(
     int n1, int n2, const R* __restrict__ x, const R* __restrict__ b, const R* __restrict__ dpm,
     const R* __restrict__ epm, const R* __restrict__ swx, const R* __restrict__ swy, R* __restrict__ bc,
-    const R* __restrict__ dinv_c, R* __restrict__ xcout, const int* __restrict__ skip) {
+    const R* __restrict__ dinv_c, R* __restrict__ xcout, const int* __restrict__ skip, long long zoff) {
+  FDE_ZSHIFT(x);
+  FDE_ZSHIFT(b);
+  FDE_ZSHIFT(dpm);
+  FDE_ZSHIFT(epm);
+  FDE_ZSHIFT(swx);
+  FDE_ZSHIFT(swy);
+  FDE_ZSHIFT(bc);
+  FDE_ZSHIFT(dinv_c);
+  FDE_ZSHIFT(xcout);
+  FDE_ZSHIFT(skip);
   extern __shared__ unsigned char smem_raw[];
   R* xr = reinterpret_cast<R*>(smem_raw);  // kTileRF x n1
   R* xc = xr + kTileRF * n1;               // n2 x kTileRF
@@ -482,7 +519,17 @@ template <typename R, bool PRO>
 __global__ __launch_bounds__(kTileThreads) void tile_jacobi_kernel(
     int n1, int n2, const R* __restrict__ x, const R* __restrict__ e, const R* __restrict__ b,
     const R* __restrict__ dpm, const R* __restrict__ epm, const R* __restrict__ dinv, const R* __restrict__ swx,
-    const R* __restrict__ swy, R* __restrict__ xout, const int* __restrict__ skip) {
+    const R* __restrict__ swy, R* __restrict__ xout, const int* __restrict__ skip, long long zoff) {
+  FDE_ZSHIFT(x);
+  FDE_ZSHIFT(e);
+  FDE_ZSHIFT(b);
+  FDE_ZSHIFT(dpm);
+  FDE_ZSHIFT(epm);
+  FDE_ZSHIFT(dinv);
+  FDE_ZSHIFT(swx);
+  FDE_ZSHIFT(swy);
+  FDE_ZSHIFT(xout);
+  FDE_ZSHIFT(skip);
   extern __shared__ unsigned char smem_raw[];
   const int k1 = (n1 - 1) / 2, k2 = (n2 - 1) / 2;
   R* xr = reinterpret_cast<R*>(smem_raw);  // kTileJ x n1
@@ -584,8 +631,9 @@ hipError_t launch_tile_resid_restrict(int n1, int n2, const R* x, const R* b, co
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((tile_resid_restrict_kernel<R>), dim3(ceil_div(k1, kTileRC), ceil_div(k2, kTileRC)),
-                     dim3(kTileThreads), bytes, st, n1, n2, x, b, dpm, epm, swx, swy, bc, dinv_c, xc, skip);
+  hipLaunchKernelGGL((tile_resid_restrict_kernel<R>), dim3(ceil_div(k1, kTileRC), ceil_div(k2, kTileRC), batch_nz()),
+                     dim3(kTileThreads), bytes, st, n1, n2, x, b, dpm, epm, swx, swy, bc, dinv_c, xc, skip,
+                     batch_zoff());
   return hipGetLastError();
 }
 
@@ -598,8 +646,9 @@ static hipError_t launch_tile_jacobi_t(int n1, int n2, const R* x, const R* e, c
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (er != hipSuccess) return er;
   }
-  hipLaunchKernelGGL((tile_jacobi_kernel<R, PRO>), dim3(ceil_div(n1, kTileJ), ceil_div(n2, kTileJ)),
-                     dim3(kTileThreads), bytes, st, n1, n2, x, e, b, dpm, epm, dinv, swx, swy, xout, skip);
+  hipLaunchKernelGGL((tile_jacobi_kernel<R, PRO>), dim3(ceil_div(n1, kTileJ), ceil_div(n2, kTileJ), batch_nz()),
+                     dim3(kTileThreads), bytes, st, n1, n2, x, e, b, dpm, epm, dinv, swx, swy, xout, skip,
+                     batch_zoff());
   return hipGetLastError();
 }
 
@@ -701,7 +750,21 @@ __device__ void coarse_jacobi(const CoarseView<R>& cv, const CoarseLds<R>& s) {
 template <typename R, int NL>
 __global__ __launch_bounds__(1024) void coarse_vcycle_kernel(CoarseView<R> cv, const R* __restrict__ b_in,
                                                              R* __restrict__ x_out,
-                                                             const int* __restrict__ skip) {
+                                                             const int* __restrict__ skip, long long zoff) {
+  FDE_ZSHIFT(b_in);
+  FDE_ZSHIFT(x_out);
+  FDE_ZSHIFT(skip);
+  if (zoff) {
+    static_for<0, NL>([&](auto lc) {
+      constexpr int l = decltype(lc)::value;
+      FDE_ZSHIFT(cv.dpm[l]);
+      FDE_ZSHIFT(cv.epm[l]);
+      FDE_ZSHIFT(cv.dinv[l]);
+      FDE_ZSHIFT(cv.swx[l]);
+      FDE_ZSHIFT(cv.swy[l]);
+    });
+    FDE_ZSHIFT(cv.inv);
+  }
   extern __shared__ unsigned char smem_raw[];
   R* base = reinterpret_cast<R*>(smem_raw);
   const CoarseLds<R> s = coarse_carve<R, NL>(cv, base);
@@ -832,7 +895,8 @@ static hipError_t launch_coarse_vcycle_n(const CoarseView<R>& cv, const R* b, R*
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((coarse_vcycle_kernel<R, NL>), dim3(1), dim3(1024), bytes, st, cv, b, x, skip);
+  hipLaunchKernelGGL((coarse_vcycle_kernel<R, NL>), dim3(1, 1, batch_nz()), dim3(1024), bytes, st, cv, b, x, skip,
+                     batch_zoff());
   return hipGetLastError();
 }
 
@@ -1006,7 +1070,11 @@ hipError_t launch_coarse_invert(const CoarseView<R>& cv, const double* dense, do
 
 template <typename R>
 __global__ void coarse_solve_kernel(int Nc, const double* __restrict__ inv, const R* __restrict__ b,
-                                    R* __restrict__ x, const int* __restrict__ skip) {
+                                    R* __restrict__ x, const int* __restrict__ skip, long long zoff) {
+  FDE_ZSHIFT(inv);
+  FDE_ZSHIFT(b);
+  FDE_ZSHIFT(x);
+  FDE_ZSHIFT(skip);
   if (skip && *skip) return;
   for (int p = threadIdx.x; p < Nc; p += blockDim.x) {
     double acc = 0.0;
@@ -1016,7 +1084,8 @@ __global__ void coarse_solve_kernel(int Nc, const double* __restrict__ inv, cons
 }
 template <typename R>
 hipError_t launch_coarse_solve(int Nc, const double* inv, const R* b, R* x, const int* skip, hipStream_t st) {
-  hipLaunchKernelGGL((coarse_solve_kernel<R>), dim3(1), dim3(256), 0, st, Nc, inv, b, x, skip);
+  hipLaunchKernelGGL((coarse_solve_kernel<R>), dim3(1, 1, batch_nz()), dim3(256), 0, st, Nc, inv, b, x, skip,
+                     batch_zoff());
   return hipGetLastError();
 }
 

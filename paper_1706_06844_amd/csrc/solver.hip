@@ -25,9 +25,17 @@ namespace {
 
 thread_local std::string g_global_error;
 
+// A fixed device region from which a handle carves all of its buffers in allocation order (the slot
+// of a batched group): handles of one shape built in equal slots get identical layouts.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+};
+
 struct DevAlloc {
   std::vector<void*> ptrs;
   size_t bytes = 0;
+  Arena* arena = nullptr;  // carve from this region instead of hipMalloc (never freed one by one)
   ~DevAlloc() { reset(); }
   void reset() {
     for (void* p : ptrs) (void)hipFree(p);
@@ -37,6 +45,13 @@ struct DevAlloc {
   template <typename T>
   T* get(size_t n) {
     if (n == 0) n = 1;
+    if (arena) {
+      const size_t off = (arena->used + 255) / 256 * 256;
+      if (off + n * sizeof(T) > arena->cap) return nullptr;
+      arena->used = off + n * sizeof(T);
+      bytes += n * sizeof(T);
+      return reinterpret_cast<T*>(arena->base + off);
+    }
     void* p = nullptr;
     if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) return nullptr;
     ptrs.push_back(p);
@@ -229,6 +244,7 @@ struct fde_handle {
   double palpha = 0, pbeta = 0;
   DevAlloc mem;
   DevAlloc hier_mem;  // rebuilt on coefficient updates
+  Arena arena;        // the slot of a batched group (mem and hier_mem carve from it), or unused
   // outer FP64 operators: cur = left-hand side level t^(m), prev = explicit level t^(m-1)
   Outer cur, prev;
   bool prev_aliases_cur = true;
@@ -500,12 +516,17 @@ void tune_cache_append(int n1, int n2, int bytes, bool direct) {
   }
 }
 
-// True if the level has to be timed now; otherwise *direct holds the cached or static choice.
-bool tune_level(int n1, int n2, int bytes, bool* direct) {
+// Levels the tuner decides (FDE_AUTOTUNE not 0 and the larger side in range).
+bool tune_range(int n1, int n2) {
   const int mx = std::max(n1, n2);
   if (mx <= one_wg_max() || mx > kDirectTuneMax) return false;
   const char* e = std::getenv("FDE_AUTOTUNE");
-  if (e && e[0] == '0') return false;
+  return !(e && e[0] == '0');
+}
+
+// True if the level has to be timed now; otherwise *direct holds the cached or static choice.
+bool tune_level(int n1, int n2, int bytes, bool* direct) {
+  if (!tune_range(n1, n2)) return false;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   tune_cache_load();
   auto it = g_tune_direct.find({n1, n2, bytes});
@@ -701,8 +722,11 @@ std::unique_ptr<Hierarchy<R>> build_hierarchy(fde_handle* h) {
       L.dinv = dalloc<R>(m, N);
       HIPCHECK(launch_diag<R>((int)N, L.dpm, L.epm, L.sx * h->pwa[1], L.sy * h->pwb[1], p.omega, L.dinv, nullptr, st));
       L.direct = std::max(n1, n2) <= direct_op_max(sizeof(R));
-      const bool tune = !galerkin && tune_level(n1, n2, (int)sizeof(R), &L.direct);
-      if (L.direct || tune) {
+      // a level the tuner may time holds the buffers of both variants, so that its layout does not
+      // depend on whether this hierarchy timed it or found the choice cached
+      const bool tunable = !galerkin && tune_range(n1, n2);
+      const bool tune = tunable && tune_level(n1, n2, (int)sizeof(R), &L.direct);
+      if (L.direct || tunable) {
         std::vector<double> sx(n1 + 1), sy(n2 + 1);
         for (int k = 0; k <= n1; ++k) sx[k] = L.sx * h->pwa[k];
         for (int k = 0; k <= n2; ++k) sy[k] = L.sy * h->pwb[k];
@@ -711,13 +735,13 @@ std::unique_ptr<Hierarchy<R>> build_hierarchy(fde_handle* h) {
       }
       // FFT levels need symbols and twiddles; so does the fine level of a Galerkin hierarchy, whose
       // transforms every coarse level reuses
-      if (!L.direct || tune || (galerkin && l == 0)) {
+      if (!L.direct || tunable || (galerkin && l == 0)) {
         L.lam_x = upload<R>(m, symbol_host(h->pwa, n1, L.L1, L.sx), st);
         L.lam_y = upload<R>(m, symbol_host(h->pwb, n2, L.L2, L.sy), st);
         L.tw_x = twiddles<R>(*H, m, L.L1, st);
         L.tw_y = twiddles<R>(*H, m, L.L2, st);
       }
-      if (!L.direct || tune) L.ay = dalloc<R>(m, N);
+      if (!L.direct || tunable) L.ay = dalloc<R>(m, N);
       if (tune) L.direct = time_direct_vs_fft<R>(h, L);
       L.tiled = L.direct && !L.mfma && std::min(n1, n2) > p.coarsest_n && tile_lds_fits<R>(n1, n2);
       if (std::is_same<R, float>::value && p.precision == FDE_MIXED_BF16GEMM && !L.direct) {
@@ -939,7 +963,7 @@ void vcycle_top(fde_handle* h, Hierarchy<R>& H, const Tv* v, const double* s, R*
   timed(h, FDE_KFAM_TRANSFER, pb, [&] { return launch_presmooth<R, Tv>(N, v, s, L0.dinv, z, L0.b, skip, h->stream); });
   if (h->p.nu_pre == 0) HIPCHECK(launch_fill<R>(L0.N(), z, R(0), h->stream));
   R* res = vcycle_from<R>(h, H, 0, z, skip, false);
-  if (res != z) HIPCHECK(hipMemcpyAsync(z, res, L0.N() * sizeof(R), hipMemcpyDeviceToDevice, h->stream));
+  if (res != z) HIPCHECK((launch_convert<R, R>(L0.N(), res, z, h->stream)));
 }
 
 // ---- flexible GMRES ----------------------------------------------------------------------------
@@ -1016,7 +1040,8 @@ void start_solve(fde_handle* h, const double* b) {
 void restart_residual(fde_handle* h, const double* b, const double* x) {
   const size_t N = h->N;
   const OpView<double> op = h->cur.view(h->tw64_x, h->tw64_y, h->n1, h->n2, h->L1, h->L2);
-  op_apply<double, double>(h, true, op, x, h->ay64, h->V, EP_RESID, b, nullptr, 0.0, nullptr);
+  // an idle slot of a batched group skips it (the flag is 0 for every other solve)
+  op_apply<double, double>(h, true, op, x, h->ay64, h->V, EP_RESID, b, nullptr, 0.0, &h->st->idle);
   if (h->basis16())
     cgs<bf16_t, float>(h, CGS_RESNORM, 0, h->V16, h->W32, h->V16, h->V, N * (sizeof(double) + sizeof(float) + 2.0));
   else if (h->cyc32())
@@ -1173,6 +1198,10 @@ void drop_graph(fde_handle* h) {
   h->as.graph = nullptr;
 }
 
+// fde_setup, optionally carving every buffer from a fixed region (a slot of a batched group)
+int setup_impl(const fde_problem* pin, const double* dp, const double* dm, const double* ep, const double* em,
+               void* stream, const Arena* ar, fde_handle** out);
+
 }  // namespace
 
 namespace fde {
@@ -1239,6 +1268,80 @@ int async_poll(fde_handle* h, int* finished, fde_stats* stats) {
 
 const double* async_result(const fde_handle* h) { return h ? h->as.xsol : nullptr; }
 
+// ---- batched groups ---------------------------------------------------------------------------------
+int group_setup(const fde_problem* p, const double* dp, const double* dm, const double* ep, const double* em,
+                hipStream_t stream, void* base, size_t cap, fde_handle** out) {
+  Arena a;
+  a.base = static_cast<char*>(base);
+  a.cap = cap;
+  return setup_impl(p, dp, dm, ep, em, stream, &a, out);
+}
+
+long long group_state_offset(const fde_handle* h) {
+  return reinterpret_cast<const char*>(h->st) - h->arena.base;
+}
+
+int group_step_start(fde_handle* h, const double* u_prev, int nsrc, const double* phi, const double* const* S) {
+  if (!h || !u_prev || !h->arena.base) return set_err(h, FDE_EINVAL, "bad arguments");
+  if (nsrc < 0 || nsrc > kMaxSrc || (nsrc > 0 && (!phi || !S))) return set_err(h, FDE_EINVAL, "bad source list");
+  return guarded(h, [&]() -> int {
+    SrcTerms src{};
+    src.n = nsrc;
+    for (int k = 0; k < nsrc; ++k) {
+      if (!S[k]) throw FdeError{FDE_EINVAL, "source field is NULL"};
+      src.phi[k] = phi[k];
+      src.S[k] = S[k];
+    }
+    const OpView<double> op = h->prev.view(h->tw64_x, h->tw64_y, h->n1, h->n2, h->L1, h->L2);
+    op_apply<double, double>(h, true, op, u_prev, h->ay64, h->rhs, EP_RHS, nullptr, &src, h->p.tau, nullptr);
+    HIPCHECK(launch_fill<double>(h->N, h->as.xsol, 0.0, h->stream));
+    start_solve(h, h->rhs);
+    return FDE_OK;
+  });
+}
+
+int group_capture_cycle(fde_handle* h, int nz, long long zoff, hipGraph_t* graph, hipGraphExec_t* gexec) {
+  if (!h || !h->arena.base || nz < 1) return set_err(h, FDE_EINVAL, "bad arguments");
+  return guarded(h, [&]() -> int {
+    BatchScope bs(nz, zoff);
+    HIPCHECK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    try {
+      if (h->fp32()) cycle_body<float>(h, *h->h32);
+      else cycle_body<double>(h, *h->h64);
+    } catch (...) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(h->stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    HIPCHECK(hipStreamEndCapture(h->stream, graph));
+    HIPCHECK(hipGraphInstantiate(gexec, *graph, nullptr, nullptr, 0));
+    return FDE_OK;
+  });
+}
+
+int group_step_result(fde_handle* h, const GmresState& s, int cycles, int* finished, fde_stats* stats) {
+  *finished = 0;
+  const bool bad = !std::isfinite(s.resnorm);
+  if (!(s.conv || s.iters >= h->p.maxit || bad)) return FDE_OK;
+  *finished = 1;
+  if (stats) {
+    stats->iters = s.iters;
+    stats->restarts = cycles - 1;
+    stats->converged = s.conv;
+    stats->reorth_steps = s.nreorth;
+    stats->relres_true = s.bnorm > 0 ? s.resnorm / s.bnorm : 0.0;
+    stats->relres_est = s.bnorm > 0 ? s.est / s.bnorm : 0.0;
+  }
+  if (bad) return set_err(h, FDE_ENONFINITE, "the iterate became non-finite");
+  if (!s.conv) return set_err(h, FDE_ENOCONV, "iteration limit reached before the tolerance");
+  return FDE_OK;
+}
+
+bool group_eligible(const fde_problem* p, int max_n) {
+  return p->precision != FDE_MIXED_BF16GEMM && p->mg_variant == FDE_MG_GEOMETRIC && std::max(p->n1, p->n2) <= max_n;
+}
+
 // Device bytes of a handle for problem p (defaults filled), following the allocations of fde_setup,
 // the hierarchy build and the asynchronous solve; 0 if p is invalid.
 size_t footprint_bytes(const fde_problem* pin) {
@@ -1268,6 +1371,7 @@ size_t footprint_bytes(const fde_problem* pin) {
   while (true) {
     const double Nl = (double)a1 * a2;
     const bool direct = std::max(a1, a2) <= direct_op_max(f32 ? 4 : 8);
+    const bool tunable = !gal && tune_range(a1, a2);
     const bool one_wg = !gal && std::max(a1, a2) <= one_wg_max();
     if (gal && l > 0) {
       b += 4.0 * a2 * p.n1 * R + 4.0 * p.n2 * a1 * R + 2.0 * Nl * R;  // fields, dinv, qx/qy (small)
@@ -1275,8 +1379,8 @@ size_t footprint_bytes(const fde_problem* pin) {
     } else {
       if (l > 0 || f32) b += 4 * Nl * R;
       b += Nl * R;
-      if (!direct || (gal && l == 0)) b += 4.0 * (2 * (a1 + 1) + 2 * (a2 + 1)) * R;
-      if (!direct) b += Nl * R;
+      if (!direct || tunable || (gal && l == 0)) b += 4.0 * (2 * (a1 + 1) + 2 * (a2 + 1)) * R;
+      if (!direct || tunable) b += Nl * R;
       if (f32 && p.precision == FDE_MIXED_BF16GEMM && !direct)
         b += 2.0 * 1024 * (mfma_table_entries(a1) + mfma_table_entries(a2));
     }
@@ -1346,6 +1450,14 @@ const char* fde_last_error(const fde_handle* h) { return h ? h->err.c_str() : g_
 
 int fde_setup(const fde_problem* pin, const double* dp, const double* dm, const double* ep, const double* em,
               void* stream, fde_handle** out) {
+  return setup_impl(pin, dp, dm, ep, em, stream, nullptr, out);
+}
+
+}  // extern "C"
+
+namespace {
+int setup_impl(const fde_problem* pin, const double* dp, const double* dm, const double* ep, const double* em,
+               void* stream, const Arena* ar, fde_handle** out) {
   if (!out) return set_err(nullptr, FDE_EINVAL, "out is NULL");
   *out = nullptr;
   if (!pin) return set_err(nullptr, FDE_EINVAL, "problem is NULL");
@@ -1355,6 +1467,11 @@ int fde_setup(const fde_problem* pin, const double* dp, const double* dm, const 
   if (validate(&p, &why) != FDE_OK) return set_err(nullptr, FDE_EINVAL, why);
   if (!dp || !dm || !ep || !em) return set_err(nullptr, FDE_EINVAL, "coefficient pointer is NULL");
   std::unique_ptr<fde_handle> h(new fde_handle());
+  if (ar) {
+    h->arena = *ar;
+    h->mem.arena = &h->arena;
+    h->hier_mem.arena = &h->arena;
+  }
   int rc = guarded(h.get(), [&]() -> int {
     h->p = p;
     h->stream = static_cast<hipStream_t>(stream);
@@ -1425,6 +1542,8 @@ int fde_setup(const fde_problem* pin, const double* dp, const double* dm, const 
     if (h->fp32()) h->Z = dalloc<float>(m, (size_t)p.restart * h->ldv);
     else h->Z = dalloc<double>(m, (size_t)p.restart * h->ldv);
     h->st = dalloc<GmresState>(m, 1);
+    // a slot of a batched group fixes every address at setup (the group's captured cycle uses them)
+    if (ar) h->as.xsol = dalloc<double>(m, N);
     h->cgs_grid = cgs_grid(N);
     h->partials = dalloc<double>(m, cgs_partials_len(N));
     HIPCHECK(hipHostMalloc((void**)&h->st_host, sizeof(GmresState), hipHostMallocDefault));
@@ -1463,6 +1582,9 @@ int fde_setup(const fde_problem* pin, const double* dp, const double* dm, const 
   *out = h.release();
   return FDE_OK;
 }
+}  // namespace
+
+extern "C" {
 
 void fde_destroy(fde_handle* h) {
   if (!h) return;
@@ -1477,6 +1599,7 @@ void fde_destroy(fde_handle* h) {
 
 int fde_update_coeffs(fde_handle* h, const double* dp, const double* dm, const double* ep, const double* em) {
   if (!h) return set_err(nullptr, FDE_EINVAL, "handle is NULL");
+  if (h->arena.base) return set_err(h, FDE_EINVAL, "handles of a batched group keep their coefficients");
   return guarded(h, [&]() -> int {
     check_fields(h, dp, dm, ep, em);
     if (h->prev_aliases_cur) {

@@ -40,7 +40,17 @@ template <typename R, typename Tin, int L, int MODE>
 __global__ __launch_bounds__((XCfg<R, L>::THREADS), FDE_XW) void toep_x_kernel(
     int n1, int n2, const Tin* x, const R* __restrict__ dpm, const R* __restrict__ mu,
     const R* __restrict__ twtab, const R* __restrict__ ay, const R* __restrict__ b,
-    const R* __restrict__ dinv, SrcTerms src, double tau, R* out, const int* __restrict__ skip) {
+    const R* __restrict__ dinv, SrcTerms src, double tau, R* out, const int* __restrict__ skip, long long zoff) {
+  // batched launches: every per-instance pointer (the source terms of EP_RHS are never batched)
+  FDE_ZSHIFT(x);
+  FDE_ZSHIFT(dpm);
+  FDE_ZSHIFT(mu);
+  FDE_ZSHIFT(twtab);
+  FDE_ZSHIFT(ay);
+  FDE_ZSHIFT(b);
+  FDE_ZSHIFT(dinv);
+  FDE_ZSHIFT(out);
+  FDE_ZSHIFT(skip);
   const int skipv = load_flag(skip);  // waited for after the row loads are issued
   using P = XPlan<R, L>;
   constexpr int E = P::E, T = P::T, S = XCfg<R, L>::S;
@@ -122,7 +132,13 @@ __global__ __launch_bounds__((XCfg<R, L>::THREADS), FDE_XW) void toep_x_kernel(
 template <typename R, typename Tin, int L>
 __global__ __launch_bounds__((YCfg<R, L>::THREADS), FDE_YW) void toep_y_kernel(
     int n1, int n2, const Tin* __restrict__ x, const R* __restrict__ epm, const R* __restrict__ mu,
-    const R* __restrict__ twtab, R* __restrict__ ay, int nstrips, const int* __restrict__ skip) {
+    const R* __restrict__ twtab, R* __restrict__ ay, int nstrips, const int* __restrict__ skip, long long zoff) {
+  FDE_ZSHIFT(x);
+  FDE_ZSHIFT(epm);
+  FDE_ZSHIFT(mu);
+  FDE_ZSHIFT(twtab);
+  FDE_ZSHIFT(ay);
+  FDE_ZSHIFT(skip);
   const int skipv = load_flag(skip);  // waited for after the column loads are issued
   using P = YPlan<R, L>;
   constexpr int E = P::E, T = P::T, S = YCfg<R, L>::S;
@@ -185,8 +201,8 @@ static hipError_t launch_y(const OpView<R>& op, const Tin* x, R* ay, const int* 
   constexpr int S = YCfg<R, L>::S;
   const int nstrips = ceil_div(op.n1, 2 * S);
   const int grid = 8 * ceil_div(nstrips, 8);
-  hipLaunchKernelGGL((toep_y_kernel<R, Tin, L>), dim3(grid), dim3(YCfg<R, L>::THREADS), 0, st, op.n1,
-                     op.n2, x, op.epm, op.mu_y, op.tw_y, ay, nstrips, skip);
+  hipLaunchKernelGGL((toep_y_kernel<R, Tin, L>), dim3(grid, 1, batch_nz()), dim3(YCfg<R, L>::THREADS), 0, st, op.n1,
+                     op.n2, x, op.epm, op.mu_y, op.tw_y, ay, nstrips, skip, batch_zoff());
   return hipGetLastError();
 }
 
@@ -194,8 +210,8 @@ template <typename R, typename Tin, int L, int MODE>
 static hipError_t launch_x_mode(const OpView<R>& op, const Tin* x, const R* ay, R* out, const R* b,
                                 const SrcTerms& src, double tau, const int* skip, hipStream_t st) {
   const int grid = ceil_div(op.n2, 2 * XCfg<R, L>::S);
-  hipLaunchKernelGGL((toep_x_kernel<R, Tin, L, MODE>), dim3(grid), dim3((XCfg<R, L>::THREADS)), 0, st, op.n1,
-                     op.n2, x, op.dpm, op.mu_x, op.tw_x, ay, b, op.dinv, src, tau, out, skip);
+  hipLaunchKernelGGL((toep_x_kernel<R, Tin, L, MODE>), dim3(grid, 1, batch_nz()), dim3((XCfg<R, L>::THREADS)), 0, st,
+                     op.n1, op.n2, x, op.dpm, op.mu_x, op.tw_x, ay, b, op.dinv, src, tau, out, skip, batch_zoff());
   return hipGetLastError();
 }
 
@@ -311,7 +327,16 @@ __global__ __launch_bounds__(512) void direct_op_kernel(int n1, int n2, const Ti
                                                         const R* __restrict__ swx, const R* __restrict__ swy,
                                                         const R* __restrict__ b, const R* __restrict__ dinv,
                                                         SrcTerms src, double tau, R* __restrict__ out,
-                                                        const int* __restrict__ skip) {
+                                                        const int* __restrict__ skip, long long zoff) {
+  FDE_ZSHIFT(x);
+  FDE_ZSHIFT(dpm);
+  FDE_ZSHIFT(epm);
+  FDE_ZSHIFT(swx);
+  FDE_ZSHIFT(swy);
+  FDE_ZSHIFT(b);
+  FDE_ZSHIFT(dinv);
+  FDE_ZSHIFT(out);
+  FDE_ZSHIFT(skip);
   if (skip && *skip) return;
   extern __shared__ unsigned char smem_raw[];
   R* xr = reinterpret_cast<R*>(smem_raw);  // n1
@@ -382,8 +407,8 @@ hipError_t launch_direct_op(int n1, int n2, const Tin* x, const R* dpm, const R*
 #define M_(MM)                                                                                                  \
   case MM:                                                                                                      \
     if constexpr (ModeSet<R, Tin>::ok(MM)) {                                                                    \
-      hipLaunchKernelGGL((direct_op_kernel<R, Tin, MM>), dim3(n2), dim3(threads), bytes, st, n1, n2, x, dpm, epm, \
-                         swx, swy, b, dinv, s, tau, out, skip);                                                 \
+      hipLaunchKernelGGL((direct_op_kernel<R, Tin, MM>), dim3(n2, 1, batch_nz()), dim3(threads), bytes, st, n1, n2, \
+                         x, dpm, epm, swx, swy, b, dinv, s, tau, out, skip, batch_zoff());                      \
       return hipGetLastError();                                                                                 \
     } else {                                                                                                    \
       return hipErrorInvalidValue;                                                                              \

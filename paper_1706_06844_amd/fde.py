@@ -240,6 +240,11 @@ def fde_batch_destroy(b: Batch) -> None:
     b.close()
 
 
+def fde_batch_set_grouping(b: Batch, max_n: int, slots: int) -> None:
+    """Requests of one shape with max(n1, n2) <= max_n share a group of `slots` slots (0 turns it off)."""
+    _check(_lib().fde_batch_set_grouping(b.ptr, int(max_n), int(slots)))
+
+
 def fde_batch_admit(b: Batch, problem: fde_problem, dp, dm, ep, em, u0, nsteps: int, t0: float = 0.0,
                     coef: Sequence[float] = (), rate: Sequence[float] = (),
                     fields: Sequence[torch.Tensor] = ()) -> int:
