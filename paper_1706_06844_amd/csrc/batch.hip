@@ -11,12 +11,14 @@
 // on the other requests, so its result is the same alone and in the mix.
 //
 // Grouped mode (fde_batch_set_grouping): requests of one shape (sizes, precision, multigrid settings)
-// up to a size limit share a group: one device region cut into equal slots, one stream, and one
-// captured restart cycle whose every launch covers all slots (grid z = slot; the kernels shift their
-// pointers by the slot size).  A group cycle is issued while any member has a solve in flight; each
-// member starts its CN steps on its own (right-hand side, norm of b) between cycles.  A member whose
-// solve is finished, and an empty slot, are skipped by every kernel of the cycle (done / idle flags),
-// so each member runs exactly the arithmetic it runs alone.
+// up to a size limit share a group: one device region cut into equal slots and one stream.  The
+// group's restart cycle is captured once per z extent of a short ladder (1, 2, 3, 4, 6, 8, 12, ...,
+// and the slot count); before each cycle the host writes the slot offsets of the members that are
+// solving into a small device table and replays the smallest capture that holds them, so every kernel
+// of the cycle is one launch over exactly the solving members (plus at most a third of padding, whose
+// workgroups exit at once).  Each member starts its CN steps on its own (right-hand side, norm of b)
+// between cycles.  A member whose solve stops inside a cycle skips the rest of it (done flag), and a
+// slot without a member is marked idle, so each member runs exactly the arithmetic it runs alone.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -69,7 +71,15 @@ void release(Request& r) {
   r = Request{};
 }
 
-// A group: `nslots` slots of `slot_bytes` in one allocation, members by slot, the captured cycle.
+// One capture of the group cycle: z extent nz, launches carrying the pointers of slot `base`.
+struct CycleGraph {
+  int nz = 0;
+  int base = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+};
+
+// A group: `nslots` slots of `slot_bytes` in one allocation, members by slot, the captured cycles.
 struct Group {
   fde_problem shape{};
   int nslots = 0;
@@ -78,8 +88,9 @@ struct Group {
   hipStream_t stream = nullptr;
   std::vector<int> member;  // request id per slot, -1 if empty
   long long st_off = 0;     // offset of the solver state within a slot
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
+  std::vector<CycleGraph> cycles;  // by increasing nz; the last one has nz = nslots
+  long long* zt_dev = nullptr;     // slot offsets of the next cycle (nslots entries)
+  long long* zt_host = nullptr;    // pinned staging of zt_dev
   hipEvent_t ev = nullptr;
   GmresState* hst = nullptr;  // pinned: the states' host-read prefix of every slot after a cycle
   GmresState* idle = nullptr;  // pinned: the state written into an empty slot
@@ -95,10 +106,27 @@ bool same_shape(const fde_problem& a, const fde_problem& b) {
          a.omega == b.omega;
 }
 
+// The z extents a group's cycle is captured for: 1, 2, 3, 4, 6, 8, 12, 16, 24, ... below nslots,
+// then nslots (consecutive extents differ by at most 1.5x).
+std::vector<int> nz_ladder(int nslots) {
+  std::vector<int> v;
+  for (int a = 1; a < nslots; a *= 2) {
+    v.push_back(a);
+    if (a >= 2 && a + a / 2 < nslots) v.push_back(a + a / 2);
+  }
+  std::sort(v.begin(), v.end());
+  v.push_back(nslots);
+  return v;
+}
+
 void destroy_group(Group& g) {
   if (g.stream) (void)hipStreamSynchronize(g.stream);
-  if (g.gexec) (void)hipGraphExecDestroy(g.gexec);
-  if (g.graph) (void)hipGraphDestroy(g.graph);
+  for (CycleGraph& c : g.cycles) {
+    if (c.gexec) (void)hipGraphExecDestroy(c.gexec);
+    if (c.graph) (void)hipGraphDestroy(c.graph);
+  }
+  if (g.zt_dev) (void)hipFree(g.zt_dev);
+  if (g.zt_host) (void)hipHostFree(g.zt_host);
   if (g.ev) (void)hipEventDestroy(g.ev);
   if (g.hst) (void)hipHostFree(g.hst);
   if (g.idle) (void)hipHostFree(g.idle);
@@ -212,7 +240,9 @@ int fde_batch_admit(fde_batch* b, const fde_problem* p, const double* dp, const 
       if (hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking) != hipSuccess ||
           hipEventCreateWithFlags(&g.ev, hipEventDisableTiming) != hipSuccess ||
           hipHostMalloc((void**)&g.hst, sizeof(GmresState) * g.nslots, hipHostMallocDefault) != hipSuccess ||
-          hipHostMalloc((void**)&g.idle, sizeof(GmresState), hipHostMallocDefault) != hipSuccess) {
+          hipHostMalloc((void**)&g.idle, sizeof(GmresState), hipHostMallocDefault) != hipSuccess ||
+          hipHostMalloc((void**)&g.zt_host, sizeof(long long) * g.nslots, hipHostMallocDefault) != hipSuccess ||
+          hipMalloc(&g.zt_dev, sizeof(long long) * g.nslots) != hipSuccess) {
         destroy_group(g);
         return FDE_EDEVICE;
       }
@@ -238,17 +268,28 @@ int fde_batch_admit(fde_batch* b, const fde_problem* p, const double* dp, const 
       release(r);
       return rc;
     }
-    if (!g.gexec) {
-      // the first member (slot 0) lays out the slots: empty ones get the idle state, and the cycle of
-      // all slots is captured once
+    if (g.cycles.empty()) {
+      // the first member (slot 0) lays out the slots: empty ones get the idle state, and the cycle is
+      // captured for every z extent of the ladder, with slot 0's pointers
       g.st_off = group_state_offset(r.h);
       for (int s = 1; s < g.nslots; ++s)
         if (mark_idle(g, s) != hipSuccess) return fail(FDE_EDEVICE, "initialising the slots failed");
-      const int cr = group_capture_cycle(r.h, g.nslots, (long long)g.slot_bytes, &g.graph, &g.gexec);
-      if (cr != FDE_OK) {
-        b->err = fde_last_error(r.h);
-        release(r);
-        return cr;
+      for (int nz : nz_ladder(g.nslots)) {
+        CycleGraph c;
+        c.nz = nz;
+        c.base = si;
+        const int cr = group_capture_cycle(r.h, nz, g.zt_dev, &c.graph, &c.gexec);
+        if (cr != FDE_OK) {
+          b->err = fde_last_error(r.h);
+          for (CycleGraph& d : g.cycles) {
+            (void)hipGraphExecDestroy(d.gexec);
+            (void)hipGraphDestroy(d.graph);
+          }
+          g.cycles.clear();
+          release(r);
+          return cr;
+        }
+        g.cycles.push_back(c);
       }
     }
   } else {
@@ -291,7 +332,7 @@ int step_groups(fde_batch* b, int* active) {
   int completed = 0;
   for (int gi = 0; gi < (int)b->groups.size(); ++gi) {
     Group& g = b->groups[gi];
-    if (!g.arena || !g.gexec) continue;
+    if (!g.arena || g.cycles.empty()) continue;
     if (g.inflight) {
       const hipError_t q = hipEventQuery(g.ev);
       if (q == hipErrorNotReady) {
@@ -337,8 +378,8 @@ int step_groups(fde_batch* b, int* active) {
         if (r.state == RS_DONE) (void)mark_idle(g, s);
       }
     }
-    // start the steps of members that wait for one, then issue a cycle if any member solves
-    bool any = false;
+    // start the steps of members that wait for one, then issue a cycle over the members that solve
+    std::vector<int> run;
     for (int s = 0; s < g.nslots; ++s) {
       if (g.member[s] < 0) continue;
       Request& r = b->reqs.at(g.member[s]);
@@ -357,10 +398,19 @@ int step_groups(fde_batch* b, int* active) {
         r.state = RS_RUNNING;
         r.cycles = 0;
       }
-      if (r.state == RS_RUNNING) any = true;
+      if (r.state == RS_RUNNING) run.push_back(s);
     }
-    if (!any) continue;
-    if (hipGraphLaunch(g.gexec, g.stream) != hipSuccess ||
+    if (run.empty()) continue;
+    const CycleGraph* cg = &g.cycles.back();
+    for (const CycleGraph& c : g.cycles)
+      if (c.nz >= (int)run.size()) {
+        cg = &c;
+        break;
+      }
+    for (int z = 0; z < cg->nz; ++z)
+      g.zt_host[z] = z < (int)run.size() ? (long long)(run[z] - cg->base) * (long long)g.slot_bytes : kZSkip;
+    if (hipMemcpyAsync(g.zt_dev, g.zt_host, sizeof(long long) * cg->nz, hipMemcpyHostToDevice, g.stream) != hipSuccess ||
+        hipGraphLaunch(cg->gexec, g.stream) != hipSuccess ||
         hipMemcpy2DAsync(g.hst, sizeof(GmresState), g.arena + g.st_off, g.slot_bytes, kStatePrefix, g.nslots,
                          hipMemcpyDeviceToHost, g.stream) != hipSuccess ||
         hipEventRecord(g.ev, g.stream) != hipSuccess) {

@@ -265,28 +265,35 @@ hipError_t launch_update_x(size_t N, const Tz* Z, size_t ldz, double* x, int fir
 // ---- small helpers -----------------------------------------------------------------------------
 inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 // ---- batched launches ---------------------------------------------------------------------------
-// Instances of one shape whose device buffers are laid out identically, `zoff` bytes apart, can be
-// advanced by one launch: the grid's z dimension runs over the instances and every kernel of the
-// solve shifts each of its pointer arguments by blockIdx.z * zoff.  The launchers read the current
-// batch from this thread's context (1 instance, offset 0 outside a batched section).
+// Instances of one shape whose device buffers are laid out identically (equal slots of one region)
+// can be advanced by one launch: the grid's z dimension runs over a table of byte offsets, and every
+// kernel of the solve shifts each of its pointer arguments by its entry ztab[blockIdx.z] (the offset
+// of an instance's slot from the slot whose pointers the launch carries).  An entry kZSkip makes the
+// workgroups of that z exit at once (padding up to the launch's fixed z extent).  The launchers read
+// the current batch from this thread's context (1 instance, no table outside a batched section).
+constexpr long long kZSkip = (long long)0x8000000000000000ull;
 struct BatchCtx {
   int nz = 1;
-  long long zoff = 0;
+  const long long* ztab = nullptr;
 };
 inline thread_local BatchCtx g_batch;
 inline int batch_nz() { return g_batch.nz; }
-inline long long batch_zoff() { return g_batch.zoff; }
+inline const long long* batch_ztab() { return g_batch.ztab; }
 // Sets the batch for the lifetime of the object (restores the previous one).
 struct BatchScope {
   BatchCtx saved;
-  BatchScope(int nz, long long zoff) : saved(g_batch) { g_batch = BatchCtx{nz, zoff}; }
+  BatchScope(int nz, const long long* ztab) : saved(g_batch) { g_batch = BatchCtx{nz, ztab}; }
   ~BatchScope() { g_batch = saved; }
 };
 template <typename T>
 __device__ __forceinline__ T* zshift(T* p, long long zoff) {
-  return (p && zoff) ? reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(p) + (uintptr_t)((long long)blockIdx.z * zoff))
-                     : p;
+  return (p && zoff) ? reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(p) + (uintptr_t)zoff) : p;
 }
+// The first statement of a batched kernel: this workgroup's slot offset (a uniform scalar load of
+// the table, none outside a batch), or exit for a padding entry.
+#define FDE_ZBEGIN                                                  \
+  const long long zoff = ztab ? ztab[blockIdx.z] : 0ll;             \
+  if (zoff == kZSkip) return
 #define FDE_ZSHIFT(p) (p = zshift(p, zoff))
 
 // Reads a device flag (the skip flag of speculatively issued Arnoldi steps) with a vector load: the

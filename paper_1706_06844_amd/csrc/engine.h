@@ -32,9 +32,10 @@ int group_setup(const fde_problem* p, const double* dp, const double* dm, const 
 long long group_state_offset(const fde_handle* h);
 // Starts a CN step of one member on its stream: right-hand side, x = 0 and the norm of b (no cycle).
 int group_step_start(fde_handle* h, const double* u_prev, int nsrc, const double* phi, const double* const* S);
-// Captures one restart cycle of every slot as a graph: the handle of slot 0 issues the launches, each
-// with nz instances zoff bytes apart.
-int group_capture_cycle(fde_handle* h, int nz, long long zoff, hipGraph_t* graph, hipGraphExec_t* gexec);
+// Captures one restart cycle as a graph whose every launch has grid z extent nz: the launches carry
+// the pointers of h's slot, and workgroup z works on the slot ztab[z] bytes away (device table of nz
+// entries, read when the graph runs; kZSkip entries are padding).
+int group_capture_cycle(fde_handle* h, int nz, const long long* ztab, hipGraph_t* graph, hipGraphExec_t* gexec);
 // After a cycle: *finished = 1 if the member's solve stopped (stats filled, fde_step's return code).
 int group_step_result(fde_handle* h, const GmresState& s, int cycles, int* finished, fde_stats* stats);
 // Whether problems of this shape can be advanced by batched launches.

@@ -214,7 +214,8 @@ template <typename TB, typename TW, int MAXV, bool FUSED>
 __global__ __launch_bounds__(kCgsBlock) void cgs_kernel(int kind, int N, int nv, const TB* __restrict__ V,
                                                         size_t ldv, TW* __restrict__ w, TB* __restrict__ vout,
                                                         const double* __restrict__ src, GmresState* st,
-                                                        double* __restrict__ partials, long long zoff) {
+                                                        double* __restrict__ partials, const long long* __restrict__ ztab) {
+  FDE_ZBEGIN;
   FDE_ZSHIFT(V);
   FDE_ZSHIFT(w);
   FDE_ZSHIFT(vout);
@@ -482,7 +483,8 @@ __device__ void finalize_block(int kind, int nv, int G, const double* partials, 
 // last-workgroup ticket of the fused form) would serialise at the memory side.
 __global__ __launch_bounds__(kFinBlock) void cgs_finalize_kernel(int kind, int nv, int G,
                                                                  const double* __restrict__ partials,
-                                                                 GmresState* gst, long long zoff) {
+                                                                 GmresState* gst, const long long* __restrict__ ztab) {
+  FDE_ZBEGIN;
   FDE_ZSHIFT(partials);
   FDE_ZSHIFT(gst);
   __shared__ FinLds<kFinLds> F;
@@ -514,10 +516,10 @@ hipError_t launch_cgs_pass(int kind, size_t N, int nv, TB* V, size_t ldv, TW* w,
 #define L_(M)                                                                                              \
   if (fused)                                                                                               \
     hipLaunchKernelGGL((cgs_kernel<TB, TW, M, true>), dim3(grid, 1, batch_nz()), dim3(kCgsBlock), 0, s, kind, n, nv, \
-                       V, ldv, w, vout, src, st, partials, batch_zoff());                                   \
+                       V, ldv, w, vout, src, st, partials, batch_ztab());                                   \
   else                                                                                                     \
     hipLaunchKernelGGL((cgs_kernel<TB, TW, M, false>), dim3(grid, 1, batch_nz()), dim3(kCgsBlock), 0, s, kind, n, nv, \
-                       V, ldv, w, vout, src, st, partials, batch_zoff())
+                       V, ldv, w, vout, src, st, partials, batch_ztab())
   if (nv <= 4) { L_(4); }
   else if (nv <= 8) { L_(8); }
   else if (nv <= 12) { L_(12); }
@@ -540,7 +542,7 @@ hipError_t launch_cgs_finalize(int kind, int nv, double* partials, GmresState* s
   if (nv > kMaxRestart + 1 || cap < 1) return hipErrorInvalidValue;
   if (cgs_fused(nv, cap)) return hipErrorInvalidValue;  // the pass has combined its partials itself
   hipLaunchKernelGGL(cgs_finalize_kernel, dim3(1, 1, batch_nz()), dim3(kFinBlock), 0, s, kind, nv, cgs_pass_grid(nv, cap),
-                     partials, st, batch_zoff());
+                     partials, st, batch_ztab());
   return hipGetLastError();
 }
 
@@ -548,7 +550,8 @@ hipError_t launch_cgs_finalize(int kind, int nv, double* partials, GmresState* s
 template <typename Tz>
 __global__ __launch_bounds__(256) void update_x_kernel(size_t N, const Tz* __restrict__ Z, size_t ldz,
                                                        double* __restrict__ x, int first, GmresState* st,
-                                                       long long zoff) {
+                                                       const long long* __restrict__ ztab) {
+  FDE_ZBEGIN;
   FDE_ZSHIFT(Z);
   FDE_ZSHIFT(x);
   FDE_ZSHIFT(st);
@@ -584,7 +587,7 @@ hipError_t launch_update_x(size_t N, const Tz* Z, size_t ldz, double* x, int fir
   if (g > 2048) g = 2048;
   if (g < 1) g = 1;
   hipLaunchKernelGGL((update_x_kernel<Tz>), dim3((int)g, 1, batch_nz()), dim3(256), 0, s, N, Z, ldz, x, first, st,
-                     batch_zoff());
+                     batch_ztab());
   return hipGetLastError();
 }
 template hipError_t launch_update_x<double>(size_t, const double*, size_t, double*, int, GmresState*,

@@ -23,7 +23,8 @@ static inline int grid_for(size_t n, int per_block = kBlock) {
 template <typename R, typename Tin>
 __global__ void presmooth_kernel(int N, const Tin* __restrict__ b, const double* __restrict__ bscale,
                                  const R* __restrict__ dinv, R* __restrict__ x, R* __restrict__ bcopy,
-                                 const int* __restrict__ skip, long long zoff) {
+                                 const int* __restrict__ skip, const long long* __restrict__ ztab) {
+  FDE_ZBEGIN;
   FDE_ZSHIFT(b);
   FDE_ZSHIFT(bscale);
   FDE_ZSHIFT(dinv);
@@ -42,7 +43,8 @@ __global__ void presmooth_kernel(int N, const Tin* __restrict__ b, const double*
 // FP32 in and out, all arrays 16-byte aligned: runs of 4 (the tail of N mod 4 elementwise).
 __global__ void presmooth4_kernel(int N, const float* __restrict__ b, const double* __restrict__ bscale,
                                   const float* __restrict__ dinv, float* __restrict__ x, float* __restrict__ bcopy,
-                                  const int* __restrict__ skip, long long zoff) {
+                                  const int* __restrict__ skip, const long long* __restrict__ ztab) {
+  FDE_ZBEGIN;
   FDE_ZSHIFT(b);
   FDE_ZSHIFT(bscale);
   FDE_ZSHIFT(dinv);
@@ -76,12 +78,12 @@ hipError_t launch_presmooth(int N, const Tin* b, const double* bscale, const R* 
                         reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(bcopy);
     if (a % 16 == 0) {
       hipLaunchKernelGGL(presmooth4_kernel, dim3(grid_for((size_t)(N + 3) / 4), 1, batch_nz()), dim3(kBlock), 0, st, N,
-                         b, bscale, dinv, x, bcopy, skip, batch_zoff());
+                         b, bscale, dinv, x, bcopy, skip, batch_ztab());
       return hipGetLastError();
     }
   }
   hipLaunchKernelGGL((presmooth_kernel<R, Tin>), dim3(grid_for(N), 1, batch_nz()), dim3(kBlock), 0, st, N, b, bscale,
-                     dinv, x, bcopy, skip, batch_zoff());
+                     dinv, x, bcopy, skip, batch_ztab());
   return hipGetLastError();
 }
 
@@ -92,7 +94,8 @@ hipError_t launch_presmooth(int N, const Tin* b, const double* bscale, const R* 
 template <typename R>
 __global__ void restrict_kernel(int n1, int n2, const R* __restrict__ r, R* __restrict__ rc,
                                 const R* __restrict__ dinv_c, R* __restrict__ xc, const int* __restrict__ skip,
-                                long long zoff) {
+                                const long long* __restrict__ ztab) {
+  FDE_ZBEGIN;
   FDE_ZSHIFT(r);
   FDE_ZSHIFT(rc);
   FDE_ZSHIFT(dinv_c);
@@ -125,7 +128,7 @@ hipError_t launch_restrict(int n1, int n2, const R* r, R* rc, const R* dinv_c, R
   if (k1 < 1 || k2 < 1) return hipErrorInvalidValue;
   if (k2 > 65535) return hipErrorInvalidValue;
   hipLaunchKernelGGL((restrict_kernel<R>), dim3(ceil_div(k1, kBlock), k2, batch_nz()), dim3(kBlock), 0, st, n1, n2, r,
-                     rc, dinv_c, xc, skip, batch_zoff());
+                     rc, dinv_c, xc, skip, batch_ztab());
   return hipGetLastError();
 }
 
@@ -158,7 +161,8 @@ __device__ __forceinline__ void coarse_nbrs(int f, int k, int* c, float* w, int*
 // of e[c-1] and e[c].  One fine row per blockIdx.y, so the row weights are uniform per workgroup.
 template <typename R>
 __global__ void prolong_kernel(int n1, int n2, const R* __restrict__ e, R* __restrict__ x,
-                               const int* __restrict__ skip, long long zoff) {
+                               const int* __restrict__ skip, const long long* __restrict__ ztab) {
+  FDE_ZBEGIN;
   FDE_ZSHIFT(e);
   FDE_ZSHIFT(x);
   FDE_ZSHIFT(skip);
@@ -183,13 +187,14 @@ hipError_t launch_prolong(int n1, int n2, const R* e, R* x, const int* skip, hip
   if (n1 < 3 || n2 < 3) return hipErrorInvalidValue;
   if (n2 > 65535) return hipErrorInvalidValue;
   hipLaunchKernelGGL((prolong_kernel<R>), dim3(ceil_div(n1, kBlock), n2, batch_nz()), dim3(kBlock), 0, st, n1, n2, e, x,
-                     skip, batch_zoff());
+                     skip, batch_ztab());
   return hipGetLastError();
 }
 
 // ---- elementwise helpers ----------------------------------------------------------------------
 template <typename Tout, typename Tin>
-__global__ void convert_kernel(size_t N, const Tin* __restrict__ in, Tout* __restrict__ out, long long zoff) {
+__global__ void convert_kernel(size_t N, const Tin* __restrict__ in, Tout* __restrict__ out, const long long* __restrict__ ztab) {
+  FDE_ZBEGIN;
   FDE_ZSHIFT(in);
   FDE_ZSHIFT(out);
   for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < N; p += (size_t)gridDim.x * blockDim.x)
@@ -198,19 +203,20 @@ __global__ void convert_kernel(size_t N, const Tin* __restrict__ in, Tout* __res
 template <typename Tout, typename Tin>
 hipError_t launch_convert(size_t N, const Tin* in, Tout* out, hipStream_t st) {
   hipLaunchKernelGGL((convert_kernel<Tout, Tin>), dim3(grid_for(N), 1, batch_nz()), dim3(kBlock), 0, st, N, in, out,
-                     batch_zoff());
+                     batch_ztab());
   return hipGetLastError();
 }
 
 template <typename R>
-__global__ void fill_kernel(size_t N, R* __restrict__ out, R v, long long zoff) {
+__global__ void fill_kernel(size_t N, R* __restrict__ out, R v, const long long* __restrict__ ztab) {
+  FDE_ZBEGIN;
   FDE_ZSHIFT(out);
   for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < N; p += (size_t)gridDim.x * blockDim.x)
     out[p] = v;
 }
 template <typename R>
 hipError_t launch_fill(size_t N, R* out, R v, hipStream_t st) {
-  hipLaunchKernelGGL((fill_kernel<R>), dim3(grid_for(N), 1, batch_nz()), dim3(kBlock), 0, st, N, out, v, batch_zoff());
+  hipLaunchKernelGGL((fill_kernel<R>), dim3(grid_for(N), 1, batch_nz()), dim3(kBlock), 0, st, N, out, v, batch_ztab());
   return hipGetLastError();
 }
 
@@ -455,7 +461,8 @@ template <typename R>
 __global__ __launch_bounds__(kTileThreads) void tile_resid_restrict_kernel(
     int n1, int n2, const R* __restrict__ x, const R* __restrict__ b, const R* __restrict__ dpm,
     const R* __restrict__ epm, const R* __restrict__ swx, const R* __restrict__ swy, R* __restrict__ bc,
-    const R* __restrict__ dinv_c, R* __restrict__ xcout, const int* __restrict__ skip, long long zoff) {
+    const R* __restrict__ dinv_c, R* __restrict__ xcout, const int* __restrict__ skip, const long long* __restrict__ ztab) {
+  FDE_ZBEGIN;
   FDE_ZSHIFT(x);
   FDE_ZSHIFT(b);
   FDE_ZSHIFT(dpm);
@@ -519,7 +526,8 @@ template <typename R, bool PRO>
 __global__ __launch_bounds__(kTileThreads) void tile_jacobi_kernel(
     int n1, int n2, const R* __restrict__ x, const R* __restrict__ e, const R* __restrict__ b,
     const R* __restrict__ dpm, const R* __restrict__ epm, const R* __restrict__ dinv, const R* __restrict__ swx,
-    const R* __restrict__ swy, R* __restrict__ xout, const int* __restrict__ skip, long long zoff) {
+    const R* __restrict__ swy, R* __restrict__ xout, const int* __restrict__ skip, const long long* __restrict__ ztab) {
+  FDE_ZBEGIN;
   FDE_ZSHIFT(x);
   FDE_ZSHIFT(e);
   FDE_ZSHIFT(b);
@@ -633,7 +641,7 @@ hipError_t launch_tile_resid_restrict(int n1, int n2, const R* x, const R* b, co
   }
   hipLaunchKernelGGL((tile_resid_restrict_kernel<R>), dim3(ceil_div(k1, kTileRC), ceil_div(k2, kTileRC), batch_nz()),
                      dim3(kTileThreads), bytes, st, n1, n2, x, b, dpm, epm, swx, swy, bc, dinv_c, xc, skip,
-                     batch_zoff());
+                     batch_ztab());
   return hipGetLastError();
 }
 
@@ -648,7 +656,7 @@ static hipError_t launch_tile_jacobi_t(int n1, int n2, const R* x, const R* e, c
   }
   hipLaunchKernelGGL((tile_jacobi_kernel<R, PRO>), dim3(ceil_div(n1, kTileJ), ceil_div(n2, kTileJ), batch_nz()),
                      dim3(kTileThreads), bytes, st, n1, n2, x, e, b, dpm, epm, dinv, swx, swy, xout, skip,
-                     batch_zoff());
+                     batch_ztab());
   return hipGetLastError();
 }
 
@@ -750,7 +758,8 @@ __device__ void coarse_jacobi(const CoarseView<R>& cv, const CoarseLds<R>& s) {
 template <typename R, int NL>
 __global__ __launch_bounds__(1024) void coarse_vcycle_kernel(CoarseView<R> cv, const R* __restrict__ b_in,
                                                              R* __restrict__ x_out,
-                                                             const int* __restrict__ skip, long long zoff) {
+                                                             const int* __restrict__ skip, const long long* __restrict__ ztab) {
+  FDE_ZBEGIN;
   FDE_ZSHIFT(b_in);
   FDE_ZSHIFT(x_out);
   FDE_ZSHIFT(skip);
@@ -896,7 +905,7 @@ static hipError_t launch_coarse_vcycle_n(const CoarseView<R>& cv, const R* b, R*
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL((coarse_vcycle_kernel<R, NL>), dim3(1, 1, batch_nz()), dim3(1024), bytes, st, cv, b, x, skip,
-                     batch_zoff());
+                     batch_ztab());
   return hipGetLastError();
 }
 
@@ -1070,7 +1079,8 @@ hipError_t launch_coarse_invert(const CoarseView<R>& cv, const double* dense, do
 
 template <typename R>
 __global__ void coarse_solve_kernel(int Nc, const double* __restrict__ inv, const R* __restrict__ b,
-                                    R* __restrict__ x, const int* __restrict__ skip, long long zoff) {
+                                    R* __restrict__ x, const int* __restrict__ skip, const long long* __restrict__ ztab) {
+  FDE_ZBEGIN;
   FDE_ZSHIFT(inv);
   FDE_ZSHIFT(b);
   FDE_ZSHIFT(x);
@@ -1085,7 +1095,7 @@ __global__ void coarse_solve_kernel(int Nc, const double* __restrict__ inv, cons
 template <typename R>
 hipError_t launch_coarse_solve(int Nc, const double* inv, const R* b, R* x, const int* skip, hipStream_t st) {
   hipLaunchKernelGGL((coarse_solve_kernel<R>), dim3(1, 1, batch_nz()), dim3(256), 0, st, Nc, inv, b, x, skip,
-                     batch_zoff());
+                     batch_ztab());
   return hipGetLastError();
 }
 

@@ -1300,10 +1300,10 @@ int group_step_start(fde_handle* h, const double* u_prev, int nsrc, const double
   });
 }
 
-int group_capture_cycle(fde_handle* h, int nz, long long zoff, hipGraph_t* graph, hipGraphExec_t* gexec) {
+int group_capture_cycle(fde_handle* h, int nz, const long long* ztab, hipGraph_t* graph, hipGraphExec_t* gexec) {
   if (!h || !h->arena.base || nz < 1) return set_err(h, FDE_EINVAL, "bad arguments");
   return guarded(h, [&]() -> int {
-    BatchScope bs(nz, zoff);
+    BatchScope bs(nz, ztab);
     HIPCHECK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
     try {
       if (h->fp32()) cycle_body<float>(h, *h->h32);

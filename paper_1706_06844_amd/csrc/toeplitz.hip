@@ -40,7 +40,8 @@ template <typename R, typename Tin, int L, int MODE>
 __global__ __launch_bounds__((XCfg<R, L>::THREADS), FDE_XW) void toep_x_kernel(
     int n1, int n2, const Tin* x, const R* __restrict__ dpm, const R* __restrict__ mu,
     const R* __restrict__ twtab, const R* __restrict__ ay, const R* __restrict__ b,
-    const R* __restrict__ dinv, SrcTerms src, double tau, R* out, const int* __restrict__ skip, long long zoff) {
+    const R* __restrict__ dinv, SrcTerms src, double tau, R* out, const int* __restrict__ skip, const long long* __restrict__ ztab) {
+  FDE_ZBEGIN;
   // batched launches: every per-instance pointer (the source terms of EP_RHS are never batched)
   FDE_ZSHIFT(x);
   FDE_ZSHIFT(dpm);
@@ -132,7 +133,8 @@ __global__ __launch_bounds__((XCfg<R, L>::THREADS), FDE_XW) void toep_x_kernel(
 template <typename R, typename Tin, int L>
 __global__ __launch_bounds__((YCfg<R, L>::THREADS), FDE_YW) void toep_y_kernel(
     int n1, int n2, const Tin* __restrict__ x, const R* __restrict__ epm, const R* __restrict__ mu,
-    const R* __restrict__ twtab, R* __restrict__ ay, int nstrips, const int* __restrict__ skip, long long zoff) {
+    const R* __restrict__ twtab, R* __restrict__ ay, int nstrips, const int* __restrict__ skip, const long long* __restrict__ ztab) {
+  FDE_ZBEGIN;
   FDE_ZSHIFT(x);
   FDE_ZSHIFT(epm);
   FDE_ZSHIFT(mu);
@@ -202,7 +204,7 @@ static hipError_t launch_y(const OpView<R>& op, const Tin* x, R* ay, const int* 
   const int nstrips = ceil_div(op.n1, 2 * S);
   const int grid = 8 * ceil_div(nstrips, 8);
   hipLaunchKernelGGL((toep_y_kernel<R, Tin, L>), dim3(grid, 1, batch_nz()), dim3(YCfg<R, L>::THREADS), 0, st, op.n1,
-                     op.n2, x, op.epm, op.mu_y, op.tw_y, ay, nstrips, skip, batch_zoff());
+                     op.n2, x, op.epm, op.mu_y, op.tw_y, ay, nstrips, skip, batch_ztab());
   return hipGetLastError();
 }
 
@@ -211,7 +213,7 @@ static hipError_t launch_x_mode(const OpView<R>& op, const Tin* x, const R* ay, 
                                 const SrcTerms& src, double tau, const int* skip, hipStream_t st) {
   const int grid = ceil_div(op.n2, 2 * XCfg<R, L>::S);
   hipLaunchKernelGGL((toep_x_kernel<R, Tin, L, MODE>), dim3(grid, 1, batch_nz()), dim3((XCfg<R, L>::THREADS)), 0, st,
-                     op.n1, op.n2, x, op.dpm, op.mu_x, op.tw_x, ay, b, op.dinv, src, tau, out, skip, batch_zoff());
+                     op.n1, op.n2, x, op.dpm, op.mu_x, op.tw_x, ay, b, op.dinv, src, tau, out, skip, batch_ztab());
   return hipGetLastError();
 }
 
@@ -327,7 +329,8 @@ __global__ __launch_bounds__(512) void direct_op_kernel(int n1, int n2, const Ti
                                                         const R* __restrict__ swx, const R* __restrict__ swy,
                                                         const R* __restrict__ b, const R* __restrict__ dinv,
                                                         SrcTerms src, double tau, R* __restrict__ out,
-                                                        const int* __restrict__ skip, long long zoff) {
+                                                        const int* __restrict__ skip, const long long* __restrict__ ztab) {
+  FDE_ZBEGIN;
   FDE_ZSHIFT(x);
   FDE_ZSHIFT(dpm);
   FDE_ZSHIFT(epm);
@@ -408,7 +411,7 @@ hipError_t launch_direct_op(int n1, int n2, const Tin* x, const R* dpm, const R*
   case MM:                                                                                                      \
     if constexpr (ModeSet<R, Tin>::ok(MM)) {                                                                    \
       hipLaunchKernelGGL((direct_op_kernel<R, Tin, MM>), dim3(n2, 1, batch_nz()), dim3(threads), bytes, st, n1, n2, \
-                         x, dpm, epm, swx, swy, b, dinv, s, tau, out, skip, batch_zoff());                      \
+                         x, dpm, epm, swx, swy, b, dinv, s, tau, out, skip, batch_ztab());                      \
       return hipGetLastError();                                                                                 \
     } else {                                                                                                    \
       return hipErrorInvalidValue;                                                                              \
