@@ -78,6 +78,7 @@ def parse():
     ap.add_argument("--maxit", type=int, default=4000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c2", action="store_true", help="skip the C2 (511^2) GPU and oracle comparison")
+    ap.add_argument("--no-c4", action="store_true", help="skip the C4 (64 batched instances) keys")
     ap.add_argument("--cpu-sample-iters", type=int, default=24)
     ap.add_argument("--only", choices=["cycle16", "cycle", "mixed", "fp64", "bf16"], default=None)
     ap.add_argument("--workload", choices=["c3", "c4", "c5"], default="c3",
@@ -323,22 +324,20 @@ def admit(b, hr, precision, rtol, maxit):
     return fde.fde_batch_admit(b, s, *F, d(hr["u0"]), p.M, 0.0, hr["coef"], hr["rate"], [d(f) for f in hr["S"]])
 
 
-def run_c4(args):
-    """64 uneven instances (n in {127,255,511}, 8 CN steps, rtol 1e-9) resident together and stepped
-    as one batch, against the same instances run one after another; FP32 restart cycles as the
-    value, the FP32 preconditioner in FP64 cycles and plain FP64 beside it."""
+def c4_results(modes=("mixed", "fp64", "cycle"), ungrouped=True, sequential=True):
+    """C4: 64 uneven instances (n in {127,255,511}, 8 CN steps, rtol 1e-9) resident together.  Per
+    precision mode: grouped batching (one group per size; every kernel of a restart cycle launched
+    once over the solving members), optionally ungrouped batching (a stream and a graph per instance)
+    and the instances one after another; grouped results are checked bitwise against the others."""
     import torch
 
     import workloads
     from paper_1706_06844_amd import fde
 
+    precs = {"mixed": fde.FDE_MIXED_FP32, "fp64": fde.FDE_FP64, "cycle": fde.FDE_MIXED_FP32_CYCLE}
     probs = workloads.config_c4_instances(64, 4, 8)
     reqs = [host_request(p) for p in probs]
-    unknown_steps = sum(p.n1 * p.n2 * p.M for p in probs)
-    steps = sum(p.M for p in probs)
-    # grouped mode: one group per size, as many slots as instances of the most frequent size
     slots = max(sum(1 for p in probs if p.n1 == n) for n in {p.n1 for p in probs})
-    out = {}
 
     def batched(prec, grouped):
         # admission (resident setup, graph capture) outside the timed region
@@ -363,62 +362,78 @@ def run_c4(args):
         b.close()
         return tb, finals, iters
 
-    for prec_name, prec in (("mixed", fde.FDE_MIXED_FP32), ("fp64", fde.FDE_FP64),
-                            ("cycle", fde.FDE_MIXED_FP32_CYCLE)):
-        tb, finals, iters = batched(prec, False)
-        tg, gfinals, giters = batched(prec, True)
-        gdiff = max(float((a - c).abs().max()) for a, c in zip(finals, gfinals))
-        log(f"c4 {prec_name}: grouped vs ungrouped max diff {gdiff:.3e}, iterations {giters} vs {iters}")
-        finals = dict(zip(range(len(probs)), finals))
-        ids = list(range(len(probs)))
-        # sequential: one resident instance at a time, same steps (setup outside the timed region)
-        ts = 0.0
-        maxdiff = 0.0
-        for rid, (r, p) in zip(ids, zip(reqs, probs)):
-            b1 = fde.fde_batch_create(200 << 30)
-            i1 = admit(b1, r, prec, 1e-9, 2000)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            while fde.fde_batch_step(b1) > 0:
-                pass
-            torch.cuda.synchronize()
-            ts += time.perf_counter() - t1
-            u = torch.empty((p.n2, p.n1), dtype=torch.float64, device="cuda:0")
-            fde.fde_batch_poll(b1, i1, u)
-            maxdiff = max(maxdiff, float((u - finals[rid]).abs().max()))
-            b1.close()
-        out[prec_name] = {"batched_s": tb, "grouped_s": tg, "sequential_s": ts, "iters": iters,
-                          "max_diff_alone_vs_mix": maxdiff, "grouped_max_diff": gdiff,
-                          "grouped_iters_equal": giters == iters}
-        log(f"c4 {prec_name}: batched {tb:.2f} s, grouped ({slots} slots) {tg:.2f} s, one at a time {ts:.2f} s, "
-            f"{iters} iterations")
-    m = out["cycle"]
+    out = {"steps": sum(p.M for p in probs), "unknown_steps": sum(p.n1 * p.n2 * p.M for p in probs),
+           "slots": slots}
+    for name in modes:
+        prec = precs[name]
+        tg, finals, iters = batched(prec, True)
+        r = {"grouped_s": tg, "iters": iters}
+        if ungrouped:
+            tb, ufinals, uiters = batched(prec, False)
+            r["batched_s"] = tb
+            r["grouped_equals_ungrouped"] = uiters == iters and all(bool(torch.equal(a, c))
+                                                                    for a, c in zip(finals, ufinals))
+        if sequential:
+            # one resident instance at a time, same steps (setup outside the timed region)
+            ts, maxdiff = 0.0, 0.0
+            for r_, p, f in zip(reqs, probs, finals):
+                b1 = fde.fde_batch_create(200 << 30)
+                i1 = admit(b1, r_, prec, 1e-9, 2000)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                while fde.fde_batch_step(b1) > 0:
+                    pass
+                torch.cuda.synchronize()
+                ts += time.perf_counter() - t1
+                u = torch.empty((p.n2, p.n1), dtype=torch.float64, device="cuda:0")
+                fde.fde_batch_poll(b1, i1, u)
+                maxdiff = max(maxdiff, float((u - f).abs().max()))
+                b1.close()
+            r["sequential_s"] = ts
+            r["max_diff_alone_vs_grouped"] = maxdiff
+        out[name] = r
+        log(f"c4 {name}: " + ", ".join(f"{k} {v:.3f}" if isinstance(v, float) else f"{k} {v}" for k, v in r.items()))
+    return out
+
+
+def c4_summary(c4):
+    """The C4 keys of a JSON line: CN steps/s per mode and batching layout."""
+    steps = c4["steps"]
+    out = {"slots_per_group": c4["slots"]}
+    for name in ("mixed", "fp64", "cycle"):
+        if name not in c4:
+            continue
+        r = c4[name]
+        out[f"{name}_grouped_steps_per_s"] = steps / r["grouped_s"]
+        if "batched_s" in r:
+            out[f"{name}_ungrouped_steps_per_s"] = steps / r["batched_s"]
+            out[f"{name}_grouped_equals_ungrouped"] = r["grouped_equals_ungrouped"]
+        if "sequential_s" in r:
+            out[f"{name}_one_at_a_time_steps_per_s"] = steps / r["sequential_s"]
+            out[f"{name}_max_diff_alone_vs_grouped"] = r["max_diff_alone_vs_grouped"]
+        out[f"{name}_iters"] = r["iters"]
+    if "mixed" in c4 and "fp64" in c4:
+        out["mixed_speedup_vs_fp64"] = c4["fp64"]["grouped_s"] / c4["mixed"]["grouped_s"]
+    return out
+
+
+def run_c4(args):
+    """The C4 line: the value is grouped batching with the FP32 V-cycle inside FP64 flexible GMRES."""
+    c4 = c4_results()
+    m = c4["mixed"]
     line = {
-        "metric": "C4 batched CN steps/s (64 uneven instances, mixed precision)",
-        "value": steps / m["batched_s"], "unit": "CN steps/s", "n_gpus": 1, "higher_is_better": True,
+        "metric": "C4 batched CN steps/s (64 uneven instances, FP32 V-cycle in FP64 FGMRES)",
+        "value": c4["steps"] / m["grouped_s"], "unit": "CN steps/s", "n_gpus": 1, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
         "config": {"workload": "C4: 64 instances (seed 4), n in {127,255,511}, alpha,beta ~ U[1.1,1.9], "
                                "c(1+ax+by^2) coefficients, tau=1/8, 8 CN steps, rtol 1e-9",
-                   "precision": "FP32 V-cycle and FP32 restart cycles (FP32 basis) refining the FP64 "
-                                "iterate from FP64 true residuals"},
-        "unknown_updates_per_s": unknown_steps / m["batched_s"],
-        "grouped_steps_per_s": steps / m["grouped_s"],
-        "grouped_slots": slots,
-        "fp32_preconditioner_grouped_steps_per_s": steps / out["mixed"]["grouped_s"],
-        "fp64_grouped_steps_per_s": steps / out["fp64"]["grouped_s"],
-        "grouped_max_abs_diff_vs_ungrouped": max(v["grouped_max_diff"] for v in out.values()),
-        "grouped_iters_equal": all(v["grouped_iters_equal"] for v in out.values()),
-        "one_at_a_time_steps_per_s": steps / m["sequential_s"],
-        "batching_speedup": m["sequential_s"] / m["batched_s"],
-        "iters": m["iters"],
-        "fp32_preconditioner_value": steps / out["mixed"]["batched_s"],
-        "fp32_preconditioner_one_at_a_time_steps_per_s": steps / out["mixed"]["sequential_s"],
-        "iters_fp32_preconditioner": out["mixed"]["iters"],
-        "fp64_value": steps / out["fp64"]["batched_s"],
-        "fp64_one_at_a_time_steps_per_s": steps / out["fp64"]["sequential_s"],
-        "iters_fp64": out["fp64"]["iters"],
-        "max_abs_diff_alone_vs_mix": max(v["max_diff_alone_vs_mix"] for v in out.values()),
+                   "precision": "FP32 V-cycle in FP64 flexible GMRES (cycle: FP32 restart cycles refining "
+                                "the FP64 iterate from FP64 true residuals)",
+                   "batching": "grouped: one group per size, every restart-cycle kernel launched once over "
+                               "the solving members"},
+        "unknown_updates_per_s": c4["unknown_steps"] / m["grouped_s"],
     }
+    line.update(c4_summary(c4))
     print(json.dumps(line), flush=True)
 
 
@@ -633,6 +648,11 @@ def main():
     if not args.no_c2:
         log("c2: 511^2 on the GPU (32 steps) and the oracle (2 steps all cores, 1 step one thread)")
         out["c2"] = c2_comparison()
+    if not args.no_c4:
+        log("c4: 64 batched instances, grouped (mixed, fp64) and ungrouped (mixed)")
+        c4 = c4_results(modes=("mixed",), ungrouped=True, sequential=False)
+        c4.update(c4_results(modes=("fp64",), ungrouped=False, sequential=False))
+        out["c4"] = c4_summary(c4)
     print(json.dumps(out), flush=True)
 
 

@@ -84,7 +84,10 @@ typedef struct fde_handle fde_handle;
 /* Problem and solver description (Sec. 2 problem statement; Sec. 4.2 and Sec. 5 solver settings). */
 typedef struct fde_problem {
   double alpha, beta;   /* fractional orders, each in (1,2) (Sec. 2)                               */
-  int32_t n1, n2;       /* interior points in x and y; multigrid needs 2^l - 1 with l >= 3         */
+  int32_t n1, n2;       /* interior points in x and y, 2^l - 1 or 2^l with l >= 3, at most 2048; on
+                           an odd side coarse point J sits at fine 2J + 1, on an even side at fine
+                           2J (0-based; the down-sampling K of Sec. 4.1).  Even sides: geometric
+                           hierarchy only, not with FDE_MIXED_BF16GEMM                           */
   double a1, b1, a2, b2;/* domain (a1,b1) x (a2,b2), a < b                                         */
   double tau;           /* time step, > 0                                                          */
   int32_t precision;    /* FDE_FP64 | FDE_MIXED_FP32 | FDE_MIXED_BF16GEMM | FDE_MIXED_FP32_CYCLE |
@@ -93,7 +96,9 @@ typedef struct fde_problem {
   double omega;         /* Jacobi damping (Lemma lemsmo), 0 < omega <= 1; 0 selects 0.7             */
   int32_t nu_pre;       /* pre-smoothing steps per level, >= 0 (< 0 selects 1)                      */
   int32_t nu_post;      /* post-smoothing steps per level, >= 0 (< 0 selects 1)                     */
-  int32_t coarsest_n;   /* coarsen while min(n1,n2) > coarsest_n; 0 selects 7 (the 8x8-cell grid)   */
+  int32_t coarsest_n;   /* coarsen while min(n1,n2) > coarsest_n; 0 selects the paper's 8 x 8
+                           coarsest grid (Sec. 4.2): 8 when both sides are 2^l (8 x 8 points),
+                           else 7 (7 x 7 points, 8 x 8 cells)                                     */
   int32_t restart;      /* GMRES restart length, 1..32; 0 selects 20 (Sec. 5)                      */
   int32_t maxit;        /* total iteration limit per solve; 0 selects 5000 (enough for the
                            strongly anisotropic 2047^2 instances, which take ~530)              */

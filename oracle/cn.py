@@ -53,7 +53,7 @@ class IterativeSolver:
     """Oracle FGMRES(restart) + oracle geometric V(1,1) cycle, tight tolerance."""
 
     def __init__(self, rtol: float = 1e-13, restart: int = 50, omega: float = 0.7,
-                 coarsest_n: int = 7, maxit: int = 1000):
+                 coarsest_n: Optional[int] = None, maxit: int = 1000):
         self.rtol, self.restart, self.omega = rtol, restart, omega
         self.coarsest_n, self.maxit = coarsest_n, maxit
         self._key, self._vc = None, None

@@ -9,14 +9,17 @@ radius < 1 and the V-cycle contraction stays flat as n grows (Theorem (theorem21
 composed Galerkin apply equals the dense triple product P^T A P / 4.
 
 Readings of the paper used here (each is listed with its reason in the design notes):
-* grid sizes n = 2^l - 1, coarse index J <-> fine index 2J (1-based), so k = (n-1)/2 (Sec. 4.1);
+* grid sizes n = 2^l - 1 or n = 2^l with k = (n - n mod 2)/2 coarse points; coarse index j sits at
+  fine index i = 2j - (n+1) mod 2 (1-based), i.e. fine 2J + 1 (odd n) or 2J (even n), 0-based
+  (Sec. 4.1, the down-sampling matrix K);
 * restriction R = P^T / 4 (2-D full weighting: "a proper scaling of the symbol p", Sec. 4.2);
 * coarse levels keep the unscaled form I - tau/2 L_l; geometric levels rediscretise with h doubled
   and the coefficient fields injected (sampled at the coarse points), Sec. 4.2;
 * Galerkin levels are R A P (TGM step 3, Sec. 4);
 * damped Jacobi with the pointwise diagonal of the level matrix, omega = 0.7, one pre- and one
   post-smoothing step, zero initial guess on every coarse level (Sec. 4, V-cycle paragraph;
-  Sec. 4.2 settings); the coarsest grid is 7 x 7 interior points (8 x 8 cells), solved exactly.
+  Sec. 4.2 settings); the coarsest grid is the paper's 8 x 8: 8 x 8 points when both sides are
+  even, 7 x 7 interior points (8 x 8 cells) otherwise, solved exactly.
 """
 from __future__ import annotations
 
@@ -32,9 +35,15 @@ from .operator import Operator
 # Transfer operators
 # ----------------------------------------------------------------------------------------------
 def coarse_size(n: int) -> int:
-    if n % 2 != 1 or n < 3:
-        raise ValueError("multigrid needs odd n >= 3")
-    return (n - 1) // 2
+    """k = (n - n mod 2) / 2 (Sec. 4.1)."""
+    if n < 2:
+        raise ValueError("multigrid needs n >= 2")
+    return (n - n % 2) // 2
+
+
+def default_coarsest(n1: int, n2: int) -> int:
+    """The paper's 8 x 8 coarsest grid (Sec. 4.2): 8 when both sides are even, else 7."""
+    return 8 if (n1 % 2 == 0 and n2 % 2 == 0) else 7
 
 
 def downsample_1d(n: int) -> np.ndarray:
@@ -75,12 +84,17 @@ def restrict(R: np.ndarray, n1: int, n2: int) -> np.ndarray:
 # ----------------------------------------------------------------------------------------------
 # Geometric hierarchy (Sec. 4.2: rediscretisation on the coarser grid)
 # ----------------------------------------------------------------------------------------------
-def geometric_hierarchy(op0: Operator, coarsest_n: int = 7) -> List[Operator]:
+def geometric_hierarchy(op0: Operator, coarsest_n: Optional[int] = None) -> List[Operator]:
+    if coarsest_n is None:
+        coarsest_n = default_coarsest(op0.n1, op0.n2)
     levels = [op0]
     while min(levels[-1].n1, levels[-1].n2) > coarsest_n:
         f = levels[-1]
         k1, k2 = coarse_size(f.n1), coarse_size(f.n2)
-        inj = lambda a: np.ascontiguousarray(a[1::2, 1::2])  # fine (2J, 2I) 1-based = [2J-1, 2I-1]
+        # injection: coarse point j is fine point 2j - (n+1) mod 2 (1-based), i.e. 0-based rows
+        # (columns) 1, 3, 5, ... of an odd side and 0, 2, 4, ... of an even one
+        o1, o2 = f.n1 % 2, f.n2 % 2
+        inj = lambda a: np.ascontiguousarray(a[o2::2, o1::2][:k2, :k1])
         levels.append(Operator(f.alpha, f.beta, k1, k2, 2.0 * f.hx, 2.0 * f.hy, f.tau,
                                inj(f.dp), inj(f.dm), inj(f.ep), inj(f.em)))
     return levels

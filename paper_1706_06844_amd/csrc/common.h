@@ -308,5 +308,17 @@ __device__ __forceinline__ int load_flag(const int* p) {
 }
 
 inline bool is_pow2m1(int n) { return n >= 1 && ((n + 1) & n) == 0; }
+inline bool is_pow2(int n) { return n >= 1 && (n & (n - 1)) == 0; }
+// Grid sides the multigrid takes: n = 2^l - 1 or n = 2^l.  The down-sampling of Sec. 4.1 keeps
+// k = (n - n mod 2) / 2 = n >> 1 coarse points, coarse index J at fine index 2J + (n mod 2)
+// (0-based): the odd fine points of an odd grid, the even ones of an even grid.
+inline bool is_mg_side(int n) { return is_pow2m1(n) || is_pow2(n); }
+// Length of the circulant embedding of an n x n Toeplitz matrix with offsets -1..n-1: the smallest
+// power of two >= 2n - 1 (2(n + 1) for n = 2^l - 1, 2n for n = 2^l).
+inline int fft_len(int n) {
+  int L = 2;
+  while (L < 2 * n - 1) L <<= 1;
+  return L;
+}
 
 }  // namespace fde

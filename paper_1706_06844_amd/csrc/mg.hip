@@ -90,7 +90,20 @@ hipError_t launch_presmooth(int N, const Tin* b, const double* bscale, const R* 
 // ---- restriction rc = P^T r / 4 ---------------------------------------------------------------
 // With xc given, also the coarse level's first Jacobi sweep from zero: xc = dinv_c .* rc (the same
 // product the pre-smoothing kernel forms, fused to save a launch).
-// One coarse row J per blockIdx.y; coarse point I reads fine rows 2J..2J+2, columns 2I..2I+2.
+// One coarse row J per blockIdx.y; coarse point (J, I) sits at fine (2J + o2, 2I + o1), o = n mod 2,
+// and reads the 3 x 3 fine block around it (on an even side the block of J = 0 starts outside the
+// grid, where the field is zero).
+
+// Full weighting at fine centre (fy, fx): [1 2 1; 2 4 2; 1 2 1] / 16, entries at index -1 zero (the
+// block never passes the last row or column).
+template <typename R>
+__device__ __forceinline__ R full_weight(const R* f, int n1, int fy, int fx) {
+  auto F = [&](int y, int x) -> R { return (y >= 0 && x >= 0) ? f[(size_t)y * n1 + x] : R(0); };
+  const R a0 = F(fy - 1, fx - 1) + 2 * F(fy - 1, fx) + F(fy - 1, fx + 1);
+  const R a1 = F(fy, fx - 1) + 2 * F(fy, fx) + F(fy, fx + 1);
+  const R a2 = F(fy + 1, fx - 1) + 2 * F(fy + 1, fx) + F(fy + 1, fx + 1);
+  return (a0 + 2 * a1 + a2) * R(0.0625);
+}
 template <typename R>
 __global__ void restrict_kernel(int n1, int n2, const R* __restrict__ r, R* __restrict__ rc,
                                 const R* __restrict__ dinv_c, R* __restrict__ xc, const int* __restrict__ skip,
@@ -102,20 +115,26 @@ __global__ void restrict_kernel(int n1, int n2, const R* __restrict__ r, R* __re
   FDE_ZSHIFT(xc);
   FDE_ZSHIFT(skip);
   const int skipv = load_flag(skip);  // waited for after the loads below are issued
-  const int k1 = (n1 - 1) / 2;
+  const int k1 = n1 >> 1;
   const int J = blockIdx.y;
   const int I = blockIdx.x * blockDim.x + threadIdx.x;
   if (I >= k1) return;
-  const R* r0 = r + (size_t)(2 * J) * n1 + 2 * I + 1;
-  const R* r1 = r0 + n1;
-  const R* r2 = r1 + n1;
   const size_t q = (size_t)J * k1 + I;
-  const R a0 = r0[-1] + 2 * r0[0] + r0[1];
-  const R a1 = r1[-1] + 2 * r1[0] + r1[1];
-  const R a2 = r2[-1] + 2 * r2[0] + r2[1];
+  R v;
+  if (n1 & n2 & 1) {
+    // odd sides: the block lies inside the grid
+    const R* r0 = r + (size_t)(2 * J) * n1 + 2 * I + 1;
+    const R* r1 = r0 + n1;
+    const R* r2 = r1 + n1;
+    const R a0 = r0[-1] + 2 * r0[0] + r0[1];
+    const R a1 = r1[-1] + 2 * r1[0] + r1[1];
+    const R a2 = r2[-1] + 2 * r2[0] + r2[1];
+    v = (a0 + 2 * a1 + a2) * R(0.0625);
+  } else {
+    v = full_weight(r, n1, 2 * J + (n2 & 1), 2 * I + (n1 & 1));
+  }
   const R dc = xc ? dinv_c[q] : R(0);
   if (skipv) return;
-  const R v = (a0 + 2 * a1 + a2) * R(0.0625);
   rc[q] = v;
   if (xc) xc[q] = dc * v;
 }
@@ -124,7 +143,7 @@ template <typename R>
 hipError_t launch_restrict(int n1, int n2, const R* r, R* rc, const R* dinv_c, R* xc, const int* skip,
                            hipStream_t st) {
   if (xc && !dinv_c) return hipErrorInvalidValue;
-  const int k1 = (n1 - 1) / 2, k2 = (n2 - 1) / 2;
+  const int k1 = n1 >> 1, k2 = n2 >> 1;
   if (k1 < 1 || k2 < 1) return hipErrorInvalidValue;
   if (k2 > 65535) return hipErrorInvalidValue;
   hipLaunchKernelGGL((restrict_kernel<R>), dim3(ceil_div(k1, kBlock), k2, batch_nz()), dim3(kBlock), 0, st, n1, n2, r,
@@ -133,10 +152,12 @@ hipError_t launch_restrict(int n1, int n2, const R* r, R* rc, const R* dinv_c, R
 }
 
 // ---- prolongation and correction x += P e -----------------------------------------------------
-// Coarse neighbours of fine index f (0-based) on a coarse grid of size k: odd f = 2c+1 -> (c, 1);
-// even f = 2c -> (c-1, 1/2), (c, 1/2), dropping indices outside [0, k).  (Used by the one-workgroup
-// V-cycle.)
-__device__ __forceinline__ void coarse_nbrs(int f, int k, int* c, float* w, int* cnt) {
+// Coarse neighbours of fine index f (0-based) on a side of n points (k = n >> 1 coarse points): with
+// g = f + 1 - n mod 2 (so that coarse J sits at g = 2J + 1), odd g = 2c+1 -> (c, 1); even g = 2c ->
+// (c-1, 1/2), (c, 1/2), dropping indices outside [0, k).  (Used by the one-workgroup V-cycle.)
+__device__ __forceinline__ void coarse_nbrs(int f, int n, int* c, float* w, int* cnt) {
+  const int k = n >> 1;
+  f += 1 - (n & 1);
   if (f & 1) {
     c[0] = (f - 1) >> 1;
     w[0] = 1.0f;
@@ -156,9 +177,10 @@ __device__ __forceinline__ void coarse_nbrs(int f, int k, int* c, float* w, int*
   }
 }
 
-// Fine index f (0-based) takes (e[(f-1)>>1] + e[f>>1]) / 2 from its coarse neighbours, entries
-// outside [0, k) being zero: an odd f = 2c+1 gets e[c] (both indices equal), an even f = 2c the mean
-// of e[c-1] and e[c].  One fine row per blockIdx.y, so the row weights are uniform per workgroup.
+// Fine index f (0-based) takes (e[(g-1)>>1] + e[g>>1]) / 2 from its coarse neighbours, g = f + 1 -
+// n mod 2, entries outside [0, k) being zero: an odd g = 2c+1 gets e[c] (both indices equal), an
+// even g = 2c the mean of e[c-1] and e[c].  One fine row per blockIdx.y, so the row weights are
+// uniform per workgroup.
 template <typename R>
 __global__ void prolong_kernel(int n1, int n2, const R* __restrict__ e, R* __restrict__ x,
                                const int* __restrict__ skip, const long long* __restrict__ ztab) {
@@ -167,12 +189,13 @@ __global__ void prolong_kernel(int n1, int n2, const R* __restrict__ e, R* __res
   FDE_ZSHIFT(x);
   FDE_ZSHIFT(skip);
   const int skipv = load_flag(skip);  // waited for after the loads below are issued
-  const int k1 = (n1 - 1) / 2, k2 = (n2 - 1) / 2;
+  const int k1 = n1 >> 1, k2 = n2 >> 1;
   const int j = blockIdx.y;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n1) return;
-  const int ya = (j - 1) >> 1, yb = j >> 1;  // coarse rows (equal for odd j)
-  const int xa = (i - 1) >> 1, xb = i >> 1;
+  const int gy = j + 1 - (n2 & 1), gx = i + 1 - (n1 & 1);
+  const int ya = (gy - 1) >> 1, yb = gy >> 1;  // coarse rows (equal for odd gy)
+  const int xa = (gx - 1) >> 1, xb = gx >> 1;
   auto E = [&](int cy, int cx) -> R {
     return (cy >= 0 && cy < k2 && cx >= 0 && cx < k1) ? e[(size_t)cy * k1 + cx] : R(0);
   };
@@ -236,17 +259,17 @@ hipError_t launch_interleave(size_t N, const double* a, const double* b, R* out,
 
 template <typename R>
 __global__ void inject_pairs_kernel(int n1, int n2, const R* __restrict__ in, R* __restrict__ out) {
-  const int k1 = (n1 - 1) / 2, k2 = (n2 - 1) / 2;
+  const int k1 = n1 >> 1, k2 = n2 >> 1;
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < k1 * k2; q += gridDim.x * blockDim.x) {
     const int J = q / k1, I = q - J * k1;
-    const size_t f = (size_t)(2 * J + 1) * n1 + (2 * I + 1);
+    const size_t f = (size_t)(2 * J + (n2 & 1)) * n1 + (2 * I + (n1 & 1));
     out[2 * q] = in[2 * f];
     out[2 * q + 1] = in[2 * f + 1];
   }
 }
 template <typename R>
 hipError_t launch_inject_pairs(int n1, int n2, const R* in, R* out, hipStream_t st) {
-  const int Kc = ((n1 - 1) / 2) * ((n2 - 1) / 2);
+  const int Kc = (n1 >> 1) * (n2 >> 1);
   hipLaunchKernelGGL((inject_pairs_kernel<R>), dim3(grid_for(Kc)), dim3(kBlock), 0, st, n1, n2, in, out);
   return hipGetLastError();
 }
@@ -632,7 +655,9 @@ hipError_t launch_tile_resid_restrict(int n1, int n2, const R* x, const R* b, co
                                       const R* swx, const R* swy, R* bc, const R* dinv_c, R* xc, const int* skip,
                                       hipStream_t st) {
   const int k1 = (n1 - 1) / 2, k2 = (n2 - 1) / 2;
-  if (k1 < 1 || k2 < 1 || (xc && !dinv_c) || !tile_lds_fits<R>(n1, n2)) return hipErrorInvalidValue;
+  // (fine blocks laid out for odd sides: coarse J at fine 2J + 1)
+  if (!(n1 & n2 & 1) || k1 < 1 || k2 < 1 || (xc && !dinv_c) || !tile_lds_fits<R>(n1, n2))
+    return hipErrorInvalidValue;
   const size_t bytes = tile_rr_lds<R>(n1, n2);
   if (bytes > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&tile_resid_restrict_kernel<R>),
@@ -663,7 +688,7 @@ static hipError_t launch_tile_jacobi_t(int n1, int n2, const R* x, const R* e, c
 template <typename R>
 hipError_t launch_tile_jacobi(int n1, int n2, const R* x, const R* e, const R* b, const R* dpm, const R* epm,
                               const R* dinv, const R* swx, const R* swy, R* xout, const int* skip, hipStream_t st) {
-  if (n1 < 3 || n2 < 3 || x == xout || !tile_lds_fits<R>(n1, n2)) return hipErrorInvalidValue;
+  if (!(n1 & n2 & 1) || n1 < 3 || n2 < 3 || x == xout || !tile_lds_fits<R>(n1, n2)) return hipErrorInvalidValue;
   const size_t bytes = tile_j_lds<R>(n1, n2);
   if (e) return launch_tile_jacobi_t<R, true>(n1, n2, x, e, b, dpm, epm, dinv, swx, swy, xout, skip, bytes, st);
   return launch_tile_jacobi_t<R, false>(n1, n2, x, e, b, dpm, epm, dinv, swx, swy, xout, skip, bytes, st);
@@ -843,16 +868,10 @@ __global__ __launch_bounds__(1024) void coarse_vcycle_kernel(CoarseView<R> cv, c
       s.T[p] = s.B[l][p] - xv + direct_l(n1, n2, j, i, s.X[l], s.swx[l], s.swy[l], s.dpm[l], s.epm[l]);
     }
     __syncthreads();
-    const int k1 = (n1 - 1) / 2, k2 = (n2 - 1) / 2;
+    const int k1 = n1 >> 1, k2 = n2 >> 1;
     for (int q = tid; q < k1 * k2; q += nt) {
       const int J = q / k1, I = q - J * k1;
-      const R* r0 = s.T + (2 * J) * n1 + 2 * I + 1;
-      const R* r1 = r0 + n1;
-      const R* r2 = r1 + n1;
-      const R a0 = r0[-1] + 2 * r0[0] + r0[1];
-      const R a1 = r1[-1] + 2 * r1[0] + r1[1];
-      const R a2 = r2[-1] + 2 * r2[0] + r2[1];
-      s.B[l + 1][q] = (a0 + 2 * a1 + a2) * R(0.0625);
+      s.B[l + 1][q] = full_weight(s.T, n1, 2 * J + (n2 & 1), 2 * I + (n1 & 1));
     }
     __syncthreads();
   });
@@ -871,14 +890,14 @@ __global__ __launch_bounds__(1024) void coarse_vcycle_kernel(CoarseView<R> cv, c
   static_for<0, last>([&](auto kc) {
     constexpr int l = last - 1 - decltype(kc)::value;
     const int n1 = cv.n1[l], n2 = cv.n2[l], N = n1 * n2;
-    const int k1 = (n1 - 1) / 2, k2 = (n2 - 1) / 2;
+    const int k1 = n1 >> 1;
     const R* E = s.X[l + 1];
     for (int p = tid; p < N; p += nt) {
       const int j = p / n1, i = p - j * n1;
       int cy[2], cx[2], ny, nx;
       float wy[2], wx[2];
-      coarse_nbrs(j, k2, cy, wy, &ny);
-      coarse_nbrs(i, k1, cx, wx, &nx);
+      coarse_nbrs(j, n2, cy, wy, &ny);
+      coarse_nbrs(i, n1, cx, wx, &nx);
       R v = 0;
       for (int a = 0; a < ny; ++a) {
         R t = 0;

@@ -136,8 +136,8 @@ extern "C" int fde_apply_noalloc(const fde_problem* p, const double* dp, const d
   if (x == y) return fail(FDE_EINVAL, "y may not alias x");
   if (!(p->alpha > 1.0 && p->alpha < 2.0) || !(p->beta > 1.0 && p->beta < 2.0))
     return fail(FDE_EINVAL, "alpha and beta must lie in (1,2)");
-  if (!is_pow2m1(p->n1) || !is_pow2m1(p->n2) || p->n1 < 7 || p->n2 < 7)
-    return fail(FDE_EINVAL, "n1 and n2 must be 2^l - 1 with l >= 3");
+  if (!is_mg_side(p->n1) || !is_mg_side(p->n2) || p->n1 < 7 || p->n2 < 7)
+    return fail(FDE_EINVAL, "n1 and n2 must be 2^l - 1 or 2^l with l >= 3");
   if (p->n1 > kNaMaxN || p->n2 > kNaMaxN)
     return fail(FDE_EINVAL, "fde_apply_noalloc: n1 and n2 are limited to FDE_NOALLOC_MAX_N (1023); "
                             "use a handle (fde_setup, fde_apply) for larger grids");
@@ -147,7 +147,7 @@ extern "C" int fde_apply_noalloc(const fde_problem* p, const double* dp, const d
   hipError_t e = scratch_ptr(&base);
   if (e != hipSuccess) return fail(FDE_EDEVICE, hipGetErrorString(e));
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const int n1 = p->n1, n2 = p->n2, L1 = 2 * (n1 + 1), L2 = 2 * (n2 + 1);
+  const int n1 = p->n1, n2 = p->n2, L1 = fft_len(n1), L2 = fft_len(n2);
   const size_t N = (size_t)n1 * n2;
   const double hx = (p->b1 - p->a1) / (n1 + 1), hy = (p->b2 - p->a2) / (n2 + 1);
   const double sx = p->tau / (2.0 * std::pow(hx, p->alpha)), sy = p->tau / (2.0 * std::pow(hy, p->beta));

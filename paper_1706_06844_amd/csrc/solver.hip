@@ -380,6 +380,10 @@ void op_apply(fde_handle* h, bool outer, const OpView<R>& op, const Tin* x, R* a
         [&] { return launch_op_x<R, Tin>(op, x, ay, out, mode, b, src, tau, skip, h->stream); });
 }
 
+// The coarsest grid of the paper's setting, 8 x 8: 8 x 8 points when both sides are 2^l, 7 x 7 interior
+// points (8 x 8 cells) otherwise.
+int default_coarsest(int n1, int n2) { return (is_pow2(n1) && is_pow2(n2)) ? 8 : 7; }
+
 int validate(const fde_problem* p, std::string* why) {
   auto bad = [&](const std::string& s) {
     *why = s;
@@ -388,9 +392,9 @@ int validate(const fde_problem* p, std::string* why) {
   if (!p) return bad("problem is NULL");
   if (!(p->alpha > 1.0 && p->alpha < 2.0) || !(p->beta > 1.0 && p->beta < 2.0))
     return bad("alpha and beta must lie in (1,2)");
-  if (!is_pow2m1(p->n1) || !is_pow2m1(p->n2) || p->n1 < 7 || p->n2 < 7)
-    return bad("n1 and n2 must be 2^l - 1 with l >= 3");
-  if (p->n1 > 2047 || p->n2 > 2047) return bad("n1 and n2 are limited to 2047 (FFT length 4096)");
+  if (!is_mg_side(p->n1) || !is_mg_side(p->n2) || p->n1 < 7 || p->n2 < 7)
+    return bad("n1 and n2 must be 2^l - 1 or 2^l with l >= 3");
+  if (p->n1 > 2048 || p->n2 > 2048) return bad("n1 and n2 are limited to 2048 (FFT length 4096)");
   if (!(p->b1 > p->a1) || !(p->b2 > p->a2)) return bad("domain needs a < b");
   if (!(p->tau > 0.0) || !std::isfinite(p->tau)) return bad("tau must be positive and finite");
   if (p->precision < FDE_FP64 || p->precision > FDE_MIXED_CYCLE_BF16) return bad("unknown precision");
@@ -405,11 +409,16 @@ int validate(const fde_problem* p, std::string* why) {
   if (p->restart < 1 || p->restart > kMaxRestart) return bad("restart must lie in 1..32");
   if (p->maxit < 1) return bad("maxit must be >= 1");
   if (!(p->rtol >= 0.0)) return bad("rtol must be >= 0");
+  const bool even = is_pow2(p->n1) || is_pow2(p->n2);
+  if (even && p->mg_variant != FDE_MG_GEOMETRIC)
+    return bad("even grid sides (n = 2^l) are supported by the geometric hierarchy only");
+  if (even && p->precision == FDE_MIXED_BF16GEMM)
+    return bad("the BF16 MFMA operator passes need n = 2^l - 1");
   // coarsest grid size of the hierarchy
   int a = p->n1, b = p->n2;
   while (std::min(a, b) > p->coarsest_n) {
-    a = (a - 1) / 2;
-    b = (b - 1) / 2;
+    a >>= 1;
+    b >>= 1;
   }
   if (a * b > 128 || std::max(a, b) > kDirectMaxN)
     return bad("the coarsest grid would exceed 128 unknowns or 31 points per side (n1, n2 too different)");
@@ -420,7 +429,7 @@ void fill_defaults(fde_problem* q) {
   if (q->omega == 0.0) q->omega = 0.7;
   if (q->nu_pre < 0) q->nu_pre = 1;
   if (q->nu_post < 0) q->nu_post = 1;
-  if (q->coarsest_n == 0) q->coarsest_n = 7;
+  if (q->coarsest_n == 0) q->coarsest_n = default_coarsest(q->n1, q->n2);
   if (q->restart == 0) q->restart = 20;
   if (q->maxit == 0) q->maxit = 5000;
   if (q->rtol == 0.0) q->rtol = 1e-10;
@@ -540,7 +549,7 @@ bool tune_level(int n1, int n2, int bytes, bool* direct) {
 template <typename R>
 bool time_direct_vs_fft(fde_handle* h, Level<R>& L) {
   hipStream_t st = h->stream;
-  const size_t N = L.N(), Nc = (size_t)((L.n1 - 1) / 2) * ((L.n2 - 1) / 2);
+  const size_t N = L.N(), Nc = (size_t)(L.n1 >> 1) * (L.n2 >> 1);
   R* x = reinterpret_cast<R*>(h->scratch64);  // 4 fine FP64 fields: x, y, b and the coarse fields
   R* y = x + N;
   R* b = y + N;
@@ -564,7 +573,7 @@ bool time_direct_vs_fft(fde_handle* h, Level<R>& L) {
       HIPCHECK((launch_operator<R, R>(v, x, L.ay, x, EP_JACOBI, b, nullptr, 0.0, nullptr, st)));
     }
   };
-  const bool can_direct = tile_lds_fits<R>(L.n1, L.n2);
+  const bool can_direct = tile_lds_fits<R>(L.n1, L.n2) && (L.n1 & L.n2 & 1);
   float best[2] = {1e30f, 1e30f};
   for (int d = 0; d < (can_direct ? 2 : 1); ++d) {
     leg(d == 1);  // warm-up
@@ -693,8 +702,8 @@ std::unique_ptr<Hierarchy<R>> build_hierarchy(fde_handle* h) {
     Level<R> L;
     L.n1 = n1;
     L.n2 = n2;
-    L.L1 = 2 * (n1 + 1);
-    L.L2 = 2 * (n2 + 1);
+    L.L1 = fft_len(n1);
+    L.L2 = fft_len(n2);
     const double hx = h->hx * (double)(1 << l), hy = h->hy * (double)(1 << l);
     L.sx = p.tau / (2.0 * std::pow(hx, h->palpha));
     L.sy = p.tau / (2.0 * std::pow(hy, h->pbeta));
@@ -743,7 +752,9 @@ std::unique_ptr<Hierarchy<R>> build_hierarchy(fde_handle* h) {
       }
       if (!L.direct || tunable) L.ay = dalloc<R>(m, N);
       if (tune) L.direct = time_direct_vs_fft<R>(h, L);
-      L.tiled = L.direct && !L.mfma && std::min(n1, n2) > p.coarsest_n && tile_lds_fits<R>(n1, n2);
+      // (the tiled kernels' fine blocks are laid out for odd sides)
+      L.tiled = L.direct && !L.mfma && std::min(n1, n2) > p.coarsest_n && tile_lds_fits<R>(n1, n2) &&
+                (n1 & n2 & 1);
       if (std::is_same<R, float>::value && p.precision == FDE_MIXED_BF16GEMM && !L.direct) {
         L.mfma = true;
         L.mv.n1 = n1;
@@ -765,8 +776,8 @@ std::unique_ptr<Hierarchy<R>> build_hierarchy(fde_handle* h) {
     L.x = dalloc<R>(m, N);
     H->lv.push_back(L);
     if (std::min(n1, n2) <= p.coarsest_n) break;
-    n1 = (n1 - 1) / 2;
-    n2 = (n2 - 1) / 2;
+    n1 >>= 1;
+    n2 >>= 1;
     ++l;
   }
   const int nlev = (int)H->lv.size();
@@ -1353,7 +1364,7 @@ size_t footprint_bytes(const fde_problem* pin) {
   const bool f32 = p.precision != FDE_FP64;
   const double R = f32 ? 4.0 : 8.0;
   const double N = (double)p.n1 * p.n2;
-  const int L1 = 2 * (p.n1 + 1), L2 = 2 * (p.n2 + 1);
+  const int L1 = fft_len(p.n1), L2 = fft_len(p.n2);
   double b = 0;
   b += 4 * N * 8;                                   // outer coefficient pairs
   b += 2.0 * (L1 + L2) * 8 + 4.0 * (L1 + L2) * 8;   // symbols, twiddles
@@ -1379,7 +1390,7 @@ size_t footprint_bytes(const fde_problem* pin) {
     } else {
       if (l > 0 || f32) b += 4 * Nl * R;
       b += Nl * R;
-      if (!direct || tunable || (gal && l == 0)) b += 4.0 * (2 * (a1 + 1) + 2 * (a2 + 1)) * R;
+      if (!direct || tunable || (gal && l == 0)) b += 4.0 * (fft_len(a1) + fft_len(a2)) * R;
       if (!direct || tunable) b += Nl * R;
       if (f32 && p.precision == FDE_MIXED_BF16GEMM && !direct)
         b += 2.0 * 1024 * (mfma_table_entries(a1) + mfma_table_entries(a2));
@@ -1387,8 +1398,8 @@ size_t footprint_bytes(const fde_problem* pin) {
     if (!one_wg) b += 2 * Nl * R;  // r, second iterate
     b += 2 * Nl * R;               // b, x
     if (std::min(a1, a2) <= p.coarsest_n) break;
-    a1 = (a1 - 1) / 2;
-    a2 = (a2 - 1) / 2;
+    a1 >>= 1;
+    a2 >>= 1;
     ++l;
   }
   b += galscratch;
@@ -1440,7 +1451,7 @@ void fde_problem_default(fde_problem* p, double alpha, double beta, int32_t n1, 
   p->omega = 0.7;
   p->nu_pre = 1;
   p->nu_post = 1;
-  p->coarsest_n = 7;
+  p->coarsest_n = default_coarsest(n1, n2);
   p->restart = 20;
   p->maxit = 5000;
   p->rtol = 1e-10;
@@ -1477,8 +1488,8 @@ int setup_impl(const fde_problem* pin, const double* dp, const double* dm, const
     h->stream = static_cast<hipStream_t>(stream);
     h->n1 = p.n1;
     h->n2 = p.n2;
-    h->L1 = 2 * (p.n1 + 1);
-    h->L2 = 2 * (p.n2 + 1);
+    h->L1 = fft_len(p.n1);
+    h->L2 = fft_len(p.n2);
     h->N = (size_t)p.n1 * p.n2;
     h->hx = (p.b1 - p.a1) / (p.n1 + 1);
     h->hy = (p.b2 - p.a2) / (p.n2 + 1);

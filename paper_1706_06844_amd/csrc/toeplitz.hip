@@ -259,7 +259,7 @@ bool fft_length_supported(int L) {
 
 template <typename R, typename Tin>
 hipError_t launch_op_y(const OpView<R>& op, const Tin* x, R* ay, const int* skip, hipStream_t st) {
-  if (!x || !ay || !op.epm || !op.mu_y || !op.tw_y || op.L2 != 2 * (op.n2 + 1)) return hipErrorInvalidValue;
+  if (!x || !ay || !op.epm || !op.mu_y || !op.tw_y || op.L2 != fft_len(op.n2)) return hipErrorInvalidValue;
   switch (op.L2) {
 #define C_(LL) \
   case LL:     \
@@ -274,7 +274,7 @@ hipError_t launch_op_y(const OpView<R>& op, const Tin* x, R* ay, const int* skip
 template <typename R, typename Tin>
 hipError_t launch_op_x(const OpView<R>& op, const Tin* x, const R* ay, R* out, int mode, const R* b,
                        const SrcTerms* src, double tau, const int* skip, hipStream_t st) {
-  if (!x || !out || !op.dpm || !op.mu_x || !op.tw_x || op.L1 != 2 * (op.n1 + 1)) return hipErrorInvalidValue;
+  if (!x || !out || !op.dpm || !op.mu_x || !op.tw_x || op.L1 != fft_len(op.n1)) return hipErrorInvalidValue;
   if ((mode == EP_RESID || mode == EP_JACOBI) && !b) return hipErrorInvalidValue;
   if (mode == EP_JACOBI && !op.dinv) return hipErrorInvalidValue;
   SrcTerms s{};

@@ -59,7 +59,8 @@ def test_problem_default(lib):
 
 @pytest.mark.parametrize("field,value,needle", [
     ("alpha", 2.0, "alpha"), ("alpha", 1.0, "alpha"), ("beta", 0.5, "alpha and beta"),
-    ("n1", 10, "2^l - 1"), ("n2", 3, "2^l - 1"), ("n1", 4095, "2047"),
+    ("n1", 10, "2^l - 1"), ("n2", 3, "2^l - 1"), ("n1", 4, "2^l - 1"), ("n1", 4095, "2048"),
+    ("n1", 4096, "2048"),
     ("tau", 0.0, "tau"), ("tau", -1.0, "tau"), ("restart", 40, "restart"),
     ("omega", 1.5, "omega"), ("b1", -1.0, "a < b"), ("precision", 7, "precision"),
     ("precision", 5, "precision"),
@@ -73,6 +74,24 @@ def test_setup_rejects_invalid_problems(lib, field, value, needle):
     rc = lib.fde_setup(ctypes.byref(p), fake, fake, fake, fake, None, ctypes.byref(out))
     assert rc == L.FDE_EINVAL and out.value is None
     assert needle in lib.fde_last_error(None).decode()
+
+
+def test_even_sides_default_to_the_8x8_coarsest_grid_and_geometric_only(lib):
+    p = L.fde_problem()
+    lib.fde_problem_default(ctypes.byref(p), 1.8, 1.6, 64, 64, 1 / 64)
+    assert p.coarsest_n == 8
+    lib.fde_problem_default(ctypes.byref(p), 1.8, 1.6, 63, 64, 1 / 64)
+    assert p.coarsest_n == 7
+    fake = ctypes.c_void_p(0x1000)
+    out = ctypes.c_void_p()
+    for field, value, needle in (("mg_variant", L.FDE_MG_GALERKIN, "geometric"),
+                                 ("mg_variant", L.FDE_MG_BAND, "geometric"),
+                                 ("precision", L.FDE_MIXED_BF16GEMM, "2^l - 1")):
+        lib.fde_problem_default(ctypes.byref(p), 1.8, 1.6, 64, 64, 1 / 64)
+        setattr(p, field, value)
+        rc = lib.fde_setup(ctypes.byref(p), fake, fake, fake, fake, None, ctypes.byref(out))
+        assert rc == L.FDE_EINVAL and out.value is None
+        assert needle in lib.fde_last_error(None).decode()
 
 
 @pytest.mark.parametrize("prec", [L.FDE_MIXED_FP32_CYCLE, L.FDE_MIXED_CYCLE_BF16])

@@ -48,3 +48,14 @@ def test_iterative_oracle_matches_direct():
     a = cn_run(p, solver=DirectSolver()).u
     b = cn_run(p, solver=IterativeSolver(rtol=1e-13)).u
     assert np.linalg.norm(a - b) <= 1e-11 * np.linalg.norm(a)
+
+
+@pytest.mark.parametrize("n", [16, 32])
+def test_iterative_oracle_on_even_grids_matches_direct(n):
+    # The paper's own grids (n = 2^l, Sec. 5): FGMRES with the even-side V-cycle (coarse point j at
+    # fine 2j - 1, 1-based, down to 8 x 8) reproduces the dense LU time stepping.
+    p = workloads.example1(n)
+    p.M = 4
+    a = cn_run(p, solver=DirectSolver()).u
+    b = cn_run(p, solver=IterativeSolver(rtol=1e-13)).u
+    assert np.linalg.norm(a - b) <= 1e-11 * np.linalg.norm(a)

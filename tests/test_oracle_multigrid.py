@@ -32,6 +32,46 @@ def test_prolongation_reproduces_linear_functions():
     np.testing.assert_allclose(fine[1:-1, 1:-1], f(Xf, Yf)[1:-1, 1:-1], atol=1e-13)
 
 
+def test_even_side_prolongation_follows_the_downsampling_definition():
+    # Sec. 4.1: [K]_{i,j} = 1 iff i = 2j - (n+1) mod 2 (1-based), k = (n - n mod 2)/2; for even n the
+    # coarse point j is fine point 2j - 1, and P = T(1 + cos t) K puts 1/2, 1, 1/2 at fine 2j-2, 2j-1,
+    # 2j (the entry at fine index 0 falls outside the grid).
+    n = 16
+    P = mg.prolong_1d(n)
+    assert P.shape == (16, 8)
+    for j in range(1, 9):
+        col = np.zeros(n + 2)  # 1-based fine indices 0..n+1
+        col[2 * j - 2], col[2 * j - 1], col[2 * j] = 0.5, 1.0, 0.5
+        np.testing.assert_array_equal(P[:, j - 1], col[1:n + 1])
+
+
+def test_even_side_prolongation_reproduces_bilinear_functions():
+    # On an even side the coarse points are x_{2j-1} = (2j-1) h (1-based), spacing 2h; the last fine
+    # point lies between the last coarse point and the boundary x = 1, where the field is 0.  So
+    # bilinear interpolation of a bilinear function that vanishes on x = 1 and y = 1 is exact at
+    # every fine point.
+    n = 32
+    h = 1.0 / (n + 1)
+    xf = h * np.arange(1, n + 1)
+    xc = h * (2 * np.arange(1, n // 2 + 1) - 1)
+    f = lambda x, y: 1.3 * (1.0 - x) * (1.0 - y)
+    Yc, Xc = np.meshgrid(xc, xc, indexing="ij")
+    Yf, Xf = np.meshgrid(xf, xf, indexing="ij")
+    np.testing.assert_allclose(mg.prolong(f(Xc, Yc), n, n), f(Xf, Yf), rtol=0, atol=1e-14)
+    # and one that does not vanish there is exact away from the last fine row and column
+    g = lambda x, y: 0.3 + 2 * x - 1.5 * y
+    np.testing.assert_allclose(mg.prolong(g(Xc, Yc), n, n)[:-1, :-1], g(Xf, Yf)[:-1, :-1], rtol=0, atol=1e-13)
+
+
+def test_even_side_full_weighting_of_constants():
+    # R = P^T/4 of a constant on an even side: unit weights except the first coarse row and column,
+    # whose stencil loses its fine index 0 (weight 1/2 of 2): 3/4 per direction.
+    n = 16
+    w = np.ones(8)
+    w[0] = 0.75
+    np.testing.assert_allclose(mg.restrict(np.ones((n, n)), n, n), np.outer(w, w), rtol=0, atol=1e-15)
+
+
 def test_full_weighting_preserves_constants():
     n = 15
     r = mg.restrict(np.ones((n, n)), n, n)
@@ -165,6 +205,21 @@ def test_geometric_hierarchy_shapes_and_injection():
     np.testing.assert_allclose(lv[1].dp, p.dp(X, Y, 0.0), rtol=1e-15)
 
 
+def test_even_geometric_hierarchy_shapes_and_injection():
+    # even sides: 64 -> 32 -> 16 -> 8 (the paper's 8 x 8 coarsest grid), coarse point J at fine 2J
+    # (0-based), so the injected coefficients are the coefficient function at x = (2J + 1) h
+    p = workloads.config_c2(64, 32)
+    op = operator_from_problem(p, 0.0)
+    lv = mg.geometric_hierarchy(op)
+    assert [l.n1 for l in lv] == [64, 32, 16, 8]
+    assert lv[1].hx == pytest.approx(2 * op.hx)
+    np.testing.assert_array_equal(lv[1].dp, op.dp[0::2, 0::2])
+    xc = (2 * np.arange(32) + 1) / 65.0
+    X, Y = np.meshgrid(xc, xc)
+    np.testing.assert_allclose(lv[1].dp, p.dp(X, Y, 0.0), rtol=1e-15)
+    np.testing.assert_allclose(lv[1].em, p.em(X, Y, 0.0), rtol=1e-15)
+
+
 def test_standalone_vcycle_iteration_contracts_at_the_spectral_radius():
     # the stand-alone V-cycle iteration propagates the error with I - V A: the residual ratios
     # settle near its spectral radius (in a norm-independent way, so within a margin) and the
@@ -212,19 +267,22 @@ def _cycle_matrix(vc):
     return V
 
 
-@pytest.mark.parametrize("variant", ["geometric", "galerkin"])
-def test_two_level_vcycle_equals_two_grid_formula(variant):
-    # Two levels (15 -> 7, exact coarse solve), one pre- and one post-sweep from a zero guess:
-    # the error propagates with S (I - P A_c^-1 R A) S, R = P^T/4, S = I - omega D^-1 A (the two-grid
-    # method of Sec. 4 with the pre-smoothing step of the V-cycle paragraph added).  For Galerkin
-    # A_c = R A P, which turns the coarse correction into the paper's I - P (P^T A P)^-1 P^T A.
-    op = _c2_op(15)
+@pytest.mark.parametrize("variant,n", [("geometric", 15), ("galerkin", 15), ("geometric", 16),
+                                       ("galerkin", 16)])
+def test_two_level_vcycle_equals_two_grid_formula(variant, n):
+    # Two levels (15 -> 7 or 16 -> 8, exact coarse solve), one pre- and one post-sweep from a zero
+    # guess: the error propagates with S (I - P A_c^-1 R A) S, R = P^T/4, S = I - omega D^-1 A (the
+    # two-grid method of Sec. 4 with the pre-smoothing step of the V-cycle paragraph added).  For
+    # Galerkin A_c = R A P, which turns the coarse correction into the paper's
+    # I - P (P^T A P)^-1 P^T A.  P is T(p) K with K the down-sampling of Sec. 4.1 for either parity.
+    op = _c2_op(n)
+    cn = mg.default_coarsest(n, n)
     levels = (mg.geometric_hierarchy(op) if variant == "geometric"
-              else mg.galerkin_hierarchy_dense(op))
+              else mg.galerkin_hierarchy_dense(op, cn))
     assert len(levels) == 2
     vc = mg.VCycle(levels, omega=0.7)
     A = op.dense()
-    P = mg.prolong_2d_dense(15, 15)
+    P = mg.prolong_2d_dense(n, n)
     Ac = levels[1].dense()
     S = _smoother(A, 0.7)
     expect = S @ (np.eye(A.shape[0]) - P @ np.linalg.solve(Ac, 0.25 * P.T @ A)) @ S
