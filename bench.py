@@ -41,14 +41,14 @@ PROFILE_STRIDE = 17
 PMC_TRAFFIC = {
     # cgs_kernel<double, double, *> (FP64 Gram-Schmidt passes): per executed pass of one C3 step with
     # the FP32 V-cycle in FP64 GMRES (1080 executed of 1606 dispatches)
-    "cgs": {"bytes_per_launch": 390.01e6,
+    "cgs": {"bytes_per_launch": 390.00e6,
              "sources": ['paper_1706_06844_amd/csrc/krylov.hip', 'paper_1706_06844_amd/csrc/common.h', 'paper_1706_06844_amd/csrc/fft.h'],
-             "sha256": "44f68dea1ba3cab87f431a0e8f991c237cfd4a11034b6679c816adfe50f73970",
+             "sha256": "5dedb037bf8e81e180ab357ccde4b3c1986b2e6d8eb68f4cbb262e568bf797b9",
              "summary": "profiles/gram_schmidt_fp64_c3_2047.md"},
     # toep_y_kernel<float, float, 4096>: 1052 dispatches of the same step
-    "mg0_y": {"bytes_per_launch": 71.13e6,
+    "mg0_y": {"bytes_per_launch": 71.30e6,
               "sources": ['paper_1706_06844_amd/csrc/toeplitz.hip', 'paper_1706_06844_amd/csrc/toep_dev.h', 'paper_1706_06844_amd/csrc/fft.h', 'paper_1706_06844_amd/csrc/common.h'],
-              "sha256": "c339191e7f7891beda39fbc7aabc8c732de3811d95048165aa358443854aab3f",
+              "sha256": "bcf38c54614a936b76f9ad8a063eaa8560e6408c7fb36f9fa2848289cb37a696",
               "summary": "profiles/fft_column_pass_c3_2047.md"},
 }
 
