@@ -84,8 +84,11 @@ def parse():
     ap.add_argument("--workload", choices=["c3", "c4", "c5"], default="c3",
                     help="c3: the single 2047^2 instance (default, the headline line); c4: 64 batched "
                          "instances; c5: served requests with Poisson arrivals")
-    ap.add_argument("--c5-count", type=int, default=60, help="measured requests (after 10 warm-up)")
-    ap.add_argument("--c5-kmax", type=int, default=10, help="largest grid 2^k - 1 of the served requests")
+    ap.add_argument("--c5-count", type=int, default=60, help="measured requests")
+    ap.add_argument("--c5-warmup", type=int, default=8, help="warm-up requests before the measured ones")
+    ap.add_argument("--c5-kmax", type=int, default=11, help="largest grid 2^k - 1 of the served requests")
+    ap.add_argument("--c5-max-running", type=int, default=2,
+                    help="ungrouped requests with a restart cycle in flight at once (0: no limit)")
     ap.add_argument("--c5-qps", type=str, default="auto",
                     help="comma-separated arrival rates, or 'auto' for 50%% and 90%% of the saturation rate")
     ap.add_argument("--bf16", action="store_true",
@@ -437,14 +440,19 @@ def run_c4(args):
     print(json.dumps(line), flush=True)
 
 
-def serve(reqs, prec, budget, warm):
-    """Continuous batching: requests join the batch as they arrive and memory allows; returns
-    per-request latencies (arrival -> result copied out) of the measured requests and the span."""
+def serve(reqs, prec, budget, warm, max_running=0, group=(0, 0)):
+    """Continuous batching: requests join the batch as they arrive and memory allows; returns the
+    measured requests' latencies (arrival -> result copied out), their grid sides and the span.
+    max_running caps the ungrouped requests with a cycle in flight (least work left first); group =
+    (max_n, slots) shares batched launches among requests of one shape up to max_n."""
     import torch
 
     from paper_1706_06844_amd import fde
 
     b = fde.fde_batch_create(budget)
+    if group[0] > 0:
+        fde.fde_batch_set_grouping(b, group[0], group[1])
+    fde.fde_batch_set_policy(b, max_running)
     pending = sorted(range(len(reqs)), key=lambda i: reqs[i]["arrival"])
     queue, inflight, lat, done_t = [], {}, {}, {}
     t_start = time.perf_counter()
@@ -478,21 +486,48 @@ def serve(reqs, prec, budget, warm):
     b.close()
     meas = [i for i in range(len(reqs)) if i >= warm]
     span = max(done_t[i] for i in meas) - min(reqs[i]["arrival"] for i in meas)
-    return [lat[i] for i in meas], span
+    return [lat[i] for i in meas], [reqs[i]["hr"]["p"].n1 for i in meas], span
+
+
+def latency_stats(lat, sides, solo=None):
+    """p50/p99 over all measured requests and per grid side (ms); with the requests' latencies alone
+    on the device (solo), also of the slowdown latency / solo latency."""
+    lat_ms = np.array(lat) * 1e3
+    out = {"p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99))}
+    sl = None if solo is None else np.array(lat) / np.array(solo)
+    if sl is not None:
+        out["slowdown_p50"] = float(np.percentile(sl, 50))
+        out["slowdown_p99"] = float(np.percentile(sl, 99))
+    per = {}
+    for n in sorted(set(sides)):
+        idx = [j for j, m in enumerate(sides) if m == n]
+        v = lat_ms[idx]
+        per[str(n)] = {"count": int(v.size), "p50_ms": float(np.percentile(v, 50)),
+                       "p99_ms": float(np.percentile(v, 99))}
+        if sl is not None:
+            per[str(n)]["slowdown_p50"] = float(np.percentile(sl[idx], 50))
+            per[str(n)]["slowdown_p99"] = float(np.percentile(sl[idx], 99))
+    out["by_side"] = per
+    return out
 
 
 def run_c5(args):
     """Served requests (Poisson arrivals, seed 5): n = 2^k - 1 with k uniform in 6..kmax, 8..128
-    steps each, mixed precision and plain FP64; solves/s, CN steps/s, p50/p99 latency."""
+    steps each; solves/s, CN steps/s, p50/p99 latency overall and per grid side.  Requests up to
+    511^2 share grouped launches; the larger ones are scheduled least-work-first with at most
+    --c5-max-running cycles in flight.  Runs: saturation (all requests at t = 0), 50 % and 90 % of it
+    with that policy, and at 90 % the plain policy (every due cycle issued at once) and FP64.
+    Slowdowns divide each request's latency by its latency alone on the device (mixed precision)."""
     import workloads
 
-    warm = 10
+    warm = args.c5_warmup
     count = warm + args.c5_count
     ks = tuple(range(6, args.c5_kmax + 1))
     base = workloads.config_c5_requests(1.0, count=count, seed=5, ks=ks)
     hrs = [host_request(r.problem) for r in base]
     gaps = np.diff([0.0] + [r.arrival for r in base])  # arrivals at qps 1; scaled per run
     budget = 200 << 30
+    group = (511, 16)
 
     def reqs_at(qps):
         t = np.cumsum(gaps) / qps
@@ -501,29 +536,59 @@ def run_c5(args):
     from paper_1706_06844_amd import fde
 
     steps_meas = sum(hrs[i]["p"].M for i in range(warm, count))
-    # saturation: every request present at t = 0
-    lat0, span0 = serve(reqs_at(1e9), fde.FDE_MIXED_FP32, budget, warm)
+    # every measured request alone on the device, one after another in one batch (so that groups,
+    # once created, are reused as in the loaded runs): the reference for slowdowns
+    import torch
+
+    solo = []
+    b = fde.fde_batch_create(budget)
+    fde.fde_batch_set_grouping(b, group[0], group[1])
+    for i in range(count):
+        t0 = time.perf_counter()
+        rid = admit(b, hrs[i], fde.FDE_MIXED_FP32, 1e-9, 4000)
+        while fde.fde_batch_step(b) > 0:
+            pass
+        p = hrs[i]["p"]
+        u = torch.empty((p.n2, p.n1), dtype=torch.float64, device="cuda:0")
+        st, _ = fde.fde_batch_poll(b, rid, u)
+        assert st >= 1, (i, st)
+        if i >= warm:
+            solo.append(time.perf_counter() - t0)
+    b.close()
+    log(f"c5 solo: {sum(solo):.1f} s in all, largest {max(solo):.1f} s")
+    mix = {str(2 ** k - 1): sum(1 for i in range(warm, count) if hrs[i]["p"].n1 == 2 ** k - 1) for k in ks}
+    cap = args.c5_max_running
+    lat0, sides0, span0 = serve(reqs_at(1e9), fde.FDE_MIXED_FP32, budget, warm, cap, group)
     sat = args.c5_count / span0
-    log(f"c5 saturation: {sat:.3f} solves/s")
+    log(f"c5 saturation: {sat:.3f} solves/s ({span0:.1f} s)")
     rates = [0.5 * sat, 0.9 * sat] if args.c5_qps == "auto" else [float(q) for q in args.c5_qps.split(",")]
+    plan = [(q, "mixed", cap) for q in rates]
+    if args.c5_qps == "auto":
+        plan += [(rates[-1], "mixed", 0), (rates[-1], "fp64", cap)]
     runs = []
-    for qps in rates:
-        for name, prec in (("mixed", fde.FDE_MIXED_FP32), ("fp64", fde.FDE_FP64)):
-            lat, span = serve(reqs_at(qps), prec, budget, warm)
-            lat_ms = np.array(lat) * 1e3
-            runs.append({"qps": qps, "precision": name, "solves_per_s": args.c5_count / span,
-                         "cn_steps_per_s": steps_meas / span, "p50_ms": float(np.percentile(lat_ms, 50)),
-                         "p99_ms": float(np.percentile(lat_ms, 99))})
-            log(f"c5 qps {qps:.3f} {name}: {runs[-1]}")
-    hi = [r for r in runs if r["precision"] == "mixed"][-1]
+    for qps, name, mr in plan:
+        prec = fde.FDE_MIXED_FP32 if name == "mixed" else fde.FDE_FP64
+        lat, sides, span = serve(reqs_at(qps), prec, budget, warm, mr, group)
+        r = {"qps": qps, "precision": name, "max_running": mr, "solves_per_s": args.c5_count / span,
+             "cn_steps_per_s": steps_meas / span}
+        r.update(latency_stats(lat, sides, solo if name == "mixed" else None))
+        runs.append(r)
+        log(f"c5 qps {qps:.3f} {name} max_running {mr}: {args.c5_count / span:.3f} solves/s, "
+            f"p50 {r['p50_ms']:.0f} ms, p99 {r['p99_ms']:.0f} ms")
+    hi = [r for r in runs if r["precision"] == "mixed" and r["max_running"] == cap][-1]
     line = {
         "metric": "C5 served solves/s with p50/p99 latency (continuous batching, mixed vs FP64)",
         "value": hi["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
         "config": {"workload": f"C5: Poisson arrivals (seed 5), {args.c5_count} measured requests after "
                                f"{warm} warm-up, n = 2^k - 1 with k in 6..{args.c5_kmax}, 8..128 CN "
-                               "steps each (tau = 1/M), rtol 1e-9"},
-        "saturation_solves_per_s": sat, "saturation_cn_steps_per_s": steps_meas / span0, "runs": runs,
+                               "steps each (tau = 1/M), rtol 1e-9, FP32 V-cycle in FP64 FGMRES",
+                   "request_mix": mix,
+                   "policy": f"sides <= 511 grouped (16 slots); larger ones least work left first, at most "
+                             f"{cap} with a cycle in flight"},
+        "saturation_solves_per_s": sat, "saturation_cn_steps_per_s": steps_meas / span0,
+        "saturation_latency": latency_stats(lat0, sides0, solo), "runs": runs,
+        "solo_latency": latency_stats(solo, sides0),
     }
     print(json.dumps(line), flush=True)
 

@@ -275,6 +275,14 @@ void fde_batch_destroy(fde_batch* b);
  * holds requests. */
 int fde_batch_set_grouping(fde_batch* b, int32_t max_n, int32_t slots);
 
+/* Scheduling of the ungrouped requests: at most max_running of them have a restart cycle in flight at
+ * once; the others wait at a cycle boundary, and each free place goes to the waiting request with the
+ * least work left (n1 * n2 * remaining steps).  Small requests then pass large ones instead of sharing
+ * the device with them (preemption at restart-cycle boundaries), at the price of some concurrency.
+ * max_running = 0 (the default) issues every due cycle at once.  Results do not depend on it.  Any
+ * time; FDE_EINVAL for max_running < 0. */
+int fde_batch_set_policy(fde_batch* b, int32_t max_running);
+
 /* Admits a request: problem *p (as for fde_setup), coefficient fields (copied), initial field u0
  * (device, copied), nsteps CN steps from t0, and a separable source sum_k phi_k(t) S_k with
  * phi_k(t) = coef[k] * exp(rate[k] * t) evaluated at the half steps (nsrc <= 4; coef, rate host

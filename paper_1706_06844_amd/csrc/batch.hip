@@ -152,6 +152,7 @@ struct fde_batch {
   int group_max_n = 0;  // 0: grouping off
   int group_slots = 0;
   std::vector<Group> groups;
+  int max_running = 0;  // ungrouped requests with a cycle in flight at once (0: no limit)
 };
 
 extern "C" {
@@ -180,6 +181,12 @@ int fde_batch_set_grouping(fde_batch* b, int32_t max_n, int32_t slots) {
   if (!b->reqs.empty()) return FDE_EINVAL;
   b->group_max_n = slots > 0 ? max_n : 0;
   b->group_slots = slots;
+  return FDE_OK;
+}
+
+int fde_batch_set_policy(fde_batch* b, int32_t max_running) {
+  if (!b || max_running < 0) return FDE_EINVAL;
+  b->max_running = max_running;
   return FDE_OK;
 }
 
@@ -323,6 +330,8 @@ int fde_batch_admit(fde_batch* b, const fde_problem* p, const double* dp, const 
   return id;
 }
 
+}  // extern "C"
+
 namespace {
 
 // Advances the grouped requests: a finished group cycle is read out (members whose solve stopped
@@ -433,34 +442,52 @@ int step_groups(fde_batch* b, int* active) {
 
 }  // namespace
 
+namespace {
+
+// Starts the next CN step of an ungrouped request (its first cycle held with defer); false on error.
+bool start_step(Request& r, bool defer) {
+  // source amplitudes at the half step t^(m-1/2), m = steps_done + 1
+  const double t = r.t0 + (r.steps_done + 0.5) * r.p.tau;
+  double phi[kMaxSrc];
+  for (int k = 0; k < r.nsrc; ++k) phi[k] = r.coef[k] * std::exp(r.rate[k] * t);
+  const int rc = async_step_start(r.h, r.u[r.cur], r.nsrc, phi, r.S, defer);
+  if (rc != FDE_OK) {
+    r.state = RS_FAILED;
+    r.err = rc;
+    return false;
+  }
+  r.state = RS_RUNNING;
+  return true;
+}
+
+// Work left in a request, for the shortest-remaining-work order: unknowns times remaining steps.
+double remaining_work(const Request& r) { return (double)r.N * (double)(r.nsteps - r.steps_done); }
+
+}  // namespace
+
+extern "C" {
+
 int fde_batch_step(fde_batch* b) {
   if (!b) return FDE_EINVAL;
   int completed = 0;
+  const bool capped = b->max_running > 0;
   while (true) {
     int active = 0;
     completed += step_groups(b, &active);
+    if (!capped) {
+      for (auto& kv : b->reqs) {
+        Request& r = kv.second;
+        if (r.group < 0 && r.state == RS_START && !start_step(r, false)) ++completed;
+      }
+    }
     for (auto& kv : b->reqs) {
       Request& r = kv.second;
       if (r.group >= 0) continue;
-      if (r.state == RS_START) {
-        // source amplitudes at the half step t^(m-1/2), m = steps_done + 1
-        const double t = r.t0 + (r.steps_done + 0.5) * r.p.tau;
-        double phi[kMaxSrc];
-        for (int k = 0; k < r.nsrc; ++k) phi[k] = r.coef[k] * std::exp(r.rate[k] * t);
-        const int rc = async_step_start(r.h, r.u[r.cur], r.nsrc, phi, r.S);
-        if (rc != FDE_OK) {
-          r.state = RS_FAILED;
-          r.err = rc;
-          ++completed;
-          continue;
-        }
-        r.state = RS_RUNNING;
-      }
       if (r.state != RS_RUNNING) continue;
       ++active;
       int fin = 0;
       fde_stats st{};
-      const int rc = async_poll(r.h, &fin, &st);
+      const int rc = async_poll(r.h, &fin, &st, capped);
       if (!fin && rc == FDE_OK) continue;
       ++completed;
       r.iters += st.iters;
@@ -481,6 +508,39 @@ int fde_batch_step(fde_batch* b) {
       r.cur = nxt;
       ++r.steps_done;
       r.state = (r.steps_done >= r.nsteps) ? RS_DONE : RS_START;
+    }
+    if (capped) {
+      // at most max_running requests with a cycle in flight; the others wait at a cycle boundary, and
+      // the next cycles go to the requests with the least work left
+      int inflight = 0;
+      std::vector<std::pair<double, Request*>> wait;
+      for (auto& kv : b->reqs) {
+        Request& r = kv.second;
+        if (r.group >= 0) continue;
+        if (r.state == RS_RUNNING && !async_held(r.h)) ++inflight;
+        else if (r.state == RS_START || r.state == RS_RUNNING) wait.emplace_back(remaining_work(r), &r);
+      }
+      std::stable_sort(wait.begin(), wait.end(),
+                       [](const std::pair<double, Request*>& a, const std::pair<double, Request*>& c) {
+                         return a.first < c.first;
+                       });
+      for (auto& w : wait) {
+        if (inflight >= b->max_running) break;
+        Request& r = *w.second;
+        if (r.state == RS_START) {
+          if (!start_step(r, false)) {
+            ++completed;
+            continue;
+          }
+        } else if (async_issue(r.h) != FDE_OK) {
+          r.state = RS_FAILED;
+          r.err = FDE_EDEVICE;
+          ++completed;
+          continue;
+        }
+        ++inflight;
+        ++active;
+      }
     }
     if (completed > 0 || active == 0) break;
     std::this_thread::yield();

@@ -9,10 +9,17 @@ namespace fde {
 
 // Starts one CN step of h from u_prev (device FP64) with sources sum_k phi[k] S[k]: right-hand
 // side, first restart cycle and a state read are issued on the handle's stream; nothing waits.
-int async_step_start(fde_handle* h, const double* u_prev, int nsrc, const double* phi, const double* const* S);
+// With defer the first cycle is held instead (issued by async_issue).
+int async_step_start(fde_handle* h, const double* u_prev, int nsrc, const double* phi, const double* const* S,
+                     bool defer = false);
 // Non-blocking: *finished = 1 once the step's solve has converged or stopped (stats filled, return
-// code as fde_step's); otherwise issues the next cycle when the previous one has completed.
-int async_poll(fde_handle* h, int* finished, fde_stats* stats);
+// code as fde_step's); otherwise issues the next cycle when the previous one has completed, or with
+// defer holds it (async_held) until async_issue.
+int async_poll(fde_handle* h, int* finished, fde_stats* stats, bool defer = false);
+// Issues the held cycle of h.
+int async_issue(fde_handle* h);
+// True if h has a step in flight whose next cycle is held.
+bool async_held(const fde_handle* h);
 // Device address of the last solution (valid until the next async_step_start).
 const double* async_result(const fde_handle* h);
 hipStream_t handle_stream(const fde_handle* h);

@@ -272,6 +272,7 @@ struct fde_handle {
   // asynchronous solves (batch engine): one restart cycle per issue, optionally as a captured graph
   struct Async {
     bool active = false;
+    bool held = false;  // a cycle is due but not issued (async_poll with defer)
     int cycles = 0;
     bool use_graph = true;
     double* xsol = nullptr;  // solution of the current solve (fixed address, so graphs can bake it in)
@@ -1217,7 +1218,8 @@ int setup_impl(const fde_problem* pin, const double* dp, const double* dm, const
 
 namespace fde {
 
-int async_step_start(fde_handle* h, const double* u_prev, int nsrc, const double* phi, const double* const* S) {
+int async_step_start(fde_handle* h, const double* u_prev, int nsrc, const double* phi, const double* const* S,
+                     bool defer) {
   if (!h || !u_prev) return set_err(h, FDE_EINVAL, "bad arguments");
   if (h->as.active) return set_err(h, FDE_EINVAL, "a step is already in flight");
   if (nsrc < 0 || nsrc > kMaxSrc || (nsrc > 0 && (!phi || !S))) return set_err(h, FDE_EINVAL, "bad source list");
@@ -1238,15 +1240,28 @@ int async_step_start(fde_handle* h, const double* u_prev, int nsrc, const double
     start_solve(h, h->rhs);
     h->as.cycles = 0;
     h->as.active = true;
+    h->as.held = defer;
+    if (!defer) issue_cycle(h);
+    return FDE_OK;
+  });
+}
+
+int async_issue(fde_handle* h) {
+  if (!h || !h->as.active || !h->as.held) return set_err(h, FDE_EINVAL, "no cycle is due");
+  return guarded(h, [&]() -> int {
+    h->as.held = false;
     issue_cycle(h);
     return FDE_OK;
   });
 }
 
-int async_poll(fde_handle* h, int* finished, fde_stats* stats) {
+bool async_held(const fde_handle* h) { return h && h->as.active && h->as.held; }
+
+int async_poll(fde_handle* h, int* finished, fde_stats* stats, bool defer) {
   if (!h || !finished) return set_err(h, FDE_EINVAL, "bad arguments");
   *finished = 0;
   if (!h->as.active) return set_err(h, FDE_EINVAL, "no step in flight");
+  if (h->as.held) return FDE_OK;
   const hipError_t q = hipEventQuery(h->as.ev);
   if (q == hipErrorNotReady) return FDE_OK;
   if (q != hipSuccess) {
@@ -1258,7 +1273,8 @@ int async_poll(fde_handle* h, int* finished, fde_stats* stats) {
     ++h->as.cycles;
     const bool bad = !std::isfinite(s.resnorm);
     if (!(s.conv || s.iters >= h->p.maxit || bad)) {
-      issue_cycle(h);
+      if (defer) h->as.held = true;
+      else issue_cycle(h);
       return FDE_OK;
     }
     h->as.active = false;

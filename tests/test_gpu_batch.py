@@ -123,3 +123,37 @@ def test_graph_replays_match_eager_over_many_cycles(precision):
     assert res[rid][1] == its and its > 60
     assert rel(res[rid][0], ref) <= 1e-14
     b.close()
+
+
+@pytest.mark.parametrize("max_running", [1, 2])
+def test_policy_cap_keeps_results_and_lets_small_requests_pass(max_running):
+    # at most max_running requests with a cycle in flight, least work left first: results equal the
+    # solo runs, and a small request admitted after a large one finishes first
+    big = _instances(1, (255,), 91, 6)[0]
+    small = _instances(3, (31, 63), 92, 2)
+    b = fde.fde_batch_create(8 << 30)
+    fde.fde_batch_set_policy(b, max_running)
+    keep, ids, shapes = [], [], {}
+    for p in [big] + small:
+        ids.append(_admit(b, p, fde.FDE_MIXED_FP32, keep))
+        shapes[ids[-1]] = (p.n2, p.n1)
+    order = []
+    pending = set(ids)
+    res = {}
+    while pending:
+        fde.fde_batch_step(b)
+        for rid in list(pending):
+            n2, n1 = shapes[rid]
+            u = torch.empty((n2, n1), dtype=torch.float64, device="cuda:0")
+            st, it = fde.fde_batch_poll(b, rid, u)
+            if st:
+                assert st == 1
+                res[rid] = (host(u), it)
+                order.append(rid)
+                pending.discard(rid)
+    assert order[-1] == ids[0], order  # the large request finishes last
+    for rid, p in zip(ids, [big] + small):
+        ref, its = solo_run(p, p.M, fde.FDE_MIXED_FP32)
+        assert res[rid][1] == its
+        assert rel(res[rid][0], ref) <= 1e-14
+    b.close()
