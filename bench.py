@@ -88,7 +88,9 @@ def parse():
     ap.add_argument("--c5-warmup", type=int, default=8, help="warm-up requests before the measured ones")
     ap.add_argument("--c5-kmax", type=int, default=11, help="largest grid 2^k - 1 of the served requests")
     ap.add_argument("--c5-max-running", type=int, default=2,
-                    help="ungrouped requests with a restart cycle in flight at once (0: no limit)")
+                    help="ungrouped requests with a cycle piece in flight at once (0: no limit)")
+    ap.add_argument("--c5-piece", type=int, default=5,
+                    help="Arnoldi steps per issued piece of a restart cycle (0: whole cycles)")
     ap.add_argument("--c5-qps", type=str, default="auto",
                     help="comma-separated arrival rates, or 'auto' for 50%% and 90%% of the saturation rate")
     ap.add_argument("--bf16", action="store_true",
@@ -440,11 +442,12 @@ def run_c4(args):
     print(json.dumps(line), flush=True)
 
 
-def serve(reqs, prec, budget, warm, max_running=0, group=(0, 0)):
+def serve(reqs, prec, budget, warm, max_running=0, group=(0, 0), piece=0):
     """Continuous batching: requests join the batch as they arrive and memory allows; returns the
     measured requests' latencies (arrival -> result copied out), their grid sides and the span.
-    max_running caps the ungrouped requests with a cycle in flight (least work left first); group =
-    (max_n, slots) shares batched launches among requests of one shape up to max_n."""
+    max_running caps the ungrouped requests with a cycle piece in flight (least work left first);
+    piece > 0 issues restart cycles in pieces of that many Arnoldi steps; group = (max_n, slots)
+    shares batched launches among requests of one shape up to max_n."""
     import torch
 
     from paper_1706_06844_amd import fde
@@ -452,7 +455,7 @@ def serve(reqs, prec, budget, warm, max_running=0, group=(0, 0)):
     b = fde.fde_batch_create(budget)
     if group[0] > 0:
         fde.fde_batch_set_grouping(b, group[0], group[1])
-    fde.fde_batch_set_policy(b, max_running)
+    fde.fde_batch_set_policy(b, max_running, piece)
     pending = sorted(range(len(reqs)), key=lambda i: reqs[i]["arrival"])
     queue, inflight, lat, done_t = [], {}, {}, {}
     t_start = time.perf_counter()
@@ -475,6 +478,8 @@ def serve(reqs, prec, budget, warm, max_running=0, group=(0, 0)):
             continue
         fde.fde_batch_step(b)
         for rid, i in list(inflight.items()):
+            if fde.fde_batch_poll(b, rid)[0] == 0:  # status only: no output buffer per poll
+                continue
             p = reqs[i]["hr"]["p"]
             u = torch.empty((p.n2, p.n1), dtype=torch.float64, device="cuda:0")
             st, _ = fde.fde_batch_poll(b, rid, u)
@@ -514,9 +519,10 @@ def latency_stats(lat, sides, solo=None):
 def run_c5(args):
     """Served requests (Poisson arrivals, seed 5): n = 2^k - 1 with k uniform in 6..kmax, 8..128
     steps each; solves/s, CN steps/s, p50/p99 latency overall and per grid side.  Requests up to
-    511^2 share grouped launches; the larger ones are scheduled least-work-first with at most
-    --c5-max-running cycles in flight.  Runs: saturation (all requests at t = 0), 50 % and 90 % of it
-    with that policy, and at 90 % the plain policy (every due cycle issued at once) and FP64.
+    511^2 share grouped launches; restart cycles are issued in pieces of --c5-piece Arnoldi steps and
+    the larger requests are scheduled least-work-first with at most --c5-max-running pieces in
+    flight.  Runs: saturation (all requests at t = 0), 50 % and 90 % of it with that policy, and at
+    90 % the plain policy (whole cycles, every due cycle issued at once) and FP64.
     Slowdowns divide each request's latency by its latency alone on the device (mixed precision)."""
     import workloads
 
@@ -536,6 +542,7 @@ def run_c5(args):
     from paper_1706_06844_amd import fde
 
     steps_meas = sum(hrs[i]["p"].M for i in range(warm, count))
+    cap, piece = args.c5_max_running, args.c5_piece
     # every measured request alone on the device, one after another in one batch (so that groups,
     # once created, are reused as in the loaded runs): the reference for slowdowns
     import torch
@@ -543,6 +550,7 @@ def run_c5(args):
     solo = []
     b = fde.fde_batch_create(budget)
     fde.fde_batch_set_grouping(b, group[0], group[1])
+    fde.fde_batch_set_policy(b, 0, piece)
     for i in range(count):
         t0 = time.perf_counter()
         rid = admit(b, hrs[i], fde.FDE_MIXED_FP32, 1e-9, 4000)
@@ -557,25 +565,24 @@ def run_c5(args):
     b.close()
     log(f"c5 solo: {sum(solo):.1f} s in all, largest {max(solo):.1f} s")
     mix = {str(2 ** k - 1): sum(1 for i in range(warm, count) if hrs[i]["p"].n1 == 2 ** k - 1) for k in ks}
-    cap = args.c5_max_running
-    lat0, sides0, span0 = serve(reqs_at(1e9), fde.FDE_MIXED_FP32, budget, warm, cap, group)
+    lat0, sides0, span0 = serve(reqs_at(1e9), fde.FDE_MIXED_FP32, budget, warm, cap, group, piece)
     sat = args.c5_count / span0
     log(f"c5 saturation: {sat:.3f} solves/s ({span0:.1f} s)")
     rates = [0.5 * sat, 0.9 * sat] if args.c5_qps == "auto" else [float(q) for q in args.c5_qps.split(",")]
-    plan = [(q, "mixed", cap) for q in rates]
+    plan = [(q, "mixed", cap, piece) for q in rates]
     if args.c5_qps == "auto":
-        plan += [(rates[-1], "mixed", 0), (rates[-1], "fp64", cap)]
+        plan += [(rates[-1], "mixed", 0, 0), (rates[-1], "fp64", cap, piece)]
     runs = []
-    for qps, name, mr in plan:
+    for qps, name, mr, pc in plan:
         prec = fde.FDE_MIXED_FP32 if name == "mixed" else fde.FDE_FP64
-        lat, sides, span = serve(reqs_at(qps), prec, budget, warm, mr, group)
-        r = {"qps": qps, "precision": name, "max_running": mr, "solves_per_s": args.c5_count / span,
-             "cn_steps_per_s": steps_meas / span}
+        lat, sides, span = serve(reqs_at(qps), prec, budget, warm, mr, group, pc)
+        r = {"qps": qps, "precision": name, "max_running": mr, "piece_steps": pc,
+             "solves_per_s": args.c5_count / span, "cn_steps_per_s": steps_meas / span}
         r.update(latency_stats(lat, sides, solo if name == "mixed" else None))
         runs.append(r)
-        log(f"c5 qps {qps:.3f} {name} max_running {mr}: {args.c5_count / span:.3f} solves/s, "
+        log(f"c5 qps {qps:.3f} {name} max_running {mr} piece {pc}: {args.c5_count / span:.3f} solves/s, "
             f"p50 {r['p50_ms']:.0f} ms, p99 {r['p99_ms']:.0f} ms")
-    hi = [r for r in runs if r["precision"] == "mixed" and r["max_running"] == cap][-1]
+    hi = [r for r in runs if r["precision"] == "mixed" and r["max_running"] == cap and r["piece_steps"] == piece][-1]
     line = {
         "metric": "C5 served solves/s with p50/p99 latency (continuous batching, mixed vs FP64)",
         "value": hi["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
@@ -584,8 +591,9 @@ def run_c5(args):
                                f"{warm} warm-up, n = 2^k - 1 with k in 6..{args.c5_kmax}, 8..128 CN "
                                "steps each (tau = 1/M), rtol 1e-9, FP32 V-cycle in FP64 FGMRES",
                    "request_mix": mix,
-                   "policy": f"sides <= 511 grouped (16 slots); larger ones least work left first, at most "
-                             f"{cap} with a cycle in flight"},
+                   "policy": f"sides <= 511 grouped (16 slots); restart cycles in pieces of {piece} Arnoldi "
+                             f"steps; larger requests least work left first, at most {cap} with a piece in "
+                             "flight (the 'plain' run: whole cycles, no cap)"},
         "saturation_solves_per_s": sat, "saturation_cn_steps_per_s": steps_meas / span0,
         "saturation_latency": latency_stats(lat0, sides0, solo), "runs": runs,
         "solo_latency": latency_stats(solo, sides0),

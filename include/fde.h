@@ -275,13 +275,18 @@ void fde_batch_destroy(fde_batch* b);
  * holds requests. */
 int fde_batch_set_grouping(fde_batch* b, int32_t max_n, int32_t slots);
 
-/* Scheduling of the ungrouped requests: at most max_running of them have a restart cycle in flight at
- * once; the others wait at a cycle boundary, and each free place goes to the waiting request with the
- * least work left (n1 * n2 * remaining steps).  Small requests then pass large ones instead of sharing
- * the device with them (preemption at restart-cycle boundaries), at the price of some concurrency.
- * max_running = 0 (the default) issues every due cycle at once.  Results do not depend on it.  Any
- * time; FDE_EINVAL for max_running < 0. */
-int fde_batch_set_policy(fde_batch* b, int32_t max_running);
+/* Scheduling.  piece_steps > 0 issues every restart cycle (Sec. 5: GMRES restarted every 20 steps) in
+ * pieces of piece_steps Arnoldi steps and a tail (x update, true residual), with a read of the solver
+ * state after each piece: once a cycle has converged its remaining steps are not issued at all, and
+ * the scheduler can switch requests between pieces; 0 (the default) issues whole cycles, which keeps
+ * the device busiest when cycles run full.  Only on an empty batch when piece_steps changes.
+ * max_running > 0: at most that many ungrouped requests have a piece in flight at once; the others
+ * wait at a piece boundary, and each free place goes to the waiting request with the least work left
+ * (n1 * n2 * remaining steps), so small requests pass large ones instead of sharing the device with
+ * them (preemption at piece boundaries), at the price of some concurrency; 0 (the default) issues
+ * every due piece at once.  Results do not depend on either setting.  FDE_EINVAL for negative values
+ * or a piece change on a batch that holds requests. */
+int fde_batch_set_policy(fde_batch* b, int32_t max_running, int32_t piece_steps);
 
 /* Admits a request: problem *p (as for fde_setup), coefficient fields (copied), initial field u0
  * (device, copied), nsteps CN steps from t0, and a separable source sum_k phi_k(t) S_k with

@@ -71,12 +71,13 @@ void release(Request& r) {
   r = Request{};
 }
 
-// One capture of the group cycle: z extent nz, launches carrying the pointers of slot `base`.
+// One capture of the group cycle: z extent nz, launches carrying the pointers of slot `base`, one
+// graph per piece (the Arnoldi pieces, then the tail).
 struct CycleGraph {
   int nz = 0;
   int base = 0;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
+  std::vector<hipGraph_t> graph;
+  std::vector<hipGraphExec_t> gexec;
 };
 
 // A group: `nslots` slots of `slot_bytes` in one allocation, members by slot, the captured cycles.
@@ -89,6 +90,9 @@ struct Group {
   std::vector<int> member;  // request id per slot, -1 if empty
   long long st_off = 0;     // offset of the solver state within a slot
   std::vector<CycleGraph> cycles;  // by increasing nz; the last one has nz = nslots
+  int npieces = 0;                 // Arnoldi pieces of a cycle (the tail is piece npieces)
+  int cg = 0;                      // the capture the cycle in flight runs
+  int piece = 0;                   // the piece in flight
   long long* zt_dev = nullptr;     // slot offsets of the next cycle (nslots entries)
   long long* zt_host = nullptr;    // pinned staging of zt_dev
   hipEvent_t ev = nullptr;
@@ -122,8 +126,10 @@ std::vector<int> nz_ladder(int nslots) {
 void destroy_group(Group& g) {
   if (g.stream) (void)hipStreamSynchronize(g.stream);
   for (CycleGraph& c : g.cycles) {
-    if (c.gexec) (void)hipGraphExecDestroy(c.gexec);
-    if (c.graph) (void)hipGraphDestroy(c.graph);
+    for (hipGraphExec_t e : c.gexec)
+      if (e) (void)hipGraphExecDestroy(e);
+    for (hipGraph_t e : c.graph)
+      if (e) (void)hipGraphDestroy(e);
   }
   if (g.zt_dev) (void)hipFree(g.zt_dev);
   if (g.zt_host) (void)hipHostFree(g.zt_host);
@@ -153,6 +159,7 @@ struct fde_batch {
   int group_slots = 0;
   std::vector<Group> groups;
   int max_running = 0;  // ungrouped requests with a cycle in flight at once (0: no limit)
+  int piece_steps = 0;  // Arnoldi steps per issued piece of a restart cycle (0: whole cycles)
 };
 
 extern "C" {
@@ -184,9 +191,11 @@ int fde_batch_set_grouping(fde_batch* b, int32_t max_n, int32_t slots) {
   return FDE_OK;
 }
 
-int fde_batch_set_policy(fde_batch* b, int32_t max_running) {
-  if (!b || max_running < 0) return FDE_EINVAL;
+int fde_batch_set_policy(fde_batch* b, int32_t max_running, int32_t piece_steps) {
+  if (!b || max_running < 0 || piece_steps < 0) return FDE_EINVAL;
+  if (piece_steps != b->piece_steps && !b->reqs.empty()) return FDE_EINVAL;
   b->max_running = max_running;
+  b->piece_steps = piece_steps;
   return FDE_OK;
 }
 
@@ -275,28 +284,36 @@ int fde_batch_admit(fde_batch* b, const fde_problem* p, const double* dp, const 
       release(r);
       return rc;
     }
+    if (async_set_piece(r.h, b->piece_steps) != FDE_OK) return fail(FDE_EINVAL, "piece setting failed");
     if (g.cycles.empty()) {
       // the first member (slot 0) lays out the slots: empty ones get the idle state, and the cycle is
       // captured for every z extent of the ladder, with slot 0's pointers
       g.st_off = group_state_offset(r.h);
       for (int s = 1; s < g.nslots; ++s)
         if (mark_idle(g, s) != hipSuccess) return fail(FDE_EDEVICE, "initialising the slots failed");
+      g.npieces = group_pieces(r.h);
       for (int nz : nz_ladder(g.nslots)) {
-        CycleGraph c;
+        g.cycles.emplace_back();
+        CycleGraph& c = g.cycles.back();
         c.nz = nz;
         c.base = si;
-        const int cr = group_capture_cycle(r.h, nz, g.zt_dev, &c.graph, &c.gexec);
-        if (cr != FDE_OK) {
-          b->err = fde_last_error(r.h);
-          for (CycleGraph& d : g.cycles) {
-            (void)hipGraphExecDestroy(d.gexec);
-            (void)hipGraphDestroy(d.graph);
+        c.graph.assign(g.npieces + 1, nullptr);
+        c.gexec.assign(g.npieces + 1, nullptr);
+        for (int pc = 0; pc <= g.npieces; ++pc) {
+          const int cr = group_capture_piece(r.h, nz, g.zt_dev, pc, &c.graph[pc], &c.gexec[pc]);
+          if (cr != FDE_OK) {
+            b->err = fde_last_error(r.h);
+            for (CycleGraph& d : g.cycles) {
+              for (hipGraphExec_t e : d.gexec)
+                if (e) (void)hipGraphExecDestroy(e);
+              for (hipGraph_t e : d.graph)
+                if (e) (void)hipGraphDestroy(e);
+            }
+            g.cycles.clear();
+            release(r);
+            return cr;
           }
-          g.cycles.clear();
-          release(r);
-          return cr;
         }
-        g.cycles.push_back(c);
       }
     }
   } else {
@@ -308,6 +325,7 @@ int fde_batch_admit(fde_batch* b, const fde_problem* p, const double* dp, const 
       release(r);
       return rc;
     }
+    if (async_set_piece(r.h, b->piece_steps) != FDE_OK) return fail(FDE_EINVAL, "piece setting failed");
   }
   for (double*& q : r.u)
     if (hipMalloc(&q, N * sizeof(double)) != hipSuccess) return fail(FDE_ENOMEM, "device allocation failed");
@@ -334,21 +352,44 @@ int fde_batch_admit(fde_batch* b, const fde_problem* p, const double* dp, const 
 
 namespace {
 
-// Advances the grouped requests: a finished group cycle is read out (members whose solve stopped
-// complete their step), members waiting for a step start it, and the next cycle is issued.  Returns
-// the number of steps completed; *active counts the groups with work in flight.
+// Issues piece pc of the group's current cycle and the read-back of the slots' states.
+hipError_t launch_piece(Group& g, int pc) {
+  g.piece = pc;
+  hipError_t e = hipGraphLaunch(g.cycles[g.cg].gexec[pc], g.stream);
+  if (e == hipSuccess)
+    e = hipMemcpy2DAsync(g.hst, sizeof(GmresState), g.arena + g.st_off, g.slot_bytes, kStatePrefix, g.nslots,
+                         hipMemcpyDeviceToHost, g.stream);
+  if (e == hipSuccess) e = hipEventRecord(g.ev, g.stream);
+  return e;
+}
+
+// Advances the grouped requests: after an Arnoldi piece of the group cycle the next one is issued
+// while a member's cycle goes on (else the tail); a finished cycle is read out (members whose solve
+// stopped complete their step), members waiting for a step start it, and the next cycle is issued.
+// Returns the number of steps completed; *active counts the groups with work in flight.
 int step_groups(fde_batch* b, int* active) {
   int completed = 0;
   for (int gi = 0; gi < (int)b->groups.size(); ++gi) {
     Group& g = b->groups[gi];
     if (!g.arena || g.cycles.empty()) continue;
     if (g.inflight) {
-      const hipError_t q = hipEventQuery(g.ev);
+      hipError_t q = hipEventQuery(g.ev);
       if (q == hipErrorNotReady) {
         ++*active;
         continue;
       }
       g.inflight = false;
+      if (q == hipSuccess && g.piece < g.npieces) {
+        bool more = false;
+        for (int s = 0; s < g.nslots && g.piece + 1 < g.npieces; ++s)
+          if (g.member[s] >= 0 && b->reqs.at(g.member[s]).state == RS_RUNNING && !g.hst[s].done) more = true;
+        q = launch_piece(g, more ? g.piece + 1 : g.npieces);
+        if (q == hipSuccess) {
+          g.inflight = true;
+          ++*active;
+          continue;
+        }
+      }
       for (int s = 0; s < g.nslots; ++s) {
         if (g.member[s] < 0) continue;
         Request& r = b->reqs.at(g.member[s]);
@@ -410,19 +451,17 @@ int step_groups(fde_batch* b, int* active) {
       if (r.state == RS_RUNNING) run.push_back(s);
     }
     if (run.empty()) continue;
-    const CycleGraph* cg = &g.cycles.back();
-    for (const CycleGraph& c : g.cycles)
-      if (c.nz >= (int)run.size()) {
-        cg = &c;
+    g.cg = (int)g.cycles.size() - 1;
+    for (int c = 0; c < (int)g.cycles.size(); ++c)
+      if (g.cycles[c].nz >= (int)run.size()) {
+        g.cg = c;
         break;
       }
-    for (int z = 0; z < cg->nz; ++z)
-      g.zt_host[z] = z < (int)run.size() ? (long long)(run[z] - cg->base) * (long long)g.slot_bytes : kZSkip;
-    if (hipMemcpyAsync(g.zt_dev, g.zt_host, sizeof(long long) * cg->nz, hipMemcpyHostToDevice, g.stream) != hipSuccess ||
-        hipGraphLaunch(cg->gexec, g.stream) != hipSuccess ||
-        hipMemcpy2DAsync(g.hst, sizeof(GmresState), g.arena + g.st_off, g.slot_bytes, kStatePrefix, g.nslots,
-                         hipMemcpyDeviceToHost, g.stream) != hipSuccess ||
-        hipEventRecord(g.ev, g.stream) != hipSuccess) {
+    const CycleGraph& cg = g.cycles[g.cg];
+    for (int z = 0; z < cg.nz; ++z)
+      g.zt_host[z] = z < (int)run.size() ? (long long)(run[z] - cg.base) * (long long)g.slot_bytes : kZSkip;
+    if (hipMemcpyAsync(g.zt_dev, g.zt_host, sizeof(long long) * cg.nz, hipMemcpyHostToDevice, g.stream) != hipSuccess ||
+        launch_piece(g, 0) != hipSuccess) {
       for (int s = 0; s < g.nslots; ++s) {
         if (g.member[s] < 0) continue;
         Request& r = b->reqs.at(g.member[s]);

@@ -20,6 +20,9 @@ int async_poll(fde_handle* h, int* finished, fde_stats* stats, bool defer = fals
 int async_issue(fde_handle* h);
 // True if h has a step in flight whose next cycle is held.
 bool async_held(const fde_handle* h);
+// Issues each restart cycle in pieces of `steps` Arnoldi steps plus a tail (0: one piece); the host
+// stops issuing pieces once the cycle is done.  Not while a step is in flight.
+int async_set_piece(fde_handle* h, int steps);
 // Device address of the last solution (valid until the next async_step_start).
 const double* async_result(const fde_handle* h);
 hipStream_t handle_stream(const fde_handle* h);
@@ -39,10 +42,15 @@ int group_setup(const fde_problem* p, const double* dp, const double* dm, const 
 long long group_state_offset(const fde_handle* h);
 // Starts a CN step of one member on its stream: right-hand side, x = 0 and the norm of b (no cycle).
 int group_step_start(fde_handle* h, const double* u_prev, int nsrc, const double* phi, const double* const* S);
-// Captures one restart cycle as a graph whose every launch has grid z extent nz: the launches carry
-// the pointers of h's slot, and workgroup z works on the slot ztab[z] bytes away (device table of nz
-// entries, read when the graph runs; kZSkip entries are padding).
-int group_capture_cycle(fde_handle* h, int nz, const long long* ztab, hipGraph_t* graph, hipGraphExec_t* gexec);
+// A restart cycle runs as group_pieces(h) pieces of Arnoldi steps (each skips its steps on the device
+// once the cycle is done, so the host may stop issuing them) and a tail, piece group_pieces(h):
+// x += Z y and the true residual.
+int group_pieces(const fde_handle* h);
+// Captures one piece of the cycle as a graph whose every launch has grid z extent nz: the launches
+// carry the pointers of h's slot, and workgroup z works on the slot ztab[z] bytes away (device table
+// of nz entries, read when the graph runs; kZSkip entries are padding).
+int group_capture_piece(fde_handle* h, int nz, const long long* ztab, int piece, hipGraph_t* graph,
+                        hipGraphExec_t* gexec);
 // After a cycle: *finished = 1 if the member's solve stopped (stats filled, fde_step's return code).
 int group_step_result(fde_handle* h, const GmresState& s, int cycles, int* finished, fde_stats* stats);
 // Whether problems of this shape can be advanced by batched launches.

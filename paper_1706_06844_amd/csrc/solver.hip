@@ -272,13 +272,16 @@ struct fde_handle {
   // asynchronous solves (batch engine): one restart cycle per issue, optionally as a captured graph
   struct Async {
     bool active = false;
-    bool held = false;  // a cycle is due but not issued (async_poll with defer)
+    bool held = false;  // a piece is due but not issued (async_poll with defer)
     int cycles = 0;
+    int piece = 0;      // the piece in flight (or last issued)
+    int due = 0;        // the piece to issue next while held
+    int piece_len = 0;  // Arnoldi steps per piece (0: the whole cycle in one piece)
     bool use_graph = true;
     double* xsol = nullptr;  // solution of the current solve (fixed address, so graphs can bake it in)
     hipEvent_t ev = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
+    std::vector<hipGraph_t> graph;  // per piece
+    std::vector<hipGraphExec_t> gexec;
   } as;
   Prof prof;
   std::string err;
@@ -1164,50 +1167,76 @@ int guarded(fde_handle* h, F&& f);
 
 // ---- asynchronous solves -------------------------------------------------------------------------
 // The solve of h->rhs into h->as.xsol as a sequence of restart cycles, each issued without waiting:
-// restart Arnoldi steps (skipped on the device once the cycle is done), x += Z y, the FP64 true
-// residual and its norm.  The pointers are fixed, so the cycle is captured once as a HIP graph and
-// replayed.  Results equal those of fde_solve: the same kernels run in the same order.
+// A restart cycle issued in pieces: Arnoldi steps in runs of piece_len (each step skips itself on
+// the device once the cycle is done), then the tail: x += Z y, the FP64 true residual and its norm.
+// After each piece the host reads the state; once the cycle is done the remaining Arnoldi pieces are
+// not issued at all (their kernels would only have skipped), so a cycle that stops early costs no
+// dispatches for its unused steps, and a scheduler can switch requests between pieces.  The pointers
+// are fixed, so every piece is captured once as a HIP graph and replayed.  Results equal those of
+// fde_solve: the same kernels run in the same order.
+int piece_steps(const fde_handle* h) {
+  return (h->as.piece_len > 0 && h->as.piece_len < h->p.restart) ? h->as.piece_len : h->p.restart;
+}
+int arnoldi_pieces(const fde_handle* h) { return (h->p.restart + piece_steps(h) - 1) / piece_steps(h); }
+
 template <typename R>
-void cycle_body(fde_handle* h, Hierarchy<R>& H) {
-  const size_t N = h->N;
-  for (int j = 0; j < h->p.restart; ++j) arnoldi<R>(h, H, j);
-  HIPCHECK(launch_update_x<R>(N, static_cast<const R*>(h->Z), h->ldv, h->as.xsol, 0, h->st, h->stream));
+void cycle_piece(fde_handle* h, Hierarchy<R>& H, int piece) {
+  if (piece < arnoldi_pieces(h)) {
+    const int len = piece_steps(h);
+    const int j1 = std::min(h->p.restart, (piece + 1) * len);
+    for (int j = piece * len; j < j1; ++j) arnoldi<R>(h, H, j);
+    return;
+  }
+  HIPCHECK(launch_update_x<R>(h->N, static_cast<const R*>(h->Z), h->ldv, h->as.xsol, 0, h->st, h->stream));
   restart_residual(h, h->rhs, h->as.xsol);
 }
 
-void issue_cycle(fde_handle* h) {
-  auto body = [&] {
-    if (h->fp32()) cycle_body<float>(h, *h->h32);
-    else cycle_body<double>(h, *h->h64);
-  };
-  if (h->as.use_graph && !h->prof.mask) {
-    if (!h->as.gexec) {
-      HIPCHECK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-      try {
-        body();
-      } catch (...) {
-        hipGraph_t g = nullptr;
-        (void)hipStreamEndCapture(h->stream, &g);
-        if (g) (void)hipGraphDestroy(g);
-        throw;
-      }
-      HIPCHECK(hipStreamEndCapture(h->stream, &h->as.graph));
-      HIPCHECK(hipGraphInstantiate(&h->as.gexec, h->as.graph, nullptr, nullptr, 0));
-    }
-    HIPCHECK(hipGraphLaunch(h->as.gexec, h->stream));
-  } else {
-    body();
+void piece_body(fde_handle* h, int piece) {
+  if (h->fp32()) cycle_piece<float>(h, *h->h32, piece);
+  else cycle_piece<double>(h, *h->h64, piece);
+}
+
+// Captures piece `piece` of the cycle on h's stream (launches as the current batch context sets).
+void capture_piece(fde_handle* h, int piece, hipGraph_t* graph, hipGraphExec_t* gexec) {
+  HIPCHECK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+  try {
+    piece_body(h, piece);
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(h->stream, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
   }
+  HIPCHECK(hipStreamEndCapture(h->stream, graph));
+  HIPCHECK(hipGraphInstantiate(gexec, *graph, nullptr, nullptr, 0));
+}
+
+void issue_piece(fde_handle* h, int piece) {
+  if (h->as.use_graph && !h->prof.mask) {
+    const size_t np = (size_t)arnoldi_pieces(h) + 1;
+    if (h->as.gexec.size() != np) {
+      h->as.graph.assign(np, nullptr);
+      h->as.gexec.assign(np, nullptr);
+    }
+    if (!h->as.gexec[piece]) capture_piece(h, piece, &h->as.graph[piece], &h->as.gexec[piece]);
+    HIPCHECK(hipGraphLaunch(h->as.gexec[piece], h->stream));
+  } else {
+    piece_body(h, piece);
+  }
+  h->as.piece = piece;
   HIPCHECK(hipMemcpyAsync(h->st_host, h->st, offsetof(GmresState, rtol), hipMemcpyDeviceToHost, h->stream));
   HIPCHECK(hipEventRecord(h->as.ev, h->stream));
 }
 
+
 // Graphs bake in the hierarchy's buffers: drop them when the hierarchy is rebuilt.
 void drop_graph(fde_handle* h) {
-  if (h->as.gexec) (void)hipGraphExecDestroy(h->as.gexec);
-  if (h->as.graph) (void)hipGraphDestroy(h->as.graph);
-  h->as.gexec = nullptr;
-  h->as.graph = nullptr;
+  for (hipGraphExec_t& g : h->as.gexec)
+    if (g) (void)hipGraphExecDestroy(g);
+  for (hipGraph_t& g : h->as.graph)
+    if (g) (void)hipGraphDestroy(g);
+  h->as.gexec.clear();
+  h->as.graph.clear();
 }
 
 // fde_setup, optionally carving every buffer from a fixed region (a slot of a batched group)
@@ -1241,7 +1270,8 @@ int async_step_start(fde_handle* h, const double* u_prev, int nsrc, const double
     h->as.cycles = 0;
     h->as.active = true;
     h->as.held = defer;
-    if (!defer) issue_cycle(h);
+    h->as.due = 0;
+    if (!defer) issue_piece(h, 0);
     return FDE_OK;
   });
 }
@@ -1250,12 +1280,22 @@ int async_issue(fde_handle* h) {
   if (!h || !h->as.active || !h->as.held) return set_err(h, FDE_EINVAL, "no cycle is due");
   return guarded(h, [&]() -> int {
     h->as.held = false;
-    issue_cycle(h);
+    issue_piece(h, h->as.due);
     return FDE_OK;
   });
 }
 
 bool async_held(const fde_handle* h) { return h && h->as.active && h->as.held; }
+
+int async_set_piece(fde_handle* h, int steps) {
+  if (!h || steps < 0) return set_err(h, FDE_EINVAL, "bad arguments");
+  if (h->as.active) return set_err(h, FDE_EINVAL, "a step is in flight");
+  if (steps != h->as.piece_len) {
+    drop_graph(h);
+    h->as.piece_len = steps;
+  }
+  return FDE_OK;
+}
 
 int async_poll(fde_handle* h, int* finished, fde_stats* stats, bool defer) {
   if (!h || !finished) return set_err(h, FDE_EINVAL, "bad arguments");
@@ -1270,11 +1310,27 @@ int async_poll(fde_handle* h, int* finished, fde_stats* stats, bool defer) {
   }
   return guarded(h, [&]() -> int {
     const GmresState s = *h->st_host;
+    const int np = arnoldi_pieces(h);
+    if (h->as.piece < np) {
+      // an Arnoldi piece: the next one while the cycle goes on, else the tail
+      const int next = (!s.done && h->as.piece + 1 < np) ? h->as.piece + 1 : np;
+      if (defer) {
+        h->as.held = true;
+        h->as.due = next;
+      } else {
+        issue_piece(h, next);
+      }
+      return FDE_OK;
+    }
     ++h->as.cycles;
     const bool bad = !std::isfinite(s.resnorm);
     if (!(s.conv || s.iters >= h->p.maxit || bad)) {
-      if (defer) h->as.held = true;
-      else issue_cycle(h);
+      if (defer) {
+        h->as.held = true;
+        h->as.due = 0;
+      } else {
+        issue_piece(h, 0);
+      }
       return FDE_OK;
     }
     h->as.active = false;
@@ -1327,22 +1383,15 @@ int group_step_start(fde_handle* h, const double* u_prev, int nsrc, const double
   });
 }
 
-int group_capture_cycle(fde_handle* h, int nz, const long long* ztab, hipGraph_t* graph, hipGraphExec_t* gexec) {
-  if (!h || !h->arena.base || nz < 1) return set_err(h, FDE_EINVAL, "bad arguments");
+int group_pieces(const fde_handle* h) { return arnoldi_pieces(h); }
+
+int group_capture_piece(fde_handle* h, int nz, const long long* ztab, int piece, hipGraph_t* graph,
+                        hipGraphExec_t* gexec) {
+  if (!h || !h->arena.base || nz < 1 || piece < 0 || piece > arnoldi_pieces(h))
+    return set_err(h, FDE_EINVAL, "bad arguments");
   return guarded(h, [&]() -> int {
     BatchScope bs(nz, ztab);
-    HIPCHECK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-    try {
-      if (h->fp32()) cycle_body<float>(h, *h->h32);
-      else cycle_body<double>(h, *h->h64);
-    } catch (...) {
-      hipGraph_t g = nullptr;
-      (void)hipStreamEndCapture(h->stream, &g);
-      if (g) (void)hipGraphDestroy(g);
-      throw;
-    }
-    HIPCHECK(hipStreamEndCapture(h->stream, graph));
-    HIPCHECK(hipGraphInstantiate(gexec, *graph, nullptr, nullptr, 0));
+    capture_piece(h, piece, graph, gexec);
     return FDE_OK;
   });
 }
@@ -1617,8 +1666,7 @@ void fde_destroy(fde_handle* h) {
   if (!h) return;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   else (void)hipDeviceSynchronize();
-  if (h->as.gexec) (void)hipGraphExecDestroy(h->as.gexec);
-  if (h->as.graph) (void)hipGraphDestroy(h->as.graph);
+  drop_graph(h);
   if (h->as.ev) (void)hipEventDestroy(h->as.ev);
   if (h->st_host) (void)hipHostFree(h->st_host);
   delete h;

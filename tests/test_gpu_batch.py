@@ -125,14 +125,15 @@ def test_graph_replays_match_eager_over_many_cycles(precision):
     b.close()
 
 
-@pytest.mark.parametrize("max_running", [1, 2])
-def test_policy_cap_keeps_results_and_lets_small_requests_pass(max_running):
-    # at most max_running requests with a cycle in flight, least work left first: results equal the
-    # solo runs, and a small request admitted after a large one finishes first
+@pytest.mark.parametrize("max_running,piece", [(1, 0), (2, 5), (1, 3)])
+def test_policy_cap_keeps_results_and_lets_small_requests_pass(max_running, piece):
+    # at most max_running requests with a piece in flight, least work left first, cycles in pieces of
+    # `piece` Arnoldi steps: results equal the solo runs, and small requests admitted after a large one
+    # finish first
     big = _instances(1, (255,), 91, 6)[0]
     small = _instances(3, (31, 63), 92, 2)
     b = fde.fde_batch_create(8 << 30)
-    fde.fde_batch_set_policy(b, max_running)
+    fde.fde_batch_set_policy(b, max_running, piece)
     keep, ids, shapes = [], [], {}
     for p in [big] + small:
         ids.append(_admit(b, p, fde.FDE_MIXED_FP32, keep))
@@ -156,4 +157,29 @@ def test_policy_cap_keeps_results_and_lets_small_requests_pass(max_running):
         ref, its = solo_run(p, p.M, fde.FDE_MIXED_FP32)
         assert res[rid][1] == its
         assert rel(res[rid][0], ref) <= 1e-14
+    b.close()
+
+
+@pytest.mark.parametrize("precision", [fde.FDE_FP64, fde.FDE_MIXED_CYCLE_BF16])
+def test_cycles_in_pieces_equal_whole_cycles(precision):
+    # restart cycles issued in pieces of 4 Arnoldi steps (the rest of a converged cycle not issued):
+    # the same kernels in the same order as whole cycles, so results and counts equal the solo runs
+    probs = _instances(4, (63, 127, 255), 93, 3)
+    b = fde.fde_batch_create(8 << 30)
+    fde.fde_batch_set_policy(b, 0, 4)
+    keep, ids, shapes = [], [], {}
+    for p in probs:
+        ids.append(_admit(b, p, precision, keep))
+        shapes[ids[-1]] = (p.n2, p.n1)
+    res = _drain(b, ids, shapes)
+    for rid, p in zip(ids, probs):
+        ref, its = solo_run(p, p.M, precision)
+        assert res[rid][1] == its
+        assert rel(res[rid][0], ref) <= 1e-14
+    # the piece length is fixed while requests are resident; the cap may change at any time
+    rid = _admit(b, probs[0], precision, keep)
+    with pytest.raises(fde.FdeError):
+        fde.fde_batch_set_policy(b, 0, 5)
+    fde.fde_batch_set_policy(b, 2, 4)
+    _drain(b, [rid], {rid: (probs[0].n2, probs[0].n1)})
     b.close()

@@ -1,5 +1,6 @@
-"""Grouped batching: requests of one shape share a group whose restart cycle is one captured graph
-with every kernel launched over all slots (grid z = slot).
+"""Grouped batching: requests of one shape share a group whose restart cycle is replayed from captured
+graphs whose every kernel is launched once over the members that solve (grid z indexes a table of
+their slot offsets).
 
 Each member must give what the same problem gives alone (fde_step_sources on its own handle: the same
 kernels over the same data, so the same result to rounding-free equality in practice, asserted to
@@ -66,13 +67,16 @@ def _check_solo(res, ids, probs, precision, **kw):
         assert rel(got, ref) <= 1e-14
 
 
-@pytest.mark.parametrize("precision", [fde.FDE_FP64, fde.FDE_MIXED_FP32, fde.FDE_MIXED_FP32_CYCLE,
-                                       fde.FDE_MIXED_CYCLE_BF16])
-def test_group_members_equal_solo(precision):
-    # 5 members in a group of 8 slots (3 stay empty); different orders, coefficients and sources
+@pytest.mark.parametrize("precision,piece", [(fde.FDE_FP64, 0), (fde.FDE_MIXED_FP32, 0),
+                                             (fde.FDE_MIXED_FP32_CYCLE, 0), (fde.FDE_MIXED_CYCLE_BF16, 0),
+                                             (fde.FDE_MIXED_FP32, 5), (fde.FDE_FP64, 3)])
+def test_group_members_equal_solo(precision, piece):
+    # 5 members in a group of 8 slots (3 stay empty); different orders, coefficients and sources;
+    # cycles whole or in pieces of `piece` Arnoldi steps
     probs = _instances(5, (63,), 21, 3)
     b = fde.fde_batch_create(8 << 30)
     fde.fde_batch_set_grouping(b, 127, 8)
+    fde.fde_batch_set_policy(b, 0, piece)
     keep, ids, shapes = [], [], {}
     for p in probs:
         ids.append(_admit(b, p, precision, keep))
