@@ -295,6 +295,11 @@ __device__ __forceinline__ T* zshift(T* p, long long zoff) {
   const long long zoff = ztab ? ztab[blockIdx.z] : 0ll;             \
   if (zoff == kZSkip) return
 #define FDE_ZSHIFT(p) (p = zshift(p, zoff))
+// The same for kernels instantiated with and without batching (ZB a template parameter): without,
+// the table lookup and every shift fold away.
+#define FDE_ZBEGIN_IF(ZB)                                \
+  const long long zoff = (ZB) ? ztab[blockIdx.z] : 0ll;  \
+  if ((ZB) && zoff == kZSkip) return
 
 // Reads a device flag (the skip flag of speculatively issued Arnoldi steps) with a vector load: the
 // index is an opaque zero in a vector register, so that waiting for the flag does not also wait for

@@ -36,12 +36,12 @@ __device__ __forceinline__ R epilogue_value(R l, Tin xv, R bv, R dv, double srcv
   else return (R)xv + l + (R)(tau * srcv);  // EP_RHS
 }
 
-template <typename R, typename Tin, int L, int MODE>
+template <typename R, typename Tin, int L, int MODE, bool ZB>
 __global__ __launch_bounds__((XCfg<R, L>::THREADS), FDE_XW) void toep_x_kernel(
     int n1, int n2, const Tin* x, const R* __restrict__ dpm, const R* __restrict__ mu,
     const R* __restrict__ twtab, const R* __restrict__ ay, const R* __restrict__ b,
     const R* __restrict__ dinv, SrcTerms src, double tau, R* out, const int* __restrict__ skip, const long long* __restrict__ ztab) {
-  FDE_ZBEGIN;
+  FDE_ZBEGIN_IF(ZB);
   // batched launches: every per-instance pointer (the source terms of EP_RHS are never batched)
   FDE_ZSHIFT(x);
   FDE_ZSHIFT(dpm);
@@ -130,11 +130,11 @@ __global__ __launch_bounds__((XCfg<R, L>::THREADS), FDE_XW) void toep_x_kernel(
   });
 }
 
-template <typename R, typename Tin, int L>
+template <typename R, typename Tin, int L, bool ZB>
 __global__ __launch_bounds__((YCfg<R, L>::THREADS), FDE_YW) void toep_y_kernel(
     int n1, int n2, const Tin* __restrict__ x, const R* __restrict__ epm, const R* __restrict__ mu,
     const R* __restrict__ twtab, R* __restrict__ ay, int nstrips, const int* __restrict__ skip, const long long* __restrict__ ztab) {
-  FDE_ZBEGIN;
+  FDE_ZBEGIN_IF(ZB);
   FDE_ZSHIFT(x);
   FDE_ZSHIFT(epm);
   FDE_ZSHIFT(mu);
@@ -203,8 +203,14 @@ static hipError_t launch_y(const OpView<R>& op, const Tin* x, R* ay, const int* 
   constexpr int S = YCfg<R, L>::S;
   const int nstrips = ceil_div(op.n1, 2 * S);
   const int grid = 8 * ceil_div(nstrips, 8);
-  hipLaunchKernelGGL((toep_y_kernel<R, Tin, L>), dim3(grid, 1, batch_nz()), dim3(YCfg<R, L>::THREADS), 0, st, op.n1,
-                     op.n2, x, op.epm, op.mu_y, op.tw_y, ay, nstrips, skip, batch_ztab());
+  // batched launches (grid z over a slot table) run their own instantiation; the plain one carries
+  // no table lookup
+  if (batch_ztab())
+    hipLaunchKernelGGL((toep_y_kernel<R, Tin, L, true>), dim3(grid, 1, batch_nz()), dim3(YCfg<R, L>::THREADS), 0, st,
+                       op.n1, op.n2, x, op.epm, op.mu_y, op.tw_y, ay, nstrips, skip, batch_ztab());
+  else
+    hipLaunchKernelGGL((toep_y_kernel<R, Tin, L, false>), dim3(grid, 1, 1), dim3(YCfg<R, L>::THREADS), 0, st, op.n1,
+                       op.n2, x, op.epm, op.mu_y, op.tw_y, ay, nstrips, skip, nullptr);
   return hipGetLastError();
 }
 
@@ -212,8 +218,18 @@ template <typename R, typename Tin, int L, int MODE>
 static hipError_t launch_x_mode(const OpView<R>& op, const Tin* x, const R* ay, R* out, const R* b,
                                 const SrcTerms& src, double tau, const int* skip, hipStream_t st) {
   const int grid = ceil_div(op.n2, 2 * XCfg<R, L>::S);
-  hipLaunchKernelGGL((toep_x_kernel<R, Tin, L, MODE>), dim3(grid, 1, batch_nz()), dim3((XCfg<R, L>::THREADS)), 0, st,
-                     op.n1, op.n2, x, op.dpm, op.mu_x, op.tw_x, ay, b, op.dinv, src, tau, out, skip, batch_ztab());
+  if (batch_ztab()) {
+    // the epilogues of a restart cycle (the right-hand side is assembled per instance)
+    if constexpr (MODE == EP_APPLY || MODE == EP_RESID || MODE == EP_JACOBI)
+      hipLaunchKernelGGL((toep_x_kernel<R, Tin, L, MODE, true>), dim3(grid, 1, batch_nz()), dim3((XCfg<R, L>::THREADS)),
+                         0, st, op.n1, op.n2, x, op.dpm, op.mu_x, op.tw_x, ay, b, op.dinv, src, tau, out, skip,
+                         batch_ztab());
+    else
+      return hipErrorInvalidValue;
+  } else {
+    hipLaunchKernelGGL((toep_x_kernel<R, Tin, L, MODE, false>), dim3(grid, 1, 1), dim3((XCfg<R, L>::THREADS)), 0, st,
+                       op.n1, op.n2, x, op.dpm, op.mu_x, op.tw_x, ay, b, op.dinv, src, tau, out, skip, nullptr);
+  }
   return hipGetLastError();
 }
 
