@@ -146,3 +146,34 @@ def test_grouping_arguments():
         fde.fde_batch_set_grouping(b, 127, 4)
     _drain(b, [rid], {rid: (p.n2, p.n1)})
     b.close()
+
+
+@pytest.mark.parametrize("precision", [fde.FDE_MIXED_FP32, fde.FDE_FP64])
+def test_group_with_fft_levels_equals_solo(precision):
+    # 511^2 members: the outer operator and the fine levels run the FFT passes in their batched
+    # instantiation (slot table), the coarser ones the tiled and one-workgroup kernels
+    probs = _instances(3, (511,), 71, 2)
+    b = fde.fde_batch_create(16 << 30)
+    fde.fde_batch_set_grouping(b, 511, 4)
+    keep, ids, shapes = [], [], {}
+    for p in probs:
+        ids.append(_admit(b, p, precision, keep))
+        shapes[ids[-1]] = (p.n2, p.n1)
+    res = _drain(b, ids, shapes)
+    _check_solo(res, ids, probs, precision)
+    b.close()
+
+
+def test_group_on_even_sides_equals_solo():
+    # the paper's even grids in a group: 64^2 -> 32 -> 16 -> 8
+    probs = _instances(3, (64,), 73, 3)
+    b = fde.fde_batch_create(8 << 30)
+    fde.fde_batch_set_grouping(b, 64, 4)
+    fde.fde_batch_set_policy(b, 0, 5)
+    keep, ids, shapes = [], [], {}
+    for p in probs:
+        ids.append(_admit(b, p, fde.FDE_MIXED_FP32, keep))
+        shapes[ids[-1]] = (p.n2, p.n1)
+    res = _drain(b, ids, shapes)
+    _check_solo(res, ids, probs, fde.FDE_MIXED_FP32)
+    b.close()
