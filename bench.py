@@ -43,12 +43,12 @@ PMC_TRAFFIC = {
     # the FP32 V-cycle in FP64 GMRES (1080 executed of 1606 dispatches)
     "cgs": {"bytes_per_launch": 390.00e6,
              "sources": ['paper_1706_06844_amd/csrc/krylov.hip', 'paper_1706_06844_amd/csrc/common.h', 'paper_1706_06844_amd/csrc/fft.h'],
-             "sha256": "bac39204770ba626a8a90dd386b4be86796eeb7cedcaa75d39ce59db5fb55e80",
+             "sha256": "5f4536c500e2326c4c0e254f4e5ff7ba1d5c8cb1b33bf21c2b10e2c3f14644be",
              "summary": "profiles/gram_schmidt_fp64_c3_2047.md"},
     # toep_y_kernel<float, float, 4096, false>: 1052 dispatches of the same step
-    "mg0_y": {"bytes_per_launch": 71.16e6,
+    "mg0_y": {"bytes_per_launch": 71.09e6,
               "sources": ['paper_1706_06844_amd/csrc/toeplitz.hip', 'paper_1706_06844_amd/csrc/toep_dev.h', 'paper_1706_06844_amd/csrc/fft.h', 'paper_1706_06844_amd/csrc/common.h'],
-              "sha256": "a70511ff4230dda8b3d58c9f08e7498c47a65c76189a9004b4bef7e567255aa8",
+              "sha256": "3ccbb63e63c2499e78020ff78c1b6fddeb7cee254663b2d9ed880219f5b290f8",
               "summary": "profiles/fft_column_pass_c3_2047.md"},
 }
 

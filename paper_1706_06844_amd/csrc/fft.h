@@ -1,7 +1,8 @@
 // Register-resident Stockham FFT for one power-of-two length L per group of T = L/E threads.
 //
 // Used by the Toeplitz operator kernels: a Toeplitz matrix-vector product is a linear convolution,
-// computed through a circulant embedding of length L = 2(n+1) >= 2n-1 (the O(N log N) product the
+// computed through a circulant embedding of power-of-two length L >= 2n-1, so n <= L/2 and the upper
+// half of every input is zero padding (the O(N log N) product the
 // paper relies on, Sec. 1 and the Toeplitz-like structure of Sec. 2).
 //
 // Data layout between stages: thread t holds element t + T*m in register m (natural order), m < E.
@@ -148,6 +149,61 @@ __device__ __forceinline__ void dft(R (&re)[N], R (&im)[N]) {
   }
 }
 
+// DFT of N points whose upper half is zero (re, im [N/2, N) are not read): the zero-padded input of
+// a circulant embedding.  Same decomposition as dft, with the first radix-4 layer reduced to its two
+// nonzero inputs: [a0, a1, 0, 0] -> [a0 + a1, a0 + W a1, a0 - a1, a0 - W a1], W = rotation by 1/4.
+template <int N, int SIGN, typename R>
+__device__ __forceinline__ void dft_half(R (&re)[N], R (&im)[N]) {
+  auto dft4h = [](R& r0, R& i0, R& r1, R& i1, R& r2, R& i2, R& r3, R& i3) {
+    const R ar = r0, ai = i0, br = r1, bi = i1;
+    R wr = br, wi = bi;
+    rot<1, 4, SIGN>(wr, wi);
+    r0 = ar + br;
+    i0 = ai + bi;
+    r2 = ar - br;
+    i2 = ai - bi;
+    r1 = ar + wr;
+    i1 = ai + wi;
+    r3 = ar - wr;
+    i3 = ai - wi;
+  };
+  if constexpr (N == 1) {
+  } else if constexpr (N == 2) {
+    re[1] = re[0];
+    im[1] = im[0];
+  } else if constexpr (N == 4) {
+    dft4h(re[0], im[0], re[1], im[1], re[2], im[2], re[3], im[3]);
+  } else {
+    constexpr int N1 = 4, N2 = N / 4;
+    R yr[N2][N1], yi[N2][N1];
+    static_for<0, N2>([&](auto n2) {
+      R ar[N1], ai[N1];
+      ar[0] = re[n2];
+      ai[0] = im[n2];
+      ar[1] = re[N2 + n2];
+      ai[1] = im[N2 + n2];
+      dft4h(ar[0], ai[0], ar[1], ai[1], ar[2], ai[2], ar[3], ai[3]);
+      static_for<0, N1>([&](auto k1) {
+        rot<decltype(n2)::value * decltype(k1)::value, N, SIGN>(ar[k1], ai[k1]);
+        yr[n2][k1] = ar[k1];
+        yi[n2][k1] = ai[k1];
+      });
+    });
+    static_for<0, N1>([&](auto k1) {
+      R br[N2], bi[N2];
+      static_for<0, N2>([&](auto n2) {
+        br[n2] = yr[n2][k1];
+        bi[n2] = yi[n2][k1];
+      });
+      dft<N2, SIGN>(br, bi);
+      static_for<0, N2>([&](auto k2) {
+        re[k1 + N1 * k2] = br[k2];
+        im[k1 + N1 * k2] = bi[k2];
+      });
+    });
+  }
+}
+
 // LDS index padding: one spare slot every 2^FDE_LPAD_SHIFT elements spreads the strided stage writes
 // over the banks.  Measured on gfx950 (SQ_LDS_BANK_CONFLICT): one slot in 32 halves the conflict
 // cycles of the FP32 row pass against one in 16 and takes 1-3 % off the FP64 passes; the transforms
@@ -228,7 +284,9 @@ using PlanFor = Plan<L, emax_for(sizeof(R), L)>;
 // are exchanged through `lds` (lds_exchange(L) reals) and read back at positions t + T*m.  The last
 // stage (possibly of smaller radix, several butterflies per thread) writes each butterfly's outputs
 // over its own inputs, which are exactly positions t + T*m.
-template <int L, int S, int SIGN, typename R, typename P>
+// ZH: the transform's input is zero from element L/2 on; the first stage (one butterfly per thread
+// over elements t + T r, so inputs r >= R/2 are those zeros) then skips them.
+template <int L, int S, int SIGN, typename R, typename P, bool ZH = false>
 __device__ __forceinline__ void fft_stage(R (&rr)[P::E], R (&ri)[P::E], R* lds, const R* bw, int t) {
   constexpr int E = P::E, T = P::T;
   constexpr int RADIX = P::radix(S);
@@ -262,7 +320,8 @@ __device__ __forceinline__ void fft_stage(R (&rr)[P::E], R (&ri)[P::E], R* lds, 
         vr[rc] = a;
       });
     }
-    dft<RADIX, SIGN>(vr, vi);
+    if constexpr (ZH && S == 0 && BPT == 1 && NS == 1) dft_half<RADIX, SIGN>(vr, vi);
+    else dft<RADIX, SIGN>(vr, vi);
     static_for<0, RADIX>([&](auto rc) {
       rr[q + rc * BPT] = vr[rc];
       ri[q + rc * BPT] = vi[rc];
@@ -323,7 +382,8 @@ struct Twiddles {
 
 // Full length-L DFT (SIGN = -1 forward, +1 unnormalised inverse) of the thread group's data.
 // Every thread of the workgroup must call this (it contains barriers) even if its group is idle.
-template <int L, int SIGN, typename R, typename P>
+// ZH: elements L/2 .. L-1 of the input are zero (their registers are not read).
+template <int L, int SIGN, bool ZH = false, typename R, typename P>
 __device__ __forceinline__ void fft(R (&rr)[P::E], R (&ri)[P::E], R* lds, const Twiddles<R, L, P>& tw, int t_in) {
   // An opaque copy of the thread index: without it the compiler computes the LDS addresses of all
   // transforms of a kernel once and keeps them live throughout, which exhausts the registers.
@@ -331,7 +391,7 @@ __device__ __forceinline__ void fft(R (&rr)[P::E], R (&ri)[P::E], R* lds, const 
   __asm__ volatile("" : "+v"(t));
   static_for<0, P::NSTAGES>([&](auto s) {
     constexpr int S = decltype(s)::value;
-    fft_stage<L, S, SIGN, R, P>(rr, ri, lds, tw.w[S < Twiddles<R, L, P>::NST ? S : 0], t);
+    fft_stage<L, S, SIGN, R, P, ZH>(rr, ri, lds, tw.w[S < Twiddles<R, L, P>::NST ? S : 0], t);
   });
 }
 

@@ -73,21 +73,29 @@ __global__ __launch_bounds__((XCfg<R, L>::THREADS), FDE_XW) void toep_x_kernel(
   const Tin* xb = U(x + oB);
   const R* dA = U(dpm + 2 * oA);
   const R* dB = U(dpm + 2 * oB);
+  // n1 <= L/2: a row occupies registers m < E/2; the rest is the zero padding of the embedding, and
+  // of the results only those registers are needed
+  constexpr int EH = E / 2;
   R zr[E], zi[E];
   static_for<0, E>([&](auto m) {
     const int i = t + T * m;
-    zr[m] = (hasA && i < n1) ? (R)xa[i] : R(0);
-    zi[m] = (hasB && i < n1) ? (R)xb[i] : R(0);
+    if constexpr (decltype(m)::value < EH) {
+      zr[m] = (hasA && i < n1) ? (R)xa[i] : R(0);
+      zi[m] = (hasB && i < n1) ? (R)xb[i] : R(0);
+    } else {
+      zr[m] = R(0);
+      zi[m] = R(0);
+    }
   });
   if (skipv) return;
-  fft<L, -1>(zr, zi, lds, tw, t);
+  fft<L, -1, true>(zr, zi, lds, tw, t);
   symbol_both<L, P>(zr, zi, zs, mu, t);
   fft<L, +1>(zr, zi, lds, tw, t);  // real part: T xa, imaginary part: T xb
   R pr[E], pi[E];
   unstash<L, P>(pr, pi, zs, t);
   using R2 = typename std::conditional<sizeof(R) == 4, float2, double2>::type;
-  R dmA[E], dmB[E];
-  chunked_for<E, kEpiGroup>([&](auto m) {
+  R dmA[EH], dmB[EH];
+  chunked_for<EH, kEpiGroup>([&](auto m) {
     const int i = t + T * m;
     R2 a{}, c{};
     if (hasA && i < n1) a = *reinterpret_cast<const R2*>(dA + 2 * i);
@@ -121,7 +129,7 @@ __global__ __launch_bounds__((XCfg<R, L>::THREADS), FDE_XW) void toep_x_kernel(
     }
     outr[i] = epilogue_value<MODE, R, Tin>(l, xv, bv, dv, sv, tau);
   };
-  chunked_for<E, kEpiGroup>([&](auto m) {
+  chunked_for<EH, kEpiGroup>([&](auto m) {
     const int i = t + T * m;
     if (hasA && i < n1) {
       finish(xa, dmA[m], ayA, bA, diA, outA, oA, zs[i], pr[m], i);
@@ -159,24 +167,32 @@ __global__ __launch_bounds__((YCfg<R, L>::THREADS), FDE_YW) void toep_y_kernel(
   tw.load(twtab, t);
   const int c0 = strip * 2 * S + 2 * slot;
   const bool v0 = c0 < n1, v1 = c0 + 1 < n1;
+  // n2 <= L/2: a column occupies registers m < E/2 (the rest is the zero padding of the embedding),
+  // and of the results only those registers are needed
+  constexpr int EH = E / 2;
   R zr[E], zi[E];
   // element offsets fit in 32 bits (n1 * n2 < 2^23); the base pointers are kernel arguments
   static_for<0, E>([&](auto m) {
     const int row = t + T * m;
     const unsigned p = (unsigned)row * (unsigned)n1 + (unsigned)c0;
-    zr[m] = (row < n2 && v0) ? (R)x[p] : R(0);
-    zi[m] = (row < n2 && v1) ? (R)x[p + 1] : R(0);
+    if constexpr (decltype(m)::value < EH) {
+      zr[m] = (row < n2 && v0) ? (R)x[p] : R(0);
+      zi[m] = (row < n2 && v1) ? (R)x[p + 1] : R(0);
+    } else {
+      zr[m] = R(0);
+      zi[m] = R(0);
+    }
   });
   if (skipv) return;
-  fft<L, -1>(zr, zi, lds, tw, t);
+  fft<L, -1, true>(zr, zi, lds, tw, t);
   symbol_both<L, P>(zr, zi, zs, mu, t);
   fft<L, +1>(zr, zi, lds, tw, t);  // T a + i T b along the columns
   R pr[E], pi[E];
   unstash<L, P>(pr, pi, zs, t);
   // (e+, e-) of both columns in one read: e+ weights the first product now, e- waits in registers
   using R2 = typename std::conditional<sizeof(R) == 4, float2, double2>::type;
-  R em0[E], em1[E];
-  chunked_for<E, kEpiGroup>([&](auto m) {
+  R em0[EH], em1[EH];
+  chunked_for<EH, kEpiGroup>([&](auto m) {
     const int row = t + T * m;
     const unsigned p = (unsigned)row * (unsigned)n1 + (unsigned)c0;
     R2 e0{}, e1{};
@@ -188,7 +204,7 @@ __global__ __launch_bounds__((YCfg<R, L>::THREADS), FDE_YW) void toep_y_kernel(
     em1[m] = e1.y;
   });
   fft<L, +1>(pr, pi, lds, tw, t);  // T^T a + i T^T b
-  chunked_for<E, kEpiGroup>([&](auto m) {
+  chunked_for<EH, kEpiGroup>([&](auto m) {
     const int row = t + T * m;
     if (row < n2) {
       const unsigned p = (unsigned)row * (unsigned)n1 + (unsigned)c0;
