@@ -91,6 +91,8 @@ def parse():
                     help="ungrouped requests with a cycle piece in flight at once (0: no limit)")
     ap.add_argument("--c5-piece", type=int, default=5,
                     help="Arnoldi steps per issued piece of a restart cycle (0: whole cycles)")
+    ap.add_argument("--c5-busy-running", type=int, default=1,
+                    help="ungrouped (larger) requests with a piece in flight while a group has work (-1: no cap)")
     ap.add_argument("--c5-qps", type=str, default="auto",
                     help="comma-separated arrival rates, or 'auto' for 50%% and 90%% of the saturation rate")
     ap.add_argument("--bf16", action="store_true",
@@ -442,12 +444,13 @@ def run_c4(args):
     print(json.dumps(line), flush=True)
 
 
-def serve(reqs, prec, budget, warm, max_running=0, group=(0, 0), piece=0):
+def serve(reqs, prec, budget, warm, max_running=0, group=(0, 0), piece=0, busy_running=-1):
     """Continuous batching: requests join the batch as they arrive and memory allows; returns the
     measured requests' latencies (arrival -> result copied out), their grid sides and the span.
     max_running caps the ungrouped requests with a cycle piece in flight (least work left first);
     piece > 0 issues restart cycles in pieces of that many Arnoldi steps; group = (max_n, slots)
-    shares batched launches among requests of one shape up to max_n."""
+    shares batched launches among requests of one shape up to max_n; busy_running caps the ungrouped
+    requests with a piece in flight while a group has work (-1: no extra cap)."""
     import torch
 
     from paper_1706_06844_amd import fde
@@ -455,7 +458,7 @@ def serve(reqs, prec, budget, warm, max_running=0, group=(0, 0), piece=0):
     b = fde.fde_batch_create(budget)
     if group[0] > 0:
         fde.fde_batch_set_grouping(b, group[0], group[1])
-    fde.fde_batch_set_policy(b, max_running, piece)
+    fde.fde_batch_set_policy(b, max_running, piece, busy_running)
     pending = sorted(range(len(reqs)), key=lambda i: reqs[i]["arrival"])
     queue, inflight, lat, done_t = [], {}, {}, {}
     t_start = time.perf_counter()
@@ -542,7 +545,7 @@ def run_c5(args):
     from paper_1706_06844_amd import fde
 
     steps_meas = sum(hrs[i]["p"].M for i in range(warm, count))
-    cap, piece = args.c5_max_running, args.c5_piece
+    cap, piece, gf = args.c5_max_running, args.c5_piece, args.c5_busy_running
     # every measured request alone on the device, one after another in one batch (so that groups,
     # once created, are reused as in the loaded runs): the reference for slowdowns
     import torch
@@ -565,24 +568,28 @@ def run_c5(args):
     b.close()
     log(f"c5 solo: {sum(solo):.1f} s in all, largest {max(solo):.1f} s")
     mix = {str(2 ** k - 1): sum(1 for i in range(warm, count) if hrs[i]["p"].n1 == 2 ** k - 1) for k in ks}
-    lat0, sides0, span0 = serve(reqs_at(1e9), fde.FDE_MIXED_FP32, budget, warm, cap, group, piece)
+    lat0, sides0, span0 = serve(reqs_at(1e9), fde.FDE_MIXED_FP32, budget, warm, cap, group, piece, gf)
     sat = args.c5_count / span0
     log(f"c5 saturation: {sat:.3f} solves/s ({span0:.1f} s)")
     rates = [0.5 * sat, 0.9 * sat] if args.c5_qps == "auto" else [float(q) for q in args.c5_qps.split(",")]
-    plan = [(q, "mixed", cap, piece) for q in rates]
+    plan = [(q, "mixed", cap, piece, gf) for q in rates]
     if args.c5_qps == "auto":
-        plan += [(rates[-1], "mixed", 0, 0), (rates[-1], "fp64", cap, piece)]
+        # at 90 %: the other busy cap (0 if it is set, else 1), the plain policy and FP64
+        plan += [(rates[-1], "mixed", cap, piece, 0 if gf != 0 else 1),
+                 (rates[-1], "mixed", 0, 0, -1), (rates[-1], "fp64", cap, piece, gf)]
     runs = []
-    for qps, name, mr, pc in plan:
+    for qps, name, mr, pc, g1 in plan:
         prec = fde.FDE_MIXED_FP32 if name == "mixed" else fde.FDE_FP64
-        lat, sides, span = serve(reqs_at(qps), prec, budget, warm, mr, group, pc)
-        r = {"qps": qps, "precision": name, "max_running": mr, "piece_steps": pc,
+        lat, sides, span = serve(reqs_at(qps), prec, budget, warm, mr, group, pc, g1)
+        r = {"qps": qps, "precision": name, "max_running": mr, "piece_steps": pc, "busy_running": g1,
              "solves_per_s": args.c5_count / span, "cn_steps_per_s": steps_meas / span}
         r.update(latency_stats(lat, sides, solo if name == "mixed" else None))
         runs.append(r)
-        log(f"c5 qps {qps:.3f} {name} max_running {mr} piece {pc}: {args.c5_count / span:.3f} solves/s, "
+        log(f"c5 qps {qps:.3f} {name} max_running {mr} piece {pc} busy_running {g1}: "
+            f"{args.c5_count / span:.3f} solves/s, "
             f"p50 {r['p50_ms']:.0f} ms, p99 {r['p99_ms']:.0f} ms")
-    hi = [r for r in runs if r["precision"] == "mixed" and r["max_running"] == cap and r["piece_steps"] == piece][-1]
+    hi = [r for r in runs if r["precision"] == "mixed" and r["max_running"] == cap and r["piece_steps"] == piece
+          and r["busy_running"] == gf][-1]
     line = {
         "metric": "C5 served solves/s with p50/p99 latency (continuous batching, mixed vs FP64)",
         "value": hi["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
@@ -593,7 +600,7 @@ def run_c5(args):
                    "request_mix": mix,
                    "policy": f"sides <= 511 grouped (16 slots); restart cycles in pieces of {piece} Arnoldi "
                              f"steps; larger requests least work left first, at most {cap} with a piece in "
-                             "flight (the 'plain' run: whole cycles, no cap)"},
+                             f"flight, {gf} while a group has work (the 'plain' run: whole cycles, no cap)"},
         "saturation_solves_per_s": sat, "saturation_cn_steps_per_s": steps_meas / span0,
         "saturation_latency": latency_stats(lat0, sides0, solo), "runs": runs,
         "solo_latency": latency_stats(solo, sides0),

@@ -284,9 +284,12 @@ int fde_batch_set_grouping(fde_batch* b, int32_t max_n, int32_t slots);
  * wait at a piece boundary, and each free place goes to the waiting request with the least work left
  * (n1 * n2 * remaining steps), so small requests pass large ones instead of sharing the device with
  * them (preemption at piece boundaries), at the price of some concurrency; 0 (the default) issues
- * every due piece at once.  Results do not depend on either setting.  FDE_EINVAL for negative values
- * or a piece change on a batch that holds requests. */
-int fde_batch_set_policy(fde_batch* b, int32_t max_running, int32_t piece_steps);
+ * every due piece at once.  busy_running >= 0: while any group (grouping, above) has a member with a
+ * step to do, at most busy_running ungrouped requests have a piece in flight (0: none — the small
+ * grouped requests then have the device to themselves for their short solves); -1: no extra limit.
+ * Results do not depend on any setting.  FDE_EINVAL for values out of range or a piece change on a
+ * batch that holds requests. */
+int fde_batch_set_policy(fde_batch* b, int32_t max_running, int32_t piece_steps, int32_t busy_running);
 
 /* Admits a request: problem *p (as for fde_setup), coefficient fields (copied), initial field u0
  * (device, copied), nsteps CN steps from t0, and a separable source sum_k phi_k(t) S_k with

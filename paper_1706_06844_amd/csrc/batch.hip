@@ -21,6 +21,7 @@
 // slot without a member is marked idle, so each member runs exactly the arithmetic it runs alone.
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -160,6 +161,7 @@ struct fde_batch {
   std::vector<Group> groups;
   int max_running = 0;  // ungrouped requests with a cycle in flight at once (0: no limit)
   int piece_steps = 0;  // Arnoldi steps per issued piece of a restart cycle (0: whole cycles)
+  int busy_running = -1;  // ungrouped requests with a piece in flight while a group has work (-1: max_running)
 };
 
 extern "C" {
@@ -191,11 +193,12 @@ int fde_batch_set_grouping(fde_batch* b, int32_t max_n, int32_t slots) {
   return FDE_OK;
 }
 
-int fde_batch_set_policy(fde_batch* b, int32_t max_running, int32_t piece_steps) {
-  if (!b || max_running < 0 || piece_steps < 0) return FDE_EINVAL;
+int fde_batch_set_policy(fde_batch* b, int32_t max_running, int32_t piece_steps, int32_t busy_running) {
+  if (!b || max_running < 0 || piece_steps < 0 || busy_running < -1) return FDE_EINVAL;
   if (piece_steps != b->piece_steps && !b->reqs.empty()) return FDE_EINVAL;
   b->max_running = max_running;
   b->piece_steps = piece_steps;
+  b->busy_running = busy_running;
   return FDE_OK;
 }
 
@@ -509,7 +512,7 @@ extern "C" {
 int fde_batch_step(fde_batch* b) {
   if (!b) return FDE_EINVAL;
   int completed = 0;
-  const bool capped = b->max_running > 0;
+  const bool capped = b->max_running > 0 || b->busy_running >= 0;
   while (true) {
     int active = 0;
     completed += step_groups(b, &active);
@@ -549,8 +552,25 @@ int fde_batch_step(fde_batch* b) {
       r.state = (r.steps_done >= r.nsteps) ? RS_DONE : RS_START;
     }
     if (capped) {
-      // at most max_running requests with a cycle in flight; the others wait at a cycle boundary, and
-      // the next cycles go to the requests with the least work left
+      // at most max_running requests with a piece in flight (busy_running while a group has work);
+      // the others wait at a piece boundary, and the next pieces go to the requests with the least
+      // work left
+      int limit = b->max_running > 0 ? b->max_running : INT_MAX;
+      if (b->busy_running >= 0) {
+        for (const Group& g : b->groups) {
+          if (!g.arena) continue;
+          bool busy = g.inflight;
+          for (int s = 0; s < g.nslots && !busy; ++s)
+            if (g.member[s] >= 0) {
+              const int st = b->reqs.at(g.member[s]).state;
+              busy = st == RS_START || st == RS_RUNNING;
+            }
+          if (busy) {
+            limit = std::min(limit, b->busy_running);
+            break;
+          }
+        }
+      }
       int inflight = 0;
       std::vector<std::pair<double, Request*>> wait;
       for (auto& kv : b->reqs) {
@@ -564,7 +584,7 @@ int fde_batch_step(fde_batch* b) {
                          return a.first < c.first;
                        });
       for (auto& w : wait) {
-        if (inflight >= b->max_running) break;
+        if (inflight >= limit) break;
         Request& r = *w.second;
         if (r.state == RS_START) {
           if (!start_step(r, false)) {

@@ -245,10 +245,11 @@ def fde_batch_set_grouping(b: Batch, max_n: int, slots: int) -> None:
     _check(_lib().fde_batch_set_grouping(b.ptr, int(max_n), int(slots)))
 
 
-def fde_batch_set_policy(b: Batch, max_running: int, piece_steps: int = 0) -> None:
+def fde_batch_set_policy(b: Batch, max_running: int, piece_steps: int = 0, busy_running: int = -1) -> None:
     """Restart cycles issued in pieces of piece_steps Arnoldi steps (0: whole cycles); at most
-    max_running ungrouped requests with a piece in flight, least work left first (0: no limit)."""
-    _check(_lib().fde_batch_set_policy(b.ptr, int(max_running), int(piece_steps)))
+    max_running ungrouped requests with a piece in flight, least work left first (0: no limit), and
+    at most busy_running of them while a group has work (-1: no extra limit)."""
+    _check(_lib().fde_batch_set_policy(b.ptr, int(max_running), int(piece_steps), int(busy_running)))
 
 
 def fde_batch_admit(b: Batch, problem: fde_problem, dp, dm, ep, em, u0, nsteps: int, t0: float = 0.0,

@@ -183,3 +183,34 @@ def test_cycles_in_pieces_equal_whole_cycles(precision):
     fde.fde_batch_set_policy(b, 2, 4)
     _drain(b, [rid], {rid: (probs[0].n2, probs[0].n1)})
     b.close()
+
+
+def test_groups_first_holds_large_requests():
+    # with busy_running = 0 no piece of the ungrouped request is issued while the group has work: the
+    # grouped requests, admitted after it, finish first; every result equals its solo run
+    big = _instances(1, (255,), 95, 3)[0]
+    small = _instances(3, (63,), 96, 4)
+    b = fde.fde_batch_create(8 << 30)
+    fde.fde_batch_set_grouping(b, 127, 4)
+    fde.fde_batch_set_policy(b, 2, 5, 0)
+    keep, ids, shapes = [], [], {}
+    for p in [big] + small:
+        ids.append(_admit(b, p, fde.FDE_MIXED_FP32, keep))
+        shapes[ids[-1]] = (p.n2, p.n1)
+    order, res, pending = [], {}, set(ids)
+    while pending:
+        fde.fde_batch_step(b)
+        for rid in list(pending):
+            n2, n1 = shapes[rid]
+            u = torch.empty((n2, n1), dtype=torch.float64, device="cuda:0")
+            st, it = fde.fde_batch_poll(b, rid, u)
+            if st:
+                res[rid] = (host(u), it)
+                order.append(rid)
+                pending.discard(rid)
+    assert order[-1] == ids[0], order
+    for rid, p in zip(ids, [big] + small):
+        ref, its = solo_run(p, p.M, fde.FDE_MIXED_FP32)
+        assert res[rid][1] == its
+        assert rel(res[rid][0], ref) <= 1e-14
+    b.close()
