@@ -91,6 +91,8 @@ def parse():
                     help="ungrouped requests with a cycle piece in flight at once (0: no limit)")
     ap.add_argument("--c5-piece", type=int, default=5,
                     help="Arnoldi steps per issued piece of a restart cycle (0: whole cycles)")
+    ap.add_argument("--c5-lanes", type=int, default=0,
+                    help="streams shared by the batch: larger requests on one, groups on the others (0: own streams)")
     ap.add_argument("--c5-busy-running", type=int, default=1,
                     help="ungrouped (larger) requests with a piece in flight while a group has work (-1: no cap)")
     ap.add_argument("--c5-qps", type=str, default="auto",
@@ -444,7 +446,7 @@ def run_c4(args):
     print(json.dumps(line), flush=True)
 
 
-def serve(reqs, prec, budget, warm, max_running=0, group=(0, 0), piece=0, busy_running=-1):
+def serve(reqs, prec, budget, warm, max_running=0, group=(0, 0), piece=0, busy_running=-1, lanes=0):
     """Continuous batching: requests join the batch as they arrive and memory allows; returns the
     measured requests' latencies (arrival -> result copied out), their grid sides and the span.
     max_running caps the ungrouped requests with a cycle piece in flight (least work left first);
@@ -456,6 +458,8 @@ def serve(reqs, prec, budget, warm, max_running=0, group=(0, 0), piece=0, busy_r
     from paper_1706_06844_amd import fde
 
     b = fde.fde_batch_create(budget)
+    if lanes:
+        fde.fde_batch_set_lanes(b, lanes)
     if group[0] > 0:
         fde.fde_batch_set_grouping(b, group[0], group[1])
     fde.fde_batch_set_policy(b, max_running, piece, busy_running)
@@ -545,7 +549,7 @@ def run_c5(args):
     from paper_1706_06844_amd import fde
 
     steps_meas = sum(hrs[i]["p"].M for i in range(warm, count))
-    cap, piece, gf = args.c5_max_running, args.c5_piece, args.c5_busy_running
+    cap, piece, gf, lanes = args.c5_max_running, args.c5_piece, args.c5_busy_running, args.c5_lanes
     # every measured request alone on the device, one after another in one batch (so that groups,
     # once created, are reused as in the loaded runs): the reference for slowdowns
     import torch
@@ -568,7 +572,7 @@ def run_c5(args):
     b.close()
     log(f"c5 solo: {sum(solo):.1f} s in all, largest {max(solo):.1f} s")
     mix = {str(2 ** k - 1): sum(1 for i in range(warm, count) if hrs[i]["p"].n1 == 2 ** k - 1) for k in ks}
-    lat0, sides0, span0 = serve(reqs_at(1e9), fde.FDE_MIXED_FP32, budget, warm, cap, group, piece, gf)
+    lat0, sides0, span0 = serve(reqs_at(1e9), fde.FDE_MIXED_FP32, budget, warm, cap, group, piece, gf, lanes)
     sat = args.c5_count / span0
     log(f"c5 saturation: {sat:.3f} solves/s ({span0:.1f} s)")
     rates = [0.5 * sat, 0.9 * sat] if args.c5_qps == "auto" else [float(q) for q in args.c5_qps.split(",")]
@@ -580,7 +584,7 @@ def run_c5(args):
     runs = []
     for qps, name, mr, pc, g1 in plan:
         prec = fde.FDE_MIXED_FP32 if name == "mixed" else fde.FDE_FP64
-        lat, sides, span = serve(reqs_at(qps), prec, budget, warm, mr, group, pc, g1)
+        lat, sides, span = serve(reqs_at(qps), prec, budget, warm, mr, group, pc, g1, lanes if mr else 0)
         r = {"qps": qps, "precision": name, "max_running": mr, "piece_steps": pc, "busy_running": g1,
              "solves_per_s": args.c5_count / span, "cn_steps_per_s": steps_meas / span}
         r.update(latency_stats(lat, sides, solo if name == "mixed" else None))

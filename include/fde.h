@@ -275,6 +275,14 @@ void fde_batch_destroy(fde_batch* b);
  * holds requests. */
 int fde_batch_set_grouping(fde_batch* b, int32_t max_n, int32_t slots);
 
+/* Streams.  lanes = 0 (the default): every ungrouped request and every group gets a stream of its own.
+ * lanes >= 2: the batch creates that many streams at once (consecutive streams go to different
+ * hardware queues of the device); every ungrouped request runs on the first, the groups are dealt to
+ * the others in turn.  The larger (ungrouped) requests then share one hardware queue instead of
+ * queueing in front of the small requests' kernels; ungrouped requests no longer overlap each other.
+ * Only on an empty batch (no requests or groups); FDE_EINVAL for lanes 1 or above 16. */
+int fde_batch_set_lanes(fde_batch* b, int32_t lanes);
+
 /* Scheduling.  piece_steps > 0 issues every restart cycle (Sec. 5: GMRES restarted every 20 steps) in
  * pieces of piece_steps Arnoldi steps and a tail (x update, true residual), with a read of the solver
  * state after each piece: once a cycle has converged its remaining steps are not issued at all, and

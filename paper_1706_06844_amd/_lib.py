@@ -100,6 +100,7 @@ SIGNATURES = {
     "fde_batch_destroy": (None, [_P]),
     "fde_batch_set_grouping": (_I, [_P, _I32, _I32]),
     "fde_batch_set_policy": (_I, [_P, _I32, _I32, _I32]),
+    "fde_batch_set_lanes": (_I, [_P, _I32]),
     "fde_batch_admit": (_I, [_P, ctypes.POINTER(fde_problem), _P, _P, _P, _P, _P, _I32, _D, _I32,
                              ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_P)]),
     "fde_batch_step": (_I, [_P]),

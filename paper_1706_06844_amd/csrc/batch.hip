@@ -43,6 +43,7 @@ struct Request {
   fde_handle* h = nullptr;
   hipStream_t stream = nullptr;
   int group = -1;  // index of its group in grouped mode (the stream then belongs to the group)
+  bool own_stream = false;  // the stream was created for this request
   int slot = -1;
   int cycles = 0;  // restart cycles of the solve in flight (grouped mode)
   fde_problem p{};
@@ -68,7 +69,7 @@ void release(Request& r) {
     if (p) (void)hipFree(p);
   for (int k = 0; k < kMaxSrc; ++k)
     if (r.S[k]) (void)hipFree(r.S[k]);
-  if (r.stream && r.group < 0) (void)hipStreamDestroy(r.stream);
+  if (r.stream && r.own_stream) (void)hipStreamDestroy(r.stream);
   r = Request{};
 }
 
@@ -88,6 +89,7 @@ struct Group {
   size_t slot_bytes = 0;
   char* arena = nullptr;
   hipStream_t stream = nullptr;
+  bool own_stream = false;  // the stream was created for this group (not a lane of the batch)
   std::vector<int> member;  // request id per slot, -1 if empty
   long long st_off = 0;     // offset of the solver state within a slot
   std::vector<CycleGraph> cycles;  // by increasing nz; the last one has nz = nslots
@@ -138,7 +140,7 @@ void destroy_group(Group& g) {
   if (g.hst) (void)hipHostFree(g.hst);
   if (g.idle) (void)hipHostFree(g.idle);
   if (g.arena) (void)hipFree(g.arena);
-  if (g.stream) (void)hipStreamDestroy(g.stream);
+  if (g.stream && g.own_stream) (void)hipStreamDestroy(g.stream);
   g = Group{};
 }
 
@@ -162,6 +164,11 @@ struct fde_batch {
   int max_running = 0;  // ungrouped requests with a cycle in flight at once (0: no limit)
   int piece_steps = 0;  // Arnoldi steps per issued piece of a restart cycle (0: whole cycles)
   int busy_running = -1;  // ungrouped requests with a piece in flight while a group has work (-1: max_running)
+  // lanes: streams created together at set-up (so that they map to distinct hardware queues): the
+  // first for every ungrouped request, the others dealt to the groups in turn; empty: a stream per
+  // request and per group
+  std::vector<hipStream_t> lanes;
+  int groups_made = 0;
 };
 
 extern "C" {
@@ -182,7 +189,25 @@ void fde_batch_destroy(fde_batch* b) {
     if (g.stream) (void)hipStreamSynchronize(g.stream);
   for (auto& kv : b->reqs) release(kv.second);
   for (Group& g : b->groups) destroy_group(g);
+  for (hipStream_t s : b->lanes) (void)hipStreamDestroy(s);
   delete b;
+}
+
+int fde_batch_set_lanes(fde_batch* b, int32_t lanes) {
+  if (!b || lanes < 0 || lanes == 1 || lanes > 16) return FDE_EINVAL;
+  if (!b->reqs.empty() || !b->groups.empty()) return FDE_EINVAL;
+  for (hipStream_t s : b->lanes) (void)hipStreamDestroy(s);
+  b->lanes.clear();
+  for (int k = 0; k < lanes; ++k) {
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+      for (hipStream_t t : b->lanes) (void)hipStreamDestroy(t);
+      b->lanes.clear();
+      return FDE_EDEVICE;
+    }
+    b->lanes.push_back(s);
+  }
+  return FDE_OK;
 }
 
 int fde_batch_set_grouping(fde_batch* b, int32_t max_n, int32_t slots) {
@@ -256,8 +281,13 @@ int fde_batch_admit(fde_batch* b, const fde_problem* p, const double* dp, const 
       if (b->used + gbytes + extra > b->budget) return FDE_EAGAIN;
       g.member.assign(g.nslots, -1);
       if (hipMalloc(&g.arena, gbytes) != hipSuccess) return FDE_ENOMEM;
-      if (hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking) != hipSuccess ||
-          hipEventCreateWithFlags(&g.ev, hipEventDisableTiming) != hipSuccess ||
+      if (!b->lanes.empty()) {
+        g.stream = b->lanes[1 + b->groups_made % ((int)b->lanes.size() - 1)];
+      } else if (hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking) == hipSuccess) {
+        g.own_stream = true;
+      }
+      ++b->groups_made;
+      if (!g.stream || hipEventCreateWithFlags(&g.ev, hipEventDisableTiming) != hipSuccess ||
           hipHostMalloc((void**)&g.hst, sizeof(GmresState) * g.nslots, hipHostMallocDefault) != hipSuccess ||
           hipHostMalloc((void**)&g.idle, sizeof(GmresState), hipHostMallocDefault) != hipSuccess ||
           hipHostMalloc((void**)&g.zt_host, sizeof(long long) * g.nslots, hipHostMallocDefault) != hipSuccess ||
@@ -320,8 +350,13 @@ int fde_batch_admit(fde_batch* b, const fde_problem* p, const double* dp, const 
       }
     }
   } else {
-    if (hipStreamCreateWithFlags(&r.stream, hipStreamNonBlocking) != hipSuccess)
-      return fail(FDE_EDEVICE, "stream creation failed");
+    if (!b->lanes.empty()) {
+      r.stream = b->lanes[0];
+    } else {
+      if (hipStreamCreateWithFlags(&r.stream, hipStreamNonBlocking) != hipSuccess)
+        return fail(FDE_EDEVICE, "stream creation failed");
+      r.own_stream = true;
+    }
     const int rc = fde_setup(p, dp, dm, ep, em, r.stream, &r.h);
     if (rc != FDE_OK) {
       b->err = fde_last_error(nullptr);

@@ -245,6 +245,12 @@ def fde_batch_set_grouping(b: Batch, max_n: int, slots: int) -> None:
     _check(_lib().fde_batch_set_grouping(b.ptr, int(max_n), int(slots)))
 
 
+def fde_batch_set_lanes(b: Batch, lanes: int) -> None:
+    """Ungrouped requests on one stream and the groups on lanes - 1 others, created together (0: a
+    stream per request and group)."""
+    _check(_lib().fde_batch_set_lanes(b.ptr, int(lanes)))
+
+
 def fde_batch_set_policy(b: Batch, max_running: int, piece_steps: int = 0, busy_running: int = -1) -> None:
     """Restart cycles issued in pieces of piece_steps Arnoldi steps (0: whole cycles); at most
     max_running ungrouped requests with a piece in flight, least work left first (0: no limit), and

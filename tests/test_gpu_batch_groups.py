@@ -87,13 +87,17 @@ def test_group_members_equal_solo(precision, piece):
     b.close()
 
 
-def test_group_join_leave_and_mixed_shapes():
+@pytest.mark.parametrize("lanes", [0, 4])
+def test_group_join_leave_and_mixed_shapes(lanes):
     # members join while the group is stepping, one is cancelled mid-run and its slot reused; a
-    # larger request beyond the size limit runs ungrouped beside the group
+    # larger request beyond the size limit runs ungrouped beside the group; with lanes the batch's
+    # shared streams carry them
     precision = fde.FDE_MIXED_FP32
     probs = _instances(6, (127,), 33, 4)
     big = _instances(1, (255,), 34, 3)[0]
     b = fde.fde_batch_create(8 << 30)
+    if lanes:
+        fde.fde_batch_set_lanes(b, lanes)
     fde.fde_batch_set_grouping(b, 127, 4)
     keep, ids, shapes = [], [], {}
     for p in probs[:3]:
