@@ -2,18 +2,21 @@
 // coefficients and source) resident on one GPU and advanced together (the CN recursion of
 // eq. (CNWSGD) / (system), one solve per step, applied to independent problems).
 //
-// Every request owns a solver handle on its own HIP stream (default priority): its Toeplitz symbols,
-// hierarchy and Krylov storage stay resident until the request is released.  A step is a chain of
-// restart cycles replayed from a captured HIP graph; the host only starts steps and reads the solver
-// state between cycles, without blocking, so the cycles of all requests overlap on the device.
+// Every request owns a solver handle on its own HIP stream (default priority; or on one of the batch's
+// lanes, fde_batch_set_lanes): its Toeplitz symbols, hierarchy and Krylov storage stay resident until
+// the request is released.  A step is a chain of restart cycles replayed from captured HIP graphs,
+// whole or in pieces of Arnoldi steps (fde_batch_set_policy); the host only starts steps and reads the
+// solver state between cycles (or pieces), without blocking, so the work of all requests overlaps on
+// the device.  With a cap on the requests in flight the host hands each free place to the waiting
+// request with the least work left.
 // Requests are admitted against a device-memory budget and may join or leave between calls to
 // fde_batch_step (continuous batching).  The kernels a request runs, and their order, do not depend
 // on the other requests, so its result is the same alone and in the mix.
 //
 // Grouped mode (fde_batch_set_grouping): requests of one shape (sizes, precision, multigrid settings)
 // up to a size limit share a group: one device region cut into equal slots and one stream.  The
-// group's restart cycle is captured once per z extent of a short ladder (1, 2, 3, 4, 6, 8, 12, ...,
-// and the slot count); before each cycle the host writes the slot offsets of the members that are
+// group's restart cycle (each of its pieces) is captured once per z extent of a short ladder (1, 2,
+// 3, 4, 6, 8, 12, ..., and the slot count); before each cycle the host writes the slot offsets of the members that are
 // solving into a small device table and replays the smallest capture that holds them, so every kernel
 // of the cycle is one launch over exactly the solving members (plus at most a third of padding, whose
 // workgroups exit at once).  Each member starts its CN steps on its own (right-hand side, norm of b)
@@ -176,7 +179,7 @@ extern "C" {
 size_t fde_footprint(const fde_problem* p) { return footprint_bytes(p); }
 
 int fde_batch_create(size_t budget_bytes, void* stream, fde_batch** out) {
-  (void)stream;  // every request runs on a stream of its own
+  (void)stream;  // requests and groups get streams of their own, or the batch's lanes
   if (!out) return FDE_EINVAL;
   *out = new fde_batch();
   (*out)->budget = budget_bytes;
@@ -319,8 +322,8 @@ int fde_batch_admit(fde_batch* b, const fde_problem* p, const double* dp, const 
     }
     if (async_set_piece(r.h, b->piece_steps) != FDE_OK) return fail(FDE_EINVAL, "piece setting failed");
     if (g.cycles.empty()) {
-      // the first member (slot 0) lays out the slots: empty ones get the idle state, and the cycle is
-      // captured for every z extent of the ladder, with slot 0's pointers
+      // the group's first member lays out the slots: the others get the idle state, and every piece
+      // of the cycle is captured for every z extent of the ladder, with this member's pointers
       g.st_off = group_state_offset(r.h);
       for (int s = 1; s < g.nslots; ++s)
         if (mark_idle(g, s) != hipSuccess) return fail(FDE_EDEVICE, "initialising the slots failed");
