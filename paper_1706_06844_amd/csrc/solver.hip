@@ -93,8 +93,17 @@ int one_wg_max() {
   }();
   return v;
 }
-// The outer FP64 operator of grids with max(n1, n2) <= kOuterDirectMax uses the direct kernel.
-constexpr int kOuterDirectMax = 255;
+// The outer FP64 operator of grids with max(n1, n2) <= outer_direct_max() uses the direct kernel
+// (FDE_OUTER_DIRECT_MAX overrides the limit for measurements).  Measured on gfx950 (whole CN steps,
+// FP32 V-cycle in FP64 GMRES): the FP64 transforms beat the dense sums by 13 % per iteration at 127^2
+// and 24 % at 255^2 (3 % and 7 % in FP64); at 63^2 the two tie.
+int outer_direct_max() {
+  static const int v = [] {
+    const char* e = std::getenv("FDE_OUTER_DIRECT_MAX");
+    return e ? std::atoi(e) : 63;
+  }();
+  return v;
+}
 // Levels with max(n1, n2) <= direct_op_max() use the direct (dense-Toeplitz) kernels: 255 in FP64, 127
 // in FP32 (at 255^2 the FP32 transforms and the tiled direct kernels cost the same; at 511^2 the
 // transforms win by 20 %).  The environment variables FDE_DIRECT_MAX_F64 / FDE_DIRECT_MAX_F32 override
@@ -195,7 +204,7 @@ struct Outer {
     v.tw_y = twy;
     v.swx = swx;
     v.swy = swy;
-    v.direct = std::max(n1, n2) <= kOuterDirectMax ? 1 : 0;
+    v.direct = std::max(n1, n2) <= outer_direct_max() ? 1 : 0;
     return v;
   }
 };
