@@ -81,6 +81,8 @@ def parse():
     ap.add_argument("--no-c4", action="store_true", help="skip the C4 (64 batched instances) keys")
     ap.add_argument("--c4-modes", type=str, default="mixed,fp64,cycle",
                     help="--workload c4: precision modes (the first of mixed/fp64/cycle present gives the value)")
+    ap.add_argument("--c4-piece", type=int, default=0,
+                    help="--workload c4: Arnoldi steps per issued piece of a restart cycle (0: whole cycles)")
     ap.add_argument("--c4-grouped-only", action="store_true",
                     help="--workload c4: grouped batching only (no ungrouped and one-at-a-time runs)")
     ap.add_argument("--cpu-sample-iters", type=int, default=24)
@@ -337,7 +339,7 @@ def admit(b, hr, precision, rtol, maxit):
     return fde.fde_batch_admit(b, s, *F, d(hr["u0"]), p.M, 0.0, hr["coef"], hr["rate"], [d(f) for f in hr["S"]])
 
 
-def c4_results(modes=("mixed", "fp64", "cycle"), ungrouped=True, sequential=True):
+def c4_results(modes=("mixed", "fp64", "cycle"), ungrouped=True, sequential=True, piece=0):
     """C4: 64 uneven instances (n in {127,255,511}, 8 CN steps, rtol 1e-9) resident together.  Per
     precision mode: grouped batching (one group per size; every kernel of a restart cycle launched
     once over the solving members), optionally ungrouped batching (a stream and a graph per instance)
@@ -360,6 +362,7 @@ def c4_results(modes=("mixed", "fp64", "cycle"), ungrouped=True, sequential=True
         b = fde.fde_batch_create(200 << 30)
         if grouped:
             fde.fde_batch_set_grouping(b, 511, slots)
+        fde.fde_batch_set_policy(b, 0, piece)
         ids = [admit(b, r, prec, 1e-9, 2000) for r in reqs]
         assert min(ids) >= 0
         marker.fill_(1.0)
@@ -438,7 +441,7 @@ def c4_summary(c4):
 def run_c4(args):
     """The C4 line: the value is grouped batching with the FP32 V-cycle inside FP64 flexible GMRES."""
     c4 = c4_results(modes=tuple(args.c4_modes.split(",")), ungrouped=not args.c4_grouped_only,
-                    sequential=not args.c4_grouped_only)
+                    sequential=not args.c4_grouped_only, piece=args.c4_piece)
     name = "mixed" if "mixed" in c4 else args.c4_modes.split(",")[0]
     m = c4[name]
     line = {

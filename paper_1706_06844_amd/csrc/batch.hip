@@ -97,8 +97,9 @@ struct Group {
   long long st_off = 0;     // offset of the solver state within a slot
   std::vector<CycleGraph> cycles;  // by increasing nz; the last one has nz = nslots
   int npieces = 0;                 // Arnoldi pieces of a cycle (the tail is piece npieces)
-  int cg = 0;                      // the capture the cycle in flight runs
+  int cg = 0;                      // the capture the piece in flight runs
   int piece = 0;                   // the piece in flight
+  std::vector<int> cyc;            // slots of the members in the cycle in flight
   long long* zt_dev = nullptr;     // slot offsets of the next cycle (nslots entries)
   long long* zt_host = nullptr;    // pinned staging of zt_dev
   hipEvent_t ev = nullptr;
@@ -393,6 +394,23 @@ int fde_batch_admit(fde_batch* b, const fde_problem* p, const double* dp, const 
 
 namespace {
 
+// Index of the smallest capture whose z extent holds n members.
+int capture_for(const Group& g, int n) {
+  for (int c = 0; c < (int)g.cycles.size(); ++c)
+    if (g.cycles[c].nz >= n) return c;
+  return (int)g.cycles.size() - 1;
+}
+
+// Selects the capture for the members in `slots` and writes their slot offsets (then padding) into
+// the device table, ordered before the next launch on the group's stream.
+hipError_t set_table(Group& g, const std::vector<int>& slots) {
+  g.cg = capture_for(g, (int)slots.size());
+  const CycleGraph& cg = g.cycles[g.cg];
+  for (int z = 0; z < cg.nz; ++z)
+    g.zt_host[z] = z < (int)slots.size() ? (long long)(slots[z] - cg.base) * (long long)g.slot_bytes : kZSkip;
+  return hipMemcpyAsync(g.zt_dev, g.zt_host, sizeof(long long) * cg.nz, hipMemcpyHostToDevice, g.stream);
+}
+
 // Issues piece pc of the group's current cycle and the read-back of the slots' states.
 hipError_t launch_piece(Group& g, int pc) {
   g.piece = pc;
@@ -421,10 +439,18 @@ int step_groups(fde_batch* b, int* active) {
       }
       g.inflight = false;
       if (q == hipSuccess && g.piece < g.npieces) {
-        bool more = false;
-        for (int s = 0; s < g.nslots && g.piece + 1 < g.npieces; ++s)
-          if (g.member[s] >= 0 && b->reqs.at(g.member[s]).state == RS_RUNNING && !g.hst[s].done) more = true;
-        q = launch_piece(g, more ? g.piece + 1 : g.npieces);
+        // the members whose cycle goes on: the next Arnoldi piece runs over them alone (a smaller
+        // capture once they fit one), the tail over every member of the cycle
+        std::vector<int> act;
+        for (int s : g.cyc)
+          if (g.member[s] >= 0 && b->reqs.at(g.member[s]).state == RS_RUNNING && !g.hst[s].done) act.push_back(s);
+        if (!act.empty() && g.piece + 1 < g.npieces) {
+          if (capture_for(g, (int)act.size()) < g.cg) q = set_table(g, act);
+          if (q == hipSuccess) q = launch_piece(g, g.piece + 1);
+        } else {
+          if (capture_for(g, (int)g.cyc.size()) != g.cg) q = set_table(g, g.cyc);
+          if (q == hipSuccess) q = launch_piece(g, g.npieces);
+        }
         if (q == hipSuccess) {
           g.inflight = true;
           ++*active;
@@ -492,17 +518,8 @@ int step_groups(fde_batch* b, int* active) {
       if (r.state == RS_RUNNING) run.push_back(s);
     }
     if (run.empty()) continue;
-    g.cg = (int)g.cycles.size() - 1;
-    for (int c = 0; c < (int)g.cycles.size(); ++c)
-      if (g.cycles[c].nz >= (int)run.size()) {
-        g.cg = c;
-        break;
-      }
-    const CycleGraph& cg = g.cycles[g.cg];
-    for (int z = 0; z < cg.nz; ++z)
-      g.zt_host[z] = z < (int)run.size() ? (long long)(run[z] - cg.base) * (long long)g.slot_bytes : kZSkip;
-    if (hipMemcpyAsync(g.zt_dev, g.zt_host, sizeof(long long) * cg.nz, hipMemcpyHostToDevice, g.stream) != hipSuccess ||
-        launch_piece(g, 0) != hipSuccess) {
+    g.cyc = run;
+    if (set_table(g, run) != hipSuccess || launch_piece(g, 0) != hipSuccess) {
       for (int s = 0; s < g.nslots; ++s) {
         if (g.member[s] < 0) continue;
         Request& r = b->reqs.at(g.member[s]);
