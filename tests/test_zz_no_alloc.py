@@ -1,7 +1,7 @@
 """The entry point that allocates nothing (fde_apply_noalloc) against the handle's FP64 system
 operator (fde_apply at level 0, FDE_FP64) and the oracle's operator of eq. (system): two calls in a
-row, the second on a smaller grid, then a rectangular one; the FP64 bar of the operator (1e-12
-relative 2-norm).  Sizes beyond the static buffer are rejected with FDE_EINVAL."""
+row, the second on a smaller grid, then a rectangular one, and even sides; the FP64 bar of the
+operator (1e-12 relative 2-norm).  Sizes beyond the static buffer are rejected with FDE_EINVAL."""
 import numpy as np
 import pytest
 import torch
@@ -37,6 +37,14 @@ def test_noalloc_apply_matches_handle_twice_then_smaller():
     p = workloads.config_c2(63, 32)
     p.n2 = 127
     _case(p, 3)                                      # rectangular
+
+
+def test_noalloc_apply_on_even_sides():
+    # the paper's even grids: embedding length 2n
+    _case(workloads.example1(64), 4)
+    p = workloads.config_c2(128, 32)
+    p.n2 = 63
+    _case(p, 5)
 
 
 def test_noalloc_rejects_grids_beyond_its_buffer():
