@@ -277,10 +277,11 @@ int fde_batch_set_grouping(fde_batch* b, int32_t max_n, int32_t slots);
 
 /* Streams.  lanes = 0 (the default): every ungrouped request and every group gets a stream of its own.
  * lanes >= 2: the batch creates that many streams at once (consecutive streams go to different
- * hardware queues of the device); every ungrouped request runs on the first, the groups are dealt to
- * the others in turn.  The larger (ungrouped) requests then share one hardware queue instead of
- * queueing in front of the small requests' kernels; ungrouped requests no longer overlap each other.
- * Only on an empty batch (no requests or groups); FDE_EINVAL for lanes 1 or above 16. */
+ * hardware queues of the device); the ungrouped requests are dealt in turn to the first lanes / 2 of
+ * them, with at most one piece in flight per lane, and the groups to the others.  The larger
+ * (ungrouped) requests then keep to their own hardware queues instead of queueing in front of the
+ * small requests' kernels.  Only on an empty batch (no requests or groups); FDE_EINVAL for lanes 1 or
+ * above 16. */
 int fde_batch_set_lanes(fde_batch* b, int32_t lanes);
 
 /* Scheduling.  piece_steps > 0 issues every restart cycle (Sec. 5: GMRES restarted every 20 steps) in

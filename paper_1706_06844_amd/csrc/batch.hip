@@ -47,6 +47,7 @@ struct Request {
   hipStream_t stream = nullptr;
   int group = -1;  // index of its group in grouped mode (the stream then belongs to the group)
   bool own_stream = false;  // the stream was created for this request
+  int lane = -1;            // index of its lane when the batch has lanes
   int slot = -1;
   int cycles = 0;  // restart cycles of the solve in flight (grouped mode)
   fde_problem p{};
@@ -169,10 +170,11 @@ struct fde_batch {
   int piece_steps = 0;  // Arnoldi steps per issued piece of a restart cycle (0: whole cycles)
   int busy_running = -1;  // ungrouped requests with a piece in flight while a group has work (-1: max_running)
   // lanes: streams created together at set-up (so that they map to distinct hardware queues): the
-  // first for every ungrouped request, the others dealt to the groups in turn; empty: a stream per
-  // request and per group
+  // first half for the ungrouped requests (dealt in turn, at most one piece in flight per lane), the
+  // others dealt to the groups in turn; empty: a stream per request and per group
   std::vector<hipStream_t> lanes;
   int groups_made = 0;
+  int ungrouped_made = 0;
 };
 
 extern "C" {
@@ -286,7 +288,8 @@ int fde_batch_admit(fde_batch* b, const fde_problem* p, const double* dp, const 
       g.member.assign(g.nslots, -1);
       if (hipMalloc(&g.arena, gbytes) != hipSuccess) return FDE_ENOMEM;
       if (!b->lanes.empty()) {
-        g.stream = b->lanes[1 + b->groups_made % ((int)b->lanes.size() - 1)];
+        const int nb = (int)b->lanes.size() / 2;
+        g.stream = b->lanes[nb + b->groups_made % ((int)b->lanes.size() - nb)];
       } else if (hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking) == hipSuccess) {
         g.own_stream = true;
       }
@@ -355,7 +358,8 @@ int fde_batch_admit(fde_batch* b, const fde_problem* p, const double* dp, const 
     }
   } else {
     if (!b->lanes.empty()) {
-      r.stream = b->lanes[0];
+      r.lane = b->ungrouped_made++ % ((int)b->lanes.size() / 2);
+      r.stream = b->lanes[r.lane];
     } else {
       if (hipStreamCreateWithFlags(&r.stream, hipStreamNonBlocking) != hipSuccess)
         return fail(FDE_EDEVICE, "stream creation failed");
@@ -567,7 +571,7 @@ extern "C" {
 int fde_batch_step(fde_batch* b) {
   if (!b) return FDE_EINVAL;
   int completed = 0;
-  const bool capped = b->max_running > 0 || b->busy_running >= 0;
+  const bool capped = b->max_running > 0 || b->busy_running >= 0 || !b->lanes.empty();
   while (true) {
     int active = 0;
     completed += step_groups(b, &active);
@@ -627,12 +631,17 @@ int fde_batch_step(fde_batch* b) {
         }
       }
       int inflight = 0;
+      int lane_busy[16] = {};
       std::vector<std::pair<double, Request*>> wait;
       for (auto& kv : b->reqs) {
         Request& r = kv.second;
         if (r.group >= 0) continue;
-        if (r.state == RS_RUNNING && !async_held(r.h)) ++inflight;
-        else if (r.state == RS_START || r.state == RS_RUNNING) wait.emplace_back(remaining_work(r), &r);
+        if (r.state == RS_RUNNING && !async_held(r.h)) {
+          ++inflight;
+          if (r.lane >= 0) ++lane_busy[r.lane];
+        } else if (r.state == RS_START || r.state == RS_RUNNING) {
+          wait.emplace_back(remaining_work(r), &r);
+        }
       }
       std::stable_sort(wait.begin(), wait.end(),
                        [](const std::pair<double, Request*>& a, const std::pair<double, Request*>& c) {
@@ -641,6 +650,7 @@ int fde_batch_step(fde_batch* b) {
       for (auto& w : wait) {
         if (inflight >= limit) break;
         Request& r = *w.second;
+        if (r.lane >= 0 && lane_busy[r.lane] > 0) continue;  // one piece in flight per lane
         if (r.state == RS_START) {
           if (!start_step(r, false)) {
             ++completed;
@@ -654,6 +664,7 @@ int fde_batch_step(fde_batch* b) {
         }
         ++inflight;
         ++active;
+        if (r.lane >= 0) ++lane_busy[r.lane];
       }
     }
     if (completed > 0 || active == 0) break;
