@@ -31,6 +31,8 @@ if ROOT not in sys.path:
 
 METRIC = "MG-GMRES CN time-steps/s at 2047² + p50/p99 latency, mixed vs FP64 plain"
 HBM_PEAK_GBS = 8000.0
+FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X dense FP64 vector
+FP32_VALU_PEAK_TFLOPS = 157.3  # MI355X FP32 vector
 # live timing of the dominant kernel samples every PROFILE_STRIDE-th launch (coprime to the two or three
 # Gram-Schmidt passes per step and to the restart length 20)
 PROFILE_STRIDE = 17
@@ -193,6 +195,53 @@ def run_precision(prec, p, dev_fields, S, phis, u0, steps, warmup, maxit, profil
     out = {"elapsed": elapsed, "lat": lat, "iters": its, "u": u_final.clone(), "family": fam,
            "live": live, "fin": fin, "warm_profile": prof, "reorth": reo}
     h.close()
+    return out
+
+
+def copy_bandwidth(nbytes=33521672, reps=20):
+    """Device-to-device copy of a field (torch), timed with events: the practical HBM rate the
+    streaming kernels are compared with besides the nominal peak (GB/s counting read + write)."""
+    import torch
+
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    b.synchronize()
+    return 2.0 * nbytes * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+
+
+def family_rates(prof, n1, n2):
+    """Per kernel family of a fully timed step: launches, mean duration and algorithmic GB/s; for the
+    fine-level FFT passes also the transform arithmetic (5 L log2 L flops per complex transform, three
+    transforms per pair of rows or columns) against the vector peak of their precision."""
+    import math
+
+    L1 = 1 << math.ceil(math.log2(2 * n1 - 1))
+    L2 = 1 << math.ceil(math.log2(2 * n2 - 1))
+    fft_flops = {"y": 3 * 5 * L2 * math.log2(L2) * math.ceil(n1 / 2),
+                 "x": 3 * 5 * L1 * math.log2(L1) * math.ceil(n2 / 2)}
+    out = {}
+    for fam, v in prof.items():
+        if not v["launches"] or v["ms"] <= 0:
+            continue
+        us = 1e3 * v["ms"] / v["launches"]
+        r = {"launches": int(v["launches"]), "us_per_launch": round(us, 2)}
+        if v["bytes"] > 0:
+            gbs = v["bytes"] / v["launches"] / (us * 1e-6) / 1e9
+            r["GB_s"] = round(gbs, 1)
+            r["frac_hbm"] = round(gbs / HBM_PEAK_GBS, 4)
+        if fam in ("outer_y", "outer_x", "mg0_y", "mg0_x"):
+            fl = fft_flops[fam[-1]] / (us * 1e-6) / 1e12
+            peak = FP64_VALU_PEAK_TFLOPS if fam.startswith("outer") else FP32_VALU_PEAK_TFLOPS
+            r["fft_TFLOPs"] = round(fl, 2)
+            r["frac_valu"] = round(fl / peak, 4)
+        out[fam] = r
     return out
 
 
@@ -741,6 +790,12 @@ def main():
     if "fp64" in res and main_name != "fp64":
         out["speedup_vs_fp64"] = out["value"] / out["fp64_value"]
     out["warm_profile_ms"] = {k: round(v["ms"], 3) for k, v in m["warm_profile"].items()}
+    # every family of one fully timed step (events around each launch, so slightly slower than the
+    # timed run): rates against HBM and, for the fine-level transforms, against the vector peak
+    out["family_rates"] = family_rates(m["warm_profile"], p.n1, p.n2)
+    copy_gbs = copy_bandwidth()
+    out["roofline"]["copy_GB_s"] = round(copy_gbs, 1)
+    out["roofline"]["frac_of_copy"] = round(achieved / copy_gbs, 4)
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(p, out["iters_per_step"], args.cpu_sample_iters)
