@@ -83,6 +83,8 @@ def parse():
     ap.add_argument("--no-c4", action="store_true", help="skip the C4 (64 batched instances) keys")
     ap.add_argument("--c4-modes", type=str, default="mixed,fp64,cycle",
                     help="--workload c4: precision modes (the first of mixed/fp64/cycle present gives the value)")
+    ap.add_argument("--c4-slots", type=int, default=0,
+                    help="--workload c4: slots per group (0: the count of the most frequent size)")
     ap.add_argument("--c4-piece", type=int, default=0,
                     help="--workload c4: Arnoldi steps per issued piece of a restart cycle (0: whole cycles)")
     ap.add_argument("--c4-grouped-only", action="store_true",
@@ -388,7 +390,7 @@ def admit(b, hr, precision, rtol, maxit):
     return fde.fde_batch_admit(b, s, *F, d(hr["u0"]), p.M, 0.0, hr["coef"], hr["rate"], [d(f) for f in hr["S"]])
 
 
-def c4_results(modes=("mixed", "fp64", "cycle"), ungrouped=True, sequential=True, piece=0):
+def c4_results(modes=("mixed", "fp64", "cycle"), ungrouped=True, sequential=True, piece=0, slots=0):
     """C4: 64 uneven instances (n in {127,255,511}, 8 CN steps, rtol 1e-9) resident together.  Per
     precision mode: grouped batching (one group per size; every kernel of a restart cycle launched
     once over the solving members), optionally ungrouped batching (a stream and a graph per instance)
@@ -401,7 +403,8 @@ def c4_results(modes=("mixed", "fp64", "cycle"), ungrouped=True, sequential=True
     precs = {"mixed": fde.FDE_MIXED_FP32, "fp64": fde.FDE_FP64, "cycle": fde.FDE_MIXED_FP32_CYCLE}
     probs = workloads.config_c4_instances(64, 4, 8)
     reqs = [host_request(p) for p in probs]
-    slots = max(sum(1 for p in probs if p.n1 == n) for n in {p.n1 for p in probs})
+    # one group per size by default: as many slots as instances of the most frequent size
+    slots = slots or max(sum(1 for p in probs if p.n1 == n) for n in {p.n1 for p in probs})
 
     marker = torch.empty(7, device="cuda:0")
 
@@ -490,7 +493,7 @@ def c4_summary(c4):
 def run_c4(args):
     """The C4 line: the value is grouped batching with the FP32 V-cycle inside FP64 flexible GMRES."""
     c4 = c4_results(modes=tuple(args.c4_modes.split(",")), ungrouped=not args.c4_grouped_only,
-                    sequential=not args.c4_grouped_only, piece=args.c4_piece)
+                    sequential=not args.c4_grouped_only, piece=args.c4_piece, slots=args.c4_slots)
     name = "mixed" if "mixed" in c4 else args.c4_modes.split(",")[0]
     m = c4[name]
     line = {
