@@ -166,3 +166,31 @@ def test_footprint_and_budget_admission_on_host():
     assert lib.fde_batch_info(out, ctypes.byref(active), ctypes.byref(used)) == 0
     assert active.value == 0 and used.value == 0
     lib.fde_batch_destroy(out)
+
+
+def test_batch_settings_are_validated_on_host():
+    # grouping, scheduling and lane settings check their arguments before touching the device
+    import ctypes
+
+    from paper_1706_06844_amd import _lib as L
+
+    lib = L.load()
+    out = ctypes.c_void_p()
+    assert lib.fde_batch_create(ctypes.c_size_t(1 << 30), None, ctypes.byref(out)) == 0
+    assert lib.fde_batch_set_grouping(out, 127, 0) == L.FDE_EINVAL
+    assert lib.fde_batch_set_grouping(out, 127, 2000) == L.FDE_EINVAL
+    assert lib.fde_batch_set_grouping(out, -1, 4) == L.FDE_EINVAL
+    assert lib.fde_batch_set_grouping(out, 511, 16) == 0
+    assert lib.fde_batch_set_grouping(out, 0, 0) == 0
+    assert lib.fde_batch_set_policy(out, -1, 0, -1) == L.FDE_EINVAL
+    assert lib.fde_batch_set_policy(out, 2, -1, -1) == L.FDE_EINVAL
+    assert lib.fde_batch_set_policy(out, 2, 5, -2) == L.FDE_EINVAL
+    assert lib.fde_batch_set_policy(out, 2, 5, 1) == 0
+    assert lib.fde_batch_set_policy(out, 0, 0, -1) == 0
+    assert lib.fde_batch_set_lanes(out, 1) == L.FDE_EINVAL
+    assert lib.fde_batch_set_lanes(out, 17) == L.FDE_EINVAL
+    assert lib.fde_batch_set_lanes(out, 0) == 0
+    assert lib.fde_batch_set_grouping(None, 127, 4) == L.FDE_EINVAL
+    assert lib.fde_batch_set_policy(None, 0, 0, -1) == L.FDE_EINVAL
+    assert lib.fde_batch_set_lanes(None, 0) == L.FDE_EINVAL
+    lib.fde_batch_destroy(out)
