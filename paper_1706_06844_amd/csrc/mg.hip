@@ -40,9 +40,37 @@ __global__ void presmooth_kernel(int N, const Tin* __restrict__ b, const double*
   }
 }
 
-// FP32 in and out, all arrays 16-byte aligned: runs of 4 (the tail of N mod 4 elementwise).
-__global__ void presmooth4_kernel(int N, const float* __restrict__ b, const double* __restrict__ bscale,
-                                  const float* __restrict__ dinv, float* __restrict__ x, float* __restrict__ bcopy,
+// Runs of 4 entries per thread with 16-byte accesses (an FP64 run takes two), all arrays 16-byte
+// aligned; the tail of N mod 4 elementwise.  Same arithmetic as presmooth_kernel.
+template <typename T>
+__device__ __forceinline__ void load4(const T* p, T (&v)[4]) {
+  if constexpr (sizeof(T) == 4) {
+    const float4 a = *reinterpret_cast<const float4*>(p);
+    v[0] = a.x;
+    v[1] = a.y;
+    v[2] = a.z;
+    v[3] = a.w;
+  } else {
+    const double2 a = *reinterpret_cast<const double2*>(p);
+    const double2 c = *reinterpret_cast<const double2*>(p + 2);
+    v[0] = a.x;
+    v[1] = a.y;
+    v[2] = c.x;
+    v[3] = c.y;
+  }
+}
+template <typename T>
+__device__ __forceinline__ void store4(T* p, const T (&v)[4]) {
+  if constexpr (sizeof(T) == 4) {
+    *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+  } else {
+    *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
+    *reinterpret_cast<double2*>(p + 2) = make_double2(v[2], v[3]);
+  }
+}
+template <typename R, typename Tin>
+__global__ void presmooth4_kernel(int N, const Tin* __restrict__ b, const double* __restrict__ bscale,
+                                  const R* __restrict__ dinv, R* __restrict__ x, R* __restrict__ bcopy,
                                   const int* __restrict__ skip, const long long* __restrict__ ztab) {
   FDE_ZBEGIN;
   FDE_ZSHIFT(b);
@@ -55,16 +83,20 @@ __global__ void presmooth4_kernel(int N, const float* __restrict__ b, const doub
   const double s = bscale ? *bscale : 1.0;
   const int N4 = N >> 2;
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < N4; q += gridDim.x * blockDim.x) {
-    const float4 bv4 = reinterpret_cast<const float4*>(b)[q];
-    const float4 d4 = reinterpret_cast<const float4*>(dinv)[q];
-    const float4 v = make_float4((float)(s * (double)bv4.x), (float)(s * (double)bv4.y), (float)(s * (double)bv4.z),
-                                 (float)(s * (double)bv4.w));
-    if (bcopy) reinterpret_cast<float4*>(bcopy)[q] = v;
-    reinterpret_cast<float4*>(x)[q] = make_float4(d4.x * v.x, d4.y * v.y, d4.z * v.z, d4.w * v.w);
+    Tin bb[4];
+    R d4[4], v[4], xo[4];
+    load4(b + 4 * q, bb);
+    load4(dinv + 4 * q, d4);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = (R)(s * (double)bb[k]);
+    if (bcopy) store4(bcopy + 4 * q, v);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) xo[k] = d4[k] * v[k];
+    store4(x + 4 * q, xo);
   }
   if (blockIdx.x == 0 && (int)threadIdx.x < N - 4 * N4) {
     const int p = 4 * N4 + threadIdx.x;
-    const float bv = (float)(s * (double)b[p]);
+    const R bv = (R)(s * (double)b[p]);
     if (bcopy) bcopy[p] = bv;
     x[p] = dinv[p] * bv;
   }
@@ -73,14 +105,12 @@ __global__ void presmooth4_kernel(int N, const float* __restrict__ b, const doub
 template <typename R, typename Tin>
 hipError_t launch_presmooth(int N, const Tin* b, const double* bscale, const R* dinv, R* x, R* bcopy,
                             const int* skip, hipStream_t st) {
-  if constexpr (std::is_same<R, float>::value && std::is_same<Tin, float>::value) {
-    const uintptr_t a = reinterpret_cast<uintptr_t>(b) | reinterpret_cast<uintptr_t>(dinv) |
-                        reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(bcopy);
-    if (a % 16 == 0) {
-      hipLaunchKernelGGL(presmooth4_kernel, dim3(grid_for((size_t)(N + 3) / 4), 1, batch_nz()), dim3(kBlock), 0, st, N,
-                         b, bscale, dinv, x, bcopy, skip, batch_ztab());
-      return hipGetLastError();
-    }
+  const uintptr_t a = reinterpret_cast<uintptr_t>(b) | reinterpret_cast<uintptr_t>(dinv) |
+                      reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(bcopy);
+  if (a % 16 == 0) {
+    hipLaunchKernelGGL((presmooth4_kernel<R, Tin>), dim3(grid_for((size_t)(N + 3) / 4), 1, batch_nz()), dim3(kBlock), 0,
+                       st, N, b, bscale, dinv, x, bcopy, skip, batch_ztab());
+    return hipGetLastError();
   }
   hipLaunchKernelGGL((presmooth_kernel<R, Tin>), dim3(grid_for(N), 1, batch_nz()), dim3(kBlock), 0, st, N, b, bscale,
                      dinv, x, bcopy, skip, batch_ztab());

@@ -42,6 +42,22 @@ __device__ __forceinline__ void symbol_both(R (&zr)[P::E], R (&zi)[P::E], R* zs,
   });
 }
 
+// The same products from symbol values already in registers (lr, li at positions t + T*m), for
+// kernels that load the symbol ahead of the forward transform.
+template <int L, typename P, typename R>
+__device__ __forceinline__ void symbol_both_regs(R (&zr)[P::E], R (&zi)[P::E], R* zs, const R (&lr)[P::E],
+                                                 const R (&li)[P::E], int t) {
+  constexpr int E = P::E, T = P::T;
+  static_for<0, E>([&](auto m) {
+    const int k = t + T * m;
+    const R a = zr[m], b = zi[m];
+    zr[m] = lr[m] * a - li[m] * b;
+    zi[m] = lr[m] * b + li[m] * a;
+    zs[k] = lr[m] * a + li[m] * b;
+    zs[L + k] = lr[m] * b - li[m] * a;
+  });
+}
+
 template <int L, typename P, typename R>
 __device__ __forceinline__ void unstash(R (&pr)[P::E], R (&pi)[P::E], const R* zs, int t) {
   constexpr int E = P::E, T = P::T;
@@ -87,11 +103,33 @@ using XPlan = Plan<L, (emax_for(sizeof(R), L) < FDE_EMAX_X ? emax_for(sizeof(R),
 template <typename R, int L>
 using YPlan = PlanFor<R, L>;
 
+// Loads issued one transform ahead.  The transforms of a pass are separated by LDS barriers, so a
+// load placed next to its use waits out its whole latency with every wave of the workgroup.
+// Row passes (toep_x_kernel): the operands of the epilogue (x, ay, b, 1/diag) are loaded before the
+// last inverse transform, for L >= FDE_X_PREFETCH_EPI_L; where a workgroup fills a CU's LDS (one
+// workgroup per CU, 2 waves per SIMD, so up to 256 registers cost no occupancy) the symbol is also
+// loaded before the forward transform and the (d+, d-) pairs before the first inverse one.
+// Measured at 2047^2 on gfx950 (kernel trace of one CN step): FP64 row pass at L = 4096 85.3 ->
+// 61.3 us, FP32 row passes 41.5 -> 34.0 us (L = 4096) and 16.1 -> 12.8 us (L = 2048), with the
+// same register occupancy; at L = 512 the FP64 Jacobi pass would lose a wave per SIMD, so the
+// threshold stays at 1024.  Results are unchanged (same arithmetic in the same order).
+#ifndef FDE_X_PREFETCH
+#define FDE_X_PREFETCH 1
+#endif
+#ifndef FDE_X_PREFETCH_EPI
+#define FDE_X_PREFETCH_EPI 1
+#endif
+#ifndef FDE_X_PREFETCH_EPI_L
+#define FDE_X_PREFETCH_EPI_L 1024
+#endif
 // Row pairs (transforms) per workgroup of the row pass: short transforms share a wavefront.
 template <typename R, int L>
 struct XCfg {
   static constexpr int S = XPlan<R, L>::T >= 64 ? 1 : 64 / XPlan<R, L>::T;
   static constexpr int THREADS = XPlan<R, L>::T * S;
+  static constexpr int LDS_BYTES = S * (lds_exchange(L) + 2 * L) * (int)sizeof(R);
+  static constexpr bool PREFETCH = FDE_X_PREFETCH && LDS_BYTES > 80 * 1024;
+  static constexpr bool PREFETCH_EPI = PREFETCH || (FDE_X_PREFETCH_EPI && L >= FDE_X_PREFETCH_EPI_L);
 };
 
 #ifndef FDE_Y_THREADS
@@ -104,6 +142,12 @@ struct XCfg {
 // row reads of a workgroup contiguous, but too many slots leave CUs idle on the shorter levels.
 // Measured on gfx950: L/1024 slots (at least a full wavefront, at most 512 threads) is best for
 // L = 1024..4096.
+// Column passes (toep_y_kernel) whose workgroup fills a CU's LDS load the symbol before the forward
+// transform and the (e+, e-) pairs before the first inverse one.  FP64 only: at L = 4096 it took the
+// FP64 pass from 96.0 to 92.4 us, while the FP32 pass went from 48.9 to 49.6 us.
+#ifndef FDE_Y_PREFETCH
+#define FDE_Y_PREFETCH 1
+#endif
 template <typename R, int L>
 struct YCfg {
   static constexpr int T_ = YPlan<R, L>::T;
@@ -111,6 +155,8 @@ struct YCfg {
   static constexpr int S0 = SW > 64 / T_ ? SW : 64 / T_;
   static constexpr int S = T_ * S0 <= FDE_Y_THREADS ? S0 : (T_ >= FDE_Y_THREADS ? 1 : FDE_Y_THREADS / T_);
   static constexpr int THREADS = YPlan<R, L>::T * S;
+  static constexpr int LDS_BYTES = S * (lds_exchange(L) + 2 * L) * (int)sizeof(R);
+  static constexpr bool PREFETCH = FDE_Y_PREFETCH && LDS_BYTES > 80 * 1024 && sizeof(R) == 8;
 };
 
 }  // namespace fde

@@ -87,13 +87,97 @@ __global__ __launch_bounds__((XCfg<R, L>::THREADS), FDE_XW) void toep_x_kernel(
       zi[m] = R(0);
     }
   });
+  using R2 = typename std::conditional<sizeof(R) == 4, float2, double2>::type;
+  constexpr bool PF = XCfg<R, L>::PREFETCH && MODE != EP_RHS;
+  if constexpr (XCfg<R, L>::PREFETCH_EPI && MODE != EP_RHS) {
+    R dmA[EH], dmB[EH];
+    R pr[E], pi[E];
+    if constexpr (PF) {
+      R lr[E], li[E];
+      static_for<0, E>([&](auto m) {
+        const int k = t + T * m;
+        lr[m] = mu[2 * k];
+        li[m] = mu[2 * k + 1];
+      });
+      if (skipv) return;
+      fft<L, -1, true>(zr, zi, lds, tw, t);
+      symbol_both_regs<L, P>(zr, zi, zs, lr, li, t);
+      R2 dA2[EH], dB2[EH];
+      static_for<0, EH>([&](auto m) {
+        const int i = t + T * m;
+        dA2[m] = R2{};
+        dB2[m] = R2{};
+        if (hasA && i < n1) dA2[m] = *reinterpret_cast<const R2*>(dA + 2 * i);
+        if (hasB && i < n1) dB2[m] = *reinterpret_cast<const R2*>(dB + 2 * i);
+      });
+      fft<L, +1>(zr, zi, lds, tw, t);  // real part: T xa, imaginary part: T xb
+      unstash<L, P>(pr, pi, zs, t);
+      static_for<0, EH>([&](auto m) {
+        const int i = t + T * m;
+        zs[i] = dA2[m].x * zr[m];
+        zs[L + i] = dB2[m].x * zi[m];
+        dmA[m] = dA2[m].y;
+        dmB[m] = dB2[m].y;
+      });
+    } else {
+      if (skipv) return;
+      fft<L, -1, true>(zr, zi, lds, tw, t);
+      symbol_both<L, P>(zr, zi, zs, mu, t);
+      fft<L, +1>(zr, zi, lds, tw, t);  // real part: T xa, imaginary part: T xb
+      unstash<L, P>(pr, pi, zs, t);
+      chunked_for<EH, kEpiGroup>([&](auto m) {
+        const int i = t + T * m;
+        R2 a{}, c{};
+        if (hasA && i < n1) a = *reinterpret_cast<const R2*>(dA + 2 * i);
+        if (hasB && i < n1) c = *reinterpret_cast<const R2*>(dB + 2 * i);
+        zs[i] = a.x * zr[m];
+        zs[L + i] = c.x * zi[m];
+        dmA[m] = a.y;
+        dmB[m] = c.y;
+      });
+    }
+    // the epilogue's operands of both rows, loaded before the second inverse transform
+    constexpr bool NX = MODE != EP_LOUT, NB = MODE == EP_RESID || MODE == EP_JACOBI, ND = MODE == EP_JACOBI;
+    Tin xv[2][EH];
+    R ayv[2][EH], bv[2][EH], dv[2][EH];
+    const size_t oR[2] = {oA, oB};
+    const bool hasR[2] = {hasA, hasB};
+    static_for<0, 2>([&](auto rc) {
+      constexpr int r = decltype(rc)::value;
+      const size_t o = oR[r];
+      static_for<0, EH>([&](auto m) {
+        const int i = t + T * m;
+        const bool ok = hasR[r] && i < n1;
+        xv[r][m] = Tin(0);
+        ayv[r][m] = bv[r][m] = dv[r][m] = R(0);
+        if (ok) {
+          if constexpr (NX) xv[r][m] = x[o + i];
+          if (ay) ayv[r][m] = ay[o + i];
+          if constexpr (NB) bv[r][m] = b[o + i];
+          if constexpr (ND) dv[r][m] = dinv[o + i];
+        }
+      });
+    });
+    fft<L, +1>(pr, pi, lds, tw, t);  // real part: T^T xa, imaginary part: T^T xb
+    static_for<0, EH>([&](auto m) {
+      const int i = t + T * m;
+      if (hasA && i < n1) {
+        const R l = zs[i] + dmA[m] * pr[m] + ayv[0][m];
+        out[oA + i] = epilogue_value<MODE, R, Tin>(l, xv[0][m], bv[0][m], dv[0][m], 0.0, tau);
+        if (hasB) {
+          const R l2 = zs[L + i] + dmB[m] * pi[m] + ayv[1][m];
+          out[oB + i] = epilogue_value<MODE, R, Tin>(l2, xv[1][m], bv[1][m], dv[1][m], 0.0, tau);
+        }
+      }
+    });
+    return;
+  }
   if (skipv) return;
   fft<L, -1, true>(zr, zi, lds, tw, t);
   symbol_both<L, P>(zr, zi, zs, mu, t);
   fft<L, +1>(zr, zi, lds, tw, t);  // real part: T xa, imaginary part: T xb
   R pr[E], pi[E];
   unstash<L, P>(pr, pi, zs, t);
-  using R2 = typename std::conditional<sizeof(R) == 4, float2, double2>::type;
   R dmA[EH], dmB[EH];
   chunked_for<EH, kEpiGroup>([&](auto m) {
     const int i = t + T * m;
@@ -134,6 +218,22 @@ __global__ __launch_bounds__((XCfg<R, L>::THREADS), FDE_XW) void toep_x_kernel(
     if (hasA && i < n1) {
       finish(xa, dmA[m], ayA, bA, diA, outA, oA, zs[i], pr[m], i);
       if (hasB) finish(xb, dmB[m], ayB, bB, diB, outB, oB, zs[L + i], pi[m], i);
+    }
+  });
+}
+
+// ay = e+ (T a) + e- (T^T a) for the column pair (c0, c0 + 1): the first products wait in zs, the
+// second in (pr, pi).
+template <int L, int EH, int T, typename R, int E>
+__device__ __forceinline__ void y_store(int n1, int n2, int c0, bool v0, bool v1, int t, const R* zs,
+                                        const R (&em0)[EH], const R (&em1)[EH], const R (&pr)[E],
+                                        const R (&pi)[E], R* __restrict__ ay) {
+  chunked_for<EH, kEpiGroup>([&](auto m) {
+    const int row = t + T * m;
+    if (row < n2) {
+      const unsigned p = (unsigned)row * (unsigned)n1 + (unsigned)c0;
+      if (v0) ay[p] = zs[row] + em0[m] * pr[m];
+      if (v1) ay[p + 1] = zs[L + row] + em1[m] * pi[m];
     }
   });
 }
@@ -183,6 +283,41 @@ __global__ __launch_bounds__((YCfg<R, L>::THREADS), FDE_YW) void toep_y_kernel(
       zi[m] = R(0);
     }
   });
+  using R2 = typename std::conditional<sizeof(R) == 4, float2, double2>::type;
+  R em0[EH], em1[EH];
+  if constexpr (YCfg<R, L>::PREFETCH) {
+    R lr[E], li[E];
+    static_for<0, E>([&](auto m) {
+      const int k = t + T * m;
+      lr[m] = mu[2 * k];
+      li[m] = mu[2 * k + 1];
+    });
+    if (skipv) return;
+    fft<L, -1, true>(zr, zi, lds, tw, t);
+    symbol_both_regs<L, P>(zr, zi, zs, lr, li, t);
+    R2 e0[EH], e1[EH];
+    static_for<0, EH>([&](auto m) {
+      const int row = t + T * m;
+      const unsigned p = (unsigned)row * (unsigned)n1 + (unsigned)c0;
+      e0[m] = R2{};
+      e1[m] = R2{};
+      if (row < n2 && v0) e0[m] = *reinterpret_cast<const R2*>(epm + 2 * p);
+      if (row < n2 && v1) e1[m] = *reinterpret_cast<const R2*>(epm + 2 * p + 2);
+    });
+    fft<L, +1>(zr, zi, lds, tw, t);  // T a + i T b along the columns
+    R pr[E], pi[E];
+    unstash<L, P>(pr, pi, zs, t);
+    static_for<0, EH>([&](auto m) {
+      const int row = t + T * m;
+      zs[row] = e0[m].x * zr[m];
+      zs[L + row] = e1[m].x * zi[m];
+      em0[m] = e0[m].y;
+      em1[m] = e1[m].y;
+    });
+    fft<L, +1>(pr, pi, lds, tw, t);  // T^T a + i T^T b
+    y_store<L, EH, T>(n1, n2, c0, v0, v1, t, zs, em0, em1, pr, pi, ay);
+    return;
+  }
   if (skipv) return;
   fft<L, -1, true>(zr, zi, lds, tw, t);
   symbol_both<L, P>(zr, zi, zs, mu, t);
@@ -190,8 +325,6 @@ __global__ __launch_bounds__((YCfg<R, L>::THREADS), FDE_YW) void toep_y_kernel(
   R pr[E], pi[E];
   unstash<L, P>(pr, pi, zs, t);
   // (e+, e-) of both columns in one read: e+ weights the first product now, e- waits in registers
-  using R2 = typename std::conditional<sizeof(R) == 4, float2, double2>::type;
-  R em0[EH], em1[EH];
   chunked_for<EH, kEpiGroup>([&](auto m) {
     const int row = t + T * m;
     const unsigned p = (unsigned)row * (unsigned)n1 + (unsigned)c0;
@@ -204,14 +337,7 @@ __global__ __launch_bounds__((YCfg<R, L>::THREADS), FDE_YW) void toep_y_kernel(
     em1[m] = e1.y;
   });
   fft<L, +1>(pr, pi, lds, tw, t);  // T^T a + i T^T b
-  chunked_for<EH, kEpiGroup>([&](auto m) {
-    const int row = t + T * m;
-    if (row < n2) {
-      const unsigned p = (unsigned)row * (unsigned)n1 + (unsigned)c0;
-      if (v0) ay[p] = zs[row] + em0[m] * pr[m];
-      if (v1) ay[p + 1] = zs[L + row] + em1[m] * pi[m];
-    }
-  });
+  y_store<L, EH, T>(n1, n2, c0, v0, v1, t, zs, em0, em1, pr, pi, ay);
 }
 
 template <typename R, typename Tin, int L>
