@@ -94,8 +94,8 @@ def parse():
     ap.add_argument("--workload", choices=["c3", "c4", "c5"], default="c3",
                     help="c3: the single 2047^2 instance (default, the headline line); c4: 64 batched "
                          "instances; c5: served requests with Poisson arrivals")
-    ap.add_argument("--c5-count", type=int, default=60, help="measured requests")
-    ap.add_argument("--c5-warmup", type=int, default=8, help="warm-up requests before the measured ones")
+    ap.add_argument("--c5-count", type=int, default=200, help="measured requests")
+    ap.add_argument("--c5-warmup", type=int, default=20, help="warm-up requests before the measured ones")
     ap.add_argument("--c5-kmax", type=int, default=11, help="largest grid 2^k - 1 of the served requests")
     ap.add_argument("--c5-max-running", type=int, default=2,
                     help="ungrouped requests with a cycle piece in flight at once (0: no limit)")
@@ -105,8 +105,12 @@ def parse():
                     help="streams shared by the batch: larger requests on one, groups on the others (0: own streams)")
     ap.add_argument("--c5-busy-running", type=int, default=1,
                     help="ungrouped (larger) requests with a piece in flight while a group has work (-1: no cap)")
+    ap.add_argument("--c5-loads", type=str, default="0.9",
+                    help="with --c5-qps auto: arrival rates as fractions of the saturation rate")
+    ap.add_argument("--c5-compare", action="store_true",
+                    help="also run at the highest load: the other busy cap, the plain policy and FP64")
     ap.add_argument("--c5-qps", type=str, default="auto",
-                    help="comma-separated arrival rates, or 'auto' for 50%% and 90%% of the saturation rate")
+                    help="comma-separated arrival rates, or 'auto' for the --c5-loads fractions of the saturation rate")
     ap.add_argument("--bf16", action="store_true",
                     help="also time the V-cycle with BF16 MFMA operator passes on its large levels")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -562,6 +566,8 @@ def serve(reqs, prec, budget, warm, max_running=0, group=(0, 0), piece=0, busy_r
                 lat[i] = t - reqs[i]["arrival"]
                 done_t[i] = t
                 del inflight[rid]
+                if len(done_t) % 10 == 0:
+                    log(f"c5 serve: {len(done_t)} of {len(reqs)} requests done at {t:.0f} s")
     b.close()
     meas = [i for i in range(len(reqs)) if i >= warm]
     span = max(done_t[i] for i in meas) - min(reqs[i]["arrival"] for i in meas)
@@ -595,8 +601,10 @@ def run_c5(args):
     steps each; solves/s, CN steps/s, p50/p99 latency overall and per grid side.  Requests up to
     511^2 share grouped launches; restart cycles are issued in pieces of --c5-piece Arnoldi steps and
     the larger requests are scheduled least-work-first with at most --c5-max-running pieces in
-    flight.  Runs: saturation (all requests at t = 0), 50 % and 90 % of it with that policy, and at
-    90 % the plain policy (whole cycles, every due cycle issued at once) and FP64.
+    flight.  Runs: each request alone, saturation (all requests at t = 0), then the --c5-loads
+    fractions of the saturation rate with that policy (default 90 %); with --c5-compare also, at the
+    highest load, the other busy cap, the plain policy (whole cycles, every due cycle issued at once)
+    and FP64.
     Slowdowns divide each request's latency by its latency alone on the device (mixed precision)."""
     import workloads
 
@@ -636,15 +644,18 @@ def run_c5(args):
         assert st >= 1, (i, st)
         if i >= warm:
             solo.append(time.perf_counter() - t0)
+        if (i + 1) % 10 == 0:
+            log(f"c5 solo: {i + 1} of {count} requests done")
     b.close()
     log(f"c5 solo: {sum(solo):.1f} s in all, largest {max(solo):.1f} s")
     mix = {str(2 ** k - 1): sum(1 for i in range(warm, count) if hrs[i]["p"].n1 == 2 ** k - 1) for k in ks}
     lat0, sides0, span0 = serve(reqs_at(1e9), fde.FDE_MIXED_FP32, budget, warm, cap, group, piece, gf, lanes)
     sat = args.c5_count / span0
     log(f"c5 saturation: {sat:.3f} solves/s ({span0:.1f} s)")
-    rates = [0.5 * sat, 0.9 * sat] if args.c5_qps == "auto" else [float(q) for q in args.c5_qps.split(",")]
+    loads = [float(f) for f in args.c5_loads.split(",")]
+    rates = [f * sat for f in loads] if args.c5_qps == "auto" else [float(q) for q in args.c5_qps.split(",")]
     plan = [(q, "mixed", cap, piece, gf) for q in rates]
-    if args.c5_qps == "auto":
+    if args.c5_qps == "auto" and args.c5_compare:
         # at 90 %: the other busy cap (0 if it is set, else 1), the plain policy and FP64
         plan += [(rates[-1], "mixed", cap, piece, 0 if gf != 0 else 1),
                  (rates[-1], "mixed", 0, 0, -1), (rates[-1], "fp64", cap, piece, gf)]
