@@ -4,9 +4,11 @@ On an even side the down-sampling of Sec. 4.1 keeps coarse point j at fine point
 so the hierarchy runs 2^l -> 2^(l-1) -> ... -> 8 (the paper's 8 x 8 coarsest grid) and the transfer
 stencils lose their entry at fine index 0.  The circulant embedding has length 2n.  Checked against
 the oracle: every level's operator (FP64 to 1e-12, FP32 to 2e-6), restriction and prolongation,
-the V-cycle (FP64 1e-12, FP32 1e-5), whole CN runs of Example 1 (1e-9 against the oracle's dense LU
-time stepping), and the final-time error against the exact solution, which must reproduce the
-Error column the paper prints for Example 1 (Table (tabel3)).
+the V-cycle (FP64 1e-12, FP32 1e-5), whole CN runs of Examples 1-3 (1e-9 against the oracle's dense
+LU time stepping where that finishes quickly), and the final-time error against the exact solution,
+which must reproduce the Error columns the paper prints (Tables (tabel3), (tabel1) and (tabel4)).
+Example 2's coefficients grow like (1 + t), so its runs refresh the operators and the hierarchy every
+step (fde_update_coeffs).
 """
 import json
 import os
@@ -141,3 +143,69 @@ def test_example1_paper_grid_128_reproduces_printed_error():
     note(f"Example 1 n=128: max error {err:.4e} (paper {printed:.4e}); mean iterations at rtol 1e-7: "
          f"{np.mean(its7):.2f}")
     assert err == pytest.approx(printed, rel=5e-3)
+
+
+def _printed(name, n):
+    return json.load(open(os.path.join(GOLDEN, "paper_error_tables.json")))[name][str(n)]
+
+
+def _final_error(p, u):
+    X, Y = workloads.grid(p)
+    return np.abs(u - p.u_exact(X, Y, p.T)).max()
+
+
+def _gpu_run_tdep(p, prec, rtol):
+    # time-dependent coefficients: step m uses them at t_m on the left and t_(m-1) on the right
+    h = make_handle(p, precision=prec, rtol=rtol, t=0.0)
+    u = dev(workloads.sample_u0(p))
+    un = torch.empty_like(u)
+    iters = []
+    for m in range(1, p.M + 1):
+        fields = [dev(f) for f in workloads.sample(p, m * p.tau)]
+        fde.fde_update_coeffs(h, *fields)
+        v = dev(workloads.sample_source(p, (m - 0.5) * p.tau))
+        st = fde.fde_step(h, u, v, un)
+        assert st["converged"], (m, st)
+        iters.append(st["iters"])
+        u, un = un, u
+    out = host(u)
+    h.close()
+    return out, iters
+
+
+EX23 = [(16, fde.FDE_FP64), (16, fde.FDE_MIXED_FP32), (32, fde.FDE_FP64), (32, fde.FDE_MIXED_FP32),
+        (64, fde.FDE_MIXED_FP32), (128, fde.FDE_MIXED_FP32)]
+
+
+@pytest.mark.parametrize("n,prec", EX23)
+def test_example2_paper_grid_reproduces_printed_error(n, prec):
+    # Example 2 of Sec. 5.2 at n1 = n2 = M = n; the oracle's dense LU stepping (one factorisation per
+    # step) up to n = 32
+    p = workloads.example2(n)
+    u, iters = _gpu_run_tdep(p, prec, 1e-12)
+    err, printed = _final_error(p, u), _printed("example2", n)
+    _, its7 = _gpu_run_tdep(p, prec, 1e-7)
+    note(f"Example 2 n={n} prec={prec}: max error {err:.4e} (paper {printed:.4e}); mean iterations "
+         f"{np.mean(iters):.2f} at rtol 1e-12, {np.mean(its7):.2f} at the paper's 1e-7")
+    if n <= 32:
+        e = rel(u, cn_run(p, solver=DirectSolver()).u)
+        note(f"  vs the oracle's run: {e:.2e}")
+        assert e <= 1e-9
+    assert err == pytest.approx(printed, rel=5e-3)
+
+
+@pytest.mark.parametrize("n,prec", EX23)
+def test_example3_paper_grid_reproduces_printed_error(n, prec):
+    # Example 3 of Sec. 5.3 at n1 = n2 = M = n; the oracle's dense LU stepping up to n = 64
+    p = workloads.example3(n)
+    u, iters = _gpu_run(p, prec, 1e-12)
+    err, printed = _final_error(p, u), _printed("example3", n)
+    _, its7 = _gpu_run(p, prec, 1e-7)
+    note(f"Example 3 n={n} prec={prec}: max error {err:.4e} (paper {printed:.4e}); mean iterations "
+         f"{np.mean(iters):.2f} at rtol 1e-12, {np.mean(its7):.2f} at the paper's 1e-7")
+    if n <= 64:
+        e = rel(u, cn_run(p, solver=DirectSolver()).u)
+        note(f"  vs the oracle's run: {e:.2e}")
+        assert e <= 1e-9
+    assert err == pytest.approx(printed, rel=5e-3)
+
