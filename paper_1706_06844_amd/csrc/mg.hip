@@ -419,7 +419,7 @@ __device__ __forceinline__ Pair<R> load_pair(const R* p) {
 // Entry m of the zero-extended weight table (w[n + k] = sw[k] for 0 <= k <= n, 0 below).
 template <typename R>
 __device__ __forceinline__ R wext_value(const R* __restrict__ sw, int n, int m) {
-  return (m >= n && m - n <= n && m < 2 * n + 2) ? sw[m - n] : R(0);
+  return load_or_zero(sw, m - n, m >= n && m - n <= n && m < 2 * n + 2);
 }
 
 // tau/2 (L x)(j, i) from the staged row xrow (whole length n1), the staged column xcol (stride nc)
@@ -469,12 +469,12 @@ struct TileLoads {
                                        const R* __restrict__ swx, const R* __restrict__ swy) {
     const int tid = threadIdx.x;
 #pragma unroll
-    for (int r = 0; r < NR; ++r) xrv[r] = (tid < n1 && r0 + r < n2) ? x[(size_t)(r0 + r) * n1 + tid] : R(0);
+    for (int r = 0; r < NR; ++r) xrv[r] = load_or_zero(x, (size_t)(r0 + r) * n1 + tid, tid < n1 && r0 + r < n2);
     const int cc = tid % NC, i = c0 + cc;
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
       const int k = tid / NC + u * KSTEP;
-      xcv[u] = (tid < KSTEP * NC && k < n2 && i < n1) ? x[(size_t)k * n1 + i] : R(0);
+      xcv[u] = load_or_zero(x, (size_t)k * n1 + i, tid < KSTEP * NC && k < n2 && i < n1);
     }
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
@@ -543,15 +543,17 @@ __global__ __launch_bounds__(kTileThreads) void tile_resid_restrict_kernel(
   const int rr = tid / kTileRF, cc = tid - rr * kTileRF;
   const int j = r0 + rr, i = c0 + cc;
   const bool own = tid < kTileRF * kTileRF && j < n2 && i < n1;
+  // every load unconditional (index 0 for threads without a point), the values selected afterwards
   const size_t p = own ? (size_t)j * n1 + i : 0;
-  const Pair<R> dpv = own ? load_pair(dpm + 2 * p) : Pair<R>{0, 0};
-  const Pair<R> epv = own ? load_pair(epm + 2 * p) : Pair<R>{0, 0};
-  const R bv = own ? b[p] : R(0);
+  Pair<R> dpv = load_pair(dpm + 2 * p);
+  Pair<R> epv = load_pair(epm + 2 * p);
+  const R bv = load_or_zero(b, p, own);
+  if (!own) dpv = epv = Pair<R>{0, 0};
   const int JJ = tid / kTileRC, II = tid - JJ * kTileRC;
   const int J = J0 + JJ, I = I0 + II;
   const bool cown = tid < kTileRC * kTileRC && J < k2 && I < k1;
   const size_t q = cown ? (size_t)J * k1 + I : 0;
-  const R dcv = (cown && xcout) ? dinv_c[q] : R(0);
+  const R dcv = xcout ? load_or_zero(dinv_c, q, cown) : R(0);
   if (skipv) return;
   ld.store_weights(n1, n2, wx, wy);
   ld.store_x(n1, n2, r0, c0, xr, xc, [](int, int) { return R(0); });

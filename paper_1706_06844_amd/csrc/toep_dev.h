@@ -122,6 +122,10 @@ using YPlan = PlanFor<R, L>;
 #ifndef FDE_X_PREFETCH_EPI_L
 #define FDE_X_PREFETCH_EPI_L 1024
 #endif
+// FP32 row passes keep their occupancy with the epilogue's loads ahead down to L = 256.
+#ifndef FDE_X_PREFETCH_EPI_L32
+#define FDE_X_PREFETCH_EPI_L32 256
+#endif
 // Row pairs (transforms) per workgroup of the row pass: short transforms share a wavefront.
 template <typename R, int L>
 struct XCfg {
@@ -129,7 +133,8 @@ struct XCfg {
   static constexpr int THREADS = XPlan<R, L>::T * S;
   static constexpr int LDS_BYTES = S * (lds_exchange(L) + 2 * L) * (int)sizeof(R);
   static constexpr bool PREFETCH = FDE_X_PREFETCH && LDS_BYTES > 80 * 1024;
-  static constexpr bool PREFETCH_EPI = PREFETCH || (FDE_X_PREFETCH_EPI && L >= FDE_X_PREFETCH_EPI_L);
+  static constexpr bool PREFETCH_EPI =
+      PREFETCH || (FDE_X_PREFETCH_EPI && L >= (sizeof(R) == 4 ? FDE_X_PREFETCH_EPI_L32 : FDE_X_PREFETCH_EPI_L));
 };
 
 #ifndef FDE_Y_THREADS
