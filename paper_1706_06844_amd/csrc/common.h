@@ -305,15 +305,6 @@ __device__ __forceinline__ T* zshift(T* p, long long zoff) {
 // index is an opaque zero in a vector register, so that waiting for the flag does not also wait for
 // the kernel's scalar argument loads, and a kernel can issue its other loads before it needs the flag.
 __device__ const int kZeroFlag = 0;
-// p[i] where ok, else 0, with the load itself unconditional (index 0, which must be valid, where
-// !ok).  A load under a per-lane branch whose other side writes 0 into the same register is waited
-// for where the branches join, so a run of such loads would be issued one at a time.
-template <typename T, typename I>
-__device__ __forceinline__ T load_or_zero(const T* __restrict__ p, I i, bool ok) {
-  const T v = p[ok ? i : I(0)];
-  return ok ? v : T(0);
-}
-
 __device__ __forceinline__ int load_flag(const int* p) {
   int z = 0;
   __asm__ volatile("" : "+v"(z));

@@ -13,6 +13,15 @@ namespace fde {
 
 constexpr int kBlock = 256;
 
+// p[i] where ok, else 0, with the load itself unconditional (index 0, which must be valid, where
+// !ok).  A load under a per-lane branch whose other side writes 0 into the same register is waited
+// for where the branches join, so a run of such loads would be issued one at a time.
+template <typename T, typename I>
+__device__ __forceinline__ T load_or_zero(const T* __restrict__ p, I i, bool ok) {
+  const T v = p[ok ? i : I(0)];
+  return ok ? v : T(0);
+}
+
 static inline int grid_for(size_t n, int per_block = kBlock) {
   size_t g = (n + per_block - 1) / per_block;
   if (g > 65535 * 16) g = 65535 * 16;
