@@ -67,6 +67,19 @@ __device__ __forceinline__ void unstash(R (&pr)[P::E], R (&pi)[P::E], const R* z
   });
 }
 
+// p[i] where ok, else 0, with the load itself unconditional (index 0, which must be valid, where
+// !ok).  Written as (a && b) ? p[i] : 0, the load went under a per-lane branch on a and was waited
+// for before the branch closed, so the run of loads at the start of a pass went out one at a time.
+// The index passes through an empty asm statement, so the compiler cannot move the load under a
+// branch again; callers combine their conditions with & rather than &&.
+template <typename T, typename I>
+__device__ __forceinline__ T load_or_zero(const T* __restrict__ p, I i, bool ok) {
+  I j = ok ? i : I(0);
+  __asm__("" : "+v"(j));
+  const T v = p[j];
+  return ok ? v : T(0);
+}
+
 // A pointer that is the same for the whole wavefront, kept in scalar registers: loads then use a
 // scalar base plus a 32-bit per-lane offset instead of one 64-bit address per element.
 template <typename T>

@@ -66,11 +66,12 @@ __global__ __launch_bounds__((XCfg<R, L>::THREADS), FDE_XW) void toep_x_kernel(
   const int rowA = 2 * (blockIdx.x * S + slot);
   const bool hasA = rowA < n2;
   const bool hasB = rowA + 1 < n2;
-  // per-row base pointers (uniform when a workgroup holds one row pair); in-row offsets are 32-bit
+  // per-row base pointers (uniform when a workgroup holds one row pair); in-row offsets are 32-bit.
+  // The x rows of a missing row point at row 0, so that their (unused) loads stay in bounds.
   const size_t oA = (size_t)rowA * n1, oB = oA + n1;
   auto U = [&](auto* ptr) { return S == 1 ? uniform_ptr(ptr) : ptr; };
-  const Tin* xa = U(x + oA);
-  const Tin* xb = U(x + oB);
+  const Tin* xa = U(x + (hasA ? oA : 0));
+  const Tin* xb = U(x + (hasB ? oB : 0));
   const R* dA = U(dpm + 2 * oA);
   const R* dB = U(dpm + 2 * oB);
   // n1 <= L/2: a row occupies registers m < E/2; the rest is the zero padding of the embedding, and
@@ -80,8 +81,8 @@ __global__ __launch_bounds__((XCfg<R, L>::THREADS), FDE_XW) void toep_x_kernel(
   static_for<0, E>([&](auto m) {
     const int i = t + T * m;
     if constexpr (decltype(m)::value < EH) {
-      zr[m] = (hasA && i < n1) ? (R)xa[i] : R(0);
-      zi[m] = (hasB && i < n1) ? (R)xb[i] : R(0);
+      zr[m] = (R)load_or_zero(xa, i, hasA & (i < n1));
+      zi[m] = (R)load_or_zero(xb, i, hasB & (i < n1));
     } else {
       zr[m] = R(0);
       zi[m] = R(0);
@@ -276,8 +277,8 @@ __global__ __launch_bounds__((YCfg<R, L>::THREADS), FDE_YW) void toep_y_kernel(
     const int row = t + T * m;
     const unsigned p = (unsigned)row * (unsigned)n1 + (unsigned)c0;
     if constexpr (decltype(m)::value < EH) {
-      zr[m] = (row < n2 && v0) ? (R)x[p] : R(0);
-      zi[m] = (row < n2 && v1) ? (R)x[p + 1] : R(0);
+      zr[m] = (R)load_or_zero(x, p, (row < n2) & v0);
+      zi[m] = (R)load_or_zero(x, p + 1u, (row < n2) & v1);
     } else {
       zr[m] = R(0);
       zi[m] = R(0);
