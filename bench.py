@@ -48,9 +48,9 @@ PMC_TRAFFIC = {
              "sha256": "5f4536c500e2326c4c0e254f4e5ff7ba1d5c8cb1b33bf21c2b10e2c3f14644be",
              "summary": "profiles/gram_schmidt_fp64_c3_2047.md"},
     # toep_y_kernel<float, float, 4096, false>: 1052 dispatches of the same step
-    "mg0_y": {"bytes_per_launch": 71.21e6,
+    "mg0_y": {"bytes_per_launch": 70.98e6,
               "sources": ['paper_1706_06844_amd/csrc/toeplitz.hip', 'paper_1706_06844_amd/csrc/toep_dev.h', 'paper_1706_06844_amd/csrc/fft.h', 'paper_1706_06844_amd/csrc/common.h'],
-              "sha256": "1c192627c3caa764d7ffff8e9660c27d196423774a5c3c72cefa5ffae0289eaa",
+              "sha256": "d83e1263bf063f26c450e3c3026638915c19d52f25c4ce8381a31ea1f9c2f556",
               "summary": "profiles/fft_column_pass_c3_2047.md"},
 }
 
